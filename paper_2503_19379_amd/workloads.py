@@ -1,0 +1,154 @@
+"""Seeded synthetic inputs: permittivity voxel grids, Brillouin-zone k-paths
+and random start blocks.
+
+This module holds none of the method's arithmetic (no operator, symbol,
+penalty or solver): it only draws inputs, and it is the one module that both
+the HIP path's callers and the CPU oracle's callers share.  It imports numpy
+only.
+
+Geometry follows the paper's lattices where the paper gives them (simple cubic
+cell [0, L]^3, Section 6 eq. (translation_vecs); Brillouin-zone points of the
+simple cubic lattice, Section 6) and the synthetic workloads otherwise:
+a dielectric sphere, the conventional cubic cell of a diamond lattice of
+spheres, and thresholded Gaussian random fields.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS_HIGH = 13.0
+EPS_LOW = 1.0
+
+
+def _min_image(d: np.ndarray, L: float) -> np.ndarray:
+    return d - L * np.round(d / L)
+
+
+def eps_homogeneous(N: int, value: float = 1.0) -> np.ndarray:
+    return np.full((N, N, N), float(value))
+
+
+def eps_spheres(N: int, centers, r: float, L: float = 1.0, eps_in: float = EPS_HIGH,
+                eps_out: float = EPS_LOW, sub: int = 4) -> np.ndarray:
+    """Cell permittivity of periodic dielectric spheres of radius r, each cell
+    the arithmetic mean over sub^3 cell-centred sub-samples (voxel average).
+    Arrays are [z][y][x]."""
+    h = L / N
+    base = np.arange(N, dtype=np.float64)
+    cen = np.asarray(centers, dtype=np.float64)
+    frac = np.zeros((N, N, N))
+    for oz in range(sub):
+        z = (base + (oz + 0.5) / sub) * h
+        for oy in range(sub):
+            y = (base + (oy + 0.5) / sub) * h
+            for ox in range(sub):
+                x = (base + (ox + 0.5) / sub) * h
+                inside = np.zeros((N, N, N), dtype=bool)
+                for c in cen:
+                    dx = _min_image(x - c[0], L) ** 2
+                    dy = _min_image(y - c[1], L) ** 2
+                    dz = _min_image(z - c[2], L) ** 2
+                    inside |= (dz[:, None, None] + dy[None, :, None] + dx[None, None, :]) <= r * r
+                frac += inside
+    frac /= sub ** 3
+    return eps_out + (eps_in - eps_out) * frac
+
+
+def eps_sphere(N: int, r: float = 0.25, L: float = 1.0, sub: int = 4) -> np.ndarray:
+    """One sphere of radius r at the cell centre, eps 13 inside, 1 outside."""
+    return eps_spheres(N, [(0.5 * L, 0.5 * L, 0.5 * L)], r, L, sub=sub)
+
+
+DIAMOND_SITES = np.array([
+    (0.0, 0.0, 0.0), (0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0),
+    (0.25, 0.25, 0.25), (0.25, 0.75, 0.75), (0.75, 0.25, 0.75), (0.75, 0.75, 0.25),
+])
+
+
+def eps_diamond(N: int, r: float = 0.13, L: float = 1.0, sub: int = 4) -> np.ndarray:
+    """Conventional cubic cell of a diamond lattice: spheres of radius r at the
+    eight sites (fcc sites and the same shifted by (1/4, 1/4, 1/4))."""
+    return eps_spheres(N, DIAMOND_SITES * L, r, L, sub=sub)
+
+
+def eps_random_field(N: int, seed: int, corr: float = 0.15, fill: float = 0.30,
+                     L: float = 1.0) -> np.ndarray:
+    """Gaussian random field with correlation length ``corr`` (covariance
+    exp(-r^2 / (2 corr^2))), thresholded so that the top ``fill`` fraction of
+    cells get eps = 13 and the rest eps = 1."""
+    rng = np.random.default_rng(seed)
+    noise = rng.standard_normal((N, N, N)) + 1j * rng.standard_normal((N, N, N))
+    q = 2 * np.pi * np.fft.fftfreq(N, d=L / N)
+    q2 = q[:, None, None] ** 2 + q[None, :, None] ** 2 + q[None, None, :] ** 2
+    field = np.real(np.fft.ifftn(np.fft.fftn(noise) * np.exp(-q2 * corr * corr / 4.0)))
+    thr = np.quantile(field, 1.0 - fill)
+    return np.where(field > thr, EPS_HIGH, EPS_LOW)
+
+
+def sc_points(L: float = 1.0) -> dict:
+    """Symmetry points of the simple cubic Brillouin zone (Section 6): the
+    paper's L(pi/l, 0, 0) and N(pi/l, pi/l, pi/l) are the usual X and R."""
+    p = np.pi / L
+    return {"G": (0.0, 0.0, 0.0), "X": (p, 0.0, 0.0), "M": (p, p, 0.0), "R": (p, p, p)}
+
+
+def kpath(labels: str, n: int, L: float = 1.0) -> np.ndarray:
+    """n k-points uniform in arc length along the polyline through the named
+    simple cubic points (e.g. "GXMGR"), both ends included.  Shape (n, 3)."""
+    pts = sc_points(L)
+    P = np.array([pts[c] for c in labels], dtype=np.float64)
+    seg = np.linalg.norm(np.diff(P, axis=0), axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    s = np.linspace(0.0, cum[-1], n)
+    out = np.empty((n, 3))
+    for j, t in enumerate(s):
+        i = min(np.searchsorted(cum, t, side="right") - 1, len(seg) - 1)
+        f = (t - cum[i]) / seg[i]
+        out[j] = P[i] + f * (P[i + 1] - P[i])
+    out[np.abs(out) < 1e-15] = 0.0
+    return out
+
+
+def start_block(m: int, N: int, seed: int) -> np.ndarray:
+    """Seeded complex Gaussian start block, shape (m, 3, N, N, N), complex128
+    (real and imaginary parts independent standard normals)."""
+    rng = np.random.default_rng(seed)
+    shp = (m, 3, N, N, N)
+    return rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+
+
+# Synthetic workloads (shapes, seeds, paths).  Units: L = 1.
+CONFIGS = {
+    # homogeneous unit cube, dense check
+    "homog_n8": dict(N=8, eps="homogeneous", kpts=[(0.3 * np.pi, 0.2 * np.pi, 0.1 * np.pi)],
+                     nbands=8, precision="fp64"),
+    # simple cubic lattice of one sphere, FP64
+    "sphere_n32": dict(N=32, eps="sphere", path="GXMGR", nk=20, nbands=10, tol=1e-8,
+                       precision="fp64"),
+    # diamond conventional cell, mixed precision
+    "diamond_n64": dict(N=64, eps="diamond", path="GXMGR", nk=64, nbands=16, tol=1e-8,
+                        precision="mixed"),
+    # 32 random-field crystals of uneven grids
+    "random_batch": dict(Ns=(24, 32, 48, 64), ncrys=32, eps="random", path="GXMGR", nk=8,
+                         nbands=12, tol=1e-8, precision="mixed"),
+    # diamond at N = 96, learned warm start
+    "diamond_n96": dict(N=96, eps="diamond", path="GXMGRX", nk=100, nbands=20, tol=1e-8,
+                        precision="mixed"),
+}
+
+
+def crystal_eps(name: str, N: int, seed: int = 0) -> np.ndarray:
+    if name == "homogeneous":
+        return eps_homogeneous(N)
+    if name == "sphere":
+        return eps_sphere(N)
+    if name == "diamond":
+        return eps_diamond(N)
+    if name == "random":
+        return eps_random_field(N, seed)
+    raise ValueError(name)
+
+
+def random_batch_crystals(ncrys: int = 32, Ns=(24, 32, 48, 64)):
+    """(N, eps) for crystal c = 0..ncrys-1: N = Ns[c mod len(Ns)], seed c."""
+    return [(Ns[c % len(Ns)], eps_random_field(Ns[c % len(Ns)], c)) for c in range(ncrys)]
