@@ -1,0 +1,138 @@
+/*
+ * mfdkc: kernel-compensated mimetic finite differences for the Maxwell
+ * eigenproblem in photonic crystals (arXiv 2503.19379), on MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  Every function returns MFD_OK (0) or
+ * a negative mfd_status; no C++ exception crosses this boundary, and
+ * mfd_last_error() gives a thread-local detail string for the last failure.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.  The periodic cube [0, L]^3 is cut into N^3 cells of side h = L / N
+ *   (Section 4.1.1).  A grid function is stored [z][y][x], x fastest: linear
+ *   index x + N (y + N z).  This is the order implied by the Kronecker form
+ *   K_1 = I (x) I (x) D_1 / h of eq. (blocks).
+ * Fields.  The unknown H lives on cell faces F_h (eq. (DoFs_grid)).  One
+ *   field is 3 components x N^3 complex values, stored [comp][z][y][x].  A
+ *   block of nb fields is stored [band][comp][z][y][x], i.e. column-major
+ *   n x nb with n = 3 N^3.  Complex values are interleaved (re, im):
+ *   MFD_C128 = two doubles, MFD_C64 = two floats.
+ * Bloch vector.  k = (k_x, k_y, k_z) is Cartesian, in units of 1/L; it is
+ *   the shift alpha of the discrete operators (Section 4.1.2).
+ * Operator.  op(k) = A M_0 A' + gamma(k) B'B + c(k) I with A = curl_alpha,
+ *   B = div_alpha (eq. (discrete_2nd_block)), M_0 = diag(mu) on edges from
+ *   eps^-1 (Section 4.4), gamma(k) the penalty number (eq. (pnt_number)) and
+ *   c(k) the shift of Remark 5.1.  Readings of the paper used here:
+ *     mu on an edge = 4 / (sum of eps over the 4 cells sharing the edge);
+ *     gamma(k) = 2 max{ N / (2 pi), (2 pi / (L |k|))^2 }, i.e. the rule of
+ *       eq. (pnt_number) in the paper's units of lattice constant 2 pi
+ *       (the |k|^-2 term is dropped at k = 0), unless set by mfd_set_gamma;
+ *     c(k) = (pi / L)^2 if k = 0, else 0.
+ *   Eigenvalues reported by mfd_bands have c(k) subtracted.
+ * Streams.  Every call is ordered on `stream` (a hipStream_t passed as
+ *   void*; NULL = the null stream).  mfd_op_apply and mfd_precond_solve are
+ *   asynchronous to the host; mfd_bands returns once evals are on the host.
+ * Ownership.  The caller owns every buffer passed in.  The library owns the
+ *   context (device copies of M_0, FFT twiddles, solver workspace), freed by
+ *   mfd_destroy.  A context is not thread safe: use one per host thread.
+ */
+#ifndef MFDKC_H
+#define MFDKC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfd_ctx mfd_ctx;
+
+typedef enum { MFD_C64 = 1, MFD_C128 = 2 } mfd_dtype;
+
+typedef enum {
+    MFD_OK = 0,
+    MFD_EINVAL = -1,        /* bad argument (null pointer, size, non-finite or non-positive eps, aliasing) */
+    MFD_ENOMEM = -2,        /* device allocation failed */
+    MFD_EDEVICE = -3,       /* a HIP call or kernel launch failed */
+    MFD_ENOTCONV = -4,      /* max_iter reached; evals/stats hold the best values found */
+    MFD_ESPURIOUS = -5,     /* Alg 4.1 still flags a band after max_gamma_doublings */
+    MFD_EUNSUPPORTED = -6   /* grid size or stencil order this build does not handle */
+} mfd_status;
+
+/* Options of mfd_bands.  Zero-initialise, then set what you need;
+ * mfd_default_opts fills in the defaults. */
+typedef struct {
+    int max_iter;             /* LOBPCG iterations per k-point (default 400) */
+    int precision;            /* 0: FP64 throughout; 1: mixed FP32 corrections + FP64 refinement */
+    int warm_start;           /* 0: random start at every k (seed); 1: previous k's vectors */
+    unsigned long long seed;  /* random start blocks */
+    int max_gamma_doublings;  /* Alg 4.1 restarts (default 4) */
+    int guard;                /* extra block columns beyond nbands (default 0) */
+    const void* x0;           /* optional device c128 start block [nbands][3][N][N][N] for the first
+                                 k-point (NULL: random) */
+} mfd_opts;
+
+typedef struct {
+    int iters;                /* LOBPCG iterations, summed over gamma restarts */
+    int gamma_doublings;      /* Alg 4.1 restarts taken */
+    double gamma;             /* penalty number used for the returned bands */
+    double max_rel_resid;     /* max_i |op x_i - theta_i x_i| / (theta_i |x_i|), FP64 operator */
+    int spurious;             /* bands still flagged by Alg 4.1 */
+    int used_fallback;        /* warm start fell back to the random/previous-k start */
+    float ms;                 /* wall time of this k-point */
+} mfd_kstats;
+
+void mfd_default_opts(mfd_opts* opts);
+
+/* Build a context for one crystal (Section 4.4: M_0 from eps).
+ * N: cells per axis, 4 <= N <= 128, with an FFT plan for N (N = 2^a 3^b 5^c
+ *    supported by this build: see mfd_supported_n).
+ * L: cell side (> 0).  order: stencil order 2 (Table FD_1D, k = 1).
+ * eps_cells: host, N^3 doubles, [z][y][x], finite and > 0 (cell permittivity).
+ * Errors: MFD_EINVAL, MFD_EUNSUPPORTED, MFD_ENOMEM, MFD_EDEVICE. */
+int mfd_build(int N, double L, int order, const double* eps_cells, void* stream, mfd_ctx** out);
+
+/* 1 if this build has an FFT plan and stencil for grid size N, else 0. */
+int mfd_supported_n(int N);
+
+/* Override the penalty number (gamma > 0), or restore the rule (gamma <= 0). */
+int mfd_set_gamma(mfd_ctx* ctx, double gamma);
+
+/* gamma(k) and c(k) this context uses at k (host, no device work). */
+int mfd_gamma_shift(const mfd_ctx* ctx, const double k[3], double* gamma, double* shift);
+
+/* Y = op(k) X for nb fields (eq. (Ker_comp) plus the shift c(k)).
+ * X, Y: device, [nb][3][N][N][N] interleaved complex of `dtype`; must not
+ * overlap.  FP32 (MFD_C64) uses an FP32 copy of M_0. */
+int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* X, void* Y,
+                 void* stream);
+
+/* T = (P + c(k) I)^-1 R for nb fields, with P = A A' + gamma B'B the
+ * preconditioner of Section 5.1 eq. (penalised_marix), solved as in Alg 5.1:
+ * forward FFT along each axis, the 3 x 3 symbol solve at every frequency
+ * (closed-form rank-one inverse: P_hat = s I + (gamma - 1) conj(d) d^T),
+ * inverse FFT along each axis.  R and T may be the same buffer. */
+int mfd_precond_solve(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* R, void* T,
+                      void* stream);
+
+/* lambda_re of Alg 4.1: out[i] = |M_0^(1/2) A' x_i|^2 / |x_i|^2 for nb c128
+ * fields X (device).  out: host, nb doubles. */
+int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double* out, void* stream);
+
+/* Lowest nbands physical eigenpairs at each of nk Bloch vectors: LOBPCG
+ * (Section 5.1) preconditioned by mfd_precond_solve, then the recompute
+ * check of Alg 4.1 with gamma doubled on a spurious band.
+ * kpts: host nk x 3.  tol: relative residual target (see mfd_kstats).
+ * evals: host nk x nbands, ascending.  evecs: device c128
+ * [nk][nbands][3][N][N][N] or NULL.  stats: host nk entries or NULL.
+ * Returns MFD_ENOTCONV / MFD_ESPURIOUS after filling evals and stats. */
+int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol,
+              const mfd_opts* opts, double* evals, void* evecs, mfd_kstats* stats, void* stream);
+
+void mfd_destroy(mfd_ctx* ctx);
+
+const char* mfd_strerror(int status);
+const char* mfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFDKC_H */

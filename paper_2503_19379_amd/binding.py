@@ -1,0 +1,206 @@
+"""Thin ctypes binding of the mfdkc C ABI (include/mfdkc.h).
+
+Argument marshalling only: every call goes straight to libmfdkc.so, built
+in-tree by ``paper_2503_19379_amd.build``.  Device buffers are torch tensors
+(complex128 for MFD_C128, complex64 for MFD_C64) of shape (nb, 3, N, N, N);
+streams are the current torch stream unless one is passed.  There is no CPU
+fallback: if the library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfdkc.so")
+
+MFD_C64 = 1
+MFD_C128 = 2
+STATUS = {0: "MFD_OK", -1: "MFD_EINVAL", -2: "MFD_ENOMEM", -3: "MFD_EDEVICE", -4: "MFD_ENOTCONV",
+          -5: "MFD_ESPURIOUS", -6: "MFD_EUNSUPPORTED"}
+
+
+class MfdError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class mfd_opts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("precision", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("seed", ctypes.c_ulonglong), ("max_gamma_doublings", ctypes.c_int), ("guard", ctypes.c_int),
+                ("x0", ctypes.c_void_p)]
+
+
+class mfd_kstats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("gamma_doublings", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("max_rel_resid", ctypes.c_double), ("spurious", ctypes.c_int), ("used_fallback", ctypes.c_int),
+                ("ms", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_19379_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.mfd_build.argtypes = [i, d, i, dp, vp, ctypes.POINTER(vp)]
+        L.mfd_supported_n.argtypes = [i]
+        L.mfd_set_gamma.argtypes = [vp, d]
+        L.mfd_gamma_shift.argtypes = [vp, dp, dp, dp]
+        L.mfd_op_apply.argtypes = [vp, dp, i, i, vp, vp, vp]
+        L.mfd_precond_solve.argtypes = [vp, dp, i, i, vp, vp, vp]
+        L.mfd_lambda_re.argtypes = [vp, dp, i, vp, dp, vp]
+        L.mfd_bands.argtypes = [vp, i, dp, i, d, ctypes.POINTER(mfd_opts), dp, vp,
+                                ctypes.POINTER(mfd_kstats), vp]
+        L.mfd_default_opts.argtypes = [ctypes.POINTER(mfd_opts)]
+        L.mfd_default_opts.restype = None
+        L.mfd_destroy.argtypes = [vp]
+        L.mfd_destroy.restype = None
+        L.mfd_strerror.argtypes = [i]
+        L.mfd_strerror.restype = ctypes.c_char_p
+        L.mfd_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise MfdError(status, lib().mfd_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _k(k):
+    a = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(3))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _dtype(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return MFD_C128
+    if t.dtype == torch.complex64:
+        return MFD_C64
+    raise TypeError("fields must be complex64 or complex128")
+
+
+def _dev(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns an mfd_ctx handle (freed by close() or garbage collection)."""
+
+    def __init__(self, handle, N, L):
+        self.handle = handle
+        self.N = N
+        self.L = L
+
+    def close(self):
+        if self.handle:
+            lib().mfd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mfd_supported_n(N: int) -> bool:
+    return bool(lib().mfd_supported_n(int(N)))
+
+
+def mfd_build(N: int, L: float, order: int, eps, stream=None) -> Context:
+    eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
+    if eps.shape != (N, N, N):
+        raise ValueError("eps must have shape (N, N, N)")
+    h = ctypes.c_void_p()
+    _check(lib().mfd_build(int(N), float(L), int(order), eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           _stream(stream), ctypes.byref(h)))
+    return Context(h, N, L)
+
+
+def mfd_set_gamma(ctx: Context, gamma: float):
+    _check(lib().mfd_set_gamma(ctx.handle, float(gamma)))
+
+
+def mfd_gamma_shift(ctx: Context, k):
+    ka, kp = _k(k)
+    g, c = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mfd_gamma_shift(ctx.handle, kp, ctypes.byref(g), ctypes.byref(c)))
+    return g.value, c.value
+
+
+def mfd_op_apply(ctx: Context, k, X, Y, stream=None):
+    """Y <- op(k) X (device tensors of shape (nb, 3, N, N, N))."""
+    ka, kp = _k(k)
+    if X.dtype != Y.dtype or X.shape != Y.shape:
+        raise ValueError("X and Y must match in dtype and shape")
+    _check(lib().mfd_op_apply(ctx.handle, kp, int(X.shape[0]), _dtype(X), _dev(X), _dev(Y), _stream(stream)))
+    return Y
+
+
+def mfd_precond_solve(ctx: Context, k, R, T, stream=None):
+    """T <- (P + c I)^-1 R (device tensors; T may be R)."""
+    ka, kp = _k(k)
+    if R.dtype != T.dtype or R.shape != T.shape:
+        raise ValueError("R and T must match in dtype and shape")
+    _check(lib().mfd_precond_solve(ctx.handle, kp, int(R.shape[0]), _dtype(R), _dev(R), _dev(T), _stream(stream)))
+    return T
+
+
+def mfd_lambda_re(ctx: Context, k, X, stream=None):
+    ka, kp = _k(k)
+    nb = int(X.shape[0])
+    out = np.zeros(nb)
+    _check(lib().mfd_lambda_re(ctx.handle, kp, nb, _dev(X), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               _stream(stream)))
+    return out
+
+
+def default_opts(**kw) -> mfd_opts:
+    o = mfd_opts()
+    lib().mfd_default_opts(ctypes.byref(o))
+    for key, v in kw.items():
+        if key == "x0":
+            v = ctypes.c_void_p(v.data_ptr()) if v is not None else None
+        setattr(o, key, v)
+    return o
+
+
+def mfd_bands(ctx: Context, kpts, nbands: int, tol: float, opts: mfd_opts | None = None, evecs=None,
+              stream=None, raise_on=(-1, -2, -3, -6)):
+    """Returns (evals (nk, nbands), stats list, status).  evecs: optional device
+    complex128 tensor (nk, nbands, 3, N, N, N)."""
+    kp = np.ascontiguousarray(np.asarray(kpts, dtype=np.float64).reshape(-1, 3))
+    nk = kp.shape[0]
+    ev = np.zeros((nk, nbands))
+    st = (mfd_kstats * nk)()
+    o = opts if opts is not None else default_opts()
+    status = lib().mfd_bands(ctx.handle, nk, kp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(nbands),
+                             float(tol), ctypes.byref(o), ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             _dev(evecs) if evecs is not None else None, st, _stream(stream))
+    if status in raise_on:
+        _check(status)
+    stats = [dict(iters=s.iters, gamma_doublings=s.gamma_doublings, gamma=s.gamma,
+                  max_rel_resid=s.max_rel_resid, spurious=s.spurious, used_fallback=s.used_fallback, ms=s.ms)
+             for s in st]
+    return ev, stats, status

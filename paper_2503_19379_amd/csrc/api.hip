@@ -1,0 +1,470 @@
+// C ABI of the mfdkc library and the host driver of the band solve.
+// The host only orders kernels and reads back a few scalars per iteration
+// (Ritz values, residual norms); every step of the method runs on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mfdkc.h"
+#include "common.h"
+#include "internal.h"
+#include "solver.h"
+
+using namespace mfd;
+
+static thread_local std::string g_last_error;
+
+static int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+#define HIPCHK(call)                                                                                      \
+    do {                                                                                                  \
+        hipError_t _e = (call);                                                                           \
+        if (_e != hipSuccess)                                                                             \
+            return fail(_e == hipErrorOutOfMemory ? MFD_ENOMEM : MFD_EDEVICE,                             \
+                        std::string(#call) + ": " + hipGetErrorString(_e));                               \
+    } while (0)
+
+struct mfd_ctx {
+    int N = 0;
+    double L = 1.0, h = 1.0;
+    int order = 2;
+    int device = 0;
+    double gamma_override = 0.0;
+    double* mu64 = nullptr;
+    float* mu32 = nullptr;
+    void* tw64 = nullptr;
+    void* tw32 = nullptr;
+    // band-solve workspace (FP64)
+    int ws_mb = 0;
+    size_t n = 0;
+    double2* V = nullptr;
+    double2* U = nullptr;
+    double2* gpart = nullptr;
+    double2* G = nullptr;
+    double2* C = nullptr;
+    double* npart = nullptr;
+    double* norms = nullptr;
+    double* theta = nullptr;
+    int* info = nullptr;
+    double* cpart = nullptr;
+    double* cout = nullptr;
+    double* host = nullptr;   // pinned: theta | norms | info | cout
+    int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
+};
+
+namespace {
+
+__global__ void mu_kernel(const double* __restrict__ eps, int N, double* __restrict__ mu64, float* __restrict__ mu32) {
+    const size_t NN = (size_t)N * N, N3 = NN * N;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3; i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / NN);
+        const int xm = x ? x - 1 : N - 1, ym = y ? y - 1 : N - 1, zm = z ? z - 1 : N - 1;
+        auto E = [&](int a, int b, int c) { return eps[(size_t)c * NN + (size_t)b * N + a]; };
+        // Section 4.4: harmonic average of eps^-1 over the four cells sharing the edge
+        const double m1 = 4.0 / (E(x, y, z) + E(x, ym, z) + E(x, y, zm) + E(x, ym, zm));
+        const double m2 = 4.0 / (E(x, y, z) + E(xm, y, z) + E(x, y, zm) + E(xm, y, zm));
+        const double m3 = 4.0 / (E(x, y, z) + E(xm, y, z) + E(x, ym, z) + E(xm, ym, z));
+        mu64[i] = m1; mu64[N3 + i] = m2; mu64[2 * N3 + i] = m3;
+        mu32[i] = (float)m1; mu32[N3 + i] = (float)m2; mu32[2 * N3 + i] = (float)m3;
+    }
+}
+
+__global__ void twiddle_kernel(int N, double2* tw64, float2* tw32) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double s, c;
+    sincospi(-2.0 * (double)j / (double)N, &s, &c);
+    tw64[j] = make_double2(c, s);
+    tw32[j] = make_float2((float)c, (float)s);
+}
+
+OpParams params(const mfd_ctx* ctx, const double k[3]) {
+    OpParams p;
+    p.N = ctx->N;
+    p.L = ctx->L;
+    p.h = ctx->h;
+    for (int i = 0; i < 3; ++i) p.k[i] = k[i];
+    const double kn = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    if (ctx->gamma_override > 0.0) {
+        p.gamma = ctx->gamma_override;
+    } else {
+        const double a = ctx->N / (2.0 * M_PI);
+        const double b = kn > 0.0 ? std::pow(2.0 * M_PI / (ctx->L * kn), 2) : 0.0;
+        p.gamma = 2.0 * std::max(a, b);
+    }
+    p.shift = (kn == 0.0) ? std::pow(M_PI / ctx->L, 2) : 0.0;
+    return p;
+}
+
+bool finite3(const double* k) { return std::isfinite(k[0]) && std::isfinite(k[1]) && std::isfinite(k[2]); }
+
+void free_ws(mfd_ctx* c) {
+    hipFree(c->V); hipFree(c->U); hipFree(c->gpart); hipFree(c->G); hipFree(c->C);
+    hipFree(c->npart); hipFree(c->norms); hipFree(c->theta); hipFree(c->info);
+    hipFree(c->cpart); hipFree(c->cout);
+    if (c->host) hipHostFree(c->host);
+    c->V = c->U = c->gpart = c->G = c->C = nullptr;
+    c->npart = c->norms = c->theta = c->cpart = c->cout = c->host = nullptr;
+    c->info = nullptr;
+    c->ws_mb = 0;
+}
+
+int ensure_ws(mfd_ctx* c, int mb) {
+    if (c->ws_mb == mb) return MFD_OK;
+    free_ws(c);
+    const size_t n = c->n;
+    c->nparts_upd = (int)std::min<size_t>(1024, (n + 255) / 256);
+    c->nparts_gram = gram_parts(n);
+    c->nparts_col = (int)std::min<size_t>(256, (n + 255) / 256);
+    const size_t K = 3 * (size_t)mb;
+    HIPCHK(hipMalloc(&c->V, n * 6 * mb * sizeof(double2)));
+    HIPCHK(hipMalloc(&c->U, n * 6 * mb * sizeof(double2)));
+    HIPCHK(hipMalloc(&c->gpart, (size_t)c->nparts_gram * K * 2 * K * sizeof(double2)));
+    HIPCHK(hipMalloc(&c->G, K * 2 * K * sizeof(double2)));
+    HIPCHK(hipMalloc(&c->C, K * mb * sizeof(double2)));
+    HIPCHK(hipMalloc(&c->npart, (size_t)c->nparts_upd * 2 * mb * sizeof(double)));
+    HIPCHK(hipMalloc(&c->norms, 2 * mb * sizeof(double)));
+    HIPCHK(hipMalloc(&c->theta, mb * sizeof(double)));
+    HIPCHK(hipMalloc(&c->info, 8 * sizeof(int)));
+    HIPCHK(hipMalloc(&c->cpart, (size_t)std::max(c->nparts_col, 1024) * 2 * mb * sizeof(double)));
+    HIPCHK(hipMalloc(&c->cout, 2 * mb * sizeof(double)));
+    HIPCHK(hipHostMalloc(&c->host, (8 * mb + 16) * sizeof(double), hipHostMallocDefault));
+    c->ws_mb = mb;
+    return MFD_OK;
+}
+
+// Column j of the solver block V (n x 6mb, c128).
+inline double2* col(double2* V, size_t n, int j) { return V + (size_t)j * n; }
+
+struct KResult {
+    int iters = 0;
+    bool converged = false;
+    std::vector<double> theta, res;
+};
+
+// LOBPCG at one k-point from the start block in V[:, :mb] (FP64).
+int lobpcg_k(mfd_ctx* c, const OpParams& p, int mb, int nbands, double tol, int max_iter, hipStream_t s,
+             KResult& out) {
+    const size_t n = c->n;
+    const int K = 3 * mb;
+    double2* V = c->V;
+    double2* U = c->U;
+    // zero W, P, AW, AP; AX = op(X)
+    HIPCHK(hipMemsetAsync(col(V, n, mb), 0, n * 2 * mb * sizeof(double2), s));
+    HIPCHK(hipMemsetAsync(col(V, n, 4 * mb), 0, n * 2 * mb * sizeof(double2), s));
+    HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+    RRArgs ra;
+    ra.G = c->G; ra.norms = c->norms; ra.theta = c->theta; ra.C = c->C; ra.info = c->info;
+    ra.mb = mb; ra.tol = tol; ra.drop_w = 1e-10; ra.drop_p = 1e-8;
+    double* hth = c->host;
+    double* hnorm = c->host + mb;
+    int it = 0;
+    for (;; ++it) {
+        ra.first = (it == 0);
+        if (it > 0) {
+            // W = T R (in place), AW = op(W)
+            HIPCHK(launch_precond<double>(p, mb, col(V, n, mb), col(V, n, mb), c->tw64, s));
+            HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
+        }
+        HIPCHK(launch_gram(V, n, n, K, 2 * K, c->nparts_gram, c->gpart, c->G, s));
+        HIPCHK(launch_rr(ra, s));
+        HIPCHK(launch_update(V, U, n, n, mb, c->C, c->theta, c->nparts_upd, c->npart, c->norms, s));
+        std::swap(V, U);
+        HIPCHK(hipMemcpyAsync(hth, c->theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hnorm, c->norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool conv = true;
+        for (int j = 0; j < nbands; ++j) {
+            const double r = std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j]));
+            if (!(r <= tol)) conv = false;
+        }
+        if (conv || it >= max_iter) {
+            out.converged = conv;
+            break;
+        }
+    }
+    c->V = V;
+    c->U = U;
+    out.iters = it;
+    // final check with a fresh FP64 operator application: AX slot <- op(X)
+    HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+    HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, nullptr, c->nparts_col, c->cpart, c->cout, s));
+    HIPCHK(hipMemcpyAsync(c->host, c->cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    out.theta.assign(mb, 0.0);
+    for (int j = 0; j < mb; ++j) out.theta[j] = c->host[2 * j + 1] / c->host[2 * j];
+    HIPCHK(hipMemcpyAsync(c->theta, out.theta.data(), mb * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, c->theta, c->nparts_col, c->cpart, c->cout, s));
+    std::vector<double> xx(mb);
+    for (int j = 0; j < mb; ++j) xx[j] = c->host[2 * j];
+    HIPCHK(hipMemcpyAsync(c->host, c->cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    out.res.assign(mb, 0.0);
+    for (int j = 0; j < mb; ++j) out.res[j] = std::sqrt(c->host[2 * j]) / (std::fabs(out.theta[j]) * std::sqrt(xx[j]));
+    return MFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mfd_default_opts(mfd_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->max_iter = 400;
+    o->precision = 0;
+    o->warm_start = 1;
+    o->seed = 0;
+    o->max_gamma_doublings = 4;
+    o->guard = 0;
+    o->x0 = nullptr;
+}
+
+int mfd_supported_n(int N) {
+    return (N >= 4 && N <= 128 && fft_supported(N, 4)) ? 1 : 0;
+}
+
+int mfd_build(int N, double L, int order, const double* eps_cells, void* stream, mfd_ctx** out) {
+    if (!out) return fail(MFD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!eps_cells) return fail(MFD_EINVAL, "eps_cells is NULL");
+    if (N < 4 || N > 128) return fail(MFD_EINVAL, "N must be in [4, 128]");
+    if (!(L > 0.0) || !std::isfinite(L)) return fail(MFD_EINVAL, "L must be finite and > 0");
+    if (order != 2) return fail(MFD_EUNSUPPORTED, "only stencil order 2 is built");
+    if (!mfd_supported_n(N)) return fail(MFD_EUNSUPPORTED, "no FFT plan for this N");
+    const size_t N3 = (size_t)N * N * N;
+    for (size_t i = 0; i < N3; ++i)
+        if (!std::isfinite(eps_cells[i]) || !(eps_cells[i] > 0.0))
+            return fail(MFD_EINVAL, "eps must be finite and > 0");
+    hipStream_t s = (hipStream_t)stream;
+    mfd_ctx* c = new mfd_ctx();
+    c->N = N;
+    c->L = L;
+    c->h = L / N;
+    c->order = order;
+    c->n = 3 * N3;
+    hipGetDevice(&c->device);
+    double* eps_d = nullptr;
+    auto cleanup = [&](int st) {
+        hipFree(eps_d);
+        mfd_destroy(c);
+        return st;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&c->mu64, 3 * N3 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->mu32, 3 * N3 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&c->tw64, N * sizeof(double2))) != hipSuccess ||
+        (e = hipMalloc(&c->tw32, N * sizeof(float2))) != hipSuccess ||
+        (e = hipMalloc(&eps_d, N3 * sizeof(double))) != hipSuccess)
+        return cleanup(fail(MFD_ENOMEM, hipGetErrorString(e)));
+    if ((e = hipMemcpyAsync(eps_d, eps_cells, N3 * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return cleanup(fail(MFD_EDEVICE, hipGetErrorString(e)));
+    hipLaunchKernelGGL(mu_kernel, dim3(1024), dim3(256), 0, s, eps_d, N, c->mu64, c->mu32);
+    hipLaunchKernelGGL(twiddle_kernel, dim3((N + 127) / 128), dim3(128), 0, s, N, (double2*)c->tw64, (float2*)c->tw32);
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+        return cleanup(fail(MFD_EDEVICE, hipGetErrorString(e)));
+    hipFree(eps_d);
+    *out = c;
+    return MFD_OK;
+}
+
+int mfd_set_gamma(mfd_ctx* ctx, double gamma) {
+    if (!ctx) return fail(MFD_EINVAL, "ctx is NULL");
+    if (!std::isfinite(gamma)) return fail(MFD_EINVAL, "gamma must be finite");
+    ctx->gamma_override = gamma > 0.0 ? gamma : 0.0;
+    return MFD_OK;
+}
+
+int mfd_gamma_shift(const mfd_ctx* ctx, const double k[3], double* gamma, double* shift) {
+    if (!ctx || !k) return fail(MFD_EINVAL, "NULL argument");
+    if (!finite3(k)) return fail(MFD_EINVAL, "k must be finite");
+    OpParams p = params(ctx, k);
+    if (gamma) *gamma = p.gamma;
+    if (shift) *shift = p.shift;
+    return MFD_OK;
+}
+
+static int check_block(mfd_ctx* ctx, const double* k, int nb, int dtype, const void* X, const void* Y) {
+    if (!ctx || !k || !X || !Y) return fail(MFD_EINVAL, "NULL argument");
+    if (nb < 0) return fail(MFD_EINVAL, "nb < 0");
+    if (dtype != MFD_C64 && dtype != MFD_C128) return fail(MFD_EINVAL, "dtype must be MFD_C64 or MFD_C128");
+    if (!finite3(k)) return fail(MFD_EINVAL, "k must be finite");
+    return MFD_OK;
+}
+
+int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* X, void* Y, void* stream) {
+    int st = check_block(ctx, k, nb, dtype, X, Y);
+    if (st) return st;
+    const size_t bytes = ctx->n * nb * (dtype == MFD_C64 ? 8 : 16);
+    const char* x = (const char*)X;
+    const char* y = (const char*)Y;
+    if (nb > 0 && x < y + bytes && y < x + bytes) return fail(MFD_EINVAL, "X and Y overlap");
+    if (nb == 0) return MFD_OK;
+    OpParams p = params(ctx, k);
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == MFD_C128) HIPCHK(launch_stencil<double>(p, nb, X, Y, ctx->mu64, s));
+    else HIPCHK(launch_stencil<float>(p, nb, X, Y, ctx->mu32, s));
+    return MFD_OK;
+}
+
+int mfd_precond_solve(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* R, void* T, void* stream) {
+    int st = check_block(ctx, k, nb, dtype, R, T);
+    if (st) return st;
+    if (nb == 0) return MFD_OK;
+    const size_t bytes = ctx->n * nb * (dtype == MFD_C64 ? 8 : 16);
+    const char* r = (const char*)R;
+    const char* t = (const char*)T;
+    if (r != t && r < t + bytes && t < r + bytes) return fail(MFD_EINVAL, "R and T overlap partially");
+    if (!fft_supported(ctx->N, dtype == MFD_C64 ? 4 : 8))
+        return fail(MFD_EUNSUPPORTED, "no FFT plan for this N and precision");
+    OpParams p = params(ctx, k);
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == MFD_C128) HIPCHK(launch_precond<double>(p, nb, R, T, ctx->tw64, s));
+    else HIPCHK(launch_precond<float>(p, nb, R, T, ctx->tw32, s));
+    return MFD_OK;
+}
+
+int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double* out, void* stream) {
+    if (!ctx || !k || !X || !out) return fail(MFD_EINVAL, "NULL argument");
+    if (nb <= 0) return fail(MFD_EINVAL, "nb must be > 0");
+    if (!finite3(k)) return fail(MFD_EINVAL, "k must be finite");
+    OpParams p = params(ctx, k);
+    hipStream_t s = (hipStream_t)stream;
+    const int nparts = 128;
+    double *part = nullptr, *res = nullptr;
+    HIPCHK(hipMalloc(&part, (size_t)nparts * 2 * nb * sizeof(double)));
+    hipError_t e = hipMalloc(&res, 2 * nb * sizeof(double));
+    if (e != hipSuccess) { hipFree(part); return fail(MFD_ENOMEM, hipGetErrorString(e)); }
+    std::vector<double> h(2 * nb);
+    e = launch_lambda_re(p, nb, X, ctx->mu64, part, nparts, res, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), res, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(part);
+    hipFree(res);
+    if (e != hipSuccess) return fail(MFD_EDEVICE, hipGetErrorString(e));
+    for (int b = 0; b < nb; ++b) out[b] = h[2 * b] / h[2 * b + 1];
+    return MFD_OK;
+}
+
+int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol, const mfd_opts* opts,
+              double* evals, void* evecs, mfd_kstats* stats, void* stream) {
+    if (!ctx || !kpts || !evals) return fail(MFD_EINVAL, "NULL argument");
+    if (nk <= 0 || nbands <= 0) return fail(MFD_EINVAL, "nk and nbands must be > 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
+    mfd_opts o;
+    mfd_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0) return fail(MFD_EINVAL, "bad options");
+    const int mb = nbands + o.guard;
+    if (3 * mb > 64) return fail(MFD_EUNSUPPORTED, "nbands + guard must be <= 21");
+    if ((size_t)mb > ctx->n) return fail(MFD_EINVAL, "nbands exceeds the problem size");
+    for (int i = 0; i < 3 * nk; ++i)
+        if (!std::isfinite(kpts[i])) return fail(MFD_EINVAL, "k must be finite");
+    if (o.precision != 0) return fail(MFD_EUNSUPPORTED, "mixed precision not built yet");
+    int st = ensure_ws(ctx, mb);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = ctx->n;
+    const double scale = std::pow(2.0 * M_PI / ctx->L, 2);
+    int ret = MFD_OK;
+    for (int ik = 0; ik < nk; ++ik) {
+        auto t0 = std::chrono::steady_clock::now();
+        const double* k = kpts + 3 * ik;
+        OpParams p = params(ctx, k);
+        // start block
+        if (ik == 0 && o.x0) {
+            HIPCHK(hipMemcpyAsync(ctx->V, o.x0, n * nbands * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            if (mb > nbands)
+                HIPCHK(launch_fill_random(col(ctx->V, n, nbands), n * (mb - nbands), o.seed * 1000003ull + 17, s));
+        } else if (ik == 0 || !o.warm_start) {
+            HIPCHK(launch_fill_random(ctx->V, n * mb, o.seed * 1000003ull + (uint64_t)ik, s));
+        }
+        KResult kr;
+        int doublings = 0, total_iters = 0, nspur = 0;
+        std::vector<double> lam(mb), lre(nbands);
+        for (;;) {
+            st = lobpcg_k(ctx, p, mb, nbands, tol, o.max_iter, s, kr);
+            if (st) return st;
+            total_iters += kr.iters;
+            for (int j = 0; j < mb; ++j) lam[j] = kr.theta[j] - p.shift;
+            // Alg 4.1: recompute lambda_re = |M_0^(1/2) A'x|^2 / |x|^2
+            st = mfd_lambda_re(ctx, k, nbands, ctx->V, lre.data(), stream);
+            if (st) return st;
+            std::vector<int> spur;
+            for (int j = 0; j < nbands; ++j)
+                if (lam[j] - lre[j] > 1e-4 * std::fabs(lam[j]) + 1e-10 * scale) spur.push_back(j);
+            nspur = (int)spur.size();
+            if (spur.empty() || doublings >= o.max_gamma_doublings) break;
+            p.gamma *= 2.0;
+            ++doublings;
+            for (size_t q = 0; q < spur.size(); ++q)
+                HIPCHK(launch_fill_random(col(ctx->V, n, spur[q]), n,
+                                          o.seed * 1000003ull + 7919ull * doublings + spur[q] + 101ull * ik, s));
+        }
+        // sort the returned bands
+        std::vector<int> idx(mb);
+        for (int j = 0; j < mb; ++j) idx[j] = j;
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+        double maxres = 0.0;
+        for (int j = 0; j < nbands; ++j) {
+            evals[(size_t)ik * nbands + j] = lam[idx[j]];
+            maxres = std::max(maxres, kr.res[idx[j]]);
+        }
+        if (evecs) {
+            for (int j = 0; j < nbands; ++j)
+                HIPCHK(hipMemcpyAsync((double2*)evecs + ((size_t)ik * nbands + j) * n, col(ctx->V, n, idx[j]),
+                                      n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        auto t1 = std::chrono::steady_clock::now();
+        if (stats) {
+            mfd_kstats& ks = stats[ik];
+            ks.iters = total_iters;
+            ks.gamma_doublings = doublings;
+            ks.gamma = p.gamma;
+            ks.max_rel_resid = maxres;
+            ks.spurious = nspur;
+            ks.used_fallback = 0;
+            ks.ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
+        }
+        if (nspur && ret == MFD_OK) ret = fail(MFD_ESPURIOUS, "Alg 4.1 still flags a band");
+        if (!kr.converged && ret == MFD_OK) ret = fail(MFD_ENOTCONV, "max_iter reached");
+    }
+    return ret;
+}
+
+void mfd_destroy(mfd_ctx* ctx) {
+    if (!ctx) return;
+    free_ws(ctx);
+    hipFree(ctx->mu64);
+    hipFree(ctx->mu32);
+    hipFree(ctx->tw64);
+    hipFree(ctx->tw32);
+    delete ctx;
+}
+
+const char* mfd_strerror(int status) {
+    switch (status) {
+        case MFD_OK: return "ok";
+        case MFD_EINVAL: return "invalid argument";
+        case MFD_ENOMEM: return "out of device memory";
+        case MFD_EDEVICE: return "device error";
+        case MFD_ENOTCONV: return "not converged";
+        case MFD_ESPURIOUS: return "spurious eigenvalue persists";
+        case MFD_EUNSUPPORTED: return "unsupported size or order";
+        default: return "unknown status";
+    }
+}
+
+const char* mfd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+// FFT solve of the preconditioner  T = (P + c I)^-1 R,  P = A A' + gamma B'B
+// (Section 5.1 eq. (penalised_marix); Section 5.2, Alg 5.1).
+//
+// Every D_i is a Kronecker product of circulants, so the 3-D DFT diagonalises
+// all of them at once (eq. (diag_of_circ) and the corollary after it).  With
+// the forward transform u_hat(p) = sum_r u[r] exp(-2 pi i p r / N) the symbol of
+// D_i at frequency p (theta = 2 pi p / N) is
+//   d_i(p) = (e^{i theta} - 1) / h + i alpha_i (1 + e^{i theta}) / 2,
+// and by Cor 4.4 (A A' + B'B = diag(L, L, L)) the 3 x 3 symbol of P is
+//   P_hat(p) = s I + (gamma - 1) conj(d) d^T,   s = |d_1|^2 + |d_2|^2 + |d_3|^2.
+// Alg 5.1 inverts a scalar diagonal; here the per-frequency block is rank-one
+// plus a multiple of I, so its inverse is closed form (Sherman-Morrison):
+//   t_hat = ( r_hat - (gamma - 1) conj(d) (d^T r_hat) / (gamma s + c) ) / (s + c).
+//
+// Three kernels, each one read and one write of the block:
+//   1. forward DFT along x and y of every (band, component, z) plane, in LDS;
+//   2. per (band, y, run of x): forward DFT along z of all three components,
+//      the 3 x 3 solve, inverse DFT along z;
+//   3. inverse DFT along y and x of every plane.
+// The 1-D transforms are in-place Stockham radix-4/2/3/5 passes: each pass
+// stages its butterfly inputs in registers, synchronises, and writes the
+// outputs back to the same LDS buffer.
+#include "common.h"
+#include "internal.h"
+
+namespace mfd {
+
+constexpr int first_radix(int m) {
+    return (m % 4 == 0) ? 4 : (m % 2 == 0) ? 2 : (m % 3 == 0) ? 3 : (m % 5 == 0) ? 5 : 0;
+}
+constexpr bool fft_ok(int n) {
+    while (n > 1) {
+        int r = first_radix(n);
+        if (!r) return false;
+        n /= r;
+    }
+    return true;
+}
+
+// R-point DFT in place; forward uses exp(-2 pi i / R), inverse its conjugate.
+template <int R, bool INV, class T>
+__device__ __forceinline__ void dft(T* v) {
+    using S = decltype(v[0].x);
+    if constexpr (R == 2) {
+        T a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        T t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        T t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+        // -i t3 (forward) / +i t3 (inverse)
+        T jt3 = INV ? mk<T>(-t3.y, t3.x) : mk<T>(t3.y, -t3.x);
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, jt3);
+        v[3] = csub(t1, jt3);
+    } else if constexpr (R == 3) {
+        const S h3 = (S)0.86602540378443864676;   // sin(2 pi / 3)
+        T a = v[0], s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        T m = mk<T>(a.x - (S)0.5 * s.x, a.y - (S)0.5 * s.y);
+        // forward: U1 = m - i h3 d, U2 = m + i h3 d
+        T jd = INV ? mk<T>(-h3 * d.y, h3 * d.x) : mk<T>(h3 * d.y, -h3 * d.x);
+        v[0] = cadd(a, s);
+        v[1] = cadd(m, jd);
+        v[2] = csub(m, jd);
+    } else if constexpr (R == 5) {
+        const S c1 = (S)0.30901699437494742410, c2 = (S)-0.80901699437494742410;
+        const S s1 = (S)0.95105651629515357212, s2 = (S)0.58778525229247312917;
+        T a = v[0];
+        T be = cadd(v[1], v[4]), bm = csub(v[1], v[4]);
+        T cd = cadd(v[2], v[3]), cm = csub(v[2], v[3]);
+        T r1 = mk<T>(a.x + c1 * be.x + c2 * cd.x, a.y + c1 * be.y + c2 * cd.y);
+        T r2 = mk<T>(a.x + c2 * be.x + c1 * cd.x, a.y + c2 * be.y + c1 * cd.y);
+        T i1 = mk<T>(s1 * bm.x + s2 * cm.x, s1 * bm.y + s2 * cm.y);
+        T i2 = mk<T>(s2 * bm.x - s1 * cm.x, s2 * bm.y - s1 * cm.y);
+        // forward: U1 = r1 - i i1, U4 = r1 + i i1, U2 = r2 - i i2, U3 = r2 + i i2
+        T j1 = INV ? mk<T>(-i1.y, i1.x) : mk<T>(i1.y, -i1.x);
+        T j2 = INV ? mk<T>(-i2.y, i2.x) : mk<T>(i2.y, -i2.x);
+        v[0] = mk<T>(a.x + be.x + cd.x, a.y + be.y + cd.y);
+        v[1] = cadd(r1, j1);
+        v[4] = csub(r1, j1);
+        v[2] = cadd(r2, j2);
+        v[3] = csub(r2, j2);
+    }
+}
+
+// One Stockham pass of radix R on NL lines of length N held in LDS.
+// addr(l, j) gives the LDS index of element j of line l.  LFAST: consecutive
+// threads take consecutive lines (strided lines) rather than consecutive
+// butterflies of one line (contiguous lines), to keep LDS accesses unit-stride.
+template <class T, int N, int NL, int NT, bool INV, bool LFAST, int R, int NS, class Addr>
+__device__ __forceinline__ void fft_pass(T* buf, const T* tw, Addr addr, int tid) {
+    constexpr int M = N / R;
+    constexpr int NB = NL * M;
+    constexpr int PER = (NB + NT - 1) / NT;
+    T v[PER][R];
+    int dst[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+        const int idx = tid + b * NT;
+        if ((NB % NT == 0) || idx < NB) {
+            const int l = LFAST ? idx % NL : idx / M;
+            const int j = LFAST ? idx / NL : idx % M;
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = buf[addr(l, j + r * M)];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    T w = tw[k * r * (N / (NS * R))];
+                    if (INV) w.y = -w.y;
+                    v[b][r] = cmul(v[b][r], w);
+                }
+            }
+            dft<R, INV>(v[b]);
+            dst[b] = (j / NS) * NS * R + k;
+            dst[b] = dst[b] | (l << 16);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+        const int idx = tid + b * NT;
+        if ((NB % NT == 0) || idx < NB) {
+            const int l = dst[b] >> 16;
+            const int d = dst[b] & 0xffff;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[addr(l, d + r * NS)] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <class T, int N, int NL, int NT, bool INV, bool LFAST, int NS, class Addr>
+__device__ __forceinline__ void fft_lines(T* buf, const T* tw, Addr addr, int tid) {
+    if constexpr (NS < N) {
+        constexpr int R = first_radix(N / NS);
+        fft_pass<T, N, NL, NT, INV, LFAST, R, NS>(buf, tw, addr, tid);
+        fft_lines<T, N, NL, NT, INV, LFAST, NS * R>(buf, tw, addr, tid);
+    }
+}
+
+constexpr int FFT_NT = 256;
+
+// Threads of the plane kernel: about 16 elements per thread per pass.
+constexpr int plane_nt(int N) {
+    int t = (N * N / 16 + 63) / 64 * 64;
+    return t < 256 ? 256 : (t > 1024 ? 1024 : t);
+}
+
+// Kernels 1 and 3: 2-D DFT along x and y of one N x N plane per workgroup.
+template <class R, int N, bool INV>
+__global__ __launch_bounds__(plane_nt(N)) void fft_plane_kernel(const cplx<R>* in, cplx<R>* out,
+                                                                const cplx<R>* tw_g) {
+    using T = cplx<R>;
+    constexpr int NT = plane_nt(N);
+    extern __shared__ unsigned char smem_raw[];
+    T* buf = reinterpret_cast<T*>(smem_raw);
+    T* tw = buf + N * N;
+    const int tid = threadIdx.x;
+    const size_t plane = blockIdx.x;
+    const T* src = in + plane * N * N;
+    T* dst = out + plane * N * N;
+    for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+    for (int i = tid; i < N * N; i += NT) buf[i] = src[i];
+    __syncthreads();
+    if (!INV) {
+        fft_lines<T, N, N, NT, INV, false, 1>(buf, tw, [](int l, int j) { return l * N + j; }, tid);
+        fft_lines<T, N, N, NT, INV, true, 1>(buf, tw, [](int l, int j) { return j * N + l; }, tid);
+    } else {
+        fft_lines<T, N, N, NT, INV, true, 1>(buf, tw, [](int l, int j) { return j * N + l; }, tid);
+        fft_lines<T, N, N, NT, INV, false, 1>(buf, tw, [](int l, int j) { return l * N + j; }, tid);
+    }
+    for (int i = tid; i < N * N; i += NT) dst[i] = buf[i];
+}
+
+template <class R>
+struct SolveArgs {
+    const cplx<R>* in;
+    cplx<R>* out;
+    const cplx<R>* tw;
+    R inv_h, half_k[3], gm1, gamma, shift, scale;
+};
+
+// Kernel 2: DFT along z, 3 x 3 symbol solve, inverse DFT along z, for XC
+// consecutive x positions of one y row of one band.
+template <class R, int N, int XC>
+__global__ __launch_bounds__(FFT_NT) void fft_zsolve_kernel(SolveArgs<R> a) {
+    using T = cplx<R>;
+    extern __shared__ unsigned char smem_raw[];
+    T* buf = reinterpret_cast<T*>(smem_raw);   // [3][N (z)][XC]
+    T* tw = buf + 3 * N * XC;
+    const int tid = threadIdx.x;
+    constexpr int NXC = N / XC;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int xc0 = (bid % NXC) * XC;
+    const int y = (bid / NXC) % N;
+    const int band = bid / (NXC * N);
+    const size_t NN = (size_t)N * N, N3 = NN * N;
+    const T* src = a.in + (size_t)band * 3 * N3 + (size_t)y * N + xc0;
+    T* dst = a.out + (size_t)band * 3 * N3 + (size_t)y * N + xc0;
+    for (int i = tid; i < N; i += FFT_NT) tw[i] = a.tw[i];
+    for (int i = tid; i < 3 * N * XC; i += FFT_NT) {
+        const int xc = i % XC, z = (i / XC) % N, c = i / (XC * N);
+        buf[i] = src[c * N3 + z * NN + xc];
+    }
+    __syncthreads();
+    auto addr = [](int l, int j) { return (l / XC) * N * XC + j * XC + (l % XC); };
+    fft_lines<T, N, 3 * XC, FFT_NT, false, true, 1>(buf, tw, addr, tid);
+    // symbol solve at every (pz, y, x)
+    for (int i = tid; i < N * XC; i += FFT_NT) {
+        const int xc = i % XC, pz = i / XC;
+        const int px = xc0 + xc;
+        // e^{i theta} = conj(tw[p])
+        T ex = tw[px], ey = tw[y], ez = tw[pz];
+        ex.y = -ex.y; ey.y = -ey.y; ez.y = -ez.y;
+        T d1 = mk<T>((ex.x - (R)1) * a.inv_h - a.half_k[0] * ex.y, ex.y * a.inv_h + a.half_k[0] * ((R)1 + ex.x));
+        T d2 = mk<T>((ey.x - (R)1) * a.inv_h - a.half_k[1] * ey.y, ey.y * a.inv_h + a.half_k[1] * ((R)1 + ey.x));
+        T d3 = mk<T>((ez.x - (R)1) * a.inv_h - a.half_k[2] * ez.y, ez.y * a.inv_h + a.half_k[2] * ((R)1 + ez.x));
+        const R s = cabs2(d1) + cabs2(d2) + cabs2(d3);
+        T r1 = buf[i], r2 = buf[N * XC + i], r3 = buf[2 * N * XC + i];
+        T dr = cmul(d1, r1);
+        dr = cfma(dr, d2, r2);
+        dr = cfma(dr, d3, r3);
+        const R coef = a.gm1 / (a.gamma * s + a.shift);
+        const R inv = a.scale / (s + a.shift);
+        dr = cscale(dr, coef);
+        // t_i = (r_i - conj(d_i) dr) * inv
+        r1 = cscale(csub(r1, cmulc(d1, dr)), inv);
+        r2 = cscale(csub(r2, cmulc(d2, dr)), inv);
+        r3 = cscale(csub(r3, cmulc(d3, dr)), inv);
+        buf[i] = r1;
+        buf[N * XC + i] = r2;
+        buf[2 * N * XC + i] = r3;
+    }
+    __syncthreads();
+    fft_lines<T, N, 3 * XC, FFT_NT, true, true, 1>(buf, tw, addr, tid);
+    for (int i = tid; i < 3 * N * XC; i += FFT_NT) {
+        const int xc = i % XC, z = (i / XC) % N, c = i / (XC * N);
+        dst[c * N3 + z * NN + xc] = buf[i];
+    }
+}
+
+static int pick_xc(int N) {
+    for (int xc : {16, 8, 4, 2, 1})
+        if (N % xc == 0) return xc;
+    return 1;
+}
+
+template <class R, int N, int XC>
+static hipError_t zsolve_launch(const SolveArgs<R>& a, int nb, hipStream_t s) {
+    const size_t lds = (3 * N * XC + N) * sizeof(cplx<R>);
+    auto kern = fft_zsolve_kernel<R, N, XC>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nb * N * (N / XC)), dim3(FFT_NT), lds, s, a);
+    return hipGetLastError();
+}
+
+template <class R, int N>
+static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s) {
+    using T = cplx<R>;
+    const size_t lds_plane = (size_t)(N * N + N) * sizeof(T);
+    if (lds_plane > 160 * 1024) return hipErrorInvalidValue;
+    auto kf = fft_plane_kernel<R, N, false>;
+    auto ki = fft_plane_kernel<R, N, true>;
+    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_plane);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_plane);
+    if (e != hipSuccess) return e;
+    const int nplanes = nb * 3 * N;
+    hipLaunchKernelGGL(kf, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Rin, (T*)Tout, (const T*)tw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    SolveArgs<R> a;
+    a.in = (const T*)Tout;
+    a.out = (T*)Tout;
+    a.tw = (const T*)tw;
+    a.inv_h = (R)(1.0 / p.h);
+    for (int i = 0; i < 3; ++i) a.half_k[i] = (R)(0.5 * p.k[i]);
+    a.gm1 = (R)(p.gamma - 1.0);
+    a.gamma = (R)p.gamma;
+    a.shift = (R)p.shift;
+    a.scale = (R)(1.0 / ((double)N * N * N));
+    switch (pick_xc(N)) {
+        case 16: if constexpr (N % 16 == 0) e = zsolve_launch<R, N, 16>(a, nb, s); break;
+        case 8: if constexpr (N % 8 == 0) e = zsolve_launch<R, N, 8>(a, nb, s); break;
+        case 4: if constexpr (N % 4 == 0) e = zsolve_launch<R, N, 4>(a, nb, s); break;
+        case 2: if constexpr (N % 2 == 0) e = zsolve_launch<R, N, 2>(a, nb, s); break;
+        default: e = zsolve_launch<R, N, 1>(a, nb, s); break;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ki, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Tout, (T*)Tout, (const T*)tw);
+    return hipGetLastError();
+}
+
+#define MFD_FFT_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(100) X(120) X(128)
+
+bool fft_supported(int N, int real_bytes) {
+    switch (N) {
+#define CASE(n) case n: return fft_ok(n) && (size_t)(n * n + n) * 2 * real_bytes <= 160 * 1024;
+        MFD_FFT_SIZES(CASE)
+#undef CASE
+        default: return false;
+    }
+}
+
+template <class R>
+hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s) {
+    switch (p.N) {
+#define CASE(n) case n: return precond_n<R, n>(p, nb, Rin, Tout, tw, s);
+        MFD_FFT_SIZES(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_precond<float>(const OpParams&, int, const void*, void*, const void*, hipStream_t);
+template hipError_t launch_precond<double>(const OpParams&, int, const void*, void*, const void*, hipStream_t);
+
+}  // namespace mfd

@@ -1,0 +1,29 @@
+// Internal launch interfaces of the mfdkc HIP library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mfd {
+
+// Per-call operator parameters: grid, Bloch vector, penalty and shift.
+struct OpParams {
+    int N;
+    double L, h;
+    double k[3];
+    double gamma, shift;
+};
+
+// Y = (A M_0 A' + gamma B'B + shift I) X for nb fields (stencil.hip).
+template <class R>
+hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s);
+
+// T = (P + shift I)^-1 R for nb fields via FFT (fft.hip).  tw: device table
+// exp(-2 pi i j / N), j < N, of precision R.
+template <class R>
+hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s);
+bool fft_supported(int N, int real_bytes);
+
+// out[b] = sum mu |A' x_b|^2 and out[nb + b] = sum |x_b|^2, c128 fields (blas.hip).
+hipError_t launch_lambda_re(const OpParams& p, int nb, const void* X, const void* mu, double* partial,
+                            int nparts, double* out, hipStream_t s);
+
+}  // namespace mfd

@@ -1,0 +1,42 @@
+// Internal launchers of the block eigensolver (blas.hip, rr.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cstdint>
+
+namespace mfd {
+
+hipError_t launch_reduce(const double* parts, int nparts, int ncols, double* out, hipStream_t s);
+// G (P x Q, row-major c128) = V[:, :P]^H V[:, :Q], V column-major with leading dimension ld.
+hipError_t launch_gram(const void* V, size_t ld, size_t n, int P, int Q, int nparts, void* part, void* G,
+                       hipStream_t s);
+int gram_parts(size_t n);
+hipError_t launch_update(const void* V, void* U, size_t ld, size_t n, int mb, const void* C, const double* theta,
+                         int nparts, double* npart, double* norms, hipStream_t s);
+hipError_t launch_colstats(const void* X, const void* Y, size_t ld, size_t n, int nb, const double* theta,
+                           int nparts, double* part, double* out, hipStream_t s);
+hipError_t launch_fill_random(void* X, size_t count, uint64_t seed, hipStream_t s);
+hipError_t launch_convert(const void* X, void* Y, size_t count, bool to_c64, hipStream_t s);
+
+// Rayleigh-Ritz on span[X, W, P] (rr.hip).
+//   G:      3mb x 6mb row-major c128, [S^H S | S^H A S]
+//   norms:  2mb doubles: |R_j|^2 then |X_j|^2 from the last update
+//   theta:  mb doubles, current Ritz values (in) and the new ones (out)
+//   C:      3mb x mb row-major c128 coefficients (out)
+//   info:   ints (out): [0] = columns kept, [1] = 1 if P was restarted,
+//           [2] = active bands, [3] = Jacobi sweeps
+//   first:  1 on the initial step (basis = X only)
+struct RRArgs {
+    const double2* G;
+    const double* norms;
+    double* theta;
+    double2* C;
+    int* info;
+    int mb;
+    int first;
+    double tol;
+    double drop_w, drop_p;
+};
+hipError_t launch_rr(const RRArgs& a, hipStream_t s);
+
+}  // namespace mfd

@@ -1,0 +1,241 @@
+// Fused application of the compensated MFD operator
+//   w = A (M_0 (A' v)) + gamma B' (B v) + c v          (eq. (Ker_comp), Remark 5.1)
+// for a block of complex face fields, second-order stencils (Table FD_1D, k = 1).
+//
+// Per axis i the operators of eqs. (discre), (blocks) are two-point stencils
+//   (D_i u)[r]  = u[r+1] cp_i + u[r] cm_i,      cp_i = 1/h + i alpha_i/2, cm_i = -1/h + i alpha_i/2
+//   (D_i' u)[r] = u[r-1] conj(cp_i) + u[r] conj(cm_i)
+// and A' (eq. (derived_uniform_grid)), A, B, B' are assembled from them as in
+// eq. (discrete_2nd_block):
+//   e = A'v : e1 = D3'v2 - D2'v3,  e2 = D1'v3 - D3'v1,  e3 = D2'v1 - D1'v2
+//   e <- mu e  (M_0, diagonal on edges)
+//   w = A e : w1 = D2 e3 - D3 e2,  w2 = D3 e1 - D1 e3,  w3 = D1 e2 - D2 e1
+//   q = B v = D1 v1 + D2 v2 + D3 v3,   w_i += gamma D_i' q.
+//
+// Kernel design (HBM-bound: v is read once, w written once, mu read once per
+// band).  A workgroup owns an x-y tile of N x TY cells plus one halo row on
+// each side in y (x is a full periodic row, so x neighbours never leave the
+// tile) and marches through a chunk of z planes.  Each thread owns one (x, y)
+// column and keeps its z history in registers; in-plane neighbours travel
+// through LDS.  Intermediates e = mu A'v and q = Bv never touch HBM.  At step
+// t the plane v(t+1) is loaded and the thread forms e(t+1), the in-plane part
+// of q(t+1), q(t) (adding the z term from v(t), v(t+1)) and finally w(t) from
+// e(t), e(t+1), q(t-1), q(t).
+#include "common.h"
+#include "internal.h"
+
+namespace mfd {
+
+template <class R>
+struct StencilArgs {
+    const cplx<R>* X;
+    cplx<R>* Y;
+    const R* mu;          // [3][N][N][N]
+    int N, nyt, nzc, zc, nb;
+    cplx<R> cp[3], cm[3];
+    R gamma, shift;
+};
+
+template <class R, int TY>
+__global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R> a) {
+    using T = cplx<R>;
+    extern __shared__ unsigned char smem_raw[];
+    T* smem = reinterpret_cast<T*>(smem_raw);
+    constexpr int ROWS = TY + 2;
+    const int N = a.N;
+    const int plane_cells = ROWS * N;
+    T* vbuf = smem;                      // [3][ROWS][N]
+    T* ebuf = smem + 3 * plane_cells;    // [2][3][ROWS][N]
+    T* qbuf = smem + 9 * plane_cells;    // [ROWS][N]
+
+    const int tx = threadIdx.x;
+    const int ty = threadIdx.y;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int ytile = bid % a.nyt;
+    const int rest = bid / a.nyt;
+    const int zch = rest % a.nzc;
+    const int band = rest / a.nzc;
+
+    const int y0 = ytile * TY;
+    const int yg = (y0 - 1 + ty + N) % N;
+    const int z0 = zch * a.zc;
+    const int z1 = z0 + a.zc;
+    const size_t NN = (size_t)N * N;
+    const size_t N3 = NN * N;
+    const T* Xb = a.X + (size_t)band * 3 * N3;
+    T* Yb = a.Y + (size_t)band * 3 * N3;
+
+    const int txp = (tx + 1 == N) ? 0 : tx + 1;
+    const int txm = (tx == 0) ? N - 1 : tx - 1;
+    const int row = ty * N;
+
+    const T cp1 = a.cp[0], cp2 = a.cp[1], cp3 = a.cp[2];
+    const T cm1 = a.cm[0], cm2 = a.cm[1], cm3 = a.cm[2];
+    const R gam = a.gamma, sh = a.shift;
+
+    const T zero = mk<T>(0.0, 0.0);
+    T vp0 = zero, vp1 = zero, vp2 = zero;        // v(t) at own cell
+    T ec0 = zero, ec1 = zero, ec2 = zero;        // e(t) at own cell
+    T qxy_c = zero;                              // in-plane part of q(t)
+    T q_prev = zero;                             // q(t-1)
+
+    for (int t = z0 - 2; t < z1; ++t) {
+        const int zt1 = (t + 1 + 2 * N) % N;
+        const size_t off = (size_t)zt1 * NN + (size_t)yg * N + tx;
+        const T vn0 = Xb[off];
+        const T vn1 = Xb[N3 + off];
+        const T vn2 = Xb[2 * N3 + off];
+        vbuf[row + tx] = vn0;
+        vbuf[plane_cells + row + tx] = vn1;
+        vbuf[2 * plane_cells + row + tx] = vn2;
+        __syncthreads();
+
+        // e(t+1) = mu A'v at own cell (needs the row below: ty >= 1)
+        T en0 = zero, en1 = zero, en2 = zero;
+        if (ty >= 1) {
+            const T v1ym = vbuf[row - N + tx];
+            const T v3ym = vbuf[2 * plane_cells + row - N + tx];
+            const T v2xm = vbuf[plane_cells + row + txm];
+            const T v3xm = vbuf[2 * plane_cells + row + txm];
+            // D3' v2 - D2' v3
+            T s = cmulc(cp3, vp1);
+            s = cadd(s, cmulc(cm3, vn1));
+            s = csub(s, cmulc(cp2, v3ym));
+            en0 = csub(s, cmulc(cm2, vn2));
+            // D1' v3 - D3' v1
+            s = cmulc(cp1, v3xm);
+            s = cadd(s, cmulc(cm1, vn2));
+            s = csub(s, cmulc(cp3, vp0));
+            en1 = csub(s, cmulc(cm3, vn0));
+            // D2' v1 - D1' v2
+            s = cmulc(cp2, v1ym);
+            s = cadd(s, cmulc(cm2, vn0));
+            s = csub(s, cmulc(cp1, v2xm));
+            en2 = csub(s, cmulc(cm1, vn1));
+            const R* mup = a.mu + off;
+            en0 = cscale(en0, mup[0]);
+            en1 = cscale(en1, mup[N3]);
+            en2 = cscale(en2, mup[2 * N3]);
+        }
+        // in-plane part of q(t+1) and the full q(t) (needs the row above: ty <= TY)
+        T qxy_n = zero, q_t = zero;
+        if (ty <= TY) {
+            const T v1xp = vbuf[row + txp];
+            const T v2yp = vbuf[plane_cells + row + N + tx];
+            qxy_n = cmul(cp1, v1xp);
+            qxy_n = cfma(qxy_n, cm1, vn0);
+            qxy_n = cfma(qxy_n, cp2, v2yp);
+            qxy_n = cfma(qxy_n, cm2, vn1);
+            q_t = cfma(qxy_c, cp3, vn2);
+            q_t = cfma(q_t, cm3, vp2);
+        }
+        T* eb = ebuf + ((t + 1) & 1) * 3 * plane_cells;
+        eb[row + tx] = en0;
+        eb[plane_cells + row + tx] = en1;
+        eb[2 * plane_cells + row + tx] = en2;
+        qbuf[row + tx] = q_t;
+        __syncthreads();
+
+        if (t >= z0 && ty >= 1 && ty <= TY) {
+            const T* ec = ebuf + (t & 1) * 3 * plane_cells;   // e(t)
+            const T e2xp = ec[plane_cells + row + txp];
+            const T e3xp = ec[2 * plane_cells + row + txp];
+            const T e1yp = ec[row + N + tx];
+            const T e3yp = ec[2 * plane_cells + row + N + tx];
+            const T qxm = qbuf[row + txm];
+            const T qym = qbuf[row - N + tx];
+            // w1 = D2 e3 - D3 e2 + gamma D1' q
+            T w0 = cmul(cp2, e3yp);
+            w0 = cfma(w0, cm2, ec2);
+            w0 = csub(w0, cmul(cp3, en1));
+            w0 = csub(w0, cmul(cm3, ec1));
+            T g0 = cmulc(cp1, qxm);
+            g0 = cadd(g0, cmulc(cm1, q_t));
+            // w2 = D3 e1 - D1 e3 + gamma D2' q
+            T w1 = cmul(cp3, en0);
+            w1 = cfma(w1, cm3, ec0);
+            w1 = csub(w1, cmul(cp1, e3xp));
+            w1 = csub(w1, cmul(cm1, ec2));
+            T g1 = cmulc(cp2, qym);
+            g1 = cadd(g1, cmulc(cm2, q_t));
+            // w3 = D1 e2 - D2 e1 + gamma D3' q
+            T w2 = cmul(cp1, e2xp);
+            w2 = cfma(w2, cm1, ec1);
+            w2 = csub(w2, cmul(cp2, e1yp));
+            w2 = csub(w2, cmul(cm2, ec0));
+            T g2 = cmulc(cp3, q_prev);
+            g2 = cadd(g2, cmulc(cm3, q_t));
+            w0 = cadd(w0, cscale(g0, gam));
+            w1 = cadd(w1, cscale(g1, gam));
+            w2 = cadd(w2, cscale(g2, gam));
+            w0 = cadd(w0, cscale(vp0, sh));
+            w1 = cadd(w1, cscale(vp1, sh));
+            w2 = cadd(w2, cscale(vp2, sh));
+            const size_t oo = (size_t)t * NN + (size_t)yg * N + tx;
+            Yb[oo] = w0;
+            Yb[N3 + oo] = w1;
+            Yb[2 * N3 + oo] = w2;
+        }
+        vp0 = vn0; vp1 = vn1; vp2 = vn2;
+        ec0 = en0; ec1 = en1; ec2 = en2;
+        qxy_c = qxy_n;
+        q_prev = q_t;
+    }
+}
+
+// Tile height TY for grid size N: N * (TY + 2) <= 1024 threads, TY | N.
+static int stencil_ty(int N) {
+    int best = 0;
+    for (int ty : {8, 6, 4, 2, 1})
+        if (N % ty == 0 && N * (ty + 2) <= 1024) { best = ty; break; }
+    return best;
+}
+
+template <class R, int TY>
+static hipError_t launch_ty(const StencilArgs<R>& a, hipStream_t s) {
+    const size_t lds = (size_t)10 * (TY + 2) * a.N * sizeof(cplx<R>);
+    auto kern = stencil_kernel<R, TY>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dim3 block(a.N, TY + 2);
+    dim3 grid(a.nyt * a.nzc * a.nb);
+    hipLaunchKernelGGL(kern, grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s) {
+    StencilArgs<R> a;
+    a.X = (const cplx<R>*)X;
+    a.Y = (cplx<R>*)Y;
+    a.mu = (const R*)mu;
+    a.N = p.N;
+    a.nb = nb;
+    const int TY = stencil_ty(p.N);
+    if (TY == 0) return hipErrorInvalidValue;
+    a.nyt = p.N / TY;
+    // z chunks: enough workgroups to fill 256 CUs several times over, chunks
+    // of at least 8 planes (each chunk re-reads two halo planes).
+    int zc = p.N;
+    while (zc % 2 == 0 && zc >= 16 && (size_t)a.nyt * (p.N / zc) * nb < 2048) zc /= 2;
+    a.zc = zc;
+    a.nzc = p.N / zc;
+    for (int i = 0; i < 3; ++i) {
+        a.cp[i] = mk<cplx<R>>(1.0 / p.h, 0.5 * p.k[i]);
+        a.cm[i] = mk<cplx<R>>(-1.0 / p.h, 0.5 * p.k[i]);
+    }
+    a.gamma = (R)p.gamma;
+    a.shift = (R)p.shift;
+    switch (TY) {
+        case 8: return launch_ty<R, 8>(a, s);
+        case 6: return launch_ty<R, 6>(a, s);
+        case 4: return launch_ty<R, 4>(a, s);
+        case 2: return launch_ty<R, 2>(a, s);
+        default: return launch_ty<R, 1>(a, s);
+    }
+}
+
+template hipError_t launch_stencil<float>(const OpParams&, int, const void*, void*, const void*, hipStream_t);
+template hipError_t launch_stencil<double>(const OpParams&, int, const void*, void*, const void*, hipStream_t);
+
+}  // namespace mfd

@@ -1,0 +1,81 @@
+"""GPU band solve (LOBPCG + FFT preconditioner + Alg 4.1) against the oracle:
+closed form (eps = 1), dense eigendecomposition (tiny grids) and the oracle's
+LOBPCG."""
+import numpy as np
+import pytest
+
+from oracle import lobpcg as olob
+from oracle import mfd
+from paper_2503_19379_amd import workloads
+from tests.gpu_util import rand_eps
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_19379_amd import binding
+    binding.lib()
+    return binding
+
+
+def test_homog_n8_closed_form(B):
+    cfg = workloads.CONFIGS["homog_n8"]
+    N, k, m = cfg["N"], np.array(cfg["kpts"][0]), cfg["nbands"]
+    ctx = B.mfd_build(N, 1.0, 2, workloads.crystal_eps(cfg["eps"], N))
+    ev, st, status = B.mfd_bands(ctx, [k], m, 1e-10)
+    assert status == 0, st
+    g = mfd.gamma_rule(N, 1.0, k)
+    phys, _ = mfd.closed_form_spectrum(N, 1.0, k, g)
+    assert np.allclose(ev[0], phys[:m], rtol=1e-10), (ev, phys[:m])
+    assert st[0]["gamma_doublings"] == 0 and st[0]["max_rel_resid"] <= 1e-10
+
+
+def test_homog_n8_literal_gamma_alg41(B):
+    """With gamma = 16 a compensation eigenvalue sits third; Alg 4.1 flags it
+    and one doubling returns the physical bands."""
+    N, k, m = 8, np.array([0.3, 0.2, 0.1]) * np.pi, 8
+    ctx = B.mfd_build(N, 1.0, 2, np.ones((N, N, N)))
+    B.mfd_set_gamma(ctx, 16.0)
+    ev, st, status = B.mfd_bands(ctx, [k], m, 1e-10)
+    assert status == 0
+    phys, _ = mfd.closed_form_spectrum(N, 1.0, k, 16.0)
+    assert np.allclose(ev[0], phys[:m], rtol=1e-10)
+    assert st[0]["gamma_doublings"] == 1 and st[0]["gamma"] == 32.0
+
+
+@pytest.mark.parametrize("k", [np.array([0.5, 0.1, 0.2]) * np.pi, np.zeros(3), np.array([np.pi, np.pi, 0.0])])
+def test_random_eps_n8_dense(B, k):
+    rng = np.random.default_rng(1)
+    N, m = 8, 8
+    eps = rand_eps(rng, N)
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    ev, st, status = B.mfd_bands(ctx, [k], m, 1e-10)
+    assert status == 0, st
+    g = st[0]["gamma"]
+    ref = np.linalg.eigvalsh(mfd.dense_matrix(eps, 1.0, k, g))[:m]
+    if np.linalg.norm(k) == 0:
+        assert np.all(np.abs(ev[0][:3]) < 1e-8)
+        assert np.allclose(ev[0][3:], ref[3:], rtol=1e-10)
+    else:
+        assert np.allclose(ev[0], ref, rtol=1e-10)
+
+
+def test_sphere_n16_vs_oracle(B):
+    N, m = 16, 6
+    eps = workloads.eps_sphere(N)
+    kp = workloads.kpath("GXMGR", 5)
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    ev, st, status = B.mfd_bands(ctx, kp, m, 1e-10)
+    assert status == 0, st
+    for i, k in enumerate(kp):
+        lam, _, info = olob.solve_bands(eps, 1.0, k, m, tol=1e-10)
+        if np.linalg.norm(k) == 0:
+            assert np.all(np.abs(ev[i][:3]) < 1e-8)
+            assert np.allclose(ev[i][3:], lam[3:], rtol=1e-9)
+        else:
+            assert np.allclose(ev[i], lam, rtol=1e-9), (i, ev[i], lam)

@@ -1,0 +1,136 @@
+"""GPU parity of the operator, the FFT preconditioner and Alg 4.1's
+recompute against the FP64 CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import mfd
+from tests.gpu_util import rand_block, rand_eps, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_19379_amd import binding
+    binding.lib()
+    return binding
+
+
+KS = [np.array([0.7, -0.4, 1.3]), np.zeros(3), np.array([np.pi, np.pi, np.pi])]
+
+
+@pytest.mark.parametrize("N", [8, 12, 24, 32, 64])
+@pytest.mark.parametrize("ki", [0, 1, 2])
+def test_op_apply_fp64(B, N, ki):
+    rng = np.random.default_rng(100 + N + ki)
+    L = 1.0
+    k = KS[ki]
+    eps = rand_eps(rng, N)
+    nb = 3 if N <= 32 else 2
+    X = rand_block(rng, nb, N)
+    ctx = B.mfd_build(N, L, 2, eps)
+    g, c = B.mfd_gamma_shift(ctx, k)
+    assert np.isclose(g, mfd.gamma_rule(N, L, k)) and np.isclose(c, mfd.shift_rule(L, k))
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    B.mfd_op_apply(ctx, k, Xd, Yd)
+    torch.cuda.synchronize()
+    ref = mfd.apply_op(X, mfd.mu_from_eps(eps), k, L / N, g, 2, c)
+    assert rel_err(Yd.cpu().numpy(), ref) < 1e-13
+
+
+@pytest.mark.parametrize("N", [16, 48])
+def test_op_apply_fp32(B, N):
+    rng = np.random.default_rng(7 + N)
+    L, k = 1.0, np.array([0.3, 0.2, -0.9]) * np.pi
+    eps = rand_eps(rng, N)
+    X = rand_block(rng, 2, N)
+    ctx = B.mfd_build(N, L, 2, eps)
+    g, c = B.mfd_gamma_shift(ctx, k)
+    Xd = torch.from_numpy(X.astype(np.complex64)).cuda()
+    Yd = torch.empty_like(Xd)
+    B.mfd_op_apply(ctx, k, Xd, Yd)
+    torch.cuda.synchronize()
+    ref = mfd.apply_op(X.astype(np.complex64).astype(np.complex128), mfd.mu_from_eps(eps), k, L / N, g, 2, c)
+    assert rel_err(Yd.cpu().numpy(), ref) < 2e-6
+
+
+@pytest.mark.parametrize("N", [8, 12, 20, 24, 32, 48, 64])
+@pytest.mark.parametrize("ki", [0, 1])
+def test_precond_fp64(B, N, ki):
+    rng = np.random.default_rng(200 + N + ki)
+    L = 1.0
+    k = KS[ki]
+    ctx = B.mfd_build(N, L, 2, np.ones((N, N, N)))
+    g, c = B.mfd_gamma_shift(ctx, k)
+    R = rand_block(rng, 2, N)
+    Rd = torch.from_numpy(R).cuda()
+    Td = torch.empty_like(Rd)
+    B.mfd_precond_solve(ctx, k, Rd, Td)
+    torch.cuda.synchronize()
+    ref = mfd.precond_solve(R, N, L, k, g, 2, c)
+    assert rel_err(Td.cpu().numpy(), ref) < 1e-12
+    # in place
+    B.mfd_precond_solve(ctx, k, Rd, Rd)
+    torch.cuda.synchronize()
+    assert rel_err(Rd.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("N", [16, 96])
+def test_precond_fp32(B, N):
+    rng = np.random.default_rng(300 + N)
+    L, k = 1.0, np.array([0.5, -0.25, 0.1]) * np.pi
+    ctx = B.mfd_build(N, L, 2, np.ones((N, N, N)))
+    g, c = B.mfd_gamma_shift(ctx, k)
+    R = rand_block(rng, 1, N).astype(np.complex64)
+    Rd = torch.from_numpy(R).cuda()
+    Td = torch.empty_like(Rd)
+    B.mfd_precond_solve(ctx, k, Rd, Td)
+    torch.cuda.synchronize()
+    ref = mfd.precond_solve(R.astype(np.complex128), N, L, k, g, 2, c)
+    assert rel_err(Td.cpu().numpy(), ref) < 5e-6
+
+
+def test_precond_inverts_operator_homogeneous(B):
+    """eps = 1: P = the compensated operator, so precond(op(x)) = x."""
+    N, L = 32, 1.0
+    k = np.array([0.3, 0.2, 0.1]) * np.pi
+    rng = np.random.default_rng(5)
+    ctx = B.mfd_build(N, L, 2, np.ones((N, N, N)))
+    X = torch.from_numpy(rand_block(rng, 2, N)).cuda()
+    Y = torch.empty_like(X)
+    B.mfd_op_apply(ctx, k, X, Y)
+    B.mfd_precond_solve(ctx, k, Y, Y)
+    torch.cuda.synchronize()
+    assert rel_err(Y.cpu().numpy(), X.cpu().numpy()) < 1e-11
+
+
+def test_lambda_re(B):
+    N, L = 16, 1.0
+    k = np.array([0.4, 0.1, -0.3]) * np.pi
+    rng = np.random.default_rng(9)
+    eps = rand_eps(rng, N)
+    X = rand_block(rng, 3, N)
+    ctx = B.mfd_build(N, L, 2, eps)
+    got = B.mfd_lambda_re(ctx, k, torch.from_numpy(X).cuda())
+    mu = mfd.mu_from_eps(eps)
+    ref = [mfd.lambda_re(x, mu, k, L / N) for x in X]
+    assert np.allclose(got, ref, rtol=1e-12)
+
+
+def test_invalid_arguments(B):
+    N = 8
+    ctx = B.mfd_build(N, 1.0, 2, np.ones((N, N, N)))
+    X = torch.zeros((1, 3, N, N, N), dtype=torch.complex128, device="cuda")
+    with pytest.raises(B.MfdError):
+        B.mfd_op_apply(ctx, [0.1, 0.2, np.nan], X, torch.zeros_like(X))
+    with pytest.raises(B.MfdError):
+        B.mfd_op_apply(ctx, [0.1, 0.2, 0.3], X, X)          # aliasing
+    with pytest.raises(B.MfdError):
+        B.mfd_build(N, 1.0, 2, -np.ones((N, N, N)))
+    with pytest.raises(B.MfdError):
+        B.mfd_build(7, 1.0, 2, np.ones((7, 7, 7)))
