@@ -24,11 +24,15 @@
  *   eps^-1 (Section 4.4), gamma(k) the penalty number (eq. (pnt_number)) and
  *   c(k) the shift of Remark 5.1.  Readings of the paper used here:
  *     mu on an edge = 4 / (sum of eps over the 4 cells sharing the edge);
- *     gamma(k) = 2 max{ N / (2 pi), (2 pi / (L |k|))^2 }, i.e. the rule of
- *       eq. (pnt_number) in the paper's units of lattice constant 2 pi
- *       (the |k|^-2 term is dropped at k = 0), unless set by mfd_set_gamma;
- *     c(k) = (pi / L)^2 if k = 0, else 0.
- *   Eigenvalues reported by mfd_bands have c(k) subtracted.
+ *     gamma(k) = 2 max{ N / (2 pi), (2 pi / (L max(|k|, k_b)))^2 }, i.e. the
+ *       rule of eq. (pnt_number) in the paper's units of lattice constant
+ *       2 pi, with |k| clamped below at k_b = pi / (2L) (unclamped, FP64
+ *       rounding of gamma B'B x exceeds a 1e-8 relative residual near
+ *       Gamma), unless set by mfd_set_gamma;
+ *     c(k) = (pi / L)^2 if |k| < k_b, else 0 (Remark 5.1, used in the ball
+ *       around Gamma where A A' + gamma B'B is singular or nearly so).
+ *   Eigenvalues reported by mfd_bands have c(k) subtracted.  Residuals are
+ *   relative to |lambda| + c(k).
  * Streams.  Every call is ordered on `stream` (a hipStream_t passed as
  *   void*; NULL = the null stream).  mfd_op_apply and mfd_precond_solve are
  *   asynchronous to the host; mfd_bands returns once evals are on the host.
@@ -65,7 +69,8 @@ typedef struct {
     int warm_start;           /* 0: random start at every k (seed); 1: previous k's vectors */
     unsigned long long seed;  /* random start blocks */
     int max_gamma_doublings;  /* Alg 4.1 restarts (default 4) */
-    int guard;                /* extra block columns beyond nbands (default 0) */
+    int guard;                /* extra block columns beyond nbands (default 2); they also hold
+                                 compensation modes that Alg 4.1 flags and discards */
     const void* x0;           /* optional device c128 start block [nbands][3][N][N][N] for the first
                                  k-point (NULL: random) */
 } mfd_opts;
@@ -75,7 +80,8 @@ typedef struct {
     int gamma_doublings;      /* Alg 4.1 restarts taken */
     double gamma;             /* penalty number used for the returned bands */
     double max_rel_resid;     /* max_i |op x_i - theta_i x_i| / (theta_i |x_i|), FP64 operator */
-    int spurious;             /* bands still flagged by Alg 4.1 */
+    int spurious;             /* bands still flagged by Alg 4.1 among those returned */
+    int discarded;            /* flagged bands skipped in favour of the next physical ones */
     int used_fallback;        /* warm start fell back to the random/previous-k start */
     float ms;                 /* wall time of this k-point */
 } mfd_kstats;
@@ -118,14 +124,26 @@ int mfd_precond_solve(mfd_ctx* ctx, const double k[3], int nb, int dtype, const 
 int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double* out, void* stream);
 
 /* Lowest nbands physical eigenpairs at each of nk Bloch vectors: LOBPCG
- * (Section 5.1) preconditioned by mfd_precond_solve, then the recompute
- * check of Alg 4.1 with gamma doubled on a spurious band.
+ * (Section 5.1) on nbands + guard columns preconditioned by
+ * mfd_precond_solve, then the recompute check of Alg 4.1: bands it flags as
+ * spurious are discarded when enough physical ones remain among the
+ * nbands + guard, otherwise gamma is doubled and the solve repeated.
  * kpts: host nk x 3.  tol: relative residual target (see mfd_kstats).
  * evals: host nk x nbands, ascending.  evecs: device c128
  * [nk][nbands][3][N][N][N] or NULL.  stats: host nk entries or NULL.
  * Returns MFD_ENOTCONV / MFD_ESPURIOUS after filling evals and stats. */
 int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol,
               const mfd_opts* opts, double* evals, void* evecs, mfd_kstats* stats, void* stream);
+
+/* Per-kernel timing of mfd_bands with HIP events recorded on the solve's
+ * stream around each launch group.  mfd_profile(ctx, 1) clears the counters
+ * and starts recording, (ctx, 0) stops.  mfd_profile_read fills 6 entries per
+ * array, by category: 0 stencil (mfd_op_apply kernel), 1 FFT preconditioner
+ * (three kernels), 2 Gram product (+ partial-sum reduction), 3 Rayleigh-Ritz,
+ * 4 block update (+ norm reduction), 5 unused.  ms: total event time, count:
+ * launches, bytes: algorithmic HBM bytes (each block read or written once). */
+int mfd_profile(mfd_ctx* ctx, int enable);
+int mfd_profile_read(mfd_ctx* ctx, double* ms, long long* count, double* bytes);
 
 void mfd_destroy(mfd_ctx* ctx);
 

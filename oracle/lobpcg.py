@@ -33,11 +33,12 @@ def _ritz(X, AX):
     return th, X @ V, AX @ V, V
 
 
-def lobpcg(apply_A, apply_T, X0, tol, maxiter=500, drop=1e-10, restart=1e-8, lock=True):
+def lobpcg(apply_A, apply_T, X0, tol, maxiter=500, drop=1e-10, restart=1e-8, lock=True, nconv=None):
     """Smallest m eigenpairs of the Hermitian positive definite operator
     ``apply_A`` ((n, j) -> (n, j)), preconditioned by ``apply_T``.
 
-    Convergence of column i: |A x_i - th_i x_i| <= tol |th_i| |x_i|.
+    Convergence of column i: |A x_i - th_i x_i| <= tol |th_i| |x_i|; the
+    iteration stops when the lowest ``nconv`` columns (default all) converge.
     Returns (theta, X, info) with info = dict(iters, res, converged)."""
     X = np.array(X0, dtype=np.complex128)
     m = X.shape[1]
@@ -51,7 +52,7 @@ def lobpcg(apply_A, apply_T, X0, tol, maxiter=500, drop=1e-10, restart=1e-8, loc
         R = AX - X * th[None, :]
         res = np.linalg.norm(R, axis=0) / (np.abs(th) * np.linalg.norm(X, axis=0))
         active = res > tol
-        if not active.any():
+        if not active[:nconv if nconv else m].any():
             it -= 1
             break
         if not lock:
@@ -103,7 +104,7 @@ def lobpcg(apply_A, apply_T, X0, tol, maxiter=500, drop=1e-10, restart=1e-8, loc
     order = np.argsort(th)
     th, X, AX = th[order], X[:, order], AX[:, order]
     res = np.linalg.norm(AX - X * th[None, :], axis=0) / np.abs(th)
-    return th, X, dict(iters=it, res=res, converged=bool(np.all(res <= tol)))
+    return th, X, dict(iters=it, res=res, converged=bool(np.all(res[:nconv if nconv else m] <= tol)))
 
 
 def spurious_flags(lam, lam_re, scale, rel=1e-4, abs_tol=1e-10):
@@ -115,55 +116,75 @@ def spurious_flags(lam, lam_re, scale, rel=1e-4, abs_tol=1e-10):
 
 
 def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
-                maxiter=500, max_doublings=4, check=True):
+                maxiter=500, max_doublings=4, check=True, guard=2):
     """Lowest m physical eigenpairs of A M_0 A' + gamma B'B at Bloch vector k
-    (eq. (Ker_comp)), by Alg 4.1: solve, recompute lambda_re = |M_0^(1/2) A'x|^2,
-    and on a spurious band double gamma and solve again.
+    (eq. (Ker_comp)), following Alg 4.1: compute the lowest eigenpairs, recompute
+    lambda_re = |M_0^(1/2) A'x|^2 / |x|^2, and treat a band with lambda_re !=
+    lambda as spurious.  Spurious bands are discarded (the block carries
+    ``guard`` extra columns for them); if fewer than m physical bands remain
+    among the m + guard, gamma is doubled and the solve repeated.
 
     eps: cell permittivity (N, N, N); k: Cartesian Bloch vector (1/L units).
-    X0: (m, 3, N, N, N) start block (default: seeded complex Gaussian).
-    Returns (lam, X (m, 3, N, N, N), info)."""
+    X0: (m + guard, 3, N, N, N) start block (default: seeded complex Gaussian).
+    Convergence: |A x - lambda x| <= tol (|lambda| + c) |x|, c the shift of
+    ``mfd.shift_rule``.
+    Returns (lam (m,), X (m, 3, N, N, N), info)."""
     eps = np.asarray(eps, dtype=np.float64)
     N = eps.shape[0]
     n = 3 * N ** 3
     h = L / N
     k = np.asarray(k, dtype=np.float64)
+    mb = m + guard
     mu = mfd.mu_from_eps(eps)
     g = mfd.gamma_rule(N, L, k) if gamma is None else float(gamma)
     c = mfd.shift_rule(L, k)
     if X0 is None:
         rng = np.random.default_rng(seed)
-        X0 = rng.standard_normal((m, 3, N, N, N)) + 1j * rng.standard_normal((m, 3, N, N, N))
-    X0 = np.asarray(X0, dtype=np.complex128).reshape(m, n).T
+        X0 = rng.standard_normal((mb, 3, N, N, N)) + 1j * rng.standard_normal((mb, 3, N, N, N))
+    X = np.asarray(X0, dtype=np.complex128).reshape(mb, n).T
     doublings = 0
     total_iters = 0
+    nreq = m
     while True:
         Pinv = np.linalg.inv(mfd.precond_matrices(N, L, k, g, order, c))
 
-        def apply_A(X, g=g):
-            V = X.T.reshape(-1, 3, N, N, N)
+        def apply_A(Y, g=g):
+            V = Y.T.reshape(-1, 3, N, N, N)
             return mfd.apply_op(V, mu, k, h, g, order, c).reshape(-1, n).T
 
         def apply_T(R, g=g, Pinv=Pinv):
             V = R.T.reshape(-1, 3, N, N, N)
             return mfd.precond_solve(V, N, L, k, g, order, c, Pinv=Pinv).reshape(-1, n).T
 
-        th, X, info = lobpcg(apply_A, apply_T, X0, tol, maxiter)
+        th, X, info = lobpcg(apply_A, apply_T, X, tol, maxiter, nconv=nreq)
         total_iters += info["iters"]
         lam = th - c
-        Xb = X.T.reshape(m, 3, N, N, N)
+        Xb = X.T.reshape(mb, 3, N, N, N)
         lam_re = np.array([mfd.lambda_re(x, mu, k, h, order) for x in Xb])
-        spur = spurious_flags(lam, lam_re, (2 * np.pi / L) ** 2)
-        if not check or not spur.any() or doublings >= max_doublings:
-            info.update(gamma=g, doublings=doublings, lam_re=lam_re, spurious=spur,
-                        total_iters=total_iters, shift=c)
-            return lam, Xb, info
+        spur = spurious_flags(lam, lam_re, (2 * np.pi / L) ** 2) if check else np.zeros(mb, bool)
+        phys = np.flatnonzero(~spur)
+        if len(phys) >= m:
+            need = phys[m - 1] + 1
+            if need > nreq and info["iters"] < maxiter:
+                nreq = need                  # discarded bands: converge one band further
+                continue
+            sel = phys[:m]
+            info.update(gamma=g, doublings=doublings, lam_re=lam_re[sel], spurious=spur[sel],
+                        discarded=int(spur[:need].sum()), total_iters=total_iters, shift=c,
+                        res=info["res"][sel], converged=bool(info["res"][sel].max() <= tol))
+            return lam[sel], Xb[sel], info
+        if doublings >= max_doublings:
+            sel = np.arange(m)
+            info.update(gamma=g, doublings=doublings, lam_re=lam_re[sel], spurious=spur[sel],
+                        discarded=0, total_iters=total_iters, shift=c, res=info["res"][sel])
+            return lam[sel], Xb[sel], info
         g *= 2.0
         doublings += 1
-        # Restart from the physical columns; a spurious column is an exact
-        # compensation eigenvector of the new matrix too (eigenvalue doubled),
-        # so it would stay locked at zero residual: replace it by fresh noise.
+        nreq = m
+        # A spurious column is an exact compensation eigenvector of the new
+        # matrix too (eigenvalue doubled) and would stay locked at zero
+        # residual: replace it by fresh noise.
         rng = np.random.default_rng(seed + 7919 * doublings)
-        X0 = X.copy()
         ns = int(spur.sum())
-        X0[:, spur] = rng.standard_normal((n, ns)) + 1j * rng.standard_normal((n, ns))
+        X = X.copy()
+        X[:, spur] = rng.standard_normal((n, ns)) + 1j * rng.standard_normal((n, ns))

@@ -152,22 +152,33 @@ def gamma_rule(N: int, L: float, k, literal: bool = False) -> float:
     1/h carries a length, so the rule depends on units.  The paper computes
     with lattice constant 2 pi (Section 6.1); in those units h = 2 pi / N and
     |alpha| becomes L |k| / (2 pi), giving gamma = 2 max{N / (2 pi),
-    (2 pi / (L |k|))^2}.  ``literal=True`` applies the formula in the units of
-    L instead: 2 max{N / L, |k|^-2}.  At k = 0 the |k|^-2 term is dropped
-    (Remark 4.6: gamma = O(1) suffices there)."""
+    (2 pi / (L |k|))^2}.  Near Gamma the |k|^-2 term grows without bound and
+    FP64 rounding of gamma B'B x then dominates the residual of a converged
+    band; |k| is therefore clamped below at K_BALL = pi / (2 L) (inside that
+    ball the one compensation mode gamma |k|^2 may fall among the wanted bands
+    and is removed by Alg 4.1).  ``literal=True`` applies the formula in the
+    units of L with no clamp: 2 max{N / L, |k|^-2}."""
     kn = float(np.linalg.norm(np.asarray(k, dtype=np.float64)))
     if literal:
         a, b = N / L, (kn ** -2 if kn > 0 else 0.0)
     else:
-        a, b = N / (2 * np.pi), ((2 * np.pi / (L * kn)) ** 2 if kn > 0 else 0.0)
+        kc = max(kn, k_ball(L))
+        a, b = N / (2 * np.pi), (2 * np.pi / (L * kc)) ** 2
     return 2.0 * max(a, b)
 
 
+def k_ball(L: float) -> float:
+    """Radius pi / (2 L) of the neighbourhood of Gamma where the shift of
+    Remark 5.1 is used and the penalty rule is clamped."""
+    return np.pi / (2.0 * L)
+
+
 def shift_rule(L: float, k) -> float:
-    """Shift c of Remark 5.1: needed only at alpha = 0, where A A' + gamma B'B
-    is singular.  The paper gives no value; (pi / L)^2 is used (the result is
-    independent of c once c is subtracted)."""
-    return (np.pi / L) ** 2 if float(np.linalg.norm(k)) == 0.0 else 0.0
+    """Shift c of Remark 5.1.  A A' + gamma B'B is singular at alpha = 0 and its
+    smallest eigenvalue is |k|^2 near it; the shifted problem is solved (and c
+    subtracted) for |k| < pi / (2 L), with c = (pi / L)^2.  The eigenpairs do not
+    depend on c."""
+    return (np.pi / L) ** 2 if float(np.linalg.norm(k)) < k_ball(L) else 0.0
 
 
 def apply_op(v, mu, alpha, h, gamma, order=2, shift=0.0):

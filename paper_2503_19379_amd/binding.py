@@ -36,8 +36,8 @@ class mfd_opts(ctypes.Structure):
 
 class mfd_kstats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("gamma_doublings", ctypes.c_int), ("gamma", ctypes.c_double),
-                ("max_rel_resid", ctypes.c_double), ("spurious", ctypes.c_int), ("used_fallback", ctypes.c_int),
-                ("ms", ctypes.c_float)]
+                ("max_rel_resid", ctypes.c_double), ("spurious", ctypes.c_int), ("discarded", ctypes.c_int),
+                ("used_fallback", ctypes.c_int), ("ms", ctypes.c_float)]
 
 
 _lib = None
@@ -63,6 +63,8 @@ def lib():
                                 ctypes.POINTER(mfd_kstats), vp]
         L.mfd_default_opts.argtypes = [ctypes.POINTER(mfd_opts)]
         L.mfd_default_opts.restype = None
+        L.mfd_profile.argtypes = [vp, i]
+        L.mfd_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), dp]
         L.mfd_destroy.argtypes = [vp]
         L.mfd_destroy.restype = None
         L.mfd_strerror.argtypes = [i]
@@ -176,6 +178,21 @@ def mfd_lambda_re(ctx: Context, k, X, stream=None):
     return out
 
 
+PROFILE_CATEGORIES = ("stencil", "precond", "gram", "rr", "update", "other")
+
+
+def mfd_profile(ctx: Context, enable: bool):
+    _check(lib().mfd_profile(ctx.handle, int(bool(enable))))
+
+
+def mfd_profile_read(ctx: Context) -> dict:
+    ms = (ctypes.c_double * 6)()
+    cnt = (ctypes.c_longlong * 6)()
+    by = (ctypes.c_double * 6)()
+    _check(lib().mfd_profile_read(ctx.handle, ms, cnt, by))
+    return {PROFILE_CATEGORIES[i]: dict(ms=ms[i], count=cnt[i], bytes=by[i]) for i in range(6)}
+
+
 def default_opts(**kw) -> mfd_opts:
     o = mfd_opts()
     lib().mfd_default_opts(ctypes.byref(o))
@@ -201,6 +218,7 @@ def mfd_bands(ctx: Context, kpts, nbands: int, tol: float, opts: mfd_opts | None
     if status in raise_on:
         _check(status)
     stats = [dict(iters=s.iters, gamma_doublings=s.gamma_doublings, gamma=s.gamma,
-                  max_rel_resid=s.max_rel_resid, spurious=s.spurious, used_fallback=s.used_fallback, ms=s.ms)
+                  max_rel_resid=s.max_rel_resid, spurious=s.spurious, discarded=s.discarded,
+                  used_fallback=s.used_fallback, ms=s.ms)
              for s in st]
     return ev, stats, status

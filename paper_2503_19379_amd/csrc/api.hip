@@ -33,7 +33,61 @@ static int fail(int status, const std::string& msg) {
                         std::string(#call) + ": " + hipGetErrorString(_e));                               \
     } while (0)
 
+// Optional per-kernel timing with HIP events on the solve's stream.
+// Categories: 0 stencil, 1 FFT preconditioner, 2 Gram, 3 Rayleigh-Ritz,
+// 4 block update, 5 other.
+struct Prof {
+    static constexpr int NCAT = 6;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int cat; hipEvent_t a, b; double bytes; };
+    std::vector<Rec> pending;
+    double ms[NCAT] = {0}, bytes[NCAT] = {0};
+    long long count[NCAT] = {0};
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            hipEventCreate(&e);
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    hipEvent_t begin(hipStream_t s) {
+        if (!on) return nullptr;
+        hipEvent_t e = get();
+        hipEventRecord(e, s);
+        return e;
+    }
+    void end(hipEvent_t a, int cat, double by, hipStream_t s) {
+        if (!on || !a) return;
+        hipEvent_t b = get();
+        hipEventRecord(b, s);
+        pending.push_back({cat, a, b, by});
+    }
+    // call after a stream synchronisation
+    void drain() {
+        for (auto& r : pending) {
+            float t = 0.f;
+            hipEventElapsedTime(&t, r.a, r.b);
+            ms[r.cat] += t;
+            bytes[r.cat] += r.bytes;
+            count[r.cat] += 1;
+        }
+        pending.clear();
+        used = 0;
+    }
+    void reset() {
+        drain();
+        for (int i = 0; i < NCAT; ++i) { ms[i] = 0; bytes[i] = 0; count[i] = 0; }
+    }
+    ~Prof() {
+        for (auto e : pool) hipEventDestroy(e);
+    }
+};
+
 struct mfd_ctx {
+    Prof prof;
     int N = 0;
     double L = 1.0, h = 1.0;
     int order = 2;
@@ -59,6 +113,7 @@ struct mfd_ctx {
     double* cout = nullptr;
     double* host = nullptr;   // pinned: theta | norms | info | cout
     int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
+    int use_mfma = 1;   // matrix-core Gram/update (0: vector-FMA kernels)
 };
 
 namespace {
@@ -94,14 +149,18 @@ OpParams params(const mfd_ctx* ctx, const double k[3]) {
     p.h = ctx->h;
     for (int i = 0; i < 3; ++i) p.k[i] = k[i];
     const double kn = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    // Near Gamma (|k| < pi / (2L)) the shift of Remark 5.1 is used and |k| in
+    // the penalty rule is clamped at pi / (2L): the unclamped |k|^-2 term makes
+    // FP64 rounding of gamma B'B x exceed a 1e-8 relative residual there.
+    const double kball = M_PI / (2.0 * ctx->L);
     if (ctx->gamma_override > 0.0) {
         p.gamma = ctx->gamma_override;
     } else {
         const double a = ctx->N / (2.0 * M_PI);
-        const double b = kn > 0.0 ? std::pow(2.0 * M_PI / (ctx->L * kn), 2) : 0.0;
+        const double b = std::pow(2.0 * M_PI / (ctx->L * std::max(kn, kball)), 2);
         p.gamma = 2.0 * std::max(a, b);
     }
-    p.shift = (kn == 0.0) ? std::pow(M_PI / ctx->L, 2) : 0.0;
+    p.shift = (kn < kball) ? std::pow(M_PI / ctx->L, 2) : 0.0;
     return p;
 }
 
@@ -123,12 +182,13 @@ int ensure_ws(mfd_ctx* c, int mb) {
     free_ws(c);
     const size_t n = c->n;
     c->nparts_upd = (int)std::min<size_t>(1024, (n + 255) / 256);
-    c->nparts_gram = gram_parts(n);
+    c->nparts_gram = gram_mfma_parts(n);
     c->nparts_col = (int)std::min<size_t>(256, (n + 255) / 256);
     const size_t K = 3 * (size_t)mb;
     HIPCHK(hipMalloc(&c->V, n * 6 * mb * sizeof(double2)));
     HIPCHK(hipMalloc(&c->U, n * 6 * mb * sizeof(double2)));
-    HIPCHK(hipMalloc(&c->gpart, (size_t)c->nparts_gram * K * 2 * K * sizeof(double2)));
+    HIPCHK(hipMalloc(&c->gpart, std::max((size_t)c->nparts_gram * K * 2 * K,
+                                         gram_mfma_part_elems((int)K, c->nparts_gram)) * sizeof(double2)));
     HIPCHK(hipMalloc(&c->G, K * 2 * K * sizeof(double2)));
     HIPCHK(hipMalloc(&c->C, K * mb * sizeof(double2)));
     HIPCHK(hipMalloc(&c->npart, (size_t)c->nparts_upd * 2 * mb * sizeof(double)));
@@ -170,18 +230,32 @@ int lobpcg_k(mfd_ctx* c, const OpParams& p, int mb, int nbands, double tol, int 
     int it = 0;
     for (;; ++it) {
         ra.first = (it == 0);
+        const double N3 = (double)c->N * c->N * c->N;
         if (it > 0) {
             // W = T R (in place), AW = op(W)
+            hipEvent_t e0 = c->prof.begin(s);
             HIPCHK(launch_precond<double>(p, mb, col(V, n, mb), col(V, n, mb), c->tw64, s));
+            c->prof.end(e0, 1, N3 * 3 * 16.0 * 2 * mb, s);
+            e0 = c->prof.begin(s);
             HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
+            c->prof.end(e0, 0, N3 * (96.0 * mb + 24.0), s);
         }
-        HIPCHK(launch_gram(V, n, n, K, 2 * K, c->nparts_gram, c->gpart, c->G, s));
+        hipEvent_t e1 = c->prof.begin(s);
+        if (c->use_mfma) HIPCHK(launch_gram_mfma(V, n, n, K, c->nparts_gram, c->gpart, c->G, s));
+        else HIPCHK(launch_gram(V, n, n, K, 2 * K, c->nparts_gram, c->gpart, c->G, s));
+        c->prof.end(e1, 2, (double)n * 2 * K * 16.0, s);
+        e1 = c->prof.begin(s);
         HIPCHK(launch_rr(ra, s));
-        HIPCHK(launch_update(V, U, n, n, mb, c->C, c->theta, c->nparts_upd, c->npart, c->norms, s));
+        c->prof.end(e1, 3, 0.0, s);
+        e1 = c->prof.begin(s);
+        if (c->use_mfma) HIPCHK(launch_update_mfma(V, U, n, n, mb, c->C, c->theta, c->nparts_upd, c->npart, c->norms, s));
+        else HIPCHK(launch_update(V, U, n, n, mb, c->C, c->theta, c->nparts_upd, c->npart, c->norms, s));
+        c->prof.end(e1, 4, (double)n * 11 * mb * 16.0, s);
         std::swap(V, U);
         HIPCHK(hipMemcpyAsync(hth, c->theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hnorm, c->norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        c->prof.drain();
         bool conv = true;
         for (int j = 0; j < nbands; ++j) {
             const double r = std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j]));
@@ -225,7 +299,7 @@ void mfd_default_opts(mfd_opts* o) {
     o->warm_start = 1;
     o->seed = 0;
     o->max_gamma_doublings = 4;
-    o->guard = 0;
+    o->guard = 2;
     o->x0 = nullptr;
 }
 
@@ -389,30 +463,50 @@ int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol, 
             HIPCHK(launch_fill_random(ctx->V, n * mb, o.seed * 1000003ull + (uint64_t)ik, s));
         }
         KResult kr;
-        int doublings = 0, total_iters = 0, nspur = 0;
-        std::vector<double> lam(mb), lre(nbands);
+        int doublings = 0, total_iters = 0, nspur = 0, discarded = 0;
+        int nreq = nbands;
+        std::vector<double> lam(mb), lre(mb);
+        std::vector<int> sel;
         for (;;) {
-            st = lobpcg_k(ctx, p, mb, nbands, tol, o.max_iter, s, kr);
+            st = lobpcg_k(ctx, p, mb, nreq, tol, o.max_iter, s, kr);
             if (st) return st;
             total_iters += kr.iters;
             for (int j = 0; j < mb; ++j) lam[j] = kr.theta[j] - p.shift;
-            // Alg 4.1: recompute lambda_re = |M_0^(1/2) A'x|^2 / |x|^2
-            st = mfd_lambda_re(ctx, k, nbands, ctx->V, lre.data(), stream);
+            // Alg 4.1: recompute lambda_re = |M_0^(1/2) A'x|^2 / |x|^2; a band with
+            // lambda - lambda_re visibly > 0 is a compensation (spurious) mode
+            st = mfd_lambda_re(ctx, k, mb, ctx->V, lre.data(), stream);
             if (st) return st;
-            std::vector<int> spur;
-            for (int j = 0; j < nbands; ++j)
-                if (lam[j] - lre[j] > 1e-4 * std::fabs(lam[j]) + 1e-10 * scale) spur.push_back(j);
+            std::vector<int> phys, spur;
+            for (int j = 0; j < mb; ++j) {
+                const bool sp = lam[j] - lre[j] > 1e-4 * std::fabs(lam[j]) + 1e-10 * scale;
+                (sp ? spur : phys).push_back(j);
+            }
+            if ((int)phys.size() >= nbands) {
+                const int need = phys[nbands - 1] + 1;
+                if (need > nreq && kr.converged) {
+                    nreq = need;   // flagged bands are discarded: converge one band further
+                    continue;
+                }
+                sel.assign(phys.begin(), phys.begin() + nbands);
+                discarded = need - nbands;
+                nspur = 0;
+                break;
+            }
             nspur = (int)spur.size();
-            if (spur.empty() || doublings >= o.max_gamma_doublings) break;
+            if (doublings >= o.max_gamma_doublings) {
+                for (int j = 0; j < nbands; ++j) sel.push_back(j);
+                break;
+            }
+            // too few physical bands: enlarge gamma and solve again (Alg 4.1)
             p.gamma *= 2.0;
             ++doublings;
+            nreq = nbands;
             for (size_t q = 0; q < spur.size(); ++q)
                 HIPCHK(launch_fill_random(col(ctx->V, n, spur[q]), n,
                                           o.seed * 1000003ull + 7919ull * doublings + spur[q] + 101ull * ik, s));
         }
-        // sort the returned bands
-        std::vector<int> idx(mb);
-        for (int j = 0; j < mb; ++j) idx[j] = j;
+        // the returned bands, ascending
+        std::vector<int> idx(sel);
         std::sort(idx.begin(), idx.end(), [&](int a, int b) { return lam[a] < lam[b]; });
         double maxres = 0.0;
         for (int j = 0; j < nbands; ++j) {
@@ -433,13 +527,32 @@ int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol, 
             ks.gamma = p.gamma;
             ks.max_rel_resid = maxres;
             ks.spurious = nspur;
+            ks.discarded = discarded;
             ks.used_fallback = 0;
             ks.ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
         }
         if (nspur && ret == MFD_OK) ret = fail(MFD_ESPURIOUS, "Alg 4.1 still flags a band");
-        if (!kr.converged && ret == MFD_OK) ret = fail(MFD_ENOTCONV, "max_iter reached");
+        if (maxres > tol && ret == MFD_OK) ret = fail(MFD_ENOTCONV, "max_iter reached");
     }
     return ret;
+}
+
+int mfd_profile(mfd_ctx* ctx, int enable) {
+    if (!ctx) return fail(MFD_EINVAL, "ctx is NULL");
+    ctx->prof.reset();
+    ctx->prof.on = enable != 0;
+    return MFD_OK;
+}
+
+int mfd_profile_read(mfd_ctx* ctx, double* ms, long long* count, double* bytes) {
+    if (!ctx || !ms || !count || !bytes) return fail(MFD_EINVAL, "NULL argument");
+    ctx->prof.drain();
+    for (int i = 0; i < Prof::NCAT; ++i) {
+        ms[i] = ctx->prof.ms[i];
+        count[i] = ctx->prof.count[i];
+        bytes[i] = ctx->prof.bytes[i];
+    }
+    return MFD_OK;
 }
 
 void mfd_destroy(mfd_ctx* ctx) {

@@ -36,16 +36,21 @@ def test_homog_n8_closed_form(B):
 
 
 def test_homog_n8_literal_gamma_alg41(B):
-    """With gamma = 16 a compensation eigenvalue sits third; Alg 4.1 flags it
-    and one doubling returns the physical bands."""
+    """With gamma = 16 a compensation eigenvalue sits third; Alg 4.1 flags it."""
     N, k, m = 8, np.array([0.3, 0.2, 0.1]) * np.pi, 8
     ctx = B.mfd_build(N, 1.0, 2, np.ones((N, N, N)))
     B.mfd_set_gamma(ctx, 16.0)
-    ev, st, status = B.mfd_bands(ctx, [k], m, 1e-10)
-    assert status == 0
     phys, _ = mfd.closed_form_spectrum(N, 1.0, k, 16.0)
+    # as printed (no spare columns): flag, double gamma, solve again
+    ev, st, status = B.mfd_bands(ctx, [k], m, 1e-10, B.default_opts(guard=0))
+    assert status == 0
     assert np.allclose(ev[0], phys[:m], rtol=1e-10)
     assert st[0]["gamma_doublings"] == 1 and st[0]["gamma"] == 32.0
+    # with spare columns the flagged band is discarded
+    ev, st, status = B.mfd_bands(ctx, [k], m, 1e-10, B.default_opts(guard=2))
+    assert status == 0
+    assert np.allclose(ev[0], phys[:m], rtol=1e-10)
+    assert st[0]["gamma_doublings"] == 0 and st[0]["discarded"] == 1
 
 
 @pytest.mark.parametrize("k", [np.array([0.5, 0.1, 0.2]) * np.pi, np.zeros(3), np.array([np.pi, np.pi, 0.0])])
