@@ -71,6 +71,9 @@ typedef struct {
     int max_gamma_doublings;  /* Alg 4.1 restarts (default 4) */
     int guard;                /* extra block columns beyond nbands (default 2); they also hold
                                  compensation modes that Alg 4.1 flags and discards */
+    int streams;              /* k-path segments (mfd_bands) or crystals (mfd_bands_batch) solved
+                                 concurrently, each on its own stream and host thread (default 4,
+                                 at most 16) */
     const void* x0;           /* optional device c128 start block [nbands][3][N][N][N] for the first
                                  k-point (NULL: random) */
 } mfd_opts;
@@ -128,12 +131,25 @@ int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double
  * mfd_precond_solve, then the recompute check of Alg 4.1: bands it flags as
  * spurious are discarded when enough physical ones remain among the
  * nbands + guard, otherwise gamma is doubled and the solve repeated.
+ * The k-points are cut into opts->streams contiguous segments solved
+ * concurrently; inside a segment each k-point starts from the previous one's
+ * vectors (warm_start = 1).
  * kpts: host nk x 3.  tol: relative residual target (see mfd_kstats).
  * evals: host nk x nbands, ascending.  evecs: device c128
  * [nk][nbands][3][N][N][N] or NULL.  stats: host nk entries or NULL.
  * Returns MFD_ENOTCONV / MFD_ESPURIOUS after filling evals and stats. */
 int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol,
               const mfd_opts* opts, double* evals, void* evecs, mfd_kstats* stats, void* stream);
+
+/* Many crystals in one call (uneven grids allowed): crystal c has context
+ * ctxs[c] (distinct), nk[c] k-points kpts[c] (host nk[c] x 3) and writes
+ * evals[c] (host nk[c] x nbands) and stats[c] (host nk[c], or stats = NULL).
+ * Crystals are distributed over opts->streams concurrent workers; each
+ * crystal's k-path is solved in order with warm starts.  opts->x0 must be NULL.
+ * Same return codes as mfd_bands. */
+int mfd_bands_batch(int ncrys, mfd_ctx* const* ctxs, const int* nk, const double* const* kpts, int nbands,
+                    double tol, const mfd_opts* opts, double* const* evals, mfd_kstats* const* stats,
+                    void* stream);
 
 /* Per-kernel timing of mfd_bands with HIP events recorded on the solve's
  * stream around each launch group.  mfd_profile(ctx, 1) clears the counters

@@ -31,7 +31,7 @@ class MfdError(RuntimeError):
 class mfd_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("precision", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("seed", ctypes.c_ulonglong), ("max_gamma_doublings", ctypes.c_int), ("guard", ctypes.c_int),
-                ("x0", ctypes.c_void_p)]
+                ("streams", ctypes.c_int), ("x0", ctypes.c_void_p)]
 
 
 class mfd_kstats(ctypes.Structure):
@@ -61,6 +61,9 @@ def lib():
         L.mfd_lambda_re.argtypes = [vp, dp, i, vp, dp, vp]
         L.mfd_bands.argtypes = [vp, i, dp, i, d, ctypes.POINTER(mfd_opts), dp, vp,
                                 ctypes.POINTER(mfd_kstats), vp]
+        L.mfd_bands_batch.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(dp), i, d,
+                                      ctypes.POINTER(mfd_opts), ctypes.POINTER(dp),
+                                      ctypes.POINTER(ctypes.POINTER(mfd_kstats)), vp]
         L.mfd_default_opts.argtypes = [ctypes.POINTER(mfd_opts)]
         L.mfd_default_opts.restype = None
         L.mfd_profile.argtypes = [vp, i]
@@ -222,3 +225,31 @@ def mfd_bands(ctx: Context, kpts, nbands: int, tol: float, opts: mfd_opts | None
                   used_fallback=s.used_fallback, ms=s.ms)
              for s in st]
     return ev, stats, status
+
+
+def _stats_list(st):
+    return [dict(iters=s.iters, gamma_doublings=s.gamma_doublings, gamma=s.gamma,
+                 max_rel_resid=s.max_rel_resid, spurious=s.spurious, discarded=s.discarded,
+                 used_fallback=s.used_fallback, ms=s.ms) for s in st]
+
+
+def mfd_bands_batch(ctxs, kpts_list, nbands: int, tol: float, opts: mfd_opts | None = None, stream=None,
+                    raise_on=(-1, -2, -3, -6)):
+    """Many crystals (uneven grids allowed) in one call.  Returns
+    (list of evals (nk_c, nbands), list of stats lists, status)."""
+    nc = len(ctxs)
+    ks = [np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1, 3)) for k in kpts_list]
+    evs = [np.zeros((k.shape[0], nbands)) for k in ks]
+    sts = [(mfd_kstats * k.shape[0])() for k in ks]
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = (ctypes.c_void_p * nc)(*[c.handle for c in ctxs])
+    nk = (ctypes.c_int * nc)(*[k.shape[0] for k in ks])
+    kp = (dp * nc)(*[k.ctypes.data_as(dp) for k in ks])
+    ep = (dp * nc)(*[e.ctypes.data_as(dp) for e in evs])
+    sp = (ctypes.POINTER(mfd_kstats) * nc)(*[ctypes.cast(s, ctypes.POINTER(mfd_kstats)) for s in sts])
+    o = opts if opts is not None else default_opts()
+    status = lib().mfd_bands_batch(nc, h, nk, kp, int(nbands), float(tol), ctypes.byref(o), ep, sp,
+                                   _stream(stream))
+    if status in raise_on:
+        _check(status)
+    return evs, [_stats_list(s) for s in sts], status

@@ -7,9 +7,12 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
+#include <atomic>
+#include <thread>
 
 #include "../../include/mfdkc.h"
 #include "common.h"
@@ -77,31 +80,29 @@ struct Prof {
         pending.clear();
         used = 0;
     }
+    void clear() {
+        for (int i = 0; i < NCAT; ++i) { ms[i] = 0; bytes[i] = 0; count[i] = 0; }
+    }
     void reset() {
         drain();
-        for (int i = 0; i < NCAT; ++i) { ms[i] = 0; bytes[i] = 0; count[i] = 0; }
+        clear();
+    }
+    void add(const Prof& o) {
+        for (int i = 0; i < NCAT; ++i) { ms[i] += o.ms[i]; bytes[i] += o.bytes[i]; count[i] += o.count[i]; }
     }
     ~Prof() {
         for (auto e : pool) hipEventDestroy(e);
     }
 };
 
-struct mfd_ctx {
-    Prof prof;
-    int N = 0;
-    double L = 1.0, h = 1.0;
-    int order = 2;
-    int device = 0;
-    double gamma_override = 0.0;
-    double* mu64 = nullptr;
-    float* mu32 = nullptr;
-    void* tw64 = nullptr;
-    void* tw32 = nullptr;
-    // band-solve workspace (FP64)
-    int ws_mb = 0;
+// Band-solve workspace: one per concurrently solved k-path segment or
+// crystal, each with its own stream (default priority) and timing.
+struct Ws {
+    int mb = 0;
     size_t n = 0;
-    double2* V = nullptr;
-    double2* U = nullptr;
+    hipStream_t stream = nullptr;
+    double2* V = nullptr;      // n x 6mb: [X | W | P | AX | AW | AP]
+    double2* U = nullptr;      // the next V
     double2* gpart = nullptr;
     double2* G = nullptr;
     double2* C = nullptr;
@@ -111,9 +112,25 @@ struct mfd_ctx {
     int* info = nullptr;
     double* cpart = nullptr;
     double* cout = nullptr;
-    double* host = nullptr;   // pinned: theta | norms | info | cout
+    double* host = nullptr;    // pinned: theta | norms | info | column sums
     int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
-    int use_mfma = 1;   // matrix-core Gram/update (0: vector-FMA kernels)
+    Prof prof;
+};
+
+struct mfd_ctx {
+    int N = 0;
+    double L = 1.0, h = 1.0;
+    int order = 2;
+    int device = 0;
+    double gamma_override = 0.0;
+    double* mu64 = nullptr;
+    float* mu32 = nullptr;
+    void* tw64 = nullptr;
+    void* tw32 = nullptr;
+    size_t n = 0;
+    std::vector<Ws*> ws;
+    bool prof_on = false;
+    Prof prof_done;            // timing of finished solves (summed over workspaces)
 };
 
 namespace {
@@ -166,39 +183,61 @@ OpParams params(const mfd_ctx* ctx, const double k[3]) {
 
 bool finite3(const double* k) { return std::isfinite(k[0]) && std::isfinite(k[1]) && std::isfinite(k[2]); }
 
-void free_ws(mfd_ctx* c) {
-    hipFree(c->V); hipFree(c->U); hipFree(c->gpart); hipFree(c->G); hipFree(c->C);
-    hipFree(c->npart); hipFree(c->norms); hipFree(c->theta); hipFree(c->info);
-    hipFree(c->cpart); hipFree(c->cout);
-    if (c->host) hipHostFree(c->host);
-    c->V = c->U = c->gpart = c->G = c->C = nullptr;
-    c->npart = c->norms = c->theta = c->cpart = c->cout = c->host = nullptr;
-    c->info = nullptr;
-    c->ws_mb = 0;
+void ws_free(Ws* w) {
+    if (!w) return;
+    hipFree(w->V); hipFree(w->U); hipFree(w->gpart); hipFree(w->G); hipFree(w->C);
+    hipFree(w->npart); hipFree(w->norms); hipFree(w->theta); hipFree(w->info);
+    hipFree(w->cpart); hipFree(w->cout);
+    if (w->host) hipHostFree(w->host);
+    if (w->stream) hipStreamDestroy(w->stream);
+    delete w;
 }
 
-int ensure_ws(mfd_ctx* c, int mb) {
-    if (c->ws_mb == mb) return MFD_OK;
-    free_ws(c);
+int ws_alloc(const mfd_ctx* c, int mb, Ws** out) {
+    Ws* w = new Ws();
+    *out = nullptr;
     const size_t n = c->n;
-    c->nparts_upd = (int)std::min<size_t>(1024, (n + 255) / 256);
-    c->nparts_gram = gram_mfma_parts(n);
-    c->nparts_col = (int)std::min<size_t>(256, (n + 255) / 256);
+    w->mb = mb;
+    w->n = n;
+    w->nparts_upd = (int)std::min<size_t>(1024, (n + 255) / 256);
+    w->nparts_gram = gram_mfma_parts(n);
+    w->nparts_col = (int)std::min<size_t>(256, (n + 255) / 256);
     const size_t K = 3 * (size_t)mb;
-    HIPCHK(hipMalloc(&c->V, n * 6 * mb * sizeof(double2)));
-    HIPCHK(hipMalloc(&c->U, n * 6 * mb * sizeof(double2)));
-    HIPCHK(hipMalloc(&c->gpart, std::max((size_t)c->nparts_gram * K * 2 * K,
-                                         gram_mfma_part_elems((int)K, c->nparts_gram)) * sizeof(double2)));
-    HIPCHK(hipMalloc(&c->G, K * 2 * K * sizeof(double2)));
-    HIPCHK(hipMalloc(&c->C, K * mb * sizeof(double2)));
-    HIPCHK(hipMalloc(&c->npart, (size_t)c->nparts_upd * 2 * mb * sizeof(double)));
-    HIPCHK(hipMalloc(&c->norms, 2 * mb * sizeof(double)));
-    HIPCHK(hipMalloc(&c->theta, mb * sizeof(double)));
-    HIPCHK(hipMalloc(&c->info, 8 * sizeof(int)));
-    HIPCHK(hipMalloc(&c->cpart, (size_t)std::max(c->nparts_col, 1024) * 2 * mb * sizeof(double)));
-    HIPCHK(hipMalloc(&c->cout, 2 * mb * sizeof(double)));
-    HIPCHK(hipHostMalloc(&c->host, (8 * mb + 16) * sizeof(double), hipHostMallocDefault));
-    c->ws_mb = mb;
+    hipError_t e;
+    auto chk = [&](hipError_t r) { e = r; return r == hipSuccess; };
+    if (!(chk(hipStreamCreate(&w->stream)) && chk(hipMalloc(&w->V, n * 6 * mb * sizeof(double2))) &&
+          chk(hipMalloc(&w->U, n * 6 * mb * sizeof(double2))) &&
+          chk(hipMalloc(&w->gpart, std::max((size_t)w->nparts_gram * K * 2 * K,
+                                            gram_mfma_part_elems((int)K, w->nparts_gram)) * sizeof(double2))) &&
+          chk(hipMalloc(&w->G, K * 2 * K * sizeof(double2))) && chk(hipMalloc(&w->C, K * mb * sizeof(double2))) &&
+          chk(hipMalloc(&w->npart, (size_t)w->nparts_upd * 2 * mb * sizeof(double))) &&
+          chk(hipMalloc(&w->norms, 2 * mb * sizeof(double))) && chk(hipMalloc(&w->theta, mb * sizeof(double))) &&
+          chk(hipMalloc(&w->info, 16 * sizeof(int))) &&
+          chk(hipMalloc(&w->cpart, (size_t)std::max(w->nparts_col, 1024) * 2 * mb * sizeof(double))) &&
+          chk(hipMalloc(&w->cout, 2 * mb * sizeof(double))) &&
+          chk(hipHostMalloc(&w->host, (8 * mb + 32) * sizeof(double), hipHostMallocDefault)))) {
+        ws_free(w);
+        return fail(e == hipErrorOutOfMemory ? MFD_ENOMEM : MFD_EDEVICE, hipGetErrorString(e));
+    }
+    w->prof.on = c->prof_on;
+    *out = w;
+    return MFD_OK;
+}
+
+// Make ctx hold `count` workspaces for block size mb.
+int ensure_ws(mfd_ctx* c, int mb, int count) {
+    for (Ws* w : c->ws)
+        if (w->mb != mb) {
+            for (Ws* x : c->ws) ws_free(x);
+            c->ws.clear();
+            break;
+        }
+    while ((int)c->ws.size() < count) {
+        Ws* w = nullptr;
+        int st = ws_alloc(c, mb, &w);
+        if (st) return st;
+        c->ws.push_back(w);
+    }
     return MFD_OK;
 }
 
@@ -211,53 +250,68 @@ struct KResult {
     std::vector<double> theta, res;
 };
 
-// LOBPCG at one k-point from the start block in V[:, :mb] (FP64).
-int lobpcg_k(mfd_ctx* c, const OpParams& p, int mb, int nbands, double tol, int max_iter, hipStream_t s,
-             KResult& out) {
-    const size_t n = c->n;
+// LOBPCG at one k-point from the start block in V[:, :mb] (FP64).  Stops when
+// the lowest `nreq` columns have converged (or after max_iter iterations).
+int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max_iter, KResult& out) {
+    const size_t n = w.n;
+    const int mb = w.mb;
     const int K = 3 * mb;
-    double2* V = c->V;
-    double2* U = c->U;
+    hipStream_t s = w.stream;
+    double2* V = w.V;
+    double2* U = w.U;
     // zero W, P, AW, AP; AX = op(X)
     HIPCHK(hipMemsetAsync(col(V, n, mb), 0, n * 2 * mb * sizeof(double2), s));
     HIPCHK(hipMemsetAsync(col(V, n, 4 * mb), 0, n * 2 * mb * sizeof(double2), s));
     HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
     RRArgs ra;
-    ra.G = c->G; ra.norms = c->norms; ra.theta = c->theta; ra.C = c->C; ra.info = c->info;
+    ra.G = w.G; ra.norms = w.norms; ra.theta = w.theta; ra.C = w.C; ra.info = w.info;
     ra.mb = mb; ra.tol = tol; ra.drop_w = 1e-10; ra.drop_p = 1e-8;
-    double* hth = c->host;
-    double* hnorm = c->host + mb;
+    double* hth = w.host;
+    double* hnorm = w.host + mb;
+    static const bool trace = std::getenv("MFD_TRACE") != nullptr;
+    const double N3 = (double)c->N * c->N * c->N;
     int it = 0;
     for (;; ++it) {
         ra.first = (it == 0);
-        const double N3 = (double)c->N * c->N * c->N;
         if (it > 0) {
             // W = T R (in place), AW = op(W)
-            hipEvent_t e0 = c->prof.begin(s);
+            hipEvent_t e0 = w.prof.begin(s);
             HIPCHK(launch_precond<double>(p, mb, col(V, n, mb), col(V, n, mb), c->tw64, s));
-            c->prof.end(e0, 1, N3 * 3 * 16.0 * 2 * mb, s);
-            e0 = c->prof.begin(s);
+            w.prof.end(e0, 1, N3 * 3 * 16.0 * 2 * mb, s);
+            e0 = w.prof.begin(s);
             HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
-            c->prof.end(e0, 0, N3 * (96.0 * mb + 24.0), s);
+            w.prof.end(e0, 0, N3 * (96.0 * mb + 24.0), s);
         }
-        hipEvent_t e1 = c->prof.begin(s);
-        if (c->use_mfma) HIPCHK(launch_gram_mfma(V, n, n, K, c->nparts_gram, c->gpart, c->G, s));
-        else HIPCHK(launch_gram(V, n, n, K, 2 * K, c->nparts_gram, c->gpart, c->G, s));
-        c->prof.end(e1, 2, (double)n * 2 * K * 16.0, s);
-        e1 = c->prof.begin(s);
+        hipEvent_t e1 = w.prof.begin(s);
+        HIPCHK(launch_gram_mfma(V, n, n, K, w.nparts_gram, w.gpart, w.G, s));
+        w.prof.end(e1, 2, (double)n * 2 * K * 16.0, s);
+        e1 = w.prof.begin(s);
         HIPCHK(launch_rr(ra, s));
-        c->prof.end(e1, 3, 0.0, s);
-        e1 = c->prof.begin(s);
-        if (c->use_mfma) HIPCHK(launch_update_mfma(V, U, n, n, mb, c->C, c->theta, c->nparts_upd, c->npart, c->norms, s));
-        else HIPCHK(launch_update(V, U, n, n, mb, c->C, c->theta, c->nparts_upd, c->npart, c->norms, s));
-        c->prof.end(e1, 4, (double)n * 11 * mb * 16.0, s);
+        w.prof.end(e1, 3, 0.0, s);
+        e1 = w.prof.begin(s);
+        HIPCHK(launch_update_mfma(V, U, n, n, mb, w.C, w.theta, w.nparts_upd, w.npart, w.norms, s));
+        w.prof.end(e1, 4, (double)n * 11 * mb * 16.0, s);
         std::swap(V, U);
-        HIPCHK(hipMemcpyAsync(hth, c->theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(hnorm, c->norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hth, w.theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+        int* hinfo = (int*)(w.host + 3 * mb);
+        if (trace) HIPCHK(hipMemcpyAsync(hinfo, w.info, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        c->prof.drain();
+        w.prof.drain();
+        if (trace) {
+            double rmax = 0.0;
+            int nact = 0;
+            for (int j = 0; j < mb; ++j) {
+                const double r = std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j]));
+                if (j < nreq) rmax = std::max(rmax, r);
+                nact += r > tol;
+            }
+            std::fprintf(stderr, "it %4d rmax %.3e active %2d kept %2d dropP %d sweeps %d th0 %.8f thn %.8f "
+                         "rr-ticks %d %d %d %d %d Kk %d\n", it, rmax, nact, hinfo[0], hinfo[1], hinfo[3], hth[0],
+                         hth[nreq - 1], hinfo[4], hinfo[5], hinfo[6], hinfo[7], hinfo[8], hinfo[9]);
+        }
         bool conv = true;
-        for (int j = 0; j < nbands; ++j) {
+        for (int j = 0; j < nreq; ++j) {
             const double r = std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j]));
             if (!(r <= tol)) conv = false;
         }
@@ -266,24 +320,211 @@ int lobpcg_k(mfd_ctx* c, const OpParams& p, int mb, int nbands, double tol, int 
             break;
         }
     }
-    c->V = V;
-    c->U = U;
+    w.V = V;
+    w.U = U;
     out.iters = it;
     // final check with a fresh FP64 operator application: AX slot <- op(X)
     HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
-    HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, nullptr, c->nparts_col, c->cpart, c->cout, s));
-    HIPCHK(hipMemcpyAsync(c->host, c->cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, nullptr, w.nparts_col, w.cpart, w.cout, s));
+    HIPCHK(hipMemcpyAsync(w.host, w.cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     out.theta.assign(mb, 0.0);
-    for (int j = 0; j < mb; ++j) out.theta[j] = c->host[2 * j + 1] / c->host[2 * j];
-    HIPCHK(hipMemcpyAsync(c->theta, out.theta.data(), mb * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, c->theta, c->nparts_col, c->cpart, c->cout, s));
     std::vector<double> xx(mb);
-    for (int j = 0; j < mb; ++j) xx[j] = c->host[2 * j];
-    HIPCHK(hipMemcpyAsync(c->host, c->cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+    for (int j = 0; j < mb; ++j) {
+        out.theta[j] = w.host[2 * j + 1] / w.host[2 * j];
+        xx[j] = w.host[2 * j];
+    }
+    std::memcpy(w.host + 4 * mb, out.theta.data(), mb * sizeof(double));
+    HIPCHK(hipMemcpyAsync(w.theta, w.host + 4 * mb, mb * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, w.theta, w.nparts_col, w.cpart, w.cout, s));
+    HIPCHK(hipMemcpyAsync(w.host, w.cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     out.res.assign(mb, 0.0);
-    for (int j = 0; j < mb; ++j) out.res[j] = std::sqrt(c->host[2 * j]) / (std::fabs(out.theta[j]) * std::sqrt(xx[j]));
+    for (int j = 0; j < mb; ++j) out.res[j] = std::sqrt(w.host[2 * j]) / (std::fabs(out.theta[j]) * std::sqrt(xx[j]));
+    return MFD_OK;
+}
+
+// lambda_re of Alg 4.1 for nb c128 fields on the workspace's stream.
+int lambda_re_ws(mfd_ctx* c, Ws& w, const OpParams& p, int nb, const void* X, double* out) {
+    const int nparts = 128;
+    HIPCHK(launch_lambda_re(p, nb, X, c->mu64, w.cpart, nparts, w.cout, w.stream));
+    HIPCHK(hipMemcpyAsync(w.host, w.cout, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, w.stream));
+    HIPCHK(hipStreamSynchronize(w.stream));
+    for (int b = 0; b < nb; ++b) out[b] = w.host[2 * b] / w.host[2 * b + 1];
+    return MFD_OK;
+}
+
+struct KOut {
+    double* evals;       // nbands
+    double2* evecs;      // nbands x n or null
+    mfd_kstats* stats;   // or null
+};
+
+// One k-point: LOBPCG on mb = nbands + guard columns starting from V[:, :mb],
+// then Alg 4.1 (discard flagged bands, or double gamma and solve again).
+int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mfd_opts& o, uint64_t seed_k,
+            const KOut& ko, int* converged) {
+    const size_t n = w.n;
+    const int mb = w.mb;
+    hipStream_t s = w.stream;
+    auto t0 = std::chrono::steady_clock::now();
+    OpParams p = params(c, k);
+    const double scale = std::pow(2.0 * M_PI / c->L, 2);
+    KResult kr;
+    int doublings = 0, total_iters = 0, nspur = 0, discarded = 0;
+    int nreq = nbands;
+    std::vector<double> lam(mb), lre(mb);
+    std::vector<int> sel;
+    for (;;) {
+        int st = lobpcg_k(c, w, p, nreq, tol, o.max_iter, kr);
+        if (st) return st;
+        total_iters += kr.iters;
+        for (int j = 0; j < mb; ++j) lam[j] = kr.theta[j] - p.shift;
+        // Alg 4.1: recompute lambda_re = |M_0^(1/2) A'x|^2 / |x|^2; a band with
+        // lambda - lambda_re visibly > 0 is a compensation (spurious) mode
+        st = lambda_re_ws(c, w, p, mb, w.V, lre.data());
+        if (st) return st;
+        std::vector<int> phys, spur;
+        for (int j = 0; j < mb; ++j) {
+            const bool sp = lam[j] - lre[j] > 1e-4 * std::fabs(lam[j]) + 1e-10 * scale;
+            (sp ? spur : phys).push_back(j);
+        }
+        if ((int)phys.size() >= nbands) {
+            const int need = phys[nbands - 1] + 1;
+            if (need > nreq && kr.converged) {
+                nreq = need;   // flagged bands are discarded: converge one band further
+                continue;
+            }
+            sel.assign(phys.begin(), phys.begin() + nbands);
+            discarded = need - nbands;
+            nspur = 0;
+            break;
+        }
+        nspur = (int)spur.size();
+        if (doublings >= o.max_gamma_doublings) {
+            for (int j = 0; j < nbands; ++j) sel.push_back(j);
+            break;
+        }
+        // too few physical bands: enlarge gamma and solve again (Alg 4.1)
+        p.gamma *= 2.0;
+        ++doublings;
+        nreq = nbands;
+        for (size_t q = 0; q < spur.size(); ++q)
+            HIPCHK(launch_fill_random(col(w.V, n, spur[q]), n, seed_k + 7919ull * doublings + spur[q], s));
+    }
+    std::vector<int> idx(sel);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+    double maxres = 0.0;
+    for (int j = 0; j < nbands; ++j) {
+        ko.evals[j] = lam[idx[j]];
+        maxres = std::max(maxres, kr.res[idx[j]]);
+    }
+    if (ko.evecs) {
+        for (int j = 0; j < nbands; ++j)
+            HIPCHK(hipMemcpyAsync(ko.evecs + (size_t)j * n, col(w.V, n, idx[j]), n * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (ko.stats) {
+        mfd_kstats& ks = *ko.stats;
+        ks.iters = total_iters;
+        ks.gamma_doublings = doublings;
+        ks.gamma = p.gamma;
+        ks.max_rel_resid = maxres;
+        ks.spurious = nspur;
+        ks.discarded = discarded;
+        ks.used_fallback = 0;
+        ks.ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    *converged = (maxres <= tol) ? (nspur ? 2 : 1) : 0;
+    return MFD_OK;
+}
+
+// A run of consecutive k-points on one workspace: random start at the first
+// (or the caller's block), warm start from the previous k-point afterwards.
+struct Segment {
+    mfd_ctx* ctx;
+    Ws* ws;
+    const double* kpts;    // nk x 3
+    int k0, k1;            // [k0, k1)
+    int nbands;
+    double tol;
+    mfd_opts opts;
+    double* evals;         // nk x nbands
+    double2* evecs;        // nk x nbands x n or null
+    mfd_kstats* stats;     // nk or null
+    int status = MFD_OK;
+    int worst = 1;         // 1 all converged, 0 some not, 2 spurious remain
+    std::string err;
+};
+
+void run_segment(Segment* sg) {
+    mfd_ctx* c = sg->ctx;
+    Ws& w = *sg->ws;
+    const size_t n = w.n;
+    const int mb = w.mb;
+    const mfd_opts& o = sg->opts;
+    for (int ik = sg->k0; ik < sg->k1; ++ik) {
+        const uint64_t seed_k = o.seed * 1000003ull + 104729ull * (uint64_t)ik;
+        int st = MFD_OK;
+        if (ik == sg->k0 && ik == 0 && o.x0) {
+            hipError_t e = hipMemcpyAsync(w.V, o.x0, n * sg->nbands * sizeof(double2), hipMemcpyDeviceToDevice,
+                                          w.stream);
+            if (e == hipSuccess && mb > sg->nbands)
+                e = launch_fill_random(col(w.V, n, sg->nbands), n * (mb - sg->nbands), seed_k + 17, w.stream);
+            if (e != hipSuccess) st = fail(MFD_EDEVICE, hipGetErrorString(e));
+        } else if (ik == sg->k0 || !o.warm_start) {
+            hipError_t e = launch_fill_random(w.V, n * mb, seed_k, w.stream);
+            if (e != hipSuccess) st = fail(MFD_EDEVICE, hipGetErrorString(e));
+        }
+        int conv = 1;
+        if (!st) {
+            KOut ko{sg->evals + (size_t)ik * sg->nbands,
+                    sg->evecs ? sg->evecs + (size_t)ik * sg->nbands * n : nullptr,
+                    sg->stats ? sg->stats + ik : nullptr};
+            st = solve_k(c, w, sg->kpts + 3 * ik, sg->nbands, sg->tol, o, seed_k, ko, &conv);
+        }
+        if (st) {
+            sg->status = st;
+            sg->err = g_last_error;
+            return;
+        }
+        if (conv == 0) sg->worst = 0;
+        else if (conv == 2 && sg->worst == 1) sg->worst = 2;
+    }
+}
+
+// Run segments on their workspaces, one host thread each; collect timing.
+int run_segments(std::vector<Segment>& segs) {
+    std::vector<std::thread> th;
+    for (size_t i = 1; i < segs.size(); ++i) th.emplace_back(run_segment, &segs[i]);
+    if (!segs.empty()) run_segment(&segs[0]);
+    for (auto& t : th) t.join();
+    for (auto& sg : segs) {
+        sg.ws->prof.drain();
+        sg.ctx->prof_done.add(sg.ws->prof);
+        sg.ws->prof.clear();
+    }
+    for (auto& sg : segs)
+        if (sg.status) return fail(sg.status, sg.err);
+    int ret = MFD_OK;
+    for (auto& sg : segs) {
+        if (sg.worst == 2 && ret == MFD_OK) ret = fail(MFD_ESPURIOUS, "Alg 4.1 still flags a band");
+        if (sg.worst == 0 && ret == MFD_OK) ret = fail(MFD_ENOTCONV, "max_iter reached");
+    }
+    return ret;
+}
+
+int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
+    if (nbands <= 0) return fail(MFD_EINVAL, "nbands must be > 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
+    if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0 || o.streams < 1 || o.streams > 16)
+        return fail(MFD_EINVAL, "bad options");
+    const int mb = nbands + o.guard;
+    if (3 * mb > 64) return fail(MFD_EUNSUPPORTED, "nbands + guard must be <= 21");
+    if ((size_t)mb > ctx->n) return fail(MFD_EINVAL, "nbands exceeds the problem size");
+    if (o.precision != 0) return fail(MFD_EUNSUPPORTED, "mixed precision not built yet");
     return MFD_OK;
 }
 
@@ -300,6 +541,7 @@ void mfd_default_opts(mfd_opts* o) {
     o->seed = 0;
     o->max_gamma_doublings = 4;
     o->guard = 2;
+    o->streams = 4;
     o->x0 = nullptr;
 }
 
@@ -432,132 +674,132 @@ int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double
 int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol, const mfd_opts* opts,
               double* evals, void* evecs, mfd_kstats* stats, void* stream) {
     if (!ctx || !kpts || !evals) return fail(MFD_EINVAL, "NULL argument");
-    if (nk <= 0 || nbands <= 0) return fail(MFD_EINVAL, "nk and nbands must be > 0");
-    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
+    if (nk <= 0) return fail(MFD_EINVAL, "nk must be > 0");
     mfd_opts o;
     mfd_default_opts(&o);
     if (opts) o = *opts;
-    if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0) return fail(MFD_EINVAL, "bad options");
-    const int mb = nbands + o.guard;
-    if (3 * mb > 64) return fail(MFD_EUNSUPPORTED, "nbands + guard must be <= 21");
-    if ((size_t)mb > ctx->n) return fail(MFD_EINVAL, "nbands exceeds the problem size");
+    int st = check_opts(ctx, nbands, tol, o);
+    if (st) return st;
     for (int i = 0; i < 3 * nk; ++i)
         if (!std::isfinite(kpts[i])) return fail(MFD_EINVAL, "k must be finite");
-    if (o.precision != 0) return fail(MFD_EUNSUPPORTED, "mixed precision not built yet");
-    int st = ensure_ws(ctx, mb);
-    if (st) return st;
-    hipStream_t s = (hipStream_t)stream;
-    const size_t n = ctx->n;
-    const double scale = std::pow(2.0 * M_PI / ctx->L, 2);
+    const int mb = nbands + o.guard;
+    const int nseg = std::min(o.streams, nk);
+    if ((st = ensure_ws(ctx, mb, nseg))) return st;
+    // the workspaces' streams start after the caller's stream work
+    hipEvent_t ready;
+    HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ready, (hipStream_t)stream));
+    for (int i = 0; i < nseg; ++i) HIPCHK(hipStreamWaitEvent(ctx->ws[i]->stream, ready, 0));
+    hipEventDestroy(ready);
+    std::vector<Segment> segs(nseg);
+    for (int i = 0; i < nseg; ++i) {
+        Segment& sg = segs[i];
+        sg.ctx = ctx;
+        sg.ws = ctx->ws[i];
+        sg.kpts = kpts;
+        sg.k0 = (int)((long long)nk * i / nseg);
+        sg.k1 = (int)((long long)nk * (i + 1) / nseg);
+        sg.nbands = nbands;
+        sg.tol = tol;
+        sg.opts = o;
+        sg.evals = evals;
+        sg.evecs = (double2*)evecs;
+        sg.stats = stats;
+    }
+    return run_segments(segs);
+}
+
+int mfd_bands_batch(int ncrys, mfd_ctx* const* ctxs, const int* nk, const double* const* kpts, int nbands,
+                    double tol, const mfd_opts* opts, double* const* evals, mfd_kstats* const* stats, void* stream) {
+    if (ncrys <= 0 || !ctxs || !nk || !kpts || !evals) return fail(MFD_EINVAL, "NULL or empty argument");
+    mfd_opts o;
+    mfd_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.x0) return fail(MFD_EINVAL, "x0 is not used by the batch call");
+    const int mb = nbands + o.guard;
+    for (int c = 0; c < ncrys; ++c) {
+        if (!ctxs[c] || !kpts[c] || !evals[c] || nk[c] <= 0) return fail(MFD_EINVAL, "bad crystal entry");
+        int st = check_opts(ctxs[c], nbands, tol, o);
+        if (st) return st;
+        for (int i = 0; i < 3 * nk[c]; ++i)
+            if (!std::isfinite(kpts[c][i])) return fail(MFD_EINVAL, "k must be finite");
+        for (int d = 0; d < c; ++d)
+            if (ctxs[d] == ctxs[c]) return fail(MFD_EINVAL, "a context appears twice in the batch");
+    }
+    // crystals are taken in order by `streams` workers (largest grids first
+    // would balance better; the order is the caller's)
+    hipEvent_t ready;
+    HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ready, (hipStream_t)stream));
+    std::vector<Segment> segs(ncrys);
+    for (int c = 0; c < ncrys; ++c) {
+        int st = ensure_ws(ctxs[c], mb, 1);
+        if (st) { hipEventDestroy(ready); return st; }
+        HIPCHK(hipStreamWaitEvent(ctxs[c]->ws[0]->stream, ready, 0));
+        Segment& sg = segs[c];
+        sg.ctx = ctxs[c];
+        sg.ws = ctxs[c]->ws[0];
+        sg.kpts = kpts[c];
+        sg.k0 = 0;
+        sg.k1 = nk[c];
+        sg.nbands = nbands;
+        sg.tol = tol;
+        sg.opts = o;
+        sg.evals = evals[c];
+        sg.evecs = nullptr;
+        sg.stats = stats ? stats[c] : nullptr;
+    }
+    hipEventDestroy(ready);
+    const int nw = std::min(o.streams, ncrys);
+    std::atomic<int> next(0);
+    auto worker = [&]() {
+        for (int c; (c = next.fetch_add(1)) < ncrys;) run_segment(&segs[c]);
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nw; ++i) th.emplace_back(worker);
+    worker();
+    for (auto& t : th) t.join();
+    for (auto& sg : segs) {
+        sg.ws->prof.drain();
+        sg.ctx->prof_done.add(sg.ws->prof);
+        sg.ws->prof.clear();
+    }
+    for (auto& sg : segs)
+        if (sg.status) return fail(sg.status, sg.err);
     int ret = MFD_OK;
-    for (int ik = 0; ik < nk; ++ik) {
-        auto t0 = std::chrono::steady_clock::now();
-        const double* k = kpts + 3 * ik;
-        OpParams p = params(ctx, k);
-        // start block
-        if (ik == 0 && o.x0) {
-            HIPCHK(hipMemcpyAsync(ctx->V, o.x0, n * nbands * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            if (mb > nbands)
-                HIPCHK(launch_fill_random(col(ctx->V, n, nbands), n * (mb - nbands), o.seed * 1000003ull + 17, s));
-        } else if (ik == 0 || !o.warm_start) {
-            HIPCHK(launch_fill_random(ctx->V, n * mb, o.seed * 1000003ull + (uint64_t)ik, s));
-        }
-        KResult kr;
-        int doublings = 0, total_iters = 0, nspur = 0, discarded = 0;
-        int nreq = nbands;
-        std::vector<double> lam(mb), lre(mb);
-        std::vector<int> sel;
-        for (;;) {
-            st = lobpcg_k(ctx, p, mb, nreq, tol, o.max_iter, s, kr);
-            if (st) return st;
-            total_iters += kr.iters;
-            for (int j = 0; j < mb; ++j) lam[j] = kr.theta[j] - p.shift;
-            // Alg 4.1: recompute lambda_re = |M_0^(1/2) A'x|^2 / |x|^2; a band with
-            // lambda - lambda_re visibly > 0 is a compensation (spurious) mode
-            st = mfd_lambda_re(ctx, k, mb, ctx->V, lre.data(), stream);
-            if (st) return st;
-            std::vector<int> phys, spur;
-            for (int j = 0; j < mb; ++j) {
-                const bool sp = lam[j] - lre[j] > 1e-4 * std::fabs(lam[j]) + 1e-10 * scale;
-                (sp ? spur : phys).push_back(j);
-            }
-            if ((int)phys.size() >= nbands) {
-                const int need = phys[nbands - 1] + 1;
-                if (need > nreq && kr.converged) {
-                    nreq = need;   // flagged bands are discarded: converge one band further
-                    continue;
-                }
-                sel.assign(phys.begin(), phys.begin() + nbands);
-                discarded = need - nbands;
-                nspur = 0;
-                break;
-            }
-            nspur = (int)spur.size();
-            if (doublings >= o.max_gamma_doublings) {
-                for (int j = 0; j < nbands; ++j) sel.push_back(j);
-                break;
-            }
-            // too few physical bands: enlarge gamma and solve again (Alg 4.1)
-            p.gamma *= 2.0;
-            ++doublings;
-            nreq = nbands;
-            for (size_t q = 0; q < spur.size(); ++q)
-                HIPCHK(launch_fill_random(col(ctx->V, n, spur[q]), n,
-                                          o.seed * 1000003ull + 7919ull * doublings + spur[q] + 101ull * ik, s));
-        }
-        // the returned bands, ascending
-        std::vector<int> idx(sel);
-        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return lam[a] < lam[b]; });
-        double maxres = 0.0;
-        for (int j = 0; j < nbands; ++j) {
-            evals[(size_t)ik * nbands + j] = lam[idx[j]];
-            maxres = std::max(maxres, kr.res[idx[j]]);
-        }
-        if (evecs) {
-            for (int j = 0; j < nbands; ++j)
-                HIPCHK(hipMemcpyAsync((double2*)evecs + ((size_t)ik * nbands + j) * n, col(ctx->V, n, idx[j]),
-                                      n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipStreamSynchronize(s));
-        }
-        auto t1 = std::chrono::steady_clock::now();
-        if (stats) {
-            mfd_kstats& ks = stats[ik];
-            ks.iters = total_iters;
-            ks.gamma_doublings = doublings;
-            ks.gamma = p.gamma;
-            ks.max_rel_resid = maxres;
-            ks.spurious = nspur;
-            ks.discarded = discarded;
-            ks.used_fallback = 0;
-            ks.ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
-        }
-        if (nspur && ret == MFD_OK) ret = fail(MFD_ESPURIOUS, "Alg 4.1 still flags a band");
-        if (maxres > tol && ret == MFD_OK) ret = fail(MFD_ENOTCONV, "max_iter reached");
+    for (auto& sg : segs) {
+        if (sg.worst == 2 && ret == MFD_OK) ret = fail(MFD_ESPURIOUS, "Alg 4.1 still flags a band");
+        if (sg.worst == 0 && ret == MFD_OK) ret = fail(MFD_ENOTCONV, "max_iter reached");
     }
     return ret;
 }
 
 int mfd_profile(mfd_ctx* ctx, int enable) {
     if (!ctx) return fail(MFD_EINVAL, "ctx is NULL");
-    ctx->prof.reset();
-    ctx->prof.on = enable != 0;
+    ctx->prof_on = enable != 0;
+    ctx->prof_done.clear();
+    for (Ws* w : ctx->ws) {
+        w->prof.drain();
+        w->prof.clear();
+        w->prof.on = ctx->prof_on;
+    }
     return MFD_OK;
 }
 
 int mfd_profile_read(mfd_ctx* ctx, double* ms, long long* count, double* bytes) {
     if (!ctx || !ms || !count || !bytes) return fail(MFD_EINVAL, "NULL argument");
-    ctx->prof.drain();
     for (int i = 0; i < Prof::NCAT; ++i) {
-        ms[i] = ctx->prof.ms[i];
-        count[i] = ctx->prof.count[i];
-        bytes[i] = ctx->prof.bytes[i];
+        ms[i] = ctx->prof_done.ms[i];
+        count[i] = ctx->prof_done.count[i];
+        bytes[i] = ctx->prof_done.bytes[i];
     }
     return MFD_OK;
 }
 
 void mfd_destroy(mfd_ctx* ctx) {
     if (!ctx) return;
-    free_ws(ctx);
+    for (Ws* w : ctx->ws) ws_free(w);
+    ctx->ws.clear();
     hipFree(ctx->mu64);
     hipFree(ctx->mu32);
     hipFree(ctx->tw64);

@@ -70,17 +70,34 @@ __global__ __launch_bounds__(256) void gram_kernel(const C128* __restrict__ V, s
         }
 }
 
-// out[c] = sum_w in[w * ncols + c], fixed order (deterministic).
-__global__ void reduce_parts_kernel(const double* __restrict__ in, int nparts, int ncols, double* __restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
+// out[c] = sum_w in[w * ncols + c] in a fixed order (deterministic): a
+// workgroup owns CG columns; its 256 / CG thread rows stride over the parts
+// and a tree in LDS combines them.
+template <int CG>
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const double* __restrict__ in, int nparts, int ncols,
+                                                           double* __restrict__ out) {
+    constexpr int RG = 256 / CG;
+    __shared__ double red[256];
+    const int cl = threadIdx.x % CG, g = threadIdx.x / CG;
+    const int c = blockIdx.x * CG + cl;
     double s = 0.0;
-    for (int w = 0; w < nparts; ++w) s += in[(size_t)w * ncols + c];
-    out[c] = s;
+    if (c < ncols)
+        for (int w = g; w < nparts; w += RG) s += in[(size_t)w * ncols + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = RG / 2; h > 0; h >>= 1) {
+        if (g < h) red[threadIdx.x] += red[threadIdx.x + h * CG];
+        __syncthreads();
+    }
+    if (g == 0 && c < ncols) out[c] = red[cl];
 }
 
 hipError_t launch_reduce(const double* parts, int nparts, int ncols, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3((ncols + 255) / 256), dim3(256), 0, s, parts, nparts, ncols, out);
+    if (ncols <= 128)
+        hipLaunchKernelGGL(reduce_parts_kernel<1>, dim3(ncols), dim3(256), 0, s, parts, nparts, ncols, out);
+    else
+        hipLaunchKernelGGL(reduce_parts_kernel<32>, dim3((ncols + 31) / 32), dim3(256), 0, s, parts, nparts, ncols,
+                           out);
     return hipGetLastError();
 }
 

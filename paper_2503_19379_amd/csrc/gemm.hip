@@ -27,8 +27,9 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 // Workgroup w sums rows [w rows_per, (w+1) rows_per) into its own partial
 // tile set; gram_reduce_kernel adds the partials in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int GM_KS = 16;       // rows per LDS slab
+constexpr int GM_KS = 32;       // rows per LDS slab
 constexpr int GM_MAXT = 3;      // tiles per wave; one wave per GM_MAXT tiles, up to 16 waves
+constexpr int GM_PF = 12;       // prefetch registers (complex) per thread
 
 struct GramTiles {
     int n;                      // number of tiles
@@ -36,43 +37,70 @@ struct GramTiles {
     unsigned char half[80];     // 0: G_S, 1: G_A
 };
 
-__global__ __launch_bounds__(1024) void gram_mfma_kernel(const double2* __restrict__ V, size_t ld,
-                                                                 size_t n, int K, size_t rows_per, GramTiles tl,
-                                                                 double2* __restrict__ part) {
+// The next slab is loaded into registers while the current one is consumed
+// from LDS by the matrix cores.
+__global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restrict__ V, size_t ld,
+                                                         size_t n, int K, size_t rows_per, GramTiles tl,
+                                                         double2* __restrict__ part) {
     extern __shared__ unsigned char smem_raw[];
     double2* slab = reinterpret_cast<double2*>(smem_raw);   // [GM_KS][2K]
     const int C2 = 2 * K;
     const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int nwaves = blockDim.x >> 6;
+    const int nwaves = nthr >> 6;
     const size_t r0 = (size_t)blockIdx.x * rows_per;
     const size_t r1 = min(n, r0 + rows_per);
     const int my_n = (tl.n - wave + nwaves - 1) / nwaves;   // tiles wave, wave + nwaves, ...
+    const int nel = GM_KS * C2;
     d4 acc[GM_MAXT][3];
 #pragma unroll
     for (int t = 0; t < GM_MAXT; ++t)
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[t][q] = d4{0.0, 0.0, 0.0, 0.0};
     const int li = lane & 15, lk = lane >> 4;
-
+    // per-tile operand offsets in a slab row
+    int oa[GM_MAXT], ob[GM_MAXT];
+    bool va[GM_MAXT], vb[GM_MAXT];
+#pragma unroll
+    for (int t = 0; t < GM_MAXT; ++t) {
+        const int ti = min(wave + nwaves * t, tl.n - 1);
+        const int i = tl.ti[ti] * 16 + li, j = tl.tj[ti] * 16 + li;
+        va[t] = i < K;
+        vb[t] = j < K;
+        oa[t] = va[t] ? i : 0;
+        ob[t] = vb[t] ? tl.half[ti] * K + j : 0;
+    }
+    double2 pf[GM_PF];
+    auto prefetch = [&](size_t s0) {
+        const int rows = (int)min((size_t)GM_KS, r1 > s0 ? r1 - s0 : 0);
+#pragma unroll
+        for (int q = 0; q < GM_PF; ++q) {
+            const int e = tid + q * nthr;
+            pf[q] = mk<double2>(0.0, 0.0);
+            if (e < nel) {
+                const int r = e % GM_KS, c = e / GM_KS;
+                if (r < rows) pf[q] = V[(size_t)c * ld + s0 + r];
+            }
+        }
+    };
+    prefetch(r0);
     for (size_t s0 = r0; s0 < r1; s0 += GM_KS) {
-        const int rows = (int)min((size_t)GM_KS, r1 - s0);
-        for (int e = tid; e < GM_KS * C2; e += blockDim.x) {
-            const int r = e % GM_KS, c = e / GM_KS;
-            slab[r * C2 + c] = (r < rows) ? V[(size_t)c * ld + s0 + r] : mk<double2>(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < GM_PF; ++q) {
+            const int e = tid + q * nthr;
+            if (e < nel) slab[(e % GM_KS) * C2 + e / GM_KS] = pf[q];
         }
         __syncthreads();
+        if (s0 + GM_KS < r1) prefetch(s0 + GM_KS);
 #pragma unroll
         for (int k0 = 0; k0 < GM_KS; k0 += 4) {
             const double2* srow = slab + (k0 + lk) * C2;
 #pragma unroll
             for (int t = 0; t < GM_MAXT; ++t) {
                 if (t >= my_n) break;
-                const int ti = wave + nwaves * t;
-                const int i = tl.ti[ti] * 16 + li;
-                const int j = tl.tj[ti] * 16 + li;
-                const double2 a = (i < K) ? srow[i] : mk<double2>(0.0, 0.0);
-                const double2 b = (j < K) ? srow[tl.half[ti] * K + j] : mk<double2>(0.0, 0.0);
+                const double2 a = va[t] ? srow[oa[t]] : mk<double2>(0.0, 0.0);
+                const double2 b = vb[t] ? srow[ob[t]] : mk<double2>(0.0, 0.0);
                 acc[t][0] = mfma64(a.x, b.x, acc[t][0]);
                 acc[t][1] = mfma64(a.y, b.y, acc[t][1]);
                 acc[t][2] = mfma64(a.x - a.y, b.x + b.y, acc[t][2]);
@@ -95,23 +123,17 @@ __global__ __launch_bounds__(1024) void gram_mfma_kernel(const double2* __restri
     }
 }
 
-// G (K x 2K row-major) from the partial tiles; mirrors the lower triangles.
-__global__ void gram_reduce_kernel(const double2* __restrict__ part, int nparts, int K, GramTiles tl,
-                                   double2* __restrict__ G) {
+// G (K x 2K row-major) from the summed tiles; mirrors the lower triangles.
+__global__ void gram_scatter_kernel(const double2* __restrict__ sum, int K, GramTiles tl, double2* __restrict__ G) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= tl.n * 256) return;
     const int t = e / 256, rc = e % 256;
-    double sx = 0.0, sy = 0.0;
-    for (int w = 0; w < nparts; ++w) {
-        const double2 v = part[((size_t)w * tl.n + t) * 256 + rc];
-        sx += v.x;
-        sy += v.y;
-    }
+    const double2 v = sum[e];
     const int i = tl.ti[t] * 16 + rc / 16, j = tl.tj[t] * 16 + rc % 16;
     if (i >= K || j >= K) return;
     const int off = tl.half[t] * K;
-    if (i <= j) G[(size_t)i * 2 * K + off + j] = mk<double2>(sx, sy);
-    if (i < j) G[(size_t)j * 2 * K + off + i] = mk<double2>(sx, -sy);
+    if (i <= j) G[(size_t)i * 2 * K + off + j] = v;
+    if (i < j) G[(size_t)j * 2 * K + off + i] = mk<double2>(v.x, -v.y);
 }
 
 static GramTiles make_tiles(int K) {
@@ -133,14 +155,17 @@ int gram_mfma_parts(size_t n) { return (int)std::min<size_t>(512, (n + 1023) / 1
 
 size_t gram_mfma_part_elems(int K, int nparts) {
     const int T = (K + 15) / 16;
-    return (size_t)nparts * T * (T + 1) * 256;
+    return (size_t)(nparts + 1) * T * (T + 1) * 256;   // partials + their sum
 }
 
 hipError_t launch_gram_mfma(const void* V, size_t ld, size_t n, int K, int nparts, void* part, void* G,
                             hipStream_t s) {
     GramTiles tl = make_tiles(K);
-    const int nwaves = (tl.n + GM_MAXT - 1) / GM_MAXT;
-    if (nwaves > 16 || K > 64) return hipErrorInvalidValue;
+    const int nwaves_t = (tl.n + GM_MAXT - 1) / GM_MAXT;
+    if (K > 64) return hipErrorInvalidValue;
+    const int need = (int)((GM_KS * 2 * K + GM_PF * 64 - 1) / (GM_PF * 64));
+    const int nwaves = std::max(nwaves_t, need);
+    if (nwaves > 7) return hipErrorInvalidValue;
     const size_t rows_per = ((n + nparts - 1) / nparts + GM_KS - 1) / GM_KS * GM_KS;
     const int nw = (int)((n + rows_per - 1) / rows_per);
     const size_t lds = (size_t)GM_KS * 2 * K * sizeof(double2);
@@ -150,8 +175,11 @@ hipError_t launch_gram_mfma(const void* V, size_t ld, size_t n, int K, int npart
     hipLaunchKernelGGL(gram_mfma_kernel, dim3(nw), dim3(64 * nwaves), lds, s, (const double2*)V, ld, n, K,
                        rows_per, tl, (double2*)part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((tl.n * 256 + 255) / 256), dim3(256), 0, s, (const double2*)part, nw,
-                       K, tl, (double2*)G);
+    // sum the partial tiles (in place into the first part's slot after the last), then scatter
+    double2* sum = (double2*)part + (size_t)nw * tl.n * 256;
+    if ((e = launch_reduce((const double*)part, nw, tl.n * 256 * 2, (double*)sum, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(gram_scatter_kernel, dim3((tl.n * 256 + 255) / 256), dim3(256), 0, s, (const double2*)sum, K, tl,
+                       (double2*)G);
     return hipGetLastError();
 }
 
@@ -162,137 +190,164 @@ hipError_t launch_gram_mfma(const void* V, size_t ld, size_t n, int K, int npart
 // Output U = [X' | R' | P' | AX' | - | AP'].  Each wave owns 16-row strips;
 // the coefficients sit in LDS as MFMA B fragments.
 // ---------------------------------------------------------------------------
-constexpr int UP_WAVES = 4;
+constexpr int UP_RB = 32;       // rows per block
+constexpr int UP_RBP = 33;      // padded column stride of the LDS blocks (conflict-free fragment reads)
+constexpr int UP_PF = 16;       // prefetch registers (complex) per thread
 
-template <int UP_MAXJ>   // mb <= 16 UP_MAXJ (16-column output tiles)
-__global__ __launch_bounds__(64 * UP_WAVES) void update_mfma_kernel(const double2* __restrict__ V,
-                                                                   double2* __restrict__ U, size_t ld, size_t n,
-                                                                   int mb, const double2* __restrict__ Cg,
-                                                                   const double* __restrict__ theta,
-                                                                   double* __restrict__ npart) {
+// 256 threads = 4 waves: wave w computes rows 16 (w & 1) .. of the block for
+// chain w >> 1 (0: S -> P', X'; 1: AS -> AP', AX').  X' and AX' meet in LDS,
+// where R' = AX' - X' theta and the column norms are formed and written out
+// row-contiguously.
+template <int MJ>   // mb <= 16 MJ
+__global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restrict__ V, double2* __restrict__ U,
+                                                          size_t ld, size_t n, int mb,
+                                                          const double2* __restrict__ Cg,
+                                                          const double* __restrict__ theta,
+                                                          double* __restrict__ npart) {
+    constexpr int MP = 16 * MJ;
     extern __shared__ unsigned char smem_raw[];
     const int K = 3 * mb;
     const int KP = (K + 3) / 4 * 4;
-    const int MP = UP_MAXJ * 16;
-    double2* Cs = reinterpret_cast<double2*>(smem_raw);      // [KP][MP], zero padded
-    double* red = reinterpret_cast<double*>(Cs + KP * MP);   // [UP_WAVES][2][MP]
+    const int C2 = 2 * K;
+    double2* Cs = reinterpret_cast<double2*>(smem_raw);      // [KP][MP]
+    double2* slab = Cs + KP * MP;                             // [C2][UP_RBP], column-major
+    double2* xo = slab + C2 * UP_RBP;                         // [2][MP][UP_RBP]: X', AX'
+    double* red = reinterpret_cast<double*>(xo + 2 * MP * UP_RBP);   // [8][2][MP]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < KP * MP; e += 64 * UP_WAVES) {
+    const int strip = wave & 1, chain = wave >> 1;
+    for (int e = tid; e < KP * MP; e += 256) {
         const int k = e / MP, j = e % MP;
         Cs[e] = (k < K && j < mb) ? Cg[k * mb + j] : mk<double2>(0.0, 0.0);
     }
-    __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
-    const int nj = (mb + 15) / 16;
-    double th[UP_MAXJ];
-    double nr[UP_MAXJ], nx[UP_MAXJ];
+    // R phase mapping: row = tid % 32, columns jg, jg + 8, ...
+    const int rrow = tid & 31, jg = tid >> 5;
+    constexpr int NJ = MP / 8;
+    double th[NJ], nr[NJ], nx[NJ];
 #pragma unroll
-    for (int J = 0; J < UP_MAXJ; ++J) {
-        const int j = 16 * J + li;
-        th[J] = (j < mb) ? theta[j] : 0.0;
-        nr[J] = nx[J] = 0.0;
+    for (int c = 0; c < NJ; ++c) {
+        const int j = jg + 8 * c;
+        th[c] = (j < mb) ? theta[j] : 0.0;
+        nr[c] = nx[c] = 0.0;
     }
-    const size_t nstrips = (n + 15) / 16;
-    for (size_t st = (size_t)blockIdx.x * UP_WAVES + wave; st < nstrips; st += (size_t)gridDim.x * UP_WAVES) {
-        const size_t row0 = st * 16;
-        const size_t arow = row0 + li;          // A-fragment row of this lane
-        const bool rok = arow < n;
-        // accumulators: [J][chain X/AX][t1 t2 t3]
-        d4 acc[UP_MAXJ][2][3];
+    const int nel = UP_RB * C2;
+    const size_t nblk = (n + UP_RB - 1) / UP_RB;
+    double2 pf[UP_PF];
+    auto prefetch = [&](size_t blk) {
+        const size_t b0 = blk * UP_RB;
 #pragma unroll
-        for (int J = 0; J < UP_MAXJ; ++J)
+        for (int q = 0; q < UP_PF; ++q) {
+            const int e = tid + q * 256;
+            pf[q] = mk<double2>(0.0, 0.0);
+            if (e < nel && blk < nblk) {
+                const int r = e % UP_RB, c = e / UP_RB;
+                if (b0 + r < n) pf[q] = V[(size_t)c * ld + b0 + r];
+            }
+        }
+    };
+    prefetch(blockIdx.x);
+    for (size_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const size_t b0 = blk * UP_RB;
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+        for (int q = 0; q < UP_PF; ++q) {
+            const int e = tid + q * 256;
+            if (e < nel) slab[(e / UP_RB) * UP_RBP + e % UP_RB] = pf[q];
+        }
+        __syncthreads();
+        prefetch(blk + gridDim.x);
+        d4 acc[MJ][3];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) acc[J][c][q] = d4{0.0, 0.0, 0.0, 0.0};
-        // two passes over the basis columns: [mb, K) -> P', then [0, mb) -> X'
+        for (int J = 0; J < MJ; ++J)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[J][q] = d4{0.0, 0.0, 0.0, 0.0};
+        const double2* arow = slab + (size_t)chain * K * UP_RBP + 16 * strip + li;   // A fragment: row of this lane
         for (int pass = 0; pass < 2; ++pass) {
             const int kb = pass == 0 ? mb : 0;
             const int ke = pass == 0 ? K : mb;
             for (int k0 = kb; k0 < ke; k0 += 4) {
                 const int k = k0 + lk;
-                double2 s = mk<double2>(0.0, 0.0), as = mk<double2>(0.0, 0.0);
-                if (k < ke && rok) {
-                    s = V[(size_t)k * ld + arow];
-                    as = V[(size_t)(K + k) * ld + arow];
-                }
-                // rows of C: k (the wave's 4 k-rows) -- B fragment lane l: C[k0 + l/16][16 J + l%16];
-                // k beyond ke reads C rows of the next range, but the A fragment there is zero.
+                const double2 sv = (k < ke) ? arow[k * UP_RBP] : mk<double2>(0.0, 0.0);
 #pragma unroll
-                for (int J = 0; J < UP_MAXJ; ++J) {
-                    if (J >= nj) break;
+                for (int J = 0; J < MJ; ++J) {
                     const double2 c = (k < ke) ? Cs[k * MP + 16 * J + li] : mk<double2>(0.0, 0.0);
-                    const double cs = c.x + c.y;
-                    acc[J][0][0] = mfma64(s.x, c.x, acc[J][0][0]);
-                    acc[J][0][1] = mfma64(s.y, c.y, acc[J][0][1]);
-                    acc[J][0][2] = mfma64(s.x + s.y, cs, acc[J][0][2]);
-                    acc[J][1][0] = mfma64(as.x, c.x, acc[J][1][0]);
-                    acc[J][1][1] = mfma64(as.y, c.y, acc[J][1][1]);
-                    acc[J][1][2] = mfma64(as.x + as.y, cs, acc[J][1][2]);
+                    acc[J][0] = mfma64(sv.x, c.x, acc[J][0]);
+                    acc[J][1] = mfma64(sv.y, c.y, acc[J][1]);
+                    acc[J][2] = mfma64(sv.x + sv.y, c.x + c.y, acc[J][2]);
                 }
             }
-            // write P' / AP' after the first pass, X' / AX' / R' after the second
 #pragma unroll
-            for (int J = 0; J < UP_MAXJ; ++J) {
-                if (J >= nj) break;
+            for (int J = 0; J < MJ; ++J) {
                 const int j = 16 * J + li;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const size_t row = row0 + lk + 4 * r;
-                    const double t1 = acc[J][0][0][r], t2 = acc[J][0][1][r], t3 = acc[J][0][2][r];
-                    const double u1 = acc[J][1][0][r], u2 = acc[J][1][1][r], u3 = acc[J][1][2][r];
-                    const double2 x = mk<double2>(t1 - t2, t3 - t1 - t2);
-                    const double2 ax = mk<double2>(u1 - u2, u3 - u1 - u2);
-                    if (j < mb && row < n) {
-                        if (pass == 0) {
-                            U[(size_t)(2 * mb + j) * ld + row] = x;
-                            U[(size_t)(5 * mb + j) * ld + row] = ax;
-                        } else {
-                            const double2 res = mk<double2>(ax.x - th[J] * x.x, ax.y - th[J] * x.y);
-                            U[(size_t)j * ld + row] = x;
-                            U[(size_t)(3 * mb + j) * ld + row] = ax;
-                            U[(size_t)(mb + j) * ld + row] = res;
-                            nr[J] += cabs2(res);
-                            nx[J] += cabs2(x);
-                        }
+                    const int rl = 16 * strip + lk + 4 * r;
+                    const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
+                    const double2 v = mk<double2>(t1 - t2, t3 - t1 - t2);
+                    if (pass == 0) {
+                        const size_t row = b0 + rl;
+                        if (j < mb && row < n) U[(size_t)((chain ? 5 : 2) * mb + j) * ld + row] = v;
+                    } else {
+                        xo[(chain * MP + j) * UP_RBP + rl] = v;
                     }
                 }
             }
         }
-    }
-    // column sums: lanes l, l+16, l+32, l+48 share column l % 16
+        __syncthreads();
+        // R' = AX' - X' theta; write X', AX', R' row-contiguously; column norms
+        const size_t row = b0 + rrow;
+        if (row < n) {
 #pragma unroll
-    for (int J = 0; J < UP_MAXJ; ++J) {
-        double a = nr[J], b = nx[J];
-        a += __shfl_down(a, 32);
-        b += __shfl_down(b, 32);
-        a += __shfl_down(a, 16);
-        b += __shfl_down(b, 16);
-        if (lane < 16) {
-            red[(wave * 2 + 0) * MP + 16 * J + lane] = a;
-            red[(wave * 2 + 1) * MP + 16 * J + lane] = b;
+            for (int c = 0; c < NJ; ++c) {
+                const int j = jg + 8 * c;
+                if (j < mb) {
+                    const double2 x = xo[j * UP_RBP + rrow];
+                    const double2 ax = xo[(MP + j) * UP_RBP + rrow];
+                    const double2 res = mk<double2>(ax.x - th[c] * x.x, ax.y - th[c] * x.y);
+                    U[(size_t)j * ld + row] = x;
+                    U[(size_t)(3 * mb + j) * ld + row] = ax;
+                    U[(size_t)(mb + j) * ld + row] = res;
+                    nr[c] += cabs2(res);
+                    nx[c] += cabs2(x);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // column sums over the 32 threads of each column group
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+        double a = nr[c], b = nx[c];
+        for (int o = 16; o > 0; o >>= 1) {
+            a += __shfl_down(a, o, 32);
+            b += __shfl_down(b, o, 32);
+        }
+        if (rrow == 0) {
+            red[(c * 8 + jg) * 2 + 0] = a;
+            red[(c * 8 + jg) * 2 + 1] = b;
         }
     }
     __syncthreads();
     if (tid < 2 * mb) {
         const int which = tid / mb, j = tid % mb;
-        double s = 0.0;
-        for (int w = 0; w < UP_WAVES; ++w) s += red[(w * 2 + which) * MP + j];
-        npart[(size_t)blockIdx.x * 2 * mb + tid] = s;
+        const int c = j / 8, g = j % 8;
+        npart[(size_t)blockIdx.x * 2 * mb + tid] = red[(c * 8 + g) * 2 + which];
     }
 }
 
 template <int MJ>
 static hipError_t update_mj(const void* V, void* U, size_t ld, size_t n, int mb, const void* C, const double* theta,
                             int nparts, double* npart, hipStream_t s) {
+    constexpr int MP = 16 * MJ;
     const int K = 3 * mb;
     const int KP = (K + 3) / 4 * 4;
-    const size_t lds = (size_t)KP * MJ * 16 * sizeof(double2) + UP_WAVES * 2 * MJ * 16 * sizeof(double);
+    if (UP_RB * 2 * K > UP_PF * 256) return hipErrorInvalidValue;
+    const size_t lds = ((size_t)KP * MP + (size_t)UP_RBP * 2 * K + 2 * UP_RBP * MP) * sizeof(double2) +
+                       (size_t)8 * 2 * MP * sizeof(double);
     auto kern = update_mfma_kernel<MJ>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nparts), dim3(64 * UP_WAVES), lds, s, (const double2*)V, (double2*)U, ld, n, mb,
+    hipLaunchKernelGGL(kern, dim3(nparts), dim3(256), lds, s, (const double2*)V, (double2*)U, ld, n, mb,
                        (const double2*)C, theta, npart);
     return hipGetLastError();
 }

@@ -84,3 +84,36 @@ def test_sphere_n16_vs_oracle(B):
             assert np.allclose(ev[i][3:], lam[3:], rtol=1e-9)
         else:
             assert np.allclose(ev[i], lam, rtol=1e-9), (i, ev[i], lam)
+
+
+def test_stream_segments_match_single_stream(B):
+    """Cutting the k-path into concurrently solved segments changes only the
+    start blocks, not the converged eigenvalues."""
+    N, m = 16, 6
+    eps = workloads.eps_sphere(N)
+    kp = workloads.kpath("GXMGR", 8)
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    e1, s1, st1 = B.mfd_bands(ctx, kp, m, 1e-10, B.default_opts(streams=1))
+    e4, s4, st4 = B.mfd_bands(ctx, kp, m, 1e-10, B.default_opts(streams=4))
+    assert st1 == 0 and st4 == 0
+    assert np.allclose(e1, e4, rtol=1e-9, atol=1e-9)
+
+
+def test_batch_uneven_grids(B):
+    """Several random-field crystals of different N in one batch call agree
+    with solving each crystal alone."""
+    Ns = (8, 12, 16, 24)
+    crystals = [(N, workloads.eps_random_field(N, c)) for c, N in enumerate(Ns)]
+    kp = workloads.kpath("GXMGR", 3)
+    ctxs = [B.mfd_build(N, 1.0, 2, eps) for N, eps in crystals]
+    evs, sts, status = B.mfd_bands_batch(ctxs, [kp] * len(ctxs), 5, 1e-10, B.default_opts(streams=3))
+    assert status == 0
+    for c, (N, eps) in enumerate(crystals):
+        one = B.mfd_build(N, 1.0, 2, eps)
+        e1, s1, st1 = B.mfd_bands(one, kp, 5, 1e-10, B.default_opts(streams=1))
+        assert st1 == 0
+        assert np.allclose(evs[c], e1, rtol=1e-9, atol=1e-9), (N, evs[c], e1)
+    # and one crystal against the oracle
+    N, eps = crystals[1]
+    lam, _, info = olob.solve_bands(eps, 1.0, kp[1], 5, tol=1e-10)
+    assert np.allclose(evs[1][1], lam, rtol=1e-9)
