@@ -76,6 +76,9 @@ typedef struct {
                                  at most 16) */
     const void* x0;           /* optional device c128 start block [nbands][3][N][N][N] for the first
                                  k-point (NULL: random) */
+    int stall_window;         /* precision 1: iterations without a halving of the largest
+                                 residual after which the k-point continues in FP64 (default 40,
+                                 0 = never) */
 } mfd_opts;
 
 typedef struct {
@@ -86,6 +89,9 @@ typedef struct {
     int spurious;             /* bands still flagged by Alg 4.1 among those returned */
     int discarded;            /* flagged bands skipped in favour of the next physical ones */
     int used_fallback;        /* warm start fell back to the random/previous-k start */
+    int fp64_fallback;        /* precision 1 only: the FP32-stored directions stalled (no halving
+                                 of the residual in 40 iterations) and the k-point was finished
+                                 in FP64 from the current block */
     float ms;                 /* wall time of this k-point */
 } mfd_kstats;
 

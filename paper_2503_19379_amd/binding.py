@@ -31,13 +31,13 @@ class MfdError(RuntimeError):
 class mfd_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("precision", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("seed", ctypes.c_ulonglong), ("max_gamma_doublings", ctypes.c_int), ("guard", ctypes.c_int),
-                ("streams", ctypes.c_int), ("x0", ctypes.c_void_p)]
+                ("streams", ctypes.c_int), ("x0", ctypes.c_void_p), ("stall_window", ctypes.c_int)]
 
 
 class mfd_kstats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("gamma_doublings", ctypes.c_int), ("gamma", ctypes.c_double),
                 ("max_rel_resid", ctypes.c_double), ("spurious", ctypes.c_int), ("discarded", ctypes.c_int),
-                ("used_fallback", ctypes.c_int), ("ms", ctypes.c_float)]
+                ("used_fallback", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("ms", ctypes.c_float)]
 
 
 _lib = None
@@ -220,17 +220,14 @@ def mfd_bands(ctx: Context, kpts, nbands: int, tol: float, opts: mfd_opts | None
                              _dev(evecs) if evecs is not None else None, st, _stream(stream))
     if status in raise_on:
         _check(status)
-    stats = [dict(iters=s.iters, gamma_doublings=s.gamma_doublings, gamma=s.gamma,
-                  max_rel_resid=s.max_rel_resid, spurious=s.spurious, discarded=s.discarded,
-                  used_fallback=s.used_fallback, ms=s.ms)
-             for s in st]
+    stats = _stats_list(st)
     return ev, stats, status
 
 
 def _stats_list(st):
     return [dict(iters=s.iters, gamma_doublings=s.gamma_doublings, gamma=s.gamma,
                  max_rel_resid=s.max_rel_resid, spurious=s.spurious, discarded=s.discarded,
-                 used_fallback=s.used_fallback, ms=s.ms) for s in st]
+                 used_fallback=s.used_fallback, fp64_fallback=s.fp64_fallback, ms=s.ms) for s in st]
 
 
 def mfd_bands_batch(ctxs, kpts_list, nbands: int, tol: float, opts: mfd_opts | None = None, stream=None,

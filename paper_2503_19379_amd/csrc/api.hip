@@ -99,7 +99,10 @@ struct Prof {
 // crystal, each with its own stream (default priority) and timing.
 struct Ws {
     int mb = 0;
+    bool mixed = false;
     size_t n = 0;
+    float2* V32 = nullptr;     // mixed precision: FP32 W, P, AW, AP (same column positions as V)
+    float2* U32 = nullptr;
     hipStream_t stream = nullptr;
     double2* V = nullptr;      // n x 6mb: [X | W | P | AX | AW | AP]
     double2* U = nullptr;      // the next V
@@ -186,6 +189,7 @@ bool finite3(const double* k) { return std::isfinite(k[0]) && std::isfinite(k[1]
 void ws_free(Ws* w) {
     if (!w) return;
     hipFree(w->V); hipFree(w->U); hipFree(w->gpart); hipFree(w->G); hipFree(w->C);
+    hipFree(w->V32); hipFree(w->U32);
     hipFree(w->npart); hipFree(w->norms); hipFree(w->theta); hipFree(w->info);
     hipFree(w->cpart); hipFree(w->cout);
     if (w->host) hipHostFree(w->host);
@@ -193,11 +197,12 @@ void ws_free(Ws* w) {
     delete w;
 }
 
-int ws_alloc(const mfd_ctx* c, int mb, Ws** out) {
+int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
     Ws* w = new Ws();
     *out = nullptr;
     const size_t n = c->n;
     w->mb = mb;
+    w->mixed = mixed;
     w->n = n;
     w->nparts_upd = (int)std::min<size_t>(1024, (n + 255) / 256);
     w->nparts_gram = gram_mfma_parts(n);
@@ -215,7 +220,9 @@ int ws_alloc(const mfd_ctx* c, int mb, Ws** out) {
           chk(hipMalloc(&w->info, 16 * sizeof(int))) &&
           chk(hipMalloc(&w->cpart, (size_t)std::max(w->nparts_col, 1024) * 2 * mb * sizeof(double))) &&
           chk(hipMalloc(&w->cout, 2 * mb * sizeof(double))) &&
-          chk(hipHostMalloc(&w->host, (8 * mb + 32) * sizeof(double), hipHostMallocDefault)))) {
+          chk(hipHostMalloc(&w->host, (8 * mb + 32) * sizeof(double), hipHostMallocDefault)) &&
+          (!mixed || (chk(hipMalloc(&w->V32, n * 6 * mb * sizeof(float2))) &&
+                      chk(hipMalloc(&w->U32, n * 6 * mb * sizeof(float2))))))) {
         ws_free(w);
         return fail(e == hipErrorOutOfMemory ? MFD_ENOMEM : MFD_EDEVICE, hipGetErrorString(e));
     }
@@ -224,17 +231,17 @@ int ws_alloc(const mfd_ctx* c, int mb, Ws** out) {
     return MFD_OK;
 }
 
-// Make ctx hold `count` workspaces for block size mb.
-int ensure_ws(mfd_ctx* c, int mb, int count) {
+// Make ctx hold `count` workspaces for block size mb and the given precision.
+int ensure_ws(mfd_ctx* c, int mb, bool mixed, int count) {
     for (Ws* w : c->ws)
-        if (w->mb != mb) {
+        if (w->mb != mb || w->mixed != mixed) {
             for (Ws* x : c->ws) ws_free(x);
             c->ws.clear();
             break;
         }
     while ((int)c->ws.size() < count) {
         Ws* w = nullptr;
-        int st = ws_alloc(c, mb, &w);
+        int st = ws_alloc(c, mb, mixed, &w);
         if (st) return st;
         c->ws.push_back(w);
     }
@@ -247,79 +254,142 @@ inline double2* col(double2* V, size_t n, int j) { return V + (size_t)j * n; }
 struct KResult {
     int iters = 0;
     bool converged = false;
+    bool fp64_fallback = false;
     std::vector<double> theta, res;
 };
 
 // LOBPCG at one k-point from the start block in V[:, :mb] (FP64).  Stops when
 // the lowest `nreq` columns have converged (or after max_iter iterations).
-int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max_iter, KResult& out) {
+int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max_iter, int stall_window,
+             KResult& out) {
     const size_t n = w.n;
     const int mb = w.mb;
     const int K = 3 * mb;
+    bool mixed = w.mixed;
     hipStream_t s = w.stream;
     double2* V = w.V;
     double2* U = w.U;
-    // zero W, P, AW, AP; AX = op(X)
-    HIPCHK(hipMemsetAsync(col(V, n, mb), 0, n * 2 * mb * sizeof(double2), s));
-    HIPCHK(hipMemsetAsync(col(V, n, 4 * mb), 0, n * 2 * mb * sizeof(double2), s));
+    float2* V32 = w.V32;
+    float2* U32 = w.U32;
+    out.fp64_fallback = false;
+    // zero W, P, AW, AP; AX = op(X) (FP64)
+    if (mixed) {
+        HIPCHK(hipMemsetAsync(V32 + n * mb, 0, n * 2 * mb * sizeof(float2), s));
+        HIPCHK(hipMemsetAsync(V32 + n * 4 * mb, 0, n * 2 * mb * sizeof(float2), s));
+    } else {
+        HIPCHK(hipMemsetAsync(col(V, n, mb), 0, n * 2 * mb * sizeof(double2), s));
+        HIPCHK(hipMemsetAsync(col(V, n, 4 * mb), 0, n * 2 * mb * sizeof(double2), s));
+    }
     HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
     RRArgs ra;
     ra.G = w.G; ra.norms = w.norms; ra.theta = w.theta; ra.C = w.C; ra.info = w.info;
-    ra.mb = mb; ra.tol = tol; ra.drop_w = 1e-10; ra.drop_p = 1e-8;
+    ra.mb = mb; ra.tol = tol;
+    // the Gram of FP32-stored directions is exact for the stored values, but
+    // their images AW, AP carry FP32 rounding: drop nearly dependent ones sooner
+    ra.drop_w = mixed ? 1e-6 : 1e-10;
+    ra.drop_p = mixed ? 1e-5 : 1e-8;
     double* hth = w.host;
     double* hnorm = w.host + mb;
     static const bool trace = std::getenv("MFD_TRACE") != nullptr;
     const double N3 = (double)c->N * c->N * c->N;
-    int it = 0;
+    int it = 0, last_refresh = 0, refreshes = 0, best_it = 0;
+    double best = HUGE_VAL;
+    auto residuals = [&](double* rmax_out) {
+        bool conv = true;
+        double rmax = 0.0;
+        for (int j = 0; j < nreq; ++j) {
+            const double r = std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j]));
+            if (!(r <= tol)) conv = false;
+            rmax = std::max(rmax, r);
+        }
+        *rmax_out = rmax;
+        return conv;
+    };
     for (;; ++it) {
         ra.first = (it == 0);
+        const int rb = mixed ? 8 : 16;   // bytes per complex of the W/AW blocks
         if (it > 0) {
             // W = T R (in place), AW = op(W)
             hipEvent_t e0 = w.prof.begin(s);
-            HIPCHK(launch_precond<double>(p, mb, col(V, n, mb), col(V, n, mb), c->tw64, s));
-            w.prof.end(e0, 1, N3 * 3 * 16.0 * 2 * mb, s);
+            if (mixed) HIPCHK(launch_precond<float>(p, mb, V32 + n * mb, V32 + n * mb, c->tw32, s));
+            else HIPCHK(launch_precond<double>(p, mb, col(V, n, mb), col(V, n, mb), c->tw64, s));
+            w.prof.end(e0, 1, N3 * 3 * rb * 2.0 * mb, s);
             e0 = w.prof.begin(s);
-            HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
-            w.prof.end(e0, 0, N3 * (96.0 * mb + 24.0), s);
+            if (mixed) HIPCHK(launch_stencil_f64_s32(p, mb, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s));
+            else HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
+            w.prof.end(e0, 0, N3 * (6.0 * rb * mb + 24.0), s);
         }
         hipEvent_t e1 = w.prof.begin(s);
-        HIPCHK(launch_gram_mfma(V, n, n, K, w.nparts_gram, w.gpart, w.G, s));
-        w.prof.end(e1, 2, (double)n * 2 * K * 16.0, s);
+        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, K, w.nparts_gram, w.gpart, w.G, s));
+        w.prof.end(e1, 2, (double)n * (2 * mb * 16.0 + 4 * mb * rb), s);
         e1 = w.prof.begin(s);
         HIPCHK(launch_rr(ra, s));
         w.prof.end(e1, 3, 0.0, s);
         e1 = w.prof.begin(s);
-        HIPCHK(launch_update_mfma(V, U, n, n, mb, w.C, w.theta, w.nparts_upd, w.npart, w.norms, s));
-        w.prof.end(e1, 4, (double)n * 11 * mb * 16.0, s);
+        HIPCHK(launch_update_mfma(V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, mb, w.C, w.theta,
+                                  w.nparts_upd, w.npart, w.norms, s));
+        w.prof.end(e1, 4, (double)n * mb * (4 * 16.0 + 4 * rb + 3 * rb + 2 * 16.0), s);
         std::swap(V, U);
+        if (mixed) std::swap(V32, U32);
         HIPCHK(hipMemcpyAsync(hth, w.theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
         int* hinfo = (int*)(w.host + 3 * mb);
         if (trace) HIPCHK(hipMemcpyAsync(hinfo, w.info, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         w.prof.drain();
+        double rmax = 0.0;
+        bool conv = residuals(&rmax);
         if (trace) {
-            double rmax = 0.0;
             int nact = 0;
-            for (int j = 0; j < mb; ++j) {
-                const double r = std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j]));
-                if (j < nreq) rmax = std::max(rmax, r);
-                nact += r > tol;
-            }
-            std::fprintf(stderr, "it %4d rmax %.3e active %2d kept %2d dropP %d sweeps %d th0 %.8f thn %.8f "
-                         "rr-ticks %d %d %d %d %d Kk %d\n", it, rmax, nact, hinfo[0], hinfo[1], hinfo[3], hth[0],
+            for (int j = 0; j < mb; ++j)
+                nact += std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j])) > tol;
+            std::fprintf(stderr, "[%p] it %4d rmax %.3e active %2d kept %2d dropP %d sweeps %d th0 %.8f thn %.8f "
+                         "rr-ticks %d %d %d %d %d Kk %d\n", (void*)&w, it, rmax, nact, hinfo[0], hinfo[1], hinfo[3], hth[0],
                          hth[nreq - 1], hinfo[4], hinfo[5], hinfo[6], hinfo[7], hinfo[8], hinfo[9]);
         }
-        bool conv = true;
-        for (int j = 0; j < nreq; ++j) {
-            const double r = std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j]));
-            if (!(r <= tol)) conv = false;
+        // Mixed precision: the tracked AX = [AX AW AP] C drifts from A X by the
+        // FP32 rounding of AW and AP; recompute AX with the FP64 operator to
+        // confirm convergence, and every 15 iterations.
+        if (mixed && it > 0 && (conv || it - last_refresh >= 15)) {
+            HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+            HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), V32 + n * mb, true, n, n, mb, w.theta,
+                                   w.nparts_col, w.npart, w.norms, s));
+            HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            conv = residuals(&rmax);
+            last_refresh = it;
+            ++refreshes;
+            if (trace) std::fprintf(stderr, "[%p] refresh %d: rmax %.3e\n", (void*)&w, refreshes, rmax);
         }
         if (conv || it >= max_iter) {
             out.converged = conv;
             break;
         }
+        if (rmax < 0.5 * best) {
+            best = rmax;
+            best_it = it;
+        }
+        // A clustered spectrum (a compensation mode among the bands near
+        // Gamma) can stall the FP32-stored directions: when the residual has
+        // not halved in stall_window iterations, finish this k-point in FP64
+        // from the current X with fresh A X, R = A X - theta X and no P.
+        if (mixed && stall_window > 0 && it - best_it >= stall_window) {
+            mixed = false;
+            out.fp64_fallback = true;
+            HIPCHK(hipMemsetAsync(col(V, n, 2 * mb), 0, n * mb * sizeof(double2), s));
+            HIPCHK(hipMemsetAsync(col(V, n, 5 * mb), 0, n * mb * sizeof(double2), s));
+            HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+            HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), col(V, n, mb), false, n, n, mb, w.theta,
+                                   w.nparts_col, w.npart, w.norms, s));
+            ra.drop_w = 1e-10;
+            ra.drop_p = 1e-8;
+            best_it = it;
+            if (trace) std::fprintf(stderr, "[%p] it %d: mixed precision stalled at %.3e, continuing in FP64\n",
+                                    (void*)&w, it, rmax);
+        }
     }
+    w.V32 = V32;
+    w.U32 = U32;
     w.V = V;
     w.U = U;
     out.iters = it;
@@ -371,14 +441,15 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
     OpParams p = params(c, k);
     const double scale = std::pow(2.0 * M_PI / c->L, 2);
     KResult kr;
-    int doublings = 0, total_iters = 0, nspur = 0, discarded = 0;
+    int doublings = 0, total_iters = 0, nspur = 0, discarded = 0, fp64_fallback = 0;
     int nreq = nbands;
     std::vector<double> lam(mb), lre(mb);
     std::vector<int> sel;
     for (;;) {
-        int st = lobpcg_k(c, w, p, nreq, tol, o.max_iter, kr);
+        int st = lobpcg_k(c, w, p, nreq, tol, o.max_iter, o.stall_window, kr);
         if (st) return st;
         total_iters += kr.iters;
+        fp64_fallback |= kr.fp64_fallback;
         for (int j = 0; j < mb; ++j) lam[j] = kr.theta[j] - p.shift;
         // Alg 4.1: recompute lambda_re = |M_0^(1/2) A'x|^2 / |x|^2; a band with
         // lambda - lambda_re visibly > 0 is a compensation (spurious) mode
@@ -435,6 +506,7 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
         ks.spurious = nspur;
         ks.discarded = discarded;
         ks.used_fallback = 0;
+        ks.fp64_fallback = fp64_fallback;
         ks.ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     *converged = (maxres <= tol) ? (nspur ? 2 : 1) : 0;
@@ -519,12 +591,13 @@ int run_segments(std::vector<Segment>& segs) {
 int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
     if (nbands <= 0) return fail(MFD_EINVAL, "nbands must be > 0");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
-    if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0 || o.streams < 1 || o.streams > 16)
+    if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0 || o.streams < 1 || o.streams > 16 ||
+        o.stall_window < 0)
         return fail(MFD_EINVAL, "bad options");
     const int mb = nbands + o.guard;
     if (3 * mb > 64) return fail(MFD_EUNSUPPORTED, "nbands + guard must be <= 21");
     if ((size_t)mb > ctx->n) return fail(MFD_EINVAL, "nbands exceeds the problem size");
-    if (o.precision != 0) return fail(MFD_EUNSUPPORTED, "mixed precision not built yet");
+    if (o.precision != 0 && o.precision != 1) return fail(MFD_EINVAL, "precision must be 0 or 1");
     return MFD_OK;
 }
 
@@ -543,6 +616,7 @@ void mfd_default_opts(mfd_opts* o) {
     o->guard = 2;
     o->streams = 4;
     o->x0 = nullptr;
+    o->stall_window = 40;
 }
 
 int mfd_supported_n(int N) {
@@ -684,7 +758,7 @@ int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol, 
         if (!std::isfinite(kpts[i])) return fail(MFD_EINVAL, "k must be finite");
     const int mb = nbands + o.guard;
     const int nseg = std::min(o.streams, nk);
-    if ((st = ensure_ws(ctx, mb, nseg))) return st;
+    if ((st = ensure_ws(ctx, mb, o.precision == 1, nseg))) return st;
     // the workspaces' streams start after the caller's stream work
     hipEvent_t ready;
     HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
@@ -733,7 +807,7 @@ int mfd_bands_batch(int ncrys, mfd_ctx* const* ctxs, const int* nk, const double
     HIPCHK(hipEventRecord(ready, (hipStream_t)stream));
     std::vector<Segment> segs(ncrys);
     for (int c = 0; c < ncrys; ++c) {
-        int st = ensure_ws(ctxs[c], mb, 1);
+        int st = ensure_ws(ctxs[c], mb, o.precision == 1, 1);
         if (st) { hipEventDestroy(ready); return st; }
         HIPCHK(hipStreamWaitEvent(ctxs[c]->ws[0]->stream, ready, 0));
         Segment& sg = segs[c];

@@ -273,6 +273,50 @@ hipError_t launch_colstats(const void* X, const void* Y, size_t ld, size_t n, in
 }
 
 // ---------------------------------------------------------------------------
+// Residual refresh: R_j = AX_j - theta_j X_j (written as c64 or c128) and the
+// per-workgroup column sums of |R_j|^2, |X_j|^2 (layout of the update's norms).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void residual_kernel(const C128* __restrict__ X, const C128* __restrict__ AX,
+                                                       void* __restrict__ R, int r32, size_t ld, size_t n, int mb,
+                                                       const double* __restrict__ theta, double* __restrict__ npart) {
+    const int col = blockIdx.y;
+    const double th = theta[col];
+    const C128* x = X + (size_t)col * ld;
+    const C128* ax = AX + (size_t)col * ld;
+    double a = 0.0, b = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const C128 xv = x[i], yv = ax[i];
+        const double rx = yv.x - th * xv.x, ry = yv.y - th * xv.y;
+        if (r32) ((float2*)R)[(size_t)col * ld + i] = make_float2((float)rx, (float)ry);
+        else ((C128*)R)[(size_t)col * ld + i] = mk<C128>(rx, ry);
+        a += rx * rx + ry * ry;
+        b += cabs2(xv);
+    }
+    __shared__ double red[2][4];
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o);
+        b += __shfl_down(b, o);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { red[0][wid] = a; red[1][wid] = b; }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w) s += red[threadIdx.x][w];
+        npart[(size_t)blockIdx.x * 2 * mb + threadIdx.x * mb + col] = s;
+    }
+}
+
+hipError_t launch_residual(const void* X, const void* AX, void* R, bool r32, size_t ld, size_t n, int mb,
+                           const double* theta, int nparts, double* npart, double* norms, hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, dim3(nparts, mb), dim3(256), 0, s, (const C128*)X, (const C128*)AX, R,
+                       (int)r32, ld, n, mb, theta, npart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(npart, nparts, 2 * mb, norms, s);
+}
+
+// ---------------------------------------------------------------------------
 // Alg 4.1, step 2: |M_0^(1/2) A' x|^2 per field, and |x|^2.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void lambda_re_kernel(const C128* __restrict__ X, const double* __restrict__ mu,

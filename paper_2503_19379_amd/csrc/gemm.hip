@@ -22,8 +22,8 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 
 // ---------------------------------------------------------------------------
 // Gram: for the K = 3mb basis columns S = V[:, :K] and AS = V[:, K:2K],
-//   G_S = S^H S, G_A = S^H AS (both Hermitian: only 16x16 tiles touching the
-//   upper triangle are formed; the reduction mirrors them).
+//   G_S = S^H S, G_A = S^H AS (both Hermitian: only the 16x16 tiles of one
+//   triangle are formed; the reduction mirrors them).
 // Workgroup w sums rows [w rows_per, (w+1) rows_per) into its own partial
 // tile set; gram_reduce_kernel adds the partials in a fixed order.
 // ---------------------------------------------------------------------------
@@ -37,10 +37,41 @@ struct GramTiles {
     unsigned char half[80];     // 0: G_S, 1: G_A
 };
 
+// In mixed precision the W, P, AW, AP columns (basis columns [mb, 3mb) and
+// [4mb, 6mb)) are stored in FP32 (V32, same column positions) and promoted on
+// load; X and AX stay FP64.
+__device__ __forceinline__ bool col_is_f32(int c, int mb) { return (c >= mb && c < 3 * mb) || c >= 4 * mb; }
+
+// Element e of a slab of RB rows x 2K columns, in an order that visits the
+// FP64 columns (X, AX) first and the FP32 ones after, so that a wave's loads
+// are all of one precision; returns the slab column and row.
+__device__ __forceinline__ void slab_elem(int e, int RB, int mb, bool mixed, int* c, int* r) {
+    *r = e % RB;
+    int q = e / RB;   // ordinal column
+    if (mixed) {
+        // ordinals [0, mb) -> X, [mb, 2mb) -> AX, [2mb, 4mb) -> W P, [4mb, 6mb) -> AW AP
+        if (q < mb) *c = q;
+        else if (q < 2 * mb) *c = 2 * mb + q;
+        else if (q < 4 * mb) *c = q - mb;
+        else *c = q;
+    } else {
+        *c = q;
+    }
+}
+
+__device__ __forceinline__ double2 load_col(const double2* __restrict__ V, const float2* __restrict__ V32, int c,
+                                            int mb, size_t ld, size_t row) {
+    if (V32 && col_is_f32(c, mb)) {
+        const float2 v = V32[(size_t)c * ld + row];
+        return mk<double2>((double)v.x, (double)v.y);
+    }
+    return V[(size_t)c * ld + row];
+}
+
 // The next slab is loaded into registers while the current one is consumed
 // from LDS by the matrix cores.
-__global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restrict__ V, size_t ld,
-                                                         size_t n, int K, size_t rows_per, GramTiles tl,
+__global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restrict__ V, const float2* __restrict__ V32,
+                                                         size_t ld, size_t n, int K, size_t rows_per, GramTiles tl,
                                                          double2* __restrict__ part) {
     extern __shared__ unsigned char smem_raw[];
     double2* slab = reinterpret_cast<double2*>(smem_raw);   // [GM_KS][2K]
@@ -79,8 +110,9 @@ __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restric
             const int e = tid + q * nthr;
             pf[q] = mk<double2>(0.0, 0.0);
             if (e < nel) {
-                const int r = e % GM_KS, c = e / GM_KS;
-                if (r < rows) pf[q] = V[(size_t)c * ld + s0 + r];
+                int r, c;
+                slab_elem(e, GM_KS, K / 3, V32 != nullptr, &c, &r);
+                if (r < rows) pf[q] = load_col(V, V32, c, K / 3, ld, s0 + r);
             }
         }
     };
@@ -89,7 +121,11 @@ __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restric
 #pragma unroll
         for (int q = 0; q < GM_PF; ++q) {
             const int e = tid + q * nthr;
-            if (e < nel) slab[(e % GM_KS) * C2 + e / GM_KS] = pf[q];
+            if (e < nel) {
+                int r, c;
+                slab_elem(e, GM_KS, K / 3, V32 != nullptr, &c, &r);
+                slab[r * C2 + c] = pf[q];
+            }
         }
         __syncthreads();
         if (s0 + GM_KS < r1) prefetch(s0 + GM_KS);
@@ -123,7 +159,12 @@ __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restric
     }
 }
 
-// G (K x 2K row-major) from the summed tiles; mirrors the lower triangles.
+// G (K x 2K row-major) from the summed tiles.  G_S is formed from its upper
+// tiles, G_A from its lower tiles, and each is completed by the Hermitian
+// mirror.  With X first in the basis, every entry of G_A that pairs an X
+// column with a W or P column is then the product with AX (W^H AX), never the
+// product with AW or AP: in mixed precision AX is the FP64 one, while AW and AP
+// carry the FP32 rounding of the operator.
 __global__ void gram_scatter_kernel(const double2* __restrict__ sum, int K, GramTiles tl, double2* __restrict__ G) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= tl.n * 256) return;
@@ -131,9 +172,12 @@ __global__ void gram_scatter_kernel(const double2* __restrict__ sum, int K, Gram
     const double2 v = sum[e];
     const int i = tl.ti[t] * 16 + rc / 16, j = tl.tj[t] * 16 + rc % 16;
     if (i >= K || j >= K) return;
-    const int off = tl.half[t] * K;
-    if (i <= j) G[(size_t)i * 2 * K + off + j] = v;
-    if (i < j) G[(size_t)j * 2 * K + off + i] = mk<double2>(v.x, -v.y);
+    const int h = tl.half[t];
+    const int off = h * K;
+    const bool direct = h == 0 ? (i <= j) : (i >= j);
+    const bool mirror = h == 0 ? (i < j) : (i > j);
+    if (direct) G[(size_t)i * 2 * K + off + j] = v;
+    if (mirror) G[(size_t)j * 2 * K + off + i] = mk<double2>(v.x, -v.y);
 }
 
 static GramTiles make_tiles(int K) {
@@ -143,8 +187,9 @@ static GramTiles make_tiles(int K) {
     for (int h = 0; h < 2; ++h)
         for (int a = 0; a < T; ++a)
             for (int b = a; b < T; ++b) {
-                tl.ti[tl.n] = (short)a;
-                tl.tj[tl.n] = (short)b;
+                // G_S: upper tiles (a, b); G_A: lower tiles (b, a)
+                tl.ti[tl.n] = (short)(h == 0 ? a : b);
+                tl.tj[tl.n] = (short)(h == 0 ? b : a);
                 tl.half[tl.n] = (unsigned char)h;
                 ++tl.n;
             }
@@ -158,8 +203,8 @@ size_t gram_mfma_part_elems(int K, int nparts) {
     return (size_t)(nparts + 1) * T * (T + 1) * 256;   // partials + their sum
 }
 
-hipError_t launch_gram_mfma(const void* V, size_t ld, size_t n, int K, int nparts, void* part, void* G,
-                            hipStream_t s) {
+hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, int K, int nparts, void* part,
+                            void* G, hipStream_t s) {
     GramTiles tl = make_tiles(K);
     const int nwaves_t = (tl.n + GM_MAXT - 1) / GM_MAXT;
     if (K > 64) return hipErrorInvalidValue;
@@ -172,8 +217,8 @@ hipError_t launch_gram_mfma(const void* V, size_t ld, size_t n, int K, int npart
     hipError_t e = hipFuncSetAttribute((const void*)gram_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gram_mfma_kernel, dim3(nw), dim3(64 * nwaves), lds, s, (const double2*)V, ld, n, K,
-                       rows_per, tl, (double2*)part);
+    hipLaunchKernelGGL(gram_mfma_kernel, dim3(nw), dim3(64 * nwaves), lds, s, (const double2*)V, (const float2*)V32,
+                       ld, n, K, rows_per, tl, (double2*)part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // sum the partial tiles (in place into the first part's slot after the last), then scatter
     double2* sum = (double2*)part + (size_t)nw * tl.n * 256;
@@ -199,7 +244,8 @@ constexpr int UP_PF = 16;       // prefetch registers (complex) per thread
 // where R' = AX' - X' theta and the column norms are formed and written out
 // row-contiguously.
 template <int MJ>   // mb <= 16 MJ
-__global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restrict__ V, double2* __restrict__ U,
+__global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restrict__ V, const float2* __restrict__ V32,
+                                                          double2* __restrict__ U, float2* __restrict__ U32,
                                                           size_t ld, size_t n, int mb,
                                                           const double2* __restrict__ Cg,
                                                           const double* __restrict__ theta,
@@ -241,8 +287,9 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
             const int e = tid + q * 256;
             pf[q] = mk<double2>(0.0, 0.0);
             if (e < nel && blk < nblk) {
-                const int r = e % UP_RB, c = e / UP_RB;
-                if (b0 + r < n) pf[q] = V[(size_t)c * ld + b0 + r];
+                int r, c;
+                slab_elem(e, UP_RB, mb, V32 != nullptr, &c, &r);
+                if (b0 + r < n) pf[q] = load_col(V, V32, c, mb, ld, b0 + r);
             }
         }
     };
@@ -252,7 +299,11 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
 #pragma unroll
         for (int q = 0; q < UP_PF; ++q) {
             const int e = tid + q * 256;
-            if (e < nel) slab[(e / UP_RB) * UP_RBP + e % UP_RB] = pf[q];
+            if (e < nel) {
+                int r, c;
+                slab_elem(e, UP_RB, mb, V32 != nullptr, &c, &r);
+                slab[c * UP_RBP + r] = pf[q];
+            }
         }
         __syncthreads();
         prefetch(blk + gridDim.x);
@@ -286,7 +337,11 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                     const double2 v = mk<double2>(t1 - t2, t3 - t1 - t2);
                     if (pass == 0) {
                         const size_t row = b0 + rl;
-                        if (j < mb && row < n) U[(size_t)((chain ? 5 : 2) * mb + j) * ld + row] = v;
+                        if (j < mb && row < n) {
+                            const size_t o = (size_t)((chain ? 5 : 2) * mb + j) * ld + row;
+                            if (U32) U32[o] = make_float2((float)v.x, (float)v.y);
+                            else U[o] = v;
+                        }
                     } else {
                         xo[(chain * MP + j) * UP_RBP + rl] = v;
                     }
@@ -306,7 +361,8 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                     const double2 res = mk<double2>(ax.x - th[c] * x.x, ax.y - th[c] * x.y);
                     U[(size_t)j * ld + row] = x;
                     U[(size_t)(3 * mb + j) * ld + row] = ax;
-                    U[(size_t)(mb + j) * ld + row] = res;
+                    if (U32) U32[(size_t)(mb + j) * ld + row] = make_float2((float)res.x, (float)res.y);
+                    else U[(size_t)(mb + j) * ld + row] = res;
                     nr[c] += cabs2(res);
                     nx[c] += cabs2(x);
                 }
@@ -336,8 +392,8 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
 }
 
 template <int MJ>
-static hipError_t update_mj(const void* V, void* U, size_t ld, size_t n, int mb, const void* C, const double* theta,
-                            int nparts, double* npart, hipStream_t s) {
+static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n, int mb,
+                            const void* C, const double* theta, int nparts, double* npart, hipStream_t s) {
     constexpr int MP = 16 * MJ;
     const int K = 3 * mb;
     const int KP = (K + 3) / 4 * 4;
@@ -347,16 +403,17 @@ static hipError_t update_mj(const void* V, void* U, size_t ld, size_t n, int mb,
     auto kern = update_mfma_kernel<MJ>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nparts), dim3(256), lds, s, (const double2*)V, (double2*)U, ld, n, mb,
-                       (const double2*)C, theta, npart);
+    hipLaunchKernelGGL(kern, dim3(nparts), dim3(256), lds, s, (const double2*)V, (const float2*)V32, (double2*)U,
+                       (float2*)U32, ld, n, mb, (const double2*)C, theta, npart);
     return hipGetLastError();
 }
 
-hipError_t launch_update_mfma(const void* V, void* U, size_t ld, size_t n, int mb, const void* C,
-                              const double* theta, int nparts, double* npart, double* norms, hipStream_t s) {
+hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n, int mb,
+                              const void* C, const double* theta, int nparts, double* npart, double* norms,
+                              hipStream_t s) {
     hipError_t e;
-    if (mb <= 16) e = update_mj<1>(V, U, ld, n, mb, C, theta, nparts, npart, s);
-    else if (mb <= 32) e = update_mj<2>(V, U, ld, n, mb, C, theta, nparts, npart, s);
+    if (mb <= 16) e = update_mj<1>(V, V32, U, U32, ld, n, mb, C, theta, nparts, npart, s);
+    else if (mb <= 32) e = update_mj<2>(V, V32, U, U32, ld, n, mb, C, theta, nparts, npart, s);
     else return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
     return launch_reduce(npart, nparts, 2 * mb, norms, s);

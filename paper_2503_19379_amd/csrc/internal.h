@@ -16,6 +16,10 @@ struct OpParams {
 template <class R>
 hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s);
 
+// Same operator with FP64 arithmetic on FP32-stored fields (c64 in, c64 out).
+hipError_t launch_stencil_f64_s32(const OpParams& p, int nb, const void* X, void* Y, const void* mu64,
+                                  hipStream_t s);
+
 // T = (P + shift I)^-1 R for nb fields via FFT (fft.hip).  tw: device table
 // exp(-2 pi i j / N), j < N, of precision R.
 template <class R>

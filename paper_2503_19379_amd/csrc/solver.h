@@ -15,12 +15,18 @@ hipError_t launch_update(const void* V, void* U, size_t ld, size_t n, int mb, co
                          int nparts, double* npart, double* norms, hipStream_t s);
 // MFMA (FP64 matrix core) versions: Gram of K = 3mb basis columns against
 // [S | AS] (Hermitian halves only), and the block update (gemm.hip).
-hipError_t launch_gram_mfma(const void* V, size_t ld, size_t n, int K, int nparts, void* part, void* G,
-                            hipStream_t s);
+// V32 (or null): FP32 storage of the W, P, AW, AP columns (mixed precision).
+hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, int K, int nparts, void* part,
+                            void* G, hipStream_t s);
 int gram_mfma_parts(size_t n);
 size_t gram_mfma_part_elems(int K, int nparts);
-hipError_t launch_update_mfma(const void* V, void* U, size_t ld, size_t n, int mb, const void* C,
-                              const double* theta, int nparts, double* npart, double* norms, hipStream_t s);
+// U32 (or null): FP32 outputs R', P', AP' (mixed precision).
+hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n, int mb,
+                              const void* C, const double* theta, int nparts, double* npart, double* norms,
+                              hipStream_t s);
+// R = AX - X theta written to W (FP32 if R32), column norms |R|^2, |X|^2 (blas.hip).
+hipError_t launch_residual(const void* X, const void* AX, void* R, bool r32, size_t ld, size_t n, int mb,
+                           const double* theta, int nparts, double* npart, double* norms, hipStream_t s);
 hipError_t launch_colstats(const void* X, const void* Y, size_t ld, size_t n, int nb, const double* theta,
                            int nparts, double* part, double* out, hipStream_t s);
 hipError_t launch_fill_random(void* X, size_t count, uint64_t seed, hipStream_t s);

@@ -26,19 +26,22 @@
 
 namespace mfd {
 
-template <class R>
+// R: arithmetic precision; S: storage precision of X and Y (FP32 storage
+// with FP64 arithmetic keeps the operator's rounding at the FP64 level).
+template <class R, class S = R>
 struct StencilArgs {
-    const cplx<R>* X;
-    cplx<R>* Y;
+    const cplx<S>* X;
+    cplx<S>* Y;
     const R* mu;          // [3][N][N][N]
     int N, nyt, nzc, zc, nb;
     cplx<R> cp[3], cm[3];
     R gamma, shift;
 };
 
-template <class R, int TY>
-__global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R> a) {
+template <class R, class S, int TY>
+__global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R, S> a) {
     using T = cplx<R>;
+    using TS = cplx<S>;
     extern __shared__ unsigned char smem_raw[];
     T* smem = reinterpret_cast<T*>(smem_raw);
     constexpr int ROWS = TY + 2;
@@ -62,8 +65,8 @@ __global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R> a) {
     const int z1 = z0 + a.zc;
     const size_t NN = (size_t)N * N;
     const size_t N3 = NN * N;
-    const T* Xb = a.X + (size_t)band * 3 * N3;
-    T* Yb = a.Y + (size_t)band * 3 * N3;
+    const TS* Xb = a.X + (size_t)band * 3 * N3;
+    TS* Yb = a.Y + (size_t)band * 3 * N3;
 
     const int txp = (tx + 1 == N) ? 0 : tx + 1;
     const int txm = (tx == 0) ? N - 1 : tx - 1;
@@ -82,9 +85,10 @@ __global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R> a) {
     for (int t = z0 - 2; t < z1; ++t) {
         const int zt1 = (t + 1 + 2 * N) % N;
         const size_t off = (size_t)zt1 * NN + (size_t)yg * N + tx;
-        const T vn0 = Xb[off];
-        const T vn1 = Xb[N3 + off];
-        const T vn2 = Xb[2 * N3 + off];
+        const TS sv0 = Xb[off], sv1 = Xb[N3 + off], sv2 = Xb[2 * N3 + off];
+        const T vn0 = mk<T>(sv0.x, sv0.y);
+        const T vn1 = mk<T>(sv1.x, sv1.y);
+        const T vn2 = mk<T>(sv2.x, sv2.y);
         vbuf[row + tx] = vn0;
         vbuf[plane_cells + row + tx] = vn1;
         vbuf[2 * plane_cells + row + tx] = vn2;
@@ -172,9 +176,9 @@ __global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R> a) {
             w1 = cadd(w1, cscale(vp1, sh));
             w2 = cadd(w2, cscale(vp2, sh));
             const size_t oo = (size_t)t * NN + (size_t)yg * N + tx;
-            Yb[oo] = w0;
-            Yb[N3 + oo] = w1;
-            Yb[2 * N3 + oo] = w2;
+            Yb[oo] = mk<TS>(w0.x, w0.y);
+            Yb[N3 + oo] = mk<TS>(w1.x, w1.y);
+            Yb[2 * N3 + oo] = mk<TS>(w2.x, w2.y);
         }
         vp0 = vn0; vp1 = vn1; vp2 = vn2;
         ec0 = en0; ec1 = en1; ec2 = en2;
@@ -191,10 +195,10 @@ static int stencil_ty(int N) {
     return best;
 }
 
-template <class R, int TY>
-static hipError_t launch_ty(const StencilArgs<R>& a, hipStream_t s) {
+template <class R, class S, int TY>
+static hipError_t launch_ty(const StencilArgs<R, S>& a, hipStream_t s) {
     const size_t lds = (size_t)10 * (TY + 2) * a.N * sizeof(cplx<R>);
-    auto kern = stencil_kernel<R, TY>;
+    auto kern = stencil_kernel<R, S, TY>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 block(a.N, TY + 2);
@@ -203,11 +207,11 @@ static hipError_t launch_ty(const StencilArgs<R>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class R>
-hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s) {
-    StencilArgs<R> a;
-    a.X = (const cplx<R>*)X;
-    a.Y = (cplx<R>*)Y;
+template <class R, class S>
+hipError_t launch_stencil_rs(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s) {
+    StencilArgs<R, S> a;
+    a.X = (const cplx<S>*)X;
+    a.Y = (cplx<S>*)Y;
     a.mu = (const R*)mu;
     a.N = p.N;
     a.nb = nb;
@@ -227,12 +231,22 @@ hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, con
     a.gamma = (R)p.gamma;
     a.shift = (R)p.shift;
     switch (TY) {
-        case 8: return launch_ty<R, 8>(a, s);
-        case 6: return launch_ty<R, 6>(a, s);
-        case 4: return launch_ty<R, 4>(a, s);
-        case 2: return launch_ty<R, 2>(a, s);
-        default: return launch_ty<R, 1>(a, s);
+        case 8: return launch_ty<R, S, 8>(a, s);
+        case 6: return launch_ty<R, S, 6>(a, s);
+        case 4: return launch_ty<R, S, 4>(a, s);
+        case 2: return launch_ty<R, S, 2>(a, s);
+        default: return launch_ty<R, S, 1>(a, s);
     }
+}
+
+template <class R>
+hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s) {
+    return launch_stencil_rs<R, R>(p, nb, X, Y, mu, s);
+}
+
+hipError_t launch_stencil_f64_s32(const OpParams& p, int nb, const void* X, void* Y, const void* mu64,
+                                  hipStream_t s) {
+    return launch_stencil_rs<double, float>(p, nb, X, Y, mu64, s);
 }
 
 template hipError_t launch_stencil<float>(const OpParams&, int, const void*, void*, const void*, hipStream_t);

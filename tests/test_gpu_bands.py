@@ -117,3 +117,40 @@ def test_batch_uneven_grids(B):
     N, eps = crystals[1]
     lam, _, info = olob.solve_bands(eps, 1.0, kp[1], 5, tol=1e-10)
     assert np.allclose(evs[1][1], lam, rtol=1e-9)
+
+
+@pytest.mark.parametrize("N,kidx", [(16, (0, 2, 5, 7)), (24, (3,))])
+def test_mixed_precision_vs_oracle(B, N, kidx):
+    """FP32 corrections (preconditioner, stencil on W, W/P/AW/AP storage) with
+    FP64 X, AX, Gram sums, Rayleigh-Ritz and residual refresh: eigenvalues
+    within 1e-7 relative of the FP64 oracle, residuals verified with the FP64
+    operator."""
+    m = 6
+    eps = workloads.eps_diamond(N)
+    kp = workloads.kpath("GXMGR", 8)[list(kidx)]
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    ev, st, status = B.mfd_bands(ctx, kp, m, 1e-8, B.default_opts(precision=1, streams=2))
+    assert status == 0, st
+    for i, k in enumerate(kp):
+        assert st[i]["max_rel_resid"] <= 1e-8
+        lam, _, info = olob.solve_bands(eps, 1.0, k, m, tol=1e-10)
+        assert np.allclose(ev[i], lam, rtol=1e-7, atol=1e-9), (k, ev[i], lam)
+
+
+def test_mixed_precision_fp64_fallback(B):
+    """A stall window of 2 iterations forces the switch from FP32-stored
+    directions to FP64 mid-solve (the path taken when a clustered spectrum
+    stalls the mixed iteration); the bands still match the FP64 oracle."""
+    N, m = 16, 6
+    eps = workloads.eps_diamond(N)
+    kp = workloads.kpath("GXMGR", 8)[[2, 5]]
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    ev, st, status = B.mfd_bands(ctx, kp, m, 1e-8, B.default_opts(precision=1, streams=1, stall_window=2))
+    assert status == 0, st
+    assert all(s["fp64_fallback"] == 1 for s in st), st
+    for i, k in enumerate(kp):
+        assert st[i]["max_rel_resid"] <= 1e-8
+        lam, _, _ = olob.solve_bands(eps, 1.0, k, m, tol=1e-10)
+        assert np.allclose(ev[i], lam, rtol=1e-7, atol=1e-9), (k, ev[i], lam)
+    _, st0, _ = B.mfd_bands(ctx, kp, m, 1e-8, B.default_opts(precision=1, streams=1, stall_window=0))
+    assert all(s["fp64_fallback"] == 0 for s in st0)
