@@ -48,8 +48,40 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--profile-only", action="store_true", help="one short step, no JSON (for rocprofv3)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="with --profile-only: also run a plain 1 GiB read + 1 GiB write elementwise copy, "
+                         "the reference for scaling the HBM byte counters")
     ap.add_argument("--verbose", action="store_true", help="per-k statistics on stderr")
     return ap.parse_args()
+
+
+COPY_BYTES = 1 << 30
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+KERNEL_SOURCES = {"update": "gemm.hip", "gram": "gemm.hip", "stencil": "stencil.hip", "precond": "fft.hip"}
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summaries
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None
+    for a kernel whose source changed since the counters were taken."""
+    import hashlib
+    out = {}
+    for cat, src in KERNEL_SOURCES.items():
+        path = os.path.join(PROFILES, f"{cat}_{workload}_{precision}_hbm_traffic.md")
+        if not os.path.exists(path):
+            continue
+        fields = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and line.startswith("- "):
+                    key, _, val = line[2:].partition(":")
+                    fields[key.strip()] = val.strip().strip("`")
+        src_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2503_19379_amd", "csrc", src)
+        with open(src_path, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+        if fields.get("source_sha256") == digest and "traffic_bytes_per_launch" in fields:
+            out[cat] = float(fields["traffic_bytes_per_launch"])
+    return out
 
 
 def cpu_baseline(eps, L, k, m, iters, gpu_iters_per_k):
@@ -74,7 +106,11 @@ def cpu_baseline(eps, L, k, m, iters, gpu_iters_per_k):
     # lobpcg runs `iters` iterations plus the start-up and the final check
     per_iter = dt / (iters + 2)
     per_k = per_iter * gpu_iters_per_k
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except ImportError:
+        cores = 1
     return {"value": 1.0 / per_k, "unit": "k-points/s", "cores": cores, "kind": "oracle",
             "sample": f"{iters} oracle LOBPCG iterations (+ start-up and final check, {dt:.1f} s) at one "
                       f"k-point of the same workload, scaled to {gpu_iters_per_k:.1f} iterations per k-point "
@@ -85,7 +121,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
-              "(k-points would shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(k-points would shard across GPUs with no exchange between them)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2503_19379_amd import binding as B
@@ -108,24 +144,33 @@ def main():
     if args.profile_only:
         step()
         torch.cuda.synchronize()
+        if args.copy_calib:
+            x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            torch.cuda.synchronize()
+            torch.mul(x, 1.0, out=y)
+            torch.cuda.synchronize()
         return
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # Per-kernel durations: HIP events recorded by the library around each
+    # launch on the stream it is launched on, during the timed steps.
+    B.mfd_profile(ctx, True)
     t0 = time.perf_counter()
     results = []
     for _ in range(args.steps):
         results.append(step())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # Per-kernel durations: concurrent streams overlap kernels, so each
-    # kernel's HIP-event time is taken in a separate single-stream pass over
-    # the first k-points of the same path (same kernels, same shapes).
+    prof = B.mfd_profile_read(ctx)
+    # The same kernels without the overlap of concurrent segments: a
+    # single-stream pass over the first k-points of the path.
     B.mfd_profile(ctx, True)
     o1 = B.default_opts(precision=opts.precision, warm_start=1, seed=0, guard=args.guard, max_iter=500, streams=1)
     B.mfd_bands(ctx, kpts[:max(1, min(args.roofline_nk, nk))], m, args.tol, o1)
     torch.cuda.synchronize()
-    prof = B.mfd_profile_read(ctx)
+    prof_iso = B.mfd_profile_read(ctx)
     B.mfd_profile(ctx, False)
 
     if args.verbose:
@@ -146,36 +191,37 @@ def main():
     value = ok / dt
     n = 3 * N ** 3
 
-    def rate(cat):
-        p = prof[cat]
-        if p["count"] == 0 or p["ms"] == 0:
-            return None
-        avg_s = p["ms"] / p["count"] * 1e-3
-        return avg_s, p["bytes"] / p["count"]
-
     mb = m + args.guard
-    rl = {}
-    for cat in ("stencil", "precond", "gram", "update"):
-        r = rate(cat)
-        if r is None:
-            continue
-        avg_s, by = r
-        if cat == "gram":
-            flops = 8.0 * n * (3 * mb) * (6 * mb)
-            rl[cat] = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP64_PEAK / 1e12,
-                       "unit": "TFLOP/s", "frac": flops / avg_s / FP64_PEAK, "traffic": None,
-                       "avg_us": avg_s * 1e6, "total_ms": prof[cat]["ms"],
-                       "per_launch": f"8 n (3mb)(6mb) = {flops:.3e} FLOP (full complex Gram, FP64 vector FMA)"}
-        else:
-            rl[cat] = {"bound": "hbm", "achieved": by / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                       "frac": by / avg_s / HBM_PEAK, "traffic": None, "avg_us": avg_s * 1e6,
-                       "total_ms": prof[cat]["ms"], "per_launch": f"{by:.4e} algorithmic bytes"}
-    r = rate("rr")
-    if r is not None:
-        rl_rr = {"bound": "latency", "avg_us": r[0] * 1e6, "total_ms": prof["rr"]["ms"]}
-    else:
-        rl_rr = None
-    dom = max(rl, key=lambda c: rl[c]["total_ms"]) if rl else None
+    traffic = measured_traffic(args.workload, args.precision)
+
+    def rooflines(prof):
+        rl = {}
+        for cat in ("stencil", "precond", "gram", "update", "rr"):
+            p = prof[cat]
+            if p["count"] == 0 or p["ms"] == 0:
+                continue
+            avg_s = p["ms"] / p["count"] * 1e-3
+            by = p["bytes"] / p["count"]
+            if cat == "rr":
+                rl[cat] = {"bound": "latency", "avg_us": avg_s * 1e6, "total_ms": p["ms"], "launches": p["count"]}
+            elif cat == "gram":
+                K = 3 * mb   # two Hermitian K x K products over n rows, upper triangles
+                flops = 8.0 * n * K * (K + 1)
+                rl[cat] = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": FP64_PEAK / 1e12,
+                           "unit": "TFLOP/s", "frac": flops / avg_s / FP64_PEAK, "traffic": traffic.get(cat),
+                           "avg_us": avg_s * 1e6, "total_ms": p["ms"], "launches": p["count"],
+                           "per_launch": f"S^H S and S^H AS, Hermitian: 8 n K (K+1) = {flops:.3e} FLOP, K = 3 mb"}
+            else:
+                rl[cat] = {"bound": "hbm", "achieved": by / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                           "frac": by / avg_s / HBM_PEAK, "traffic": traffic.get(cat), "avg_us": avg_s * 1e6,
+                           "total_ms": p["ms"], "launches": p["count"],
+                           "per_launch": f"{by:.4e} algorithmic bytes"}
+        return rl
+
+    rl = rooflines(prof)
+    rl_iso = rooflines(prof_iso)
+    hbm = {c: v for c, v in rl.items() if v["bound"] == "hbm"}
+    dom = max(hbm, key=lambda c: hbm[c]["total_ms"]) if hbm else None
     line = {
         "metric": "k-point band solves/sec at N=64, 16 bands, 1e-8 resid; stencil HBM GB/s vs peak",
         "value": value,
@@ -194,11 +240,13 @@ def main():
                                f"{args.precision}",
                    "N": N, "nbands": m, "nk": nk, "tol": args.tol, "precision": args.precision,
                    "guard": args.guard, "streams": args.streams},
-        "roofline_source": f"HIP events on the solve stream, single-stream pass over {min(args.roofline_nk, nk)} "
-                           f"k-points of the same path after the timed steps",
+        "roofline_source": "HIP events recorded around each launch on its own stream during the timed steps "
+                           "(concurrent k-path segments overlap); kernels_isolated: the same from a "
+                           f"single-stream pass over {min(args.roofline_nk, nk)} k-points after the timed steps",
         "roofline": dict(rl[dom], kernel=dom) if dom else None,
         "stencil": rl.get("stencil"),
-        "kernels": dict(rl, rr=rl_rr) if rl_rr else rl,
+        "kernels": rl,
+        "kernels_isolated": rl_iso,
         "iters_per_k": float(np.mean(iters)) if iters else None,
         "max_rel_resid": maxres,
         "converged_kpoints": ok,

@@ -328,7 +328,8 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         e1 = w.prof.begin(s);
         HIPCHK(launch_update_mfma(V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, mb, w.C, w.theta,
                                   w.nparts_upd, w.npart, w.norms, s));
-        w.prof.end(e1, 4, (double)n * mb * (4 * 16.0 + 4 * rb + 3 * rb + 2 * 16.0), s);
+        // reads X, AX (FP64) and W, P, AW, AP; writes X', AX' (FP64) and P', AP', R'
+        w.prof.end(e1, 4, (double)n * mb * (2 * 16.0 + 4 * rb + 2 * 16.0 + 3 * rb), s);
         std::swap(V, U);
         if (mixed) std::swap(V32, U32);
         HIPCHK(hipMemcpyAsync(hth, w.theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
