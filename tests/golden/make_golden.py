@@ -1,0 +1,75 @@
+"""Writes the oracle's band energies at sampled k-points of the full-size
+workloads, for the GPU parity tests at the sizes the benchmark runs.
+
+Each file holds, for a few k-points of the path, the lowest m physical
+eigenvalues of A M_0 A' + gamma B'B (eq. (Ker_comp), filtered by Alg 4.1) from
+the FP64 CPU oracle's LOBPCG with the FFT preconditioner (Section 5), solved
+to relative residual 1e-10 from a seeded random start.  Only ``oracle/`` and
+the seeded input generators are called.
+
+    python -m tests.golden.make_golden sphere_n32     # about 10 minutes
+    python -m tests.golden.make_golden diamond_n64    # about an hour
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+from oracle import lobpcg as olob
+from paper_2503_19379_amd import workloads
+
+# workload -> (k indices on the workload's path, bands)
+SAMPLES = {
+    "sphere_n32": ((0, 5, 10, 15), 10),
+    "diamond_n64": ((0, 16, 32, 48), 16),
+}
+TOL = 1e-10
+
+
+def path(name):
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_bands.txt")
+
+
+def make(name):
+    cfg = workloads.CONFIGS[name]
+    kidx, m = SAMPLES[name]
+    N = cfg["N"]
+    eps = workloads.crystal_eps(cfg["eps"], N)
+    kp = workloads.kpath(cfg["path"], cfg["nk"])
+    lines = [f"# {name}: oracle band energies (eq. (Ker_comp) after Alg 4.1), FP64 LOBPCG with the FFT",
+             f"# preconditioner (Section 5), relative residual <= {TOL:g}, seeded random start (seed 0).",
+             f"# N = {N}, L = 1, {cfg['nk']} k-points on {cfg['path']}, m = {m}; written by",
+             f"# `python -m tests.golden.make_golden {name}` (calls only oracle/ and the input generators).",
+             "# columns: k_index kx ky kz gamma max_rel_resid lambda_1 ... lambda_m"]
+    for i in kidx:
+        t0 = time.time()
+        lam, _, info = olob.solve_bands(eps, 1.0, kp[i], m, tol=TOL)
+        res = float(np.max(info["res"]))
+        print(f"{name} k{i}: {time.time() - t0:.0f} s, iters {info['total_iters']}, res {res:.2e}, "
+              f"discarded {info['discarded']}", flush=True)
+        if not info.get("converged", False) or info["spurious"].any():
+            raise SystemExit(f"oracle did not converge cleanly at k index {i}")
+        lines.append(" ".join([str(i)] + [f"{v:.17g}" for v in kp[i]] + [f"{info['gamma']:.17g}", f"{res:.3e}"] +
+                              [f"{v:.17g}" for v in lam]))
+    with open(path(name), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def load(name):
+    """{k_index: (k (3,), gamma, lam (m,))} from a written file."""
+    out = {}
+    with open(path(name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = line.split()
+            out[int(v[0])] = (np.array([float(x) for x in v[1:4]]), float(v[4]), np.array([float(x) for x in v[6:]]))
+    return out
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or list(SAMPLES):
+        make(name)
