@@ -66,7 +66,10 @@ typedef enum {
 typedef struct {
     int max_iter;             /* LOBPCG iterations per k-point (default 400) */
     int precision;            /* 0: FP64 throughout; 1: mixed FP32 corrections + FP64 refinement */
-    int warm_start;           /* 0: random start at every k (seed); 1: previous k's vectors */
+    int warm_start;           /* 0: random start at every k (seed); 1: previous k's vectors;
+                                 2: learned: previous k's vectors plus a block proposed by a small
+                                 network trained along the path (see mfd_mlp_*), once 4 training
+                                 pairs exist; the first Rayleigh-Ritz step uses both */
     unsigned long long seed;  /* random start blocks */
     int max_gamma_doublings;  /* Alg 4.1 restarts (default 4) */
     int guard;                /* extra block columns beyond nbands (default 2); they also hold
@@ -79,6 +82,10 @@ typedef struct {
     int stall_window;         /* precision 1: iterations without a halving of the largest
                                  residual after which the k-point continues in FP64 (default 40,
                                  0 = never) */
+    int learn_steps;          /* warm_start 2: Adam steps over the replay buffer after each new
+                                 training pair (default 30; 0 = the untrained network, which
+                                 proposes the previous step's combination unchanged) */
+    float learn_rate;         /* warm_start 2: Adam learning rate (default 1e-3) */
 } mfd_opts;
 
 typedef struct {
@@ -88,7 +95,10 @@ typedef struct {
     double max_rel_resid;     /* max_i |op x_i - theta_i x_i| / (theta_i |x_i|), FP64 operator */
     int spurious;             /* bands still flagged by Alg 4.1 among those returned */
     int discarded;            /* flagged bands skipped in favour of the next physical ones */
-    int used_fallback;        /* warm start fell back to the random/previous-k start */
+    int used_fallback;        /* warm_start 2: the previous-k start was used alone, because no
+                                 proposal was available (fewer than 4 training pairs, or dependent
+                                 history blocks) or because the proposal's Ritz-value sum was not
+                                 below the previous-k block's */
     int fp64_fallback;        /* precision 1 only: the FP32-stored directions stalled (no halving
                                  of the residual in 40 iterations) and the k-point was finished
                                  in FP64 from the current block */
@@ -171,6 +181,49 @@ void mfd_destroy(mfd_ctx* ctx);
 
 const char* mfd_strerror(int status);
 const char* mfd_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start: the network's kernels.  A small multilayer perceptron
+ * x -> gelu(W1 x + b1) -> ... (nlayers hidden layers of width nhidden) ->
+ * W_out h + b_out, gelu(z) = z Phi(z) with the exact normal CDF, trained with
+ * mean-squared-error loss and Adam.  Parameters are one flat FP32 vector: per
+ * layer W (out x in, row-major) then b.  With bf16_weights the products read a
+ * bfloat16 copy of the weights (round to nearest even after every step) and
+ * accumulate in FP32; otherwise they read the FP32 parameters.  These
+ * functions serve the band solver's warm_start = 2 and direct checks of the
+ * network; the paper has no learned component.
+ * ------------------------------------------------------------------------- */
+typedef struct mfd_mlp mfd_mlp;
+
+/* Glorot-uniform hidden layers (seeded), zero output layer.  max_batch bounds
+ * the batch of every later call.  MFD_EINVAL on non-positive sizes. */
+int mfd_mlp_create(int nin, int nhidden, int nlayers, int nout, int max_batch, int bf16_weights,
+                   unsigned long long seed, mfd_mlp** out);
+long long mfd_mlp_num_params(const mfd_mlp* net);
+/* host FP32 parameters in and out; set_params also clears Adam's moments and step count */
+int mfd_mlp_set_params(mfd_mlp* net, const float* params);
+int mfd_mlp_get_params(mfd_mlp* net, float* params);
+/* Y (device, batch x nout FP32, row-major) = network(X) (device, batch x nin). */
+int mfd_mlp_forward(mfd_mlp* net, int batch, const float* X, float* Y, void* stream);
+/* loss = mean over batch and outputs of (network(X) - T)^2 (host, blocking);
+ * the gradient stays in the network for mfd_mlp_adam_step and is copied to
+ * grad (device, nparams FP32) when grad is not NULL. */
+int mfd_mlp_loss_grad(mfd_mlp* net, int batch, const float* X, const float* T, double* loss, float* grad,
+                      void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) from the last gradient. */
+int mfd_mlp_adam_step(mfd_mlp* net, float lr, void* stream);
+void mfd_mlp_destroy(mfd_mlp* net);
+
+/* Training target of the warm start from three converged blocks Xa = X_{j-1},
+ * Xb = X_j, Xc = X_{j+1} (device c128, each n x mb column-major, mb <= 21):
+ * C (device c128, 2mb x mb row-major) = Y^H Xc Q with Y = [Xb Xa] R^-1
+ * (R^H R the Gram matrix of [Xb Xa]) and Q the unitary polar factor of
+ * Xc^H Xb; Rinv (device c128, 2mb x 2mb row-major, or NULL) = R'^-1 for the
+ * Gram matrix R'^H R' of [Xc Q, Xb] (the basis of the next proposal, with Xc
+ * aligned to Xb).  Blocking.  MFD_ENOTCONV when [Xb Xa] or
+ * [Xc Xb] is numerically rank deficient (relative pivot below 1e-10). */
+int mfd_warm_target(long long n, int mb, const void* Xa, const void* Xb, const void* Xc, void* C, void* Rinv,
+                    void* stream);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,8 @@ class MfdError(RuntimeError):
 class mfd_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("precision", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("seed", ctypes.c_ulonglong), ("max_gamma_doublings", ctypes.c_int), ("guard", ctypes.c_int),
-                ("streams", ctypes.c_int), ("x0", ctypes.c_void_p), ("stall_window", ctypes.c_int)]
+                ("streams", ctypes.c_int), ("x0", ctypes.c_void_p), ("stall_window", ctypes.c_int),
+                ("learn_steps", ctypes.c_int), ("learn_rate", ctypes.c_float)]
 
 
 class mfd_kstats(ctypes.Structure):
@@ -73,6 +74,18 @@ def lib():
         L.mfd_strerror.argtypes = [i]
         L.mfd_strerror.restype = ctypes.c_char_p
         L.mfd_last_error.restype = ctypes.c_char_p
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.mfd_mlp_create.argtypes = [i, i, i, i, i, i, ctypes.c_ulonglong, ctypes.POINTER(vp)]
+        L.mfd_mlp_num_params.argtypes = [vp]
+        L.mfd_mlp_num_params.restype = ctypes.c_longlong
+        L.mfd_mlp_set_params.argtypes = [vp, fp]
+        L.mfd_mlp_get_params.argtypes = [vp, fp]
+        L.mfd_mlp_forward.argtypes = [vp, i, vp, vp, vp]
+        L.mfd_mlp_loss_grad.argtypes = [vp, i, vp, vp, dp, vp, vp]
+        L.mfd_mlp_adam_step.argtypes = [vp, ctypes.c_float, vp]
+        L.mfd_mlp_destroy.argtypes = [vp]
+        L.mfd_mlp_destroy.restype = None
+        L.mfd_warm_target.argtypes = [ctypes.c_longlong, i, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -250,3 +263,54 @@ def mfd_bands_batch(ctxs, kpts_list, nbands: int, tol: float, opts: mfd_opts | N
     if status in raise_on:
         _check(status)
     return evs, [_stats_list(s) for s in sts], status
+
+
+class Mlp:
+    """The warm start's network (mfd_mlp_*): device FP32 batches in and out."""
+
+    def __init__(self, nin, nhidden, nlayers, nout, max_batch, bf16=True, seed=0):
+        h = ctypes.c_void_p()
+        _check(lib().mfd_mlp_create(nin, nhidden, nlayers, nout, max_batch, int(bf16), seed, ctypes.byref(h)))
+        self.handle = h
+        self.nparams = int(lib().mfd_mlp_num_params(h))
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+        assert a.size == self.nparams
+        _check(lib().mfd_mlp_set_params(self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self):
+        a = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().mfd_mlp_get_params(self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return a
+
+    def forward(self, X, Y, stream=None):
+        _check(lib().mfd_mlp_forward(self.handle, X.shape[0], _dev(X), _dev(Y), _stream(stream)))
+
+    def loss_grad(self, X, T, grad=None, stream=None):
+        loss = ctypes.c_double()
+        _check(lib().mfd_mlp_loss_grad(self.handle, X.shape[0], _dev(X), _dev(T), ctypes.byref(loss),
+                                       _dev(grad) if grad is not None else None, _stream(stream)))
+        return loss.value
+
+    def adam_step(self, lr, stream=None):
+        _check(lib().mfd_mlp_adam_step(self.handle, float(lr), _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().mfd_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mfd_warm_target(Xa, Xb, Xc, C, Rinv=None, stream=None):
+    """C (2mb x mb c128) and Rinv (2mb x 2mb) from three device blocks of mb
+    columns (tensors (mb, n) c128: row q is column q of the block)."""
+    mb, n = Xa.shape
+    _check(lib().mfd_warm_target(n, mb, _dev(Xa), _dev(Xb), _dev(Xc), _dev(C),
+                                 _dev(Rinv) if Rinv is not None else None, _stream(stream)))

@@ -17,6 +17,7 @@
 #include "../../include/mfdkc.h"
 #include "common.h"
 #include "internal.h"
+#include "mlp.h"
 #include "solver.h"
 
 using namespace mfd;
@@ -117,6 +118,7 @@ struct Ws {
     double* cout = nullptr;
     double* host = nullptr;    // pinned: theta | norms | info | column sums
     int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
+    WarmStart* warm = nullptr; // learned warm start (warm_start = 2), allocated on first use
     Prof prof;
 };
 
@@ -193,6 +195,10 @@ void ws_free(Ws* w) {
     hipFree(w->npart); hipFree(w->norms); hipFree(w->theta); hipFree(w->info);
     hipFree(w->cpart); hipFree(w->cout);
     if (w->host) hipHostFree(w->host);
+    if (w->warm) {
+        w->warm->release();
+        delete w->warm;
+    }
     if (w->stream) hipStreamDestroy(w->stream);
     delete w;
 }
@@ -255,13 +261,67 @@ struct KResult {
     int iters = 0;
     bool converged = false;
     bool fp64_fallback = false;
+    bool proposal_used = false;
     std::vector<double> theta, res;
 };
 
 // LOBPCG at one k-point from the start block in V[:, :mb] (FP64).  Stops when
 // the lowest `nreq` columns have converged (or after max_iter iterations).
+// tr((S^H S)^-1 S^H A S) for the m columns at offset r of the basis, from the
+// Gram matrix G (K x 2K row-major, [S^H S | S^H A S]): the sum of the Ritz
+// values of that block (+inf when its Gram matrix is not positive definite).
+double ritz_trace(const double2* G, int K, int r, int m) {
+    std::vector<double> Lr(m * m, 0.0), Li(m * m, 0.0);
+    auto gs = [&](int i, int j) { return G[(size_t)(r + i) * 2 * K + r + j]; };
+    for (int j = 0; j < m; ++j) {
+        double d = gs(j, j).x;
+        for (int k = 0; k < j; ++k) d -= Lr[j * m + k] * Lr[j * m + k] + Li[j * m + k] * Li[j * m + k];
+        if (!(d > 0.0)) return HUGE_VAL;
+        const double ljj = std::sqrt(d);
+        Lr[j * m + j] = ljj;
+        for (int i = j + 1; i < m; ++i) {
+            double sr = gs(i, j).x, si = gs(i, j).y;
+            for (int k = 0; k < j; ++k) {   // L[i][k] conj(L[j][k])
+                sr -= Lr[i * m + k] * Lr[j * m + k] + Li[i * m + k] * Li[j * m + k];
+                si -= Li[i * m + k] * Lr[j * m + k] - Lr[i * m + k] * Li[j * m + k];
+            }
+            Lr[i * m + j] = sr / ljj;
+            Li[i * m + j] = si / ljj;
+        }
+    }
+    // tr(S^-1 A) = sum_q e_q^T L^-H L^-1 A e_q: forward solves L y = A e_q, then y_q of L^H z = y
+    double tr = 0.0;
+    std::vector<double> yr(m), yi(m);
+    for (int q = 0; q < m; ++q) {
+        for (int i = 0; i < m; ++i) {
+            const double2 a = G[(size_t)(r + i) * 2 * K + K + r + q];
+            double sr = a.x, si = a.y;
+            for (int k = 0; k < i; ++k) {
+                sr -= Lr[i * m + k] * yr[k] - Li[i * m + k] * yi[k];
+                si -= Lr[i * m + k] * yi[k] + Li[i * m + k] * yr[k];
+            }
+            yr[i] = sr / Lr[i * m + i];
+            yi[i] = si / Lr[i * m + i];
+        }
+        for (int i = m - 1; i >= q; --i) {   // back substitution with L^H, keep component q
+            double sr = yr[i], si = yi[i];
+            for (int k = i + 1; k < m; ++k) {   // conj(L[k][i]) z_k
+                sr -= Lr[k * m + i] * yr[k] + Li[k * m + i] * yi[k];
+                si -= Lr[k * m + i] * yi[k] - Li[k * m + i] * yr[k];
+            }
+            yr[i] = sr / Lr[i * m + i];
+            yi[i] = si / Lr[i * m + i];
+        }
+        tr += yr[q];
+    }
+    return tr;
+}
+
+// With union_start the W columns hold a proposed start block.  The proposal
+// replaces nothing: when the sum of its Ritz values is below that of X the
+// first Rayleigh-Ritz step runs on span[X, W], otherwise on span[X] alone.
 int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max_iter, int stall_window,
-             KResult& out) {
+             bool union_start, KResult& out) {
     const size_t n = w.n;
     const int mb = w.mb;
     const int K = 3 * mb;
@@ -272,15 +332,26 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     float2* V32 = w.V32;
     float2* U32 = w.U32;
     out.fp64_fallback = false;
-    // zero W, P, AW, AP; AX = op(X) (FP64)
+    out.proposal_used = false;
+    // zero W (unless it holds a proposal), P, AW, AP; AX = op(X) (FP64)
+    const int wz = union_start ? 1 : 0;
     if (mixed) {
-        HIPCHK(hipMemsetAsync(V32 + n * mb, 0, n * 2 * mb * sizeof(float2), s));
+        HIPCHK(hipMemsetAsync(V32 + n * (mb + wz * mb), 0, n * (2 - wz) * mb * sizeof(float2), s));
         HIPCHK(hipMemsetAsync(V32 + n * 4 * mb, 0, n * 2 * mb * sizeof(float2), s));
     } else {
-        HIPCHK(hipMemsetAsync(col(V, n, mb), 0, n * 2 * mb * sizeof(double2), s));
+        HIPCHK(hipMemsetAsync(col(V, n, mb + wz * mb), 0, n * (2 - wz) * mb * sizeof(double2), s));
         HIPCHK(hipMemsetAsync(col(V, n, 4 * mb), 0, n * 2 * mb * sizeof(double2), s));
     }
     HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+    if (union_start) {
+        // AW = op(W); residual norms set to 1 so that every W column is kept
+        if (mixed) HIPCHK(launch_stencil_f64_s32(p, mb, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s));
+        else HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
+        std::vector<double> ones(2 * mb, 1.0);
+        HIPCHK(hipMemcpyAsync(w.norms, ones.data(), 2 * mb * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(w.theta, ones.data(), mb * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     RRArgs ra;
     ra.G = w.G; ra.norms = w.norms; ra.theta = w.theta; ra.C = w.C; ra.info = w.info;
     ra.mb = mb; ra.tol = tol;
@@ -306,7 +377,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         return conv;
     };
     for (;; ++it) {
-        ra.first = (it == 0);
+        ra.first = (it == 0 && !union_start);
         const int rb = mixed ? 8 : 16;   // bytes per complex of the W/AW blocks
         if (it > 0) {
             // W = T R (in place), AW = op(W)
@@ -322,6 +393,16 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         hipEvent_t e1 = w.prof.begin(s);
         HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, K, w.nparts_gram, w.gpart, w.G, s));
         w.prof.end(e1, 2, (double)n * (2 * mb * 16.0 + 4 * mb * rb), s);
+        if (it == 0 && union_start) {
+            std::vector<double2> hG((size_t)K * 2 * K);
+            HIPCHK(hipMemcpyAsync(hG.data(), w.G, hG.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const double tx = ritz_trace(hG.data(), K, 0, mb), tw = ritz_trace(hG.data(), K, mb, mb);
+            out.proposal_used = tw < tx;
+            ra.first = !out.proposal_used;
+            if (trace) std::fprintf(stderr, "[%p] proposal: Ritz sum %.6e vs previous-k %.6e -> %s\n", (void*)&w,
+                                    tw, tx, out.proposal_used ? "used" : "dropped");
+        }
         e1 = w.prof.begin(s);
         HIPCHK(launch_rr(ra, s));
         w.prof.end(e1, 3, 0.0, s);
@@ -434,7 +515,7 @@ struct KOut {
 // One k-point: LOBPCG on mb = nbands + guard columns starting from V[:, :mb],
 // then Alg 4.1 (discard flagged bands, or double gamma and solve again).
 int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mfd_opts& o, uint64_t seed_k,
-            const KOut& ko, int* converged) {
+            const KOut& ko, bool proposal, bool* proposal_used, double* lam_all, int* converged) {
     const size_t n = w.n;
     const int mb = w.mb;
     hipStream_t s = w.stream;
@@ -447,7 +528,9 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
     std::vector<double> lam(mb), lre(mb);
     std::vector<int> sel;
     for (;;) {
-        int st = lobpcg_k(c, w, p, nreq, tol, o.max_iter, o.stall_window, kr);
+        int st = lobpcg_k(c, w, p, nreq, tol, o.max_iter, o.stall_window, proposal, kr);
+        if (proposal && proposal_used) *proposal_used = kr.proposal_used;
+        proposal = false;
         if (st) return st;
         total_iters += kr.iters;
         fp64_fallback |= kr.fp64_fallback;
@@ -484,6 +567,8 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
         for (size_t q = 0; q < spur.size(); ++q)
             HIPCHK(launch_fill_random(col(w.V, n, spur[q]), n, seed_k + 7919ull * doublings + spur[q], s));
     }
+    if (lam_all)
+        for (int j = 0; j < mb; ++j) lam_all[j] = lam[j];
     std::vector<int> idx(sel);
     std::sort(idx.begin(), idx.end(), [&](int a, int b) { return lam[a] < lam[b]; });
     double maxres = 0.0;
@@ -538,16 +623,43 @@ void run_segment(Segment* sg) {
     const size_t n = w.n;
     const int mb = w.mb;
     const mfd_opts& o = sg->opts;
+    const bool learned = o.warm_start == 2;
+    if (learned) {
+        if (!w.warm) {
+            w.warm = new WarmStart();
+            const int st = w.warm->init(n, mb, c->L, o.seed + 1);
+            if (st) {
+                w.warm->release();
+                delete w.warm;
+                w.warm = nullptr;
+                sg->status = fail(st, "learned warm start: allocation failed");
+                sg->err = g_last_error;
+                return;
+            }
+        }
+        if (w.warm->reset(w.stream)) {
+            sg->status = fail(MFD_EDEVICE, "learned warm start: reset failed");
+            sg->err = g_last_error;
+            return;
+        }
+    }
+    std::vector<double> lam_all(mb);
     for (int ik = sg->k0; ik < sg->k1; ++ik) {
         const uint64_t seed_k = o.seed * 1000003ull + 104729ull * (uint64_t)ik;
         int st = MFD_OK;
+        bool proposal = false;
+        if (learned && ik > sg->k0) {
+            void* W = w.mixed ? (void*)(w.V32 + n * mb) : (void*)col(w.V, n, mb);
+            st = w.warm->propose(sg->kpts + 3 * ik, W, w.mixed, &proposal, w.stream);
+            if (st) st = fail(st, "learned warm start: proposal failed");
+        }
         if (ik == sg->k0 && ik == 0 && o.x0) {
             hipError_t e = hipMemcpyAsync(w.V, o.x0, n * sg->nbands * sizeof(double2), hipMemcpyDeviceToDevice,
                                           w.stream);
             if (e == hipSuccess && mb > sg->nbands)
                 e = launch_fill_random(col(w.V, n, sg->nbands), n * (mb - sg->nbands), seed_k + 17, w.stream);
             if (e != hipSuccess) st = fail(MFD_EDEVICE, hipGetErrorString(e));
-        } else if (ik == sg->k0 || !o.warm_start) {
+        } else if (!st && (ik == sg->k0 || !o.warm_start)) {
             hipError_t e = launch_fill_random(w.V, n * mb, seed_k, w.stream);
             if (e != hipSuccess) st = fail(MFD_EDEVICE, hipGetErrorString(e));
         }
@@ -556,7 +668,15 @@ void run_segment(Segment* sg) {
             KOut ko{sg->evals + (size_t)ik * sg->nbands,
                     sg->evecs ? sg->evecs + (size_t)ik * sg->nbands * n : nullptr,
                     sg->stats ? sg->stats + ik : nullptr};
-            st = solve_k(c, w, sg->kpts + 3 * ik, sg->nbands, sg->tol, o, seed_k, ko, &conv);
+            bool used = false;
+            st = solve_k(c, w, sg->kpts + 3 * ik, sg->nbands, sg->tol, o, seed_k, ko, proposal, &used,
+                         lam_all.data(), &conv);
+            if (!st && ko.stats) ko.stats->used_fallback = (learned && ik > sg->k0 && !used) ? 1 : 0;
+            if (!st && learned) {
+                st = w.warm->after_solve(w.V, lam_all.data(), sg->kpts + 3 * ik, o.learn_steps, o.learn_rate,
+                                         w.stream);
+                if (st) st = fail(st, "learned warm start: training step failed");
+            }
         }
         if (st) {
             sg->status = st;
@@ -593,7 +713,8 @@ int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
     if (nbands <= 0) return fail(MFD_EINVAL, "nbands must be > 0");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
     if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0 || o.streams < 1 || o.streams > 16 ||
-        o.stall_window < 0)
+        o.stall_window < 0 || o.warm_start < 0 || o.warm_start > 2 || o.learn_steps < 0 ||
+        !(o.learn_rate >= 0.0f))
         return fail(MFD_EINVAL, "bad options");
     const int mb = nbands + o.guard;
     if (3 * mb > 64) return fail(MFD_EUNSUPPORTED, "nbands + guard must be <= 21");
@@ -618,6 +739,8 @@ void mfd_default_opts(mfd_opts* o) {
     o->streams = 4;
     o->x0 = nullptr;
     o->stall_window = 40;
+    o->learn_steps = 30;
+    o->learn_rate = 1e-3f;
 }
 
 int mfd_supported_n(int N) {
@@ -896,5 +1019,87 @@ const char* mfd_strerror(int status) {
 }
 
 const char* mfd_last_error(void) { return g_last_error.c_str(); }
+
+struct mfd_mlp {
+    mfd::Mlp net;
+};
+
+int mfd_mlp_create(int nin, int nhidden, int nlayers, int nout, int max_batch, int bf16_weights,
+                   unsigned long long seed, mfd_mlp** out) {
+    if (!out) return fail(MFD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nin < 1 || nout < 1 || nlayers < 0 || (nlayers > 0 && nhidden < 1) || max_batch < 1)
+        return fail(MFD_EINVAL, "bad network sizes");
+    mfd_mlp* m = new mfd_mlp();
+    const int st = m->net.init(nin, nlayers > 0 ? nhidden : 0, nlayers, nout, max_batch, bf16_weights != 0, seed);
+    if (st) {
+        m->net.release();
+        delete m;
+        return fail(st, "network allocation failed");
+    }
+    *out = m;
+    return MFD_OK;
+}
+
+long long mfd_mlp_num_params(const mfd_mlp* m) { return m ? (long long)m->net.nparam : 0; }
+
+int mfd_mlp_set_params(mfd_mlp* m, const float* params) {
+    if (!m || !params) return fail(MFD_EINVAL, "NULL argument");
+    const int st = m->net.set_params(params, nullptr);
+    return st ? fail(st, "set_params failed") : MFD_OK;
+}
+
+int mfd_mlp_get_params(mfd_mlp* m, float* params) {
+    if (!m || !params) return fail(MFD_EINVAL, "NULL argument");
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(params, m->net.p, m->net.nparam * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(MFD_EDEVICE, "copy failed");
+    return MFD_OK;
+}
+
+int mfd_mlp_forward(mfd_mlp* m, int batch, const float* X, float* Y, void* stream) {
+    if (!m || !X || !Y) return fail(MFD_EINVAL, "NULL argument");
+    if (batch < 1 || batch > m->net.bmax) return fail(MFD_EINVAL, "batch out of range");
+    if (m->net.forward(batch, X, Y, (hipStream_t)stream) != hipSuccess) return fail(MFD_EDEVICE, "launch failed");
+    return MFD_OK;
+}
+
+int mfd_mlp_loss_grad(mfd_mlp* m, int batch, const float* X, const float* T, double* loss, float* grad,
+                      void* stream) {
+    if (!m || !X || !T || !loss) return fail(MFD_EINVAL, "NULL argument");
+    if (batch < 1 || batch > m->net.bmax) return fail(MFD_EINVAL, "batch out of range");
+    hipStream_t s = (hipStream_t)stream;
+    if (m->net.loss_grad(batch, X, T, s) != hipSuccess) return fail(MFD_EDEVICE, "launch failed");
+    if (grad && hipMemcpyAsync(grad, m->net.g, m->net.nparam * sizeof(float), hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+        return fail(MFD_EDEVICE, "copy failed");
+    if (hipMemcpyAsync(loss, m->net.dloss, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(MFD_EDEVICE, "copy failed");
+    return MFD_OK;
+}
+
+int mfd_mlp_adam_step(mfd_mlp* m, float lr, void* stream) {
+    if (!m) return fail(MFD_EINVAL, "NULL argument");
+    if (!(lr >= 0.0f)) return fail(MFD_EINVAL, "learning rate must be >= 0");
+    if (m->net.adam(lr, (hipStream_t)stream) != hipSuccess) return fail(MFD_EDEVICE, "launch failed");
+    return MFD_OK;
+}
+
+void mfd_mlp_destroy(mfd_mlp* m) {
+    if (!m) return;
+    m->net.release();
+    delete m;
+}
+
+int mfd_warm_target(long long n, int mb, const void* Xa, const void* Xb, const void* Xc, void* C, void* Rinv,
+                    void* stream) {
+    if (!Xa || !Xb || !Xc || !C) return fail(MFD_EINVAL, "NULL argument");
+    if (n < 1 || mb < 1 || mb > 21 || 2 * mb > n) return fail(MFD_EINVAL, "bad sizes");
+    const int st = mfd::warm_target_blocks((size_t)n, mb, (const double2*)Xa, (const double2*)Xb,
+                                           (const double2*)Xc, (double2*)C, (double2*)Rinv, (hipStream_t)stream);
+    if (st == MFD_ENOTCONV) return fail(st, "history blocks are numerically dependent");
+    return st ? fail(st, "warm target failed") : MFD_OK;
+}
 
 }  // extern "C"

@@ -4,7 +4,7 @@ workloads, for the GPU parity tests at the sizes the benchmark runs.
 Each file holds, for a few k-points of the path, the lowest m physical
 eigenvalues of A M_0 A' + gamma B'B (eq. (Ker_comp), filtered by Alg 4.1) from
 the FP64 CPU oracle's LOBPCG with the FFT preconditioner (Section 5), solved
-to relative residual 1e-10 from a seeded random start.  Only ``oracle/`` and
+to a relative residual of 1e-10 (1e-9 at N = 64) from a seeded random start.  Only ``oracle/`` and
 the seeded input generators are called.
 
     python -m tests.golden.make_golden sphere_n32     # about 10 minutes
@@ -21,12 +21,13 @@ import numpy as np
 from oracle import lobpcg as olob
 from paper_2503_19379_amd import workloads
 
-# workload -> (k indices on the workload's path, bands)
+# workload -> (k indices on the workload's path, bands, relative residual).
+# At N = 64 the FP64 residual floor near Gamma lies just above 1e-10 (the
+# oracle stalls at 2e-10 there), so that workload is solved to 1e-9.
 SAMPLES = {
-    "sphere_n32": ((0, 5, 10, 15), 10),
-    "diamond_n64": ((0, 16, 32, 48), 16),
+    "sphere_n32": ((0, 5, 10, 15), 10, 1e-10),
+    "diamond_n64": ((0, 16, 32, 48), 16, 1e-9),
 }
-TOL = 1e-10
 
 
 def path(name):
@@ -35,18 +36,18 @@ def path(name):
 
 def make(name):
     cfg = workloads.CONFIGS[name]
-    kidx, m = SAMPLES[name]
+    kidx, m, tol = SAMPLES[name]
     N = cfg["N"]
     eps = workloads.crystal_eps(cfg["eps"], N)
     kp = workloads.kpath(cfg["path"], cfg["nk"])
     lines = [f"# {name}: oracle band energies (eq. (Ker_comp) after Alg 4.1), FP64 LOBPCG with the FFT",
-             f"# preconditioner (Section 5), relative residual <= {TOL:g}, seeded random start (seed 0).",
+             f"# preconditioner (Section 5), relative residual <= {tol:g}, seeded random start (seed 0).",
              f"# N = {N}, L = 1, {cfg['nk']} k-points on {cfg['path']}, m = {m}; written by",
              f"# `python -m tests.golden.make_golden {name}` (calls only oracle/ and the input generators).",
              "# columns: k_index kx ky kz gamma max_rel_resid lambda_1 ... lambda_m"]
     for i in kidx:
         t0 = time.time()
-        lam, _, info = olob.solve_bands(eps, 1.0, kp[i], m, tol=TOL)
+        lam, _, info = olob.solve_bands(eps, 1.0, kp[i], m, tol=tol)
         res = float(np.max(info["res"]))
         print(f"{name} k{i}: {time.time() - t0:.0f} s, iters {info['total_iters']}, res {res:.2e}, "
               f"discarded {info['discarded']}", flush=True)

@@ -1,0 +1,55 @@
+"""Full-size parity: the band solve of the benchmark workloads, in the
+benchmark's launch configuration (whole k-path, 4 concurrent segments, 2 guard
+columns, relative residual 1e-8), against the oracle's band energies at
+sampled k-points (tests/golden/*_bands.txt, written by
+tests/golden/make_golden.py from oracle/ only)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2503_19379_amd import workloads
+from tests.golden import make_golden
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_19379_amd import binding
+    binding.lib()
+    return binding
+
+
+def _check(B, name, precision, rtol):
+    if not os.path.exists(make_golden.path(name)):
+        pytest.skip(f"{name} golden values not written")
+    gold = make_golden.load(name)
+    cfg = workloads.CONFIGS[name]
+    N, m = cfg["N"], cfg["nbands"]
+    kp = workloads.kpath(cfg["path"], cfg["nk"])
+    ctx = B.mfd_build(N, 1.0, 2, workloads.crystal_eps(cfg["eps"], N))
+    opts = B.default_opts(precision=precision, warm_start=1, guard=2, streams=4, max_iter=500)
+    ev, st, status = B.mfd_bands(ctx, kp, m, 1e-8, opts)
+    assert status == 0, st
+    for i, s in enumerate(st):
+        assert s["max_rel_resid"] <= 1e-8 and s["spurious"] == 0, (i, s)
+    scale = (2 * np.pi) ** 2
+    for i, (k, gamma, lam) in gold.items():
+        assert np.allclose(kp[i], k, atol=1e-15)
+        assert st[i]["gamma"] == pytest.approx(gamma, rel=1e-15)
+        err = np.abs(ev[i] - lam[:m])
+        # the zero bands of Gamma are compared in absolute terms
+        assert np.all(err <= rtol * np.abs(lam[:m]) + 1e-9 * scale), (i, ev[i], lam[:m], err)
+
+
+def test_sphere_n32_fp64(B):
+    _check(B, "sphere_n32", 0, 1e-9)
+
+
+def test_diamond_n64_mixed(B):
+    _check(B, "diamond_n64", 1, 1e-7)
