@@ -59,13 +59,23 @@ __device__ __forceinline__ void slab_elem(int e, int RB, int mb, bool mixed, int
     }
 }
 
-__device__ __forceinline__ double2 load_col(const double2* __restrict__ V, const float2* __restrict__ V32, int c,
+// Prefetches keep the raw bits (an FP32 pair in .x) so that no conversion
+// waits on a load in flight; widen() promotes when the slab is written.
+__device__ __forceinline__ double2 load_raw(const double2* __restrict__ V, const float2* __restrict__ V32, int c,
                                             int mb, size_t ld, size_t row) {
     if (V32 && col_is_f32(c, mb)) {
-        const float2 v = V32[(size_t)c * ld + row];
-        return mk<double2>((double)v.x, (double)v.y);
+        double2 r;
+        r.x = __builtin_bit_cast(double, V32[(size_t)c * ld + row]);
+        r.y = 0.0;
+        return r;
     }
     return V[(size_t)c * ld + row];
+}
+
+__device__ __forceinline__ double2 widen(double2 raw, bool f32) {
+    if (!f32) return raw;
+    const float2 v = __builtin_bit_cast(float2, raw.x);
+    return mk<double2>((double)v.x, (double)v.y);
 }
 
 // The next slab is loaded into registers while the current one is consumed
@@ -112,7 +122,7 @@ __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restric
             if (e < nel) {
                 int r, c;
                 slab_elem(e, GM_KS, K / 3, V32 != nullptr, &c, &r);
-                if (r < rows) pf[q] = load_col(V, V32, c, K / 3, ld, s0 + r);
+                if (r < rows) pf[q] = load_raw(V, V32, c, K / 3, ld, s0 + r);
             }
         }
     };
@@ -124,7 +134,7 @@ __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restric
             if (e < nel) {
                 int r, c;
                 slab_elem(e, GM_KS, K / 3, V32 != nullptr, &c, &r);
-                slab[r * C2 + c] = pf[q];
+                slab[r * C2 + c] = widen(pf[q], V32 && col_is_f32(c, K / 3));
             }
         }
         __syncthreads();
@@ -289,7 +299,7 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
             if (e < nel && blk < nblk) {
                 int r, c;
                 slab_elem(e, UP_RB, mb, V32 != nullptr, &c, &r);
-                if (b0 + r < n) pf[q] = load_col(V, V32, c, mb, ld, b0 + r);
+                if (b0 + r < n) pf[q] = load_raw(V, V32, c, mb, ld, b0 + r);
             }
         }
     };
@@ -302,7 +312,7 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
             if (e < nel) {
                 int r, c;
                 slab_elem(e, UP_RB, mb, V32 != nullptr, &c, &r);
-                slab[c * UP_RBP + r] = pf[q];
+                slab[c * UP_RBP + r] = widen(pf[q], V32 && col_is_f32(c, mb));
             }
         }
         __syncthreads();
@@ -336,12 +346,10 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                     const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
                     const double2 v = mk<double2>(t1 - t2, t3 - t1 - t2);
                     if (pass == 0) {
-                        const size_t row = b0 + rl;
-                        if (j < mb && row < n) {
-                            const size_t o = (size_t)((chain ? 5 : 2) * mb + j) * ld + row;
-                            if (U32) U32[o] = make_float2((float)v.x, (float)v.y);
-                            else U[o] = v;
-                        }
+                        // P' (AP'): into this wave's rows of the W (AW) columns of the
+                        // slab, which pass 0 has finished reading and the other strip
+                        // never touches; stored row-contiguously with X' below
+                        if (j < mb) slab[(chain * K + mb + j) * UP_RBP + rl] = v;
                     } else {
                         xo[(chain * MP + j) * UP_RBP + rl] = v;
                     }
@@ -359,10 +367,19 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                     const double2 x = xo[j * UP_RBP + rrow];
                     const double2 ax = xo[(MP + j) * UP_RBP + rrow];
                     const double2 res = mk<double2>(ax.x - th[c] * x.x, ax.y - th[c] * x.y);
+                    const double2 pn = slab[(mb + j) * UP_RBP + rrow];
+                    const double2 apn = slab[(K + mb + j) * UP_RBP + rrow];
                     U[(size_t)j * ld + row] = x;
                     U[(size_t)(3 * mb + j) * ld + row] = ax;
-                    if (U32) U32[(size_t)(mb + j) * ld + row] = make_float2((float)res.x, (float)res.y);
-                    else U[(size_t)(mb + j) * ld + row] = res;
+                    if (U32) {
+                        U32[(size_t)(mb + j) * ld + row] = make_float2((float)res.x, (float)res.y);
+                        U32[(size_t)(2 * mb + j) * ld + row] = make_float2((float)pn.x, (float)pn.y);
+                        U32[(size_t)(5 * mb + j) * ld + row] = make_float2((float)apn.x, (float)apn.y);
+                    } else {
+                        U[(size_t)(mb + j) * ld + row] = res;
+                        U[(size_t)(2 * mb + j) * ld + row] = pn;
+                        U[(size_t)(5 * mb + j) * ld + row] = apn;
+                    }
                     nr[c] += cabs2(res);
                     nx[c] += cabs2(x);
                 }
