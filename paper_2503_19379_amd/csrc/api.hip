@@ -317,6 +317,41 @@ double ritz_trace(const double2* G, int K, int r, int m) {
     return tr;
 }
 
+// The Rayleigh-Ritz basis [X, W(act), P(pact)] as a column map of V.
+BasisMap make_basis(int mb, const std::vector<int>& act, const std::vector<int>& pact, bool mixed) {
+    BasisMap bm;
+    const int na = (int)act.size(), np = (int)pact.size();
+    bm.mb = mb;
+    bm.na = na;
+    bm.K = mb + na + np;
+    const int K = bm.K;
+    auto vcol = [&](int l) {   // basis column l < K -> column of V
+        if (l < mb) return l;
+        if (l < mb + na) return mb + act[l - mb];
+        return 2 * mb + pact[l - mb - na];
+    };
+    int q = 0;
+    auto put = [&](int l) {
+        bm.lc[q] = (short)l;
+        bm.pc[q] = (short)(l < K ? vcol(l) : 3 * mb + vcol(l - K));
+        ++q;
+    };
+    if (mixed) {   // FP64 columns (X, AX) first, so that a wave's loads are of one precision
+        for (int l = 0; l < mb; ++l) put(l);
+        for (int l = 0; l < mb; ++l) put(K + l);
+        for (int l = mb; l < K; ++l) put(l);
+        for (int l = mb; l < K; ++l) put(K + l);
+    } else {
+        for (int l = 0; l < 2 * K; ++l) put(l);
+    }
+    for (int j = 0; j < 32; ++j) bm.tpos[j] = -1;
+    for (int t = 0; t < na; ++t) {
+        bm.tpos[act[t]] = (signed char)t;
+        bm.act[t] = (unsigned char)act[t];
+    }
+    return bm;
+}
+
 // With union_start the W columns hold a proposed start block.  The proposal
 // replaces nothing: when the sum of its Ritz values is below that of X the
 // first Rayleigh-Ritz step runs on span[X, W], otherwise on span[X] alone.
@@ -333,28 +368,21 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     float2* U32 = w.U32;
     out.fp64_fallback = false;
     out.proposal_used = false;
-    // zero W (unless it holds a proposal), P, AW, AP; AX = op(X) (FP64)
-    const int wz = union_start ? 1 : 0;
-    if (mixed) {
-        HIPCHK(hipMemsetAsync(V32 + n * (mb + wz * mb), 0, n * (2 - wz) * mb * sizeof(float2), s));
-        HIPCHK(hipMemsetAsync(V32 + n * 4 * mb, 0, n * 2 * mb * sizeof(float2), s));
-    } else {
-        HIPCHK(hipMemsetAsync(col(V, n, mb + wz * mb), 0, n * (2 - wz) * mb * sizeof(double2), s));
-        HIPCHK(hipMemsetAsync(col(V, n, 4 * mb), 0, n * 2 * mb * sizeof(double2), s));
-    }
+    // AX = op(X) (FP64); with a proposal, AW = op(W).  The basis holds the W
+    // and P columns of unconverged bands only, so nothing needs clearing: a W
+    // column is formed before it is used, and a P column is used only when the
+    // previous update wrote it.
     HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
     if (union_start) {
-        // AW = op(W); residual norms set to 1 so that every W column is kept
         if (mixed) HIPCHK(launch_stencil_f64_s32(p, mb, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s));
         else HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
-        std::vector<double> ones(2 * mb, 1.0);
-        HIPCHK(hipMemcpyAsync(w.norms, ones.data(), 2 * mb * sizeof(double), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(w.theta, ones.data(), mb * sizeof(double), hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
     }
+    std::vector<int> act, act_prev, pact;
+    if (union_start)
+        for (int j = 0; j < mb; ++j) act.push_back(j);
     RRArgs ra;
-    ra.G = w.G; ra.norms = w.norms; ra.theta = w.theta; ra.C = w.C; ra.info = w.info;
-    ra.mb = mb; ra.tol = tol;
+    ra.G = w.G; ra.theta = w.theta; ra.C = w.C; ra.info = w.info;
+    ra.mb = mb;
     // the Gram of FP32-stored directions is exact for the stored values, but
     // their images AW, AP carry FP32 rounding: drop nearly dependent ones sooner
     ra.drop_w = mixed ? 1e-6 : 1e-10;
@@ -377,8 +405,13 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         return conv;
     };
     for (;; ++it) {
-        ra.first = (it == 0 && !union_start);
         const int rb = mixed ? 8 : 16;   // bytes per complex of the W/AW blocks
+        // P columns still valid: bands active now whose P' the last update wrote
+        pact.clear();
+        for (int b : act)
+            if (std::find(act_prev.begin(), act_prev.end(), b) != act_prev.end()) pact.push_back(b);
+        BasisMap bm = make_basis(mb, act, pact, mixed);
+        const int na = (int)act.size(), np = (int)pact.size();
         if (it > 0) {
             // W = T R (in place), AW = op(W)
             hipEvent_t e0 = w.prof.begin(s);
@@ -391,28 +424,39 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             w.prof.end(e0, 0, N3 * (6.0 * rb * mb + 24.0), s);
         }
         hipEvent_t e1 = w.prof.begin(s);
-        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, K, w.nparts_gram, w.gpart, w.G, s));
-        w.prof.end(e1, 2, (double)n * (2 * mb * 16.0 + 4 * mb * rb), s);
+        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s));
+        w.prof.end(e1, 2, (double)n * (2 * mb * 16.0 + 2 * (na + np) * rb), s);
         if (it == 0 && union_start) {
-            std::vector<double2> hG((size_t)K * 2 * K);
+            const int Kb = bm.K;
+            std::vector<double2> hG((size_t)Kb * 2 * Kb);
             HIPCHK(hipMemcpyAsync(hG.data(), w.G, hG.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            const double tx = ritz_trace(hG.data(), K, 0, mb), tw = ritz_trace(hG.data(), K, mb, mb);
+            const double tx = ritz_trace(hG.data(), Kb, 0, mb), tw = ritz_trace(hG.data(), Kb, mb, mb);
             out.proposal_used = tw < tx;
-            ra.first = !out.proposal_used;
             if (trace) std::fprintf(stderr, "[%p] proposal: Ritz sum %.6e vs previous-k %.6e -> %s\n", (void*)&w,
                                     tw, tx, out.proposal_used ? "used" : "dropped");
+            if (!out.proposal_used) {   // X alone
+                act.clear();
+                bm = make_basis(mb, act, pact, mixed);
+                HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s));
+            }
         }
+        ra.K = bm.K;
+        ra.nw = bm.na;
         e1 = w.prof.begin(s);
         HIPCHK(launch_rr(ra, s));
         w.prof.end(e1, 3, 0.0, s);
         e1 = w.prof.begin(s);
-        HIPCHK(launch_update_mfma(V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, mb, w.C, w.theta,
+        HIPCHK(launch_update_mfma(V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, bm, w.C, w.theta,
                                   w.nparts_upd, w.npart, w.norms, s));
-        // reads X, AX (FP64) and W, P, AW, AP; writes X', AX' (FP64) and P', AP', R'
-        w.prof.end(e1, 4, (double)n * mb * (2 * 16.0 + 4 * rb + 2 * 16.0 + 3 * rb), s);
+        // reads X, AX (FP64) and the W, P, AW, AP of the basis; writes X', AX'
+        // (FP64), R' for every band and P', AP' for the active ones
+        w.prof.end(e1, 4,
+                   (double)n * (2 * mb * 16.0 + 2 * (bm.na + np) * rb + 2 * mb * 16.0 + mb * rb + 2 * bm.na * rb),
+                   s);
         std::swap(V, U);
         if (mixed) std::swap(V32, U32);
+        act_prev = act;   // the update wrote P', AP' of these bands
         HIPCHK(hipMemcpyAsync(hth, w.theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
         int* hinfo = (int*)(w.host + 3 * mb);
@@ -421,6 +465,12 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         w.prof.drain();
         double rmax = 0.0;
         bool conv = residuals(&rmax);
+        auto active_set = [&]() {
+            act.clear();
+            for (int j = 0; j < mb; ++j)
+                if (!(std::sqrt(hnorm[j]) / (std::fabs(hth[j]) * std::sqrt(hnorm[mb + j])) <= tol)) act.push_back(j);
+        };
+        active_set();
         if (trace) {
             int nact = 0;
             for (int j = 0; j < mb; ++j)
@@ -439,6 +489,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             conv = residuals(&rmax);
+            active_set();
             last_refresh = it;
             ++refreshes;
             if (trace) std::fprintf(stderr, "[%p] refresh %d: rmax %.3e\n", (void*)&w, refreshes, rmax);
@@ -458,11 +509,13 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         if (mixed && stall_window > 0 && it - best_it >= stall_window) {
             mixed = false;
             out.fp64_fallback = true;
-            HIPCHK(hipMemsetAsync(col(V, n, 2 * mb), 0, n * mb * sizeof(double2), s));
-            HIPCHK(hipMemsetAsync(col(V, n, 5 * mb), 0, n * mb * sizeof(double2), s));
+            act_prev.clear();   // no P in FP64 storage yet
             HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
             HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), col(V, n, mb), false, n, n, mb, w.theta,
                                    w.nparts_col, w.npart, w.norms, s));
+            HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            active_set();
             ra.drop_w = 1e-10;
             ra.drop_p = 1e-8;
             best_it = it;

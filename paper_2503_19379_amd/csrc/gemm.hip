@@ -42,36 +42,8 @@ struct GramTiles {
 // load; X and AX stay FP64.
 __device__ __forceinline__ bool col_is_f32(int c, int mb) { return (c >= mb && c < 3 * mb) || c >= 4 * mb; }
 
-// Element e of a slab of RB rows x 2K columns, in an order that visits the
-// FP64 columns (X, AX) first and the FP32 ones after, so that a wave's loads
-// are all of one precision; returns the slab column and row.
-__device__ __forceinline__ void slab_elem(int e, int RB, int mb, bool mixed, int* c, int* r) {
-    *r = e % RB;
-    int q = e / RB;   // ordinal column
-    if (mixed) {
-        // ordinals [0, mb) -> X, [mb, 2mb) -> AX, [2mb, 4mb) -> W P, [4mb, 6mb) -> AW AP
-        if (q < mb) *c = q;
-        else if (q < 2 * mb) *c = 2 * mb + q;
-        else if (q < 4 * mb) *c = q - mb;
-        else *c = q;
-    } else {
-        *c = q;
-    }
-}
-
 // Prefetches keep the raw bits (an FP32 pair in .x) so that no conversion
 // waits on a load in flight; widen() promotes when the slab is written.
-__device__ __forceinline__ double2 load_raw(const double2* __restrict__ V, const float2* __restrict__ V32, int c,
-                                            int mb, size_t ld, size_t row) {
-    if (V32 && col_is_f32(c, mb)) {
-        double2 r;
-        r.x = __builtin_bit_cast(double, V32[(size_t)c * ld + row]);
-        r.y = 0.0;
-        return r;
-    }
-    return V[(size_t)c * ld + row];
-}
-
 __device__ __forceinline__ double2 widen(double2 raw, bool f32) {
     if (!f32) return raw;
     const float2 v = __builtin_bit_cast(float2, raw.x);
@@ -81,8 +53,9 @@ __device__ __forceinline__ double2 widen(double2 raw, bool f32) {
 // The next slab is loaded into registers while the current one is consumed
 // from LDS by the matrix cores.
 __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restrict__ V, const float2* __restrict__ V32,
-                                                         size_t ld, size_t n, int K, size_t rows_per, GramTiles tl,
-                                                         double2* __restrict__ part) {
+                                                         size_t ld, size_t n, BasisMap bm, size_t rows_per,
+                                                         GramTiles tl, double2* __restrict__ part) {
+    const int K = bm.K;
     extern __shared__ unsigned char smem_raw[];
     double2* slab = reinterpret_cast<double2*>(smem_raw);   // [GM_KS][2K]
     const int C2 = 2 * K;
@@ -112,31 +85,42 @@ __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restric
         oa[t] = va[t] ? i : 0;
         ob[t] = vb[t] ? tl.half[ti] * K + j : 0;
     }
+    // element tid + q nthr of a slab: row tid % GM_KS (nthr is a multiple of
+    // GM_KS) and load ordinal tid / GM_KS + q nthr / GM_KS, the same in every
+    // slab: resolve the columns once
+    const int srow = tid % GM_KS;
+    int scol[GM_PF], vcol[GM_PF];
+    unsigned f32m = 0, okm = 0;
+#pragma unroll
+    for (int q = 0; q < GM_PF; ++q) {
+        const int o = tid / GM_KS + q * (nthr / GM_KS);
+        scol[q] = vcol[q] = 0;
+        if (o < C2) {
+            scol[q] = bm.lc[o];
+            vcol[q] = bm.pc[o];
+            okm |= 1u << q;
+            if (V32 && col_is_f32(vcol[q], bm.mb)) f32m |= 1u << q;
+        }
+    }
+    (void)nel;
     double2 pf[GM_PF];
     auto prefetch = [&](size_t s0) {
-        const int rows = (int)min((size_t)GM_KS, r1 > s0 ? r1 - s0 : 0);
+        const bool inb = s0 + srow < r1;
 #pragma unroll
         for (int q = 0; q < GM_PF; ++q) {
-            const int e = tid + q * nthr;
             pf[q] = mk<double2>(0.0, 0.0);
-            if (e < nel) {
-                int r, c;
-                slab_elem(e, GM_KS, K / 3, V32 != nullptr, &c, &r);
-                if (r < rows) pf[q] = load_raw(V, V32, c, K / 3, ld, s0 + r);
+            if (((okm >> q) & 1u) && inb) {
+                const size_t o = (size_t)vcol[q] * ld + s0 + srow;
+                if ((f32m >> q) & 1u) pf[q].x = __builtin_bit_cast(double, V32[o]);
+                else pf[q] = V[o];
             }
         }
     };
     prefetch(r0);
     for (size_t s0 = r0; s0 < r1; s0 += GM_KS) {
 #pragma unroll
-        for (int q = 0; q < GM_PF; ++q) {
-            const int e = tid + q * nthr;
-            if (e < nel) {
-                int r, c;
-                slab_elem(e, GM_KS, K / 3, V32 != nullptr, &c, &r);
-                slab[r * C2 + c] = widen(pf[q], V32 && col_is_f32(c, K / 3));
-            }
-        }
+        for (int q = 0; q < GM_PF; ++q)
+            if ((okm >> q) & 1u) slab[srow * C2 + scol[q]] = widen(pf[q], (f32m >> q) & 1u);
         __syncthreads();
         if (s0 + GM_KS < r1) prefetch(s0 + GM_KS);
 #pragma unroll
@@ -213,8 +197,9 @@ size_t gram_mfma_part_elems(int K, int nparts) {
     return (size_t)(nparts + 1) * T * (T + 1) * 256;   // partials + their sum
 }
 
-hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, int K, int nparts, void* part,
-                            void* G, hipStream_t s) {
+hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nparts,
+                            void* part, void* G, hipStream_t s) {
+    const int K = bm.K;
     GramTiles tl = make_tiles(K);
     const int nwaves_t = (tl.n + GM_MAXT - 1) / GM_MAXT;
     if (K > 64) return hipErrorInvalidValue;
@@ -228,7 +213,7 @@ hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n,
                                        (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gram_mfma_kernel, dim3(nw), dim3(64 * nwaves), lds, s, (const double2*)V, (const float2*)V32,
-                       ld, n, K, rows_per, tl, (double2*)part);
+                       ld, n, bm, rows_per, tl, (double2*)part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // sum the partial tiles (in place into the first part's slot after the last), then scatter
     double2* sum = (double2*)part + (size_t)nw * tl.n * 256;
@@ -256,13 +241,14 @@ constexpr int UP_PF = 16;       // prefetch registers (complex) per thread
 template <int MJ>   // mb <= 16 MJ
 __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restrict__ V, const float2* __restrict__ V32,
                                                           double2* __restrict__ U, float2* __restrict__ U32,
-                                                          size_t ld, size_t n, int mb,
+                                                          size_t ld, size_t n, BasisMap bm,
                                                           const double2* __restrict__ Cg,
                                                           const double* __restrict__ theta,
                                                           double* __restrict__ npart) {
     constexpr int MP = 16 * MJ;
     extern __shared__ unsigned char smem_raw[];
-    const int K = 3 * mb;
+    const int mb = bm.mb;
+    const int K = bm.K;
     const int KP = (K + 3) / 4 * 4;
     const int C2 = 2 * K;
     double2* Cs = reinterpret_cast<double2*>(smem_raw);      // [KP][MP]
@@ -289,17 +275,34 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
     }
     const int nel = UP_RB * C2;
     const size_t nblk = (n + UP_RB - 1) / UP_RB;
+    // element tid + 256 q of a block: row tid % UP_RB and load ordinal
+    // tid / UP_RB + q 256 / UP_RB, the same in every block: resolve the columns once
+    const int srow = tid % UP_RB;
+    int scol[UP_PF], vcol[UP_PF];
+    unsigned f32m = 0, okm = 0;
+#pragma unroll
+    for (int q = 0; q < UP_PF; ++q) {
+        const int o = tid / UP_RB + q * (256 / UP_RB);
+        scol[q] = vcol[q] = 0;
+        if (o < C2) {
+            scol[q] = bm.lc[o];
+            vcol[q] = bm.pc[o];
+            okm |= 1u << q;
+            if (V32 && col_is_f32(vcol[q], mb)) f32m |= 1u << q;
+        }
+    }
+    (void)nel;
     double2 pf[UP_PF];
     auto prefetch = [&](size_t blk) {
-        const size_t b0 = blk * UP_RB;
+        const size_t row = blk * UP_RB + srow;
+        const bool inb = blk < nblk && row < n;
 #pragma unroll
         for (int q = 0; q < UP_PF; ++q) {
-            const int e = tid + q * 256;
             pf[q] = mk<double2>(0.0, 0.0);
-            if (e < nel && blk < nblk) {
-                int r, c;
-                slab_elem(e, UP_RB, mb, V32 != nullptr, &c, &r);
-                if (b0 + r < n) pf[q] = load_raw(V, V32, c, mb, ld, b0 + r);
+            if (((okm >> q) & 1u) && inb) {
+                const size_t o = (size_t)vcol[q] * ld + row;
+                if ((f32m >> q) & 1u) pf[q].x = __builtin_bit_cast(double, V32[o]);
+                else pf[q] = V[o];
             }
         }
     };
@@ -307,14 +310,8 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
     for (size_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const size_t b0 = blk * UP_RB;
 #pragma unroll
-        for (int q = 0; q < UP_PF; ++q) {
-            const int e = tid + q * 256;
-            if (e < nel) {
-                int r, c;
-                slab_elem(e, UP_RB, mb, V32 != nullptr, &c, &r);
-                slab[c * UP_RBP + r] = widen(pf[q], V32 && col_is_f32(c, mb));
-            }
-        }
+        for (int q = 0; q < UP_PF; ++q)
+            if ((okm >> q) & 1u) slab[scol[q] * UP_RBP + srow] = widen(pf[q], (f32m >> q) & 1u);
         __syncthreads();
         prefetch(blk + gridDim.x);
         d4 acc[MJ][3];
@@ -346,10 +343,12 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                     const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
                     const double2 v = mk<double2>(t1 - t2, t3 - t1 - t2);
                     if (pass == 0) {
-                        // P' (AP'): into this wave's rows of the W (AW) columns of the
-                        // slab, which pass 0 has finished reading and the other strip
-                        // never touches; stored row-contiguously with X' below
-                        if (j < mb) slab[(chain * K + mb + j) * UP_RBP + rl] = v;
+                        // P' (AP') of an active band: into this wave's rows of that
+                        // band's W (AW) column of the slab, which pass 0 has finished
+                        // reading and the other strip never touches; stored
+                        // row-contiguously with X' below
+                        const int t = (j < mb) ? bm.tpos[j] : -1;
+                        if (t >= 0) slab[(chain * K + mb + t) * UP_RBP + rl] = v;
                     } else {
                         xo[(chain * MP + j) * UP_RBP + rl] = v;
                     }
@@ -367,21 +366,29 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                     const double2 x = xo[j * UP_RBP + rrow];
                     const double2 ax = xo[(MP + j) * UP_RBP + rrow];
                     const double2 res = mk<double2>(ax.x - th[c] * x.x, ax.y - th[c] * x.y);
-                    const double2 pn = slab[(mb + j) * UP_RBP + rrow];
-                    const double2 apn = slab[(K + mb + j) * UP_RBP + rrow];
                     U[(size_t)j * ld + row] = x;
                     U[(size_t)(3 * mb + j) * ld + row] = ax;
+                    if (U32) U32[(size_t)(mb + j) * ld + row] = make_float2((float)res.x, (float)res.y);
+                    else U[(size_t)(mb + j) * ld + row] = res;
+                    nr[c] += cabs2(res);
+                    nx[c] += cabs2(x);
+                }
+            }
+            // P', AP' of the active bands (same thread mapping over the na staged columns)
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) {
+                const int t = jg + 8 * c;
+                if (t < bm.na) {
+                    const int j = bm.act[t];
+                    const double2 pn = slab[(mb + t) * UP_RBP + rrow];
+                    const double2 apn = slab[(K + mb + t) * UP_RBP + rrow];
                     if (U32) {
-                        U32[(size_t)(mb + j) * ld + row] = make_float2((float)res.x, (float)res.y);
                         U32[(size_t)(2 * mb + j) * ld + row] = make_float2((float)pn.x, (float)pn.y);
                         U32[(size_t)(5 * mb + j) * ld + row] = make_float2((float)apn.x, (float)apn.y);
                     } else {
-                        U[(size_t)(mb + j) * ld + row] = res;
                         U[(size_t)(2 * mb + j) * ld + row] = pn;
                         U[(size_t)(5 * mb + j) * ld + row] = apn;
                     }
-                    nr[c] += cabs2(res);
-                    nx[c] += cabs2(x);
                 }
             }
         }
@@ -409,10 +416,11 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
 }
 
 template <int MJ>
-static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n, int mb,
-                            const void* C, const double* theta, int nparts, double* npart, hipStream_t s) {
+static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
+                            const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
+                            hipStream_t s) {
     constexpr int MP = 16 * MJ;
-    const int K = 3 * mb;
+    const int K = bm.K;
     const int KP = (K + 3) / 4 * 4;
     if (UP_RB * 2 * K > UP_PF * 256) return hipErrorInvalidValue;
     const size_t lds = ((size_t)KP * MP + (size_t)UP_RBP * 2 * K + 2 * UP_RBP * MP) * sizeof(double2) +
@@ -421,16 +429,17 @@ static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, 
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nparts), dim3(256), lds, s, (const double2*)V, (const float2*)V32, (double2*)U,
-                       (float2*)U32, ld, n, mb, (const double2*)C, theta, npart);
+                       (float2*)U32, ld, n, bm, (const double2*)C, theta, npart);
     return hipGetLastError();
 }
 
-hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n, int mb,
-                              const void* C, const double* theta, int nparts, double* npart, double* norms,
-                              hipStream_t s) {
+hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
+                              const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
+                              double* norms, hipStream_t s) {
+    const int mb = bm.mb;
     hipError_t e;
-    if (mb <= 16) e = update_mj<1>(V, V32, U, U32, ld, n, mb, C, theta, nparts, npart, s);
-    else if (mb <= 32) e = update_mj<2>(V, V32, U, U32, ld, n, mb, C, theta, nparts, npart, s);
+    if (mb <= 16) e = update_mj<1>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s);
+    else if (mb <= 32) e = update_mj<2>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s);
     else return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
     return launch_reduce(npart, nparts, 2 * mb, norms, s);

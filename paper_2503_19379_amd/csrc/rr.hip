@@ -38,8 +38,9 @@ struct Rot {
 __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
     extern __shared__ unsigned char smem_raw[];
     const int mb = a.mb;
-    const int K = 3 * mb;
-    const int Q = 6 * mb;
+    const int K = a.K;
+    const int Q = 2 * K;
+    const int pbeg = mb + a.nw;           // first P column of the basis
     __shared__ int idx[RR_KMAX];        // compact index -> basis column
     __shared__ double dsc[RR_KMAX];
     __shared__ int dropped[RR_KMAX];
@@ -52,29 +53,14 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
     long long tstamp[6];
     tstamp[0] = wall_clock64();
 
-    // 1. kept columns (compacted in basis order X, W, P)
+    // 1. kept columns: the basis holds only the W and P columns of unconverged
+    //    bands (soft locking is done by the caller); zero columns are left out
     if (tid == 0) {
-        int kk = 0, act = 0;
-        for (int j = 0; j < K; ++j) {
-            int keep = 1;
-            if (j >= mb) {
-                if (a.first) keep = 0;
-                else {
-                    const int b = (j < 2 * mb) ? j - mb : j - 2 * mb;
-                    const double res = sqrt(a.norms[b]) / (fabs(a.theta[b]) * sqrt(a.norms[mb + b]));
-                    keep = res > a.tol;
-                }
-            }
-            if (!(a.G[j * Q + j].x > 0.0)) keep = 0;
-            if (keep) idx[kk++] = j;
-        }
-        if (!a.first)
-            for (int b = 0; b < mb; ++b) {
-                const double res = sqrt(a.norms[b]) / (fabs(a.theta[b]) * sqrt(a.norms[mb + b]));
-                act += res > a.tol;
-            }
+        int kk = 0;
+        for (int j = 0; j < K; ++j)
+            if (a.G[j * Q + j].x > 0.0) idx[kk++] = j;
         Kk_s = kk;
-        active_s = act;
+        active_s = a.nw;
         dropP = 0;
     }
     __syncthreads();
@@ -108,7 +94,7 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
     for (int j = 0; j < Kk; ++j) {
         if (tid == 0) {
             double rjj = 0.0;
-            const bool isP = idx[j] >= 2 * mb;
+            const bool isP = idx[j] >= pbeg;
             const double piv = A[j * KE + j].x;
             const double thr = isP ? a.drop_p : a.drop_w;
             if (!(piv > thr) || (isP && dropP)) {
@@ -141,7 +127,7 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
         __syncthreads();
     }
     // a restarted P drops every P column; isolate dropped columns
-    if (tid < Kk && dropP && idx[tid] >= 2 * mb) dropped[tid] = 1;
+    if (tid < Kk && dropP && idx[tid] >= pbeg) dropped[tid] = 1;
     __syncthreads();
     for (int e = tid; e < KE * KE; e += RR_NT) {
         const int i = e / KE, l = e % KE;
@@ -364,8 +350,8 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
 }
 
 hipError_t launch_rr(const RRArgs& a, hipStream_t s) {
-    const int K = 3 * a.mb;
-    if (K > RR_KMAX) return hipErrorInvalidValue;
+    const int K = a.K;
+    if (K > RR_KMAX || K < a.mb || a.nw < 0 || a.mb + a.nw > K) return hipErrorInvalidValue;
     const int KE = K + (K & 1);
     const size_t lds = (size_t)2 * KE * KE * sizeof(C128);
     hipError_t e = hipFuncSetAttribute((const void*)rr_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

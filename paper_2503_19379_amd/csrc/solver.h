@@ -13,17 +13,32 @@ hipError_t launch_gram(const void* V, size_t ld, size_t n, int P, int Q, int npa
 int gram_parts(size_t n);
 hipError_t launch_update(const void* V, void* U, size_t ld, size_t n, int mb, const void* C, const double* theta,
                          int nparts, double* npart, double* norms, hipStream_t s);
-// MFMA (FP64 matrix core) versions: Gram of K = 3mb basis columns against
+// The basis of one Rayleigh-Ritz step: X (mb columns), the W columns of the
+// na unconverged bands and the np P columns still valid for them, K = mb + na
+// + np, with the images AX, AW, AP at basis columns K..2K.  V holds
+// [X | W | P | AX | AW | AP], mb columns each, in band order.
+struct BasisMap {
+    int mb, K, na;
+    short lc[128];             // load ordinal -> basis column (FP64 columns first in mixed precision)
+    short pc[128];             // load ordinal -> column of V
+    signed char tpos[32];      // band -> its W column among the na (-1: converged)
+    unsigned char act[32];     // W column t -> band
+};
+
+// MFMA (FP64 matrix core) versions: Gram of the K basis columns against
 // [S | AS] (Hermitian halves only), and the block update (gemm.hip).
 // V32 (or null): FP32 storage of the W, P, AW, AP columns (mixed precision).
-hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, int K, int nparts, void* part,
-                            void* G, hipStream_t s);
+hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nparts,
+                            void* part, void* G, hipStream_t s);
 int gram_mfma_parts(size_t n);
 size_t gram_mfma_part_elems(int K, int nparts);
-// U32 (or null): FP32 outputs R', P', AP' (mixed precision).
-hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n, int mb,
-                              const void* C, const double* theta, int nparts, double* npart, double* norms,
-                              hipStream_t s);
+// U = [X' | R' | P' | AX' | - | AP'] from the K x mb coefficients C: X', AX'
+// and R' for every band, P' and AP' for the na active bands (their columns of
+// the other bands are left as they are).  U32 (or null): FP32 outputs R', P',
+// AP' (mixed precision).
+hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
+                              const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
+                              double* norms, hipStream_t s);
 // R = AX - X theta written to W (FP32 if R32), column norms |R|^2, |X|^2 (blas.hip).
 hipError_t launch_residual(const void* X, const void* AX, void* R, bool r32, size_t ld, size_t n, int mb,
                            const double* theta, int nparts, double* npart, double* norms, hipStream_t s);
@@ -32,23 +47,20 @@ hipError_t launch_colstats(const void* X, const void* Y, size_t ld, size_t n, in
 hipError_t launch_fill_random(void* X, size_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_convert(const void* X, void* Y, size_t count, bool to_c64, hipStream_t s);
 
-// Rayleigh-Ritz on span[X, W, P] (rr.hip).
-//   G:      3mb x 6mb row-major c128, [S^H S | S^H A S]
-//   norms:  2mb doubles: |R_j|^2 then |X_j|^2 from the last update
-//   theta:  mb doubles, current Ritz values (in) and the new ones (out)
-//   C:      3mb x mb row-major c128 coefficients (out)
+// Rayleigh-Ritz on span[X, W, P] (rr.hip) for a basis of K = mb + nw + np
+// columns: X (mb), then the nw W columns and the np P columns of the
+// unconverged bands.
+//   G:      K x 2K row-major c128, [S^H S | S^H A S]
+//   theta:  mb doubles, the new Ritz values (out)
+//   C:      K x mb row-major c128 coefficients (out)
 //   info:   ints (out): [0] = columns kept, [1] = 1 if P was restarted,
-//           [2] = active bands, [3] = Jacobi sweeps
-//   first:  1 on the initial step (basis = X only)
+//           [2] = active bands (nw), [3] = Jacobi sweeps, [4..8] phase ticks, [9] = kept
 struct RRArgs {
     const double2* G;
-    const double* norms;
     double* theta;
     double2* C;
     int* info;
-    int mb;
-    int first;
-    double tol;
+    int mb, K, nw;
     double drop_w, drop_p;
 };
 hipError_t launch_rr(const RRArgs& a, hipStream_t s);
