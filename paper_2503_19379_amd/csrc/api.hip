@@ -412,16 +412,19 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             if (std::find(act_prev.begin(), act_prev.end(), b) != act_prev.end()) pact.push_back(b);
         BasisMap bm = make_basis(mb, act, pact, mixed);
         const int na = (int)act.size(), np = (int)pact.size();
-        if (it > 0) {
-            // W = T R (in place), AW = op(W)
+        if (it > 0 && na > 0) {
+            // W = T R (in place), AW = op(W), for the active bands' columns
+            FieldList fl;
+            fl.on = 1;
+            for (int t = 0; t < na; ++t) fl.idx[t] = (unsigned char)act[t];
             hipEvent_t e0 = w.prof.begin(s);
-            if (mixed) HIPCHK(launch_precond<float>(p, mb, V32 + n * mb, V32 + n * mb, c->tw32, s));
-            else HIPCHK(launch_precond<double>(p, mb, col(V, n, mb), col(V, n, mb), c->tw64, s));
-            w.prof.end(e0, 1, N3 * 3 * rb * 2.0 * mb, s);
+            if (mixed) HIPCHK(launch_precond<float>(p, na, V32 + n * mb, V32 + n * mb, c->tw32, s, fl));
+            else HIPCHK(launch_precond<double>(p, na, col(V, n, mb), col(V, n, mb), c->tw64, s, fl));
+            w.prof.end(e0, 1, N3 * 3 * rb * 2.0 * na, s);
             e0 = w.prof.begin(s);
-            if (mixed) HIPCHK(launch_stencil_f64_s32(p, mb, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s));
-            else HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
-            w.prof.end(e0, 0, N3 * (6.0 * rb * mb + 24.0), s);
+            if (mixed) HIPCHK(launch_stencil_f64_s32(p, na, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s, fl));
+            else HIPCHK(launch_stencil<double>(p, na, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s, fl));
+            w.prof.end(e0, 0, N3 * (6.0 * rb * na + 24.0), s);
         }
         hipEvent_t e1 = w.prof.begin(s);
         HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s));

@@ -151,14 +151,14 @@ constexpr int plane_nt(int N) {
 // Kernels 1 and 3: 2-D DFT along x and y of one N x N plane per workgroup.
 template <class R, int N, bool INV>
 __global__ __launch_bounds__(plane_nt(N)) void fft_plane_kernel(const cplx<R>* in, cplx<R>* out,
-                                                                const cplx<R>* tw_g) {
+                                                                const cplx<R>* tw_g, FieldList fl) {
     using T = cplx<R>;
     constexpr int NT = plane_nt(N);
     extern __shared__ unsigned char smem_raw[];
     T* buf = reinterpret_cast<T*>(smem_raw);
     T* tw = buf + N * N;
     const int tid = threadIdx.x;
-    const size_t plane = blockIdx.x;
+    const size_t plane = (size_t)fl(blockIdx.x / (3 * N)) * 3 * N + blockIdx.x % (3 * N);
     const T* src = in + plane * N * N;
     T* dst = out + plane * N * N;
     for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
@@ -180,6 +180,7 @@ struct SolveArgs {
     cplx<R>* out;
     const cplx<R>* tw;
     R inv_h, half_k[3], gm1, gamma, shift, scale;
+    FieldList fl;
 };
 
 // Kernel 2: DFT along z, 3 x 3 symbol solve, inverse DFT along z, for XC
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(FFT_NT) void fft_zsolve_kernel(SolveArgs<R> a) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int xc0 = (bid % NXC) * XC;
     const int y = (bid / NXC) % N;
-    const int band = bid / (NXC * N);
+    const int band = a.fl(bid / (NXC * N));
     const size_t NN = (size_t)N * N, N3 = NN * N;
     const T* src = a.in + (size_t)band * 3 * N3 + (size_t)y * N + xc0;
     T* dst = a.out + (size_t)band * 3 * N3 + (size_t)y * N + xc0;
@@ -258,7 +259,9 @@ static hipError_t zsolve_launch(const SolveArgs<R>& a, int nb, hipStream_t s) {
 }
 
 template <class R, int N>
-static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s) {
+static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s,
+                            const FieldList& fl) {
+    if (fl.on && nb > 32) return hipErrorInvalidValue;
     using T = cplx<R>;
     const size_t lds_plane = (size_t)(N * N + N) * sizeof(T);
     if (lds_plane > 160 * 1024) return hipErrorInvalidValue;
@@ -269,7 +272,8 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
     e = hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_plane);
     if (e != hipSuccess) return e;
     const int nplanes = nb * 3 * N;
-    hipLaunchKernelGGL(kf, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Rin, (T*)Tout, (const T*)tw);
+    hipLaunchKernelGGL(kf, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Rin, (T*)Tout, (const T*)tw,
+                       fl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     SolveArgs<R> a;
     a.in = (const T*)Tout;
@@ -281,6 +285,7 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
     a.gamma = (R)p.gamma;
     a.shift = (R)p.shift;
     a.scale = (R)(1.0 / ((double)N * N * N));
+    a.fl = fl;
     switch (pick_xc(N)) {
         case 16: if constexpr (N % 16 == 0) e = zsolve_launch<R, N, 16>(a, nb, s); break;
         case 8: if constexpr (N % 8 == 0) e = zsolve_launch<R, N, 8>(a, nb, s); break;
@@ -289,7 +294,8 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
         default: e = zsolve_launch<R, N, 1>(a, nb, s); break;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ki, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Tout, (T*)Tout, (const T*)tw);
+    hipLaunchKernelGGL(ki, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Tout, (T*)Tout, (const T*)tw,
+                       fl);
     return hipGetLastError();
 }
 
@@ -305,16 +311,19 @@ bool fft_supported(int N, int real_bytes) {
 }
 
 template <class R>
-hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s) {
+hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s,
+                          const FieldList& fl) {
     switch (p.N) {
-#define CASE(n) case n: return precond_n<R, n>(p, nb, Rin, Tout, tw, s);
+#define CASE(n) case n: return precond_n<R, n>(p, nb, Rin, Tout, tw, s, fl);
         MFD_FFT_SIZES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_precond<float>(const OpParams&, int, const void*, void*, const void*, hipStream_t);
-template hipError_t launch_precond<double>(const OpParams&, int, const void*, void*, const void*, hipStream_t);
+template hipError_t launch_precond<float>(const OpParams&, int, const void*, void*, const void*, hipStream_t,
+                                          const FieldList&);
+template hipError_t launch_precond<double>(const OpParams&, int, const void*, void*, const void*, hipStream_t,
+                                           const FieldList&);
 
 }  // namespace mfd

@@ -12,18 +12,28 @@ struct OpParams {
     double gamma, shift;
 };
 
+// Which fields of a block a launch processes: field b of the launch is field
+// idx[b] of the block when a list is given (at most 32), else field b.
+struct FieldList {
+    unsigned char idx[32];
+    int on = 0;
+    __host__ __device__ int operator()(int b) const { return on ? idx[b] : b; }
+};
+
 // Y = (A M_0 A' + gamma B'B + shift I) X for nb fields (stencil.hip).
 template <class R>
-hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s);
+hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
+                          const FieldList& fl = FieldList());
 
 // Same operator with FP64 arithmetic on FP32-stored fields (c64 in, c64 out).
 hipError_t launch_stencil_f64_s32(const OpParams& p, int nb, const void* X, void* Y, const void* mu64,
-                                  hipStream_t s);
+                                  hipStream_t s, const FieldList& fl = FieldList());
 
 // T = (P + shift I)^-1 R for nb fields via FFT (fft.hip).  tw: device table
 // exp(-2 pi i j / N), j < N, of precision R.
 template <class R>
-hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s);
+hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s,
+                          const FieldList& fl = FieldList());
 bool fft_supported(int N, int real_bytes);
 
 // out[b] = sum mu |A' x_b|^2 and out[nb + b] = sum |x_b|^2, c128 fields (blas.hip).

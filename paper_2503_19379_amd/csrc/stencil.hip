@@ -34,6 +34,7 @@ struct StencilArgs {
     cplx<S>* Y;
     const R* mu;          // [3][N][N][N]
     int N, nyt, nzc, zc, nb;
+    FieldList fl;
     cplx<R> cp[3], cm[3];
     R gamma, shift;
 };
@@ -65,8 +66,8 @@ __global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R, S> a) {
     const int z1 = z0 + a.zc;
     const size_t NN = (size_t)N * N;
     const size_t N3 = NN * N;
-    const TS* Xb = a.X + (size_t)band * 3 * N3;
-    TS* Yb = a.Y + (size_t)band * 3 * N3;
+    const TS* Xb = a.X + (size_t)a.fl(band) * 3 * N3;
+    TS* Yb = a.Y + (size_t)a.fl(band) * 3 * N3;
 
     const int txp = (tx + 1 == N) ? 0 : tx + 1;
     const int txm = (tx == 0) ? N - 1 : tx - 1;
@@ -208,8 +209,11 @@ static hipError_t launch_ty(const StencilArgs<R, S>& a, hipStream_t s) {
 }
 
 template <class R, class S>
-hipError_t launch_stencil_rs(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s) {
+hipError_t launch_stencil_rs(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
+                             const FieldList& fl) {
+    if (fl.on && nb > 32) return hipErrorInvalidValue;
     StencilArgs<R, S> a;
+    a.fl = fl;
     a.X = (const cplx<S>*)X;
     a.Y = (cplx<S>*)Y;
     a.mu = (const R*)mu;
@@ -240,16 +244,19 @@ hipError_t launch_stencil_rs(const OpParams& p, int nb, const void* X, void* Y, 
 }
 
 template <class R>
-hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s) {
-    return launch_stencil_rs<R, R>(p, nb, X, Y, mu, s);
+hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
+                          const FieldList& fl) {
+    return launch_stencil_rs<R, R>(p, nb, X, Y, mu, s, fl);
 }
 
 hipError_t launch_stencil_f64_s32(const OpParams& p, int nb, const void* X, void* Y, const void* mu64,
-                                  hipStream_t s) {
-    return launch_stencil_rs<double, float>(p, nb, X, Y, mu64, s);
+                                  hipStream_t s, const FieldList& fl) {
+    return launch_stencil_rs<double, float>(p, nb, X, Y, mu64, s, fl);
 }
 
-template hipError_t launch_stencil<float>(const OpParams&, int, const void*, void*, const void*, hipStream_t);
-template hipError_t launch_stencil<double>(const OpParams&, int, const void*, void*, const void*, hipStream_t);
+template hipError_t launch_stencil<float>(const OpParams&, int, const void*, void*, const void*, hipStream_t,
+                                          const FieldList&);
+template hipError_t launch_stencil<double>(const OpParams&, int, const void*, void*, const void*, hipStream_t,
+                                           const FieldList&);
 
 }  // namespace mfd
