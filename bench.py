@@ -4,12 +4,15 @@
 Metric: k-point band solves per second on the diamond-lattice workload
 (conventional cubic cell, 8 spheres r = 0.13, eps 13 in 1, N = 64, i.e.
 786,432 complex unknowns), 16 bands, relative residual 1e-8, 64 k-points along
-Gamma-X-M-Gamma-R.  One step = one mfd_bands call over the whole k-path (warm
-start from the previous k-point along the path, random start at the first).
-A k-point counts when every band's residual, recomputed with the FP64
-operator, is <= 1e-8.
+Gamma-X-M-Gamma-R, in mixed precision (FP32 corrections, FP64 refinement).
+One step = one mfd_bands call over the whole k-path, cut into concurrently
+solved segments (random start at a segment's first k-point, warm start from
+the previous k-point after it).  A k-point counts when every band's residual,
+recomputed with the FP64 operator, is <= 1e-8.
 
 Also reported (same JSON line):
+  variants      - one timed step each of the plain FP64 solve and of the
+                  learned warm start, on the same GPU;
   roofline      - the dominant kernel's achieved rate against its MI355X peak,
                   from HIP events recorded inside the library on the solve's
                   stream during the timed steps;
@@ -39,11 +42,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="diamond_n64")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"],
+                    help="mixed: FP32 corrections with FP64 refinement, the workload's own precision")
     ap.add_argument("--nk", type=int, default=0, help="k-points per step (0: the workload's path)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--guard", type=int, default=2)
-    ap.add_argument("--streams", type=int, default=4, help="k-path segments solved concurrently")
+    ap.add_argument("--streams", type=int, default=8, help="k-path segments solved concurrently")
+    ap.add_argument("--warm", default="prev", choices=["prev", "learned"],
+                    help="start block after a segment's first k-point: previous k, or the learned proposal")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the one-step comparison runs (FP64 solve, learned warm start)")
     ap.add_argument("--roofline-nk", type=int, default=6, help="k-points of the single-stream timing pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
@@ -82,6 +90,35 @@ def measured_traffic(workload, precision):
         if fields.get("source_sha256") == digest and "traffic_bytes_per_launch" in fields:
             out[cat] = float(fields["traffic_bytes_per_launch"])
     return out
+
+
+def batch_variant(B, args, torch, count):
+    """Many crystals of uneven grids in one mfd_bands_batch call: 32 seeded
+    random-field crystals (N = 24, 32, 48, 64 in turn), 8 k-points on
+    Gamma-X-M-Gamma-R and 12 bands each, mixed precision, crystals handed to
+    the workers in a queue.  One timed call after an untimed one that sizes
+    every crystal's workspace."""
+    from paper_2503_19379_amd import workloads
+    cfg = workloads.CONFIGS["random_batch"]
+    crystals = workloads.random_batch_crystals(cfg["ncrys"], cfg["Ns"])
+    ctxs = [B.mfd_build(N, 1.0, 2, eps) for N, eps in crystals]
+    kp = workloads.kpath(cfg["path"], cfg["nk"])
+    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=args.guard, max_iter=500, streams=args.streams)
+    B.mfd_bands_batch(ctxs, [kp[:1]] * len(ctxs), cfg["nbands"], cfg["tol"], o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs, sts, status = B.mfd_bands_batch(ctxs, [kp] * len(ctxs), cfg["nbands"], cfg["tol"], o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok, iters, maxres = count([(None, st, status) for st in sts])
+    for c in ctxs:
+        c.close()
+    return {"value": ok / dt, "unit": "k-points/s", "steps": 1, "ms_per_step": dt * 1e3,
+            "iters_per_k": float(np.mean(iters)), "converged_kpoints": ok, "total_kpoints": len(iters),
+            "max_rel_resid": maxres, "precision": "mixed", "warm_start": "prev",
+            "workload": f"{cfg['ncrys']} random-field crystals (correlation length 0.15, 30% eps 13 in 1), "
+                        f"N in {cfg['Ns']}, {cfg['nk']} k-points on {cfg['path']}, {cfg['nbands']} bands, "
+                        f"tol {cfg['tol']:g}"}
 
 
 def cpu_baseline(eps, L, k, m, iters, gpu_iters_per_k):
@@ -135,11 +172,24 @@ def main():
     kpts = workloads.kpath(cfg["path"], cfg["nk"])[:nk]
     torch.cuda.set_device(0)
     ctx = B.mfd_build(N, L, 2, eps)
-    opts = B.default_opts(precision=1 if args.precision == "mixed" else 0, warm_start=1, seed=0,
-                          guard=args.guard, max_iter=500, streams=args.streams)
+    def make_opts(precision, warm):
+        return B.default_opts(precision=1 if precision == "mixed" else 0, warm_start=2 if warm == "learned" else 1,
+                              seed=0, guard=args.guard, max_iter=500, streams=args.streams)
 
-    def step():
-        return B.mfd_bands(ctx, kpts, m, args.tol, opts)
+    opts = make_opts(args.precision, args.warm)
+
+    def step(o=opts):
+        return B.mfd_bands(ctx, kpts, m, args.tol, o)
+
+    def count(results):
+        ok, iters, maxres = 0, [], 0.0
+        for ev, st, status in results:
+            for s in st:
+                iters.append(s["iters"])
+                maxres = max(maxres, s["max_rel_resid"])
+                if s["max_rel_resid"] <= args.tol and s["spurious"] == 0:
+                    ok += 1
+        return ok, iters, maxres
 
     if args.profile_only:
         step()
@@ -179,16 +229,28 @@ def main():
                 print(f"k{i:3d} {np.array2string(kpts[i], precision=3)} iters={s['iters']:4d} "
                       f"res={s['max_rel_resid']:.2e} dbl={s['gamma_doublings']} spur={s['spurious']} "
                       f"ms={s['ms']:.1f} ev0={ev[i][0]:.6f} ev15={ev[i][-1]:.6f}", file=sys.stderr)
-    ok = 0
-    iters = []
-    maxres = 0.0
-    for ev, st, status in results:
-        for s in st:
-            iters.append(s["iters"])
-            maxres = max(maxres, s["max_rel_resid"])
-            if s["max_rel_resid"] <= args.tol and s["spurious"] == 0:
-                ok += 1
+    ok, iters, maxres = count(results)
     value = ok / dt
+
+    # One-step comparison runs on the same GPU: the plain FP64 solve, and the
+    # learned warm start (each after an untimed call that sizes its workspaces).
+    variants = {}
+    if not args.no_variants:
+        for name, prec, warm in (("fp64_prev", "fp64", "prev"), ("mixed_learned", "mixed", "learned")):
+            if (prec, warm) == (args.precision, args.warm):
+                continue
+            o = make_opts(prec, warm)
+            B.mfd_bands(ctx, kpts[:min(nk, args.streams)], m, args.tol, o)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = step(o)
+            torch.cuda.synchronize()
+            d1 = time.perf_counter() - t1
+            vok, vit, vres = count([r])
+            variants[name] = {"value": vok / d1, "unit": "k-points/s", "steps": 1, "ms_per_step": d1 * 1e3,
+                              "iters_per_k": float(np.mean(vit)), "converged_kpoints": vok,
+                              "max_rel_resid": vres, "precision": prec, "warm_start": warm}
+        variants["random_batch"] = batch_variant(B, args, torch, count)
     n = 3 * N ** 3
 
     mb = m + args.guard
@@ -237,9 +299,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: diamond cell, 8 spheres r=0.13a eps 13/1, N={N} "
                                f"({n} unknowns), {nk} k-points on {cfg['path']}, {m} bands, tol {args.tol:g}, "
-                               f"{args.precision}",
+                               f"{args.precision}, {args.streams} concurrent k-path segments",
                    "N": N, "nbands": m, "nk": nk, "tol": args.tol, "precision": args.precision,
-                   "guard": args.guard, "streams": args.streams},
+                   "warm_start": args.warm, "guard": args.guard, "streams": args.streams},
         "roofline_source": "HIP events recorded around each launch on its own stream during the timed steps "
                            "(concurrent k-path segments overlap); kernels_isolated: the same from a "
                            f"single-stream pass over {min(args.roofline_nk, nk)} k-points after the timed steps",
@@ -251,6 +313,7 @@ def main():
         "max_rel_resid": maxres,
         "converged_kpoints": ok,
         "total_kpoints": len(iters),
+        "variants": variants,
     }
     if not args.no_cpu_baseline:
         kidx = min(16, len(kpts) - 1)
