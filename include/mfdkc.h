@@ -100,8 +100,8 @@ typedef struct {
                                  history blocks) or because the proposal's Ritz-value sum was not
                                  below the previous-k block's */
     int fp64_fallback;        /* precision 1 only: the FP32-stored directions stalled (no halving
-                                 of the residual in 40 iterations) and the k-point was finished
-                                 in FP64 from the current block */
+                                 of the residual in stall_window iterations) and the k-point was
+                                 finished in FP64 from the current block */
     float ms;                 /* wall time of this k-point */
 } mfd_kstats;
 
@@ -110,7 +110,11 @@ void mfd_default_opts(mfd_opts* opts);
 /* Build a context for one crystal (Section 4.4: M_0 from eps).
  * N: cells per axis, 4 <= N <= 128, with an FFT plan for N (N = 2^a 3^b 5^c
  *    supported by this build: see mfd_supported_n).
- * L: cell side (> 0).  order: stencil order 2 (Table FD_1D, k = 1).
+ * L: cell side (> 0).  order: stencil order 2, 4, 6 or 8 (Section 4.1.3,
+ *    eq. (2kfdm), Table FD_1D with k = order / 2; the sixth-order c_1 is read as
+ *    75/64, the value the stencil's consistency requires).  Order 2 uses the
+ *    fused single-pass stencil; higher orders use a two-pass operator with a
+ *    scratch buffer owned by the context (and one per band-solve workspace).
  * eps_cells: host, N^3 doubles, [z][y][x], finite and > 0 (cell permittivity).
  * Errors: MFD_EINVAL, MFD_EUNSUPPORTED, MFD_ENOMEM, MFD_EDEVICE. */
 int mfd_build(int N, double L, int order, const double* eps_cells, void* stream, mfd_ctx** out);

@@ -119,6 +119,7 @@ struct Ws {
     double* host = nullptr;    // pinned: theta | norms | info | column sums
     int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
     WarmStart* warm = nullptr; // learned warm start (warm_start = 2), allocated on first use
+    void* wtmp = nullptr;      // orders > 2: operator scratch of this workspace's stream
     Prof prof;
 };
 
@@ -127,6 +128,8 @@ struct mfd_ctx {
     double L = 1.0, h = 1.0;
     int order = 2;
     int device = 0;
+    void* wtmp = nullptr;      // orders > 2: operator scratch for the ABI calls
+    int wtmp_bands = 0;
     double gamma_override = 0.0;
     double* mu64 = nullptr;
     float* mu32 = nullptr;
@@ -183,7 +186,17 @@ OpParams params(const mfd_ctx* ctx, const double k[3]) {
         p.gamma = 2.0 * std::max(a, b);
     }
     p.shift = (kn < kball) ? std::pow(M_PI / ctx->L, 2) : 0.0;
+    p.order = ctx->order;
+    p.wtmp = ctx->wtmp;
+    p.wtmp_bands = ctx->wtmp_bands;
     return p;
+}
+
+// Bands of scratch for the two-pass higher-order operator: 4 FP64 complex
+// fields per band, at most 8 bands (or 256 MB) per pass.
+int wide_bands(int N) {
+    const size_t per = 4 * (size_t)N * N * N * sizeof(double2);
+    return (int)std::max<size_t>(1, std::min<size_t>(8, (256u << 20) / per));
 }
 
 bool finite3(const double* k) { return std::isfinite(k[0]) && std::isfinite(k[1]) && std::isfinite(k[2]); }
@@ -193,7 +206,7 @@ void ws_free(Ws* w) {
     hipFree(w->V); hipFree(w->U); hipFree(w->gpart); hipFree(w->G); hipFree(w->C);
     hipFree(w->V32); hipFree(w->U32);
     hipFree(w->npart); hipFree(w->norms); hipFree(w->theta); hipFree(w->info);
-    hipFree(w->cpart); hipFree(w->cout);
+    hipFree(w->cpart); hipFree(w->cout); hipFree(w->wtmp);
     if (w->host) hipHostFree(w->host);
     if (w->warm) {
         w->warm->release();
@@ -228,7 +241,8 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
           chk(hipMalloc(&w->cout, 2 * mb * sizeof(double))) &&
           chk(hipHostMalloc(&w->host, (8 * mb + 32) * sizeof(double), hipHostMallocDefault)) &&
           (!mixed || (chk(hipMalloc(&w->V32, n * 6 * mb * sizeof(float2))) &&
-                      chk(hipMalloc(&w->U32, n * 6 * mb * sizeof(float2))))))) {
+                      chk(hipMalloc(&w->U32, n * 6 * mb * sizeof(float2))))) &&
+          (c->order == 2 || chk(hipMalloc(&w->wtmp, (size_t)c->wtmp_bands * 4 * (n / 3) * sizeof(double2)))))) {
         ws_free(w);
         return fail(e == hipErrorOutOfMemory ? MFD_ENOMEM : MFD_EDEVICE, hipGetErrorString(e));
     }
@@ -577,6 +591,7 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
     hipStream_t s = w.stream;
     auto t0 = std::chrono::steady_clock::now();
     OpParams p = params(c, k);
+    p.wtmp = w.wtmp;
     const double scale = std::pow(2.0 * M_PI / c->L, 2);
     KResult kr;
     int doublings = 0, total_iters = 0, nspur = 0, discarded = 0, fp64_fallback = 0;
@@ -809,7 +824,8 @@ int mfd_build(int N, double L, int order, const double* eps_cells, void* stream,
     if (!eps_cells) return fail(MFD_EINVAL, "eps_cells is NULL");
     if (N < 4 || N > 128) return fail(MFD_EINVAL, "N must be in [4, 128]");
     if (!(L > 0.0) || !std::isfinite(L)) return fail(MFD_EINVAL, "L must be finite and > 0");
-    if (order != 2) return fail(MFD_EUNSUPPORTED, "only stencil order 2 is built");
+    if (order != 2 && order != 4 && order != 6 && order != 8)
+        return fail(MFD_EUNSUPPORTED, "stencil order must be 2, 4, 6 or 8");
     if (!mfd_supported_n(N)) return fail(MFD_EUNSUPPORTED, "no FFT plan for this N");
     const size_t N3 = (size_t)N * N * N;
     for (size_t i = 0; i < N3; ++i)
@@ -830,7 +846,9 @@ int mfd_build(int N, double L, int order, const double* eps_cells, void* stream,
         return st;
     };
     hipError_t e;
-    if ((e = hipMalloc(&c->mu64, 3 * N3 * sizeof(double))) != hipSuccess ||
+    if (order > 2) c->wtmp_bands = wide_bands(N);
+    if ((order > 2 && (e = hipMalloc(&c->wtmp, (size_t)c->wtmp_bands * 4 * N3 * sizeof(double2))) != hipSuccess) ||
+        (e = hipMalloc(&c->mu64, 3 * N3 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->mu32, 3 * N3 * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&c->tw64, N * sizeof(double2))) != hipSuccess ||
         (e = hipMalloc(&c->tw32, N * sizeof(float2))) != hipSuccess ||
@@ -1058,6 +1076,7 @@ void mfd_destroy(mfd_ctx* ctx) {
     hipFree(ctx->mu32);
     hipFree(ctx->tw64);
     hipFree(ctx->tw32);
+    hipFree(ctx->wtmp);
     delete ctx;
 }
 

@@ -319,23 +319,40 @@ hipError_t launch_residual(const void* X, const void* AX, void* R, bool r32, siz
 // ---------------------------------------------------------------------------
 // Alg 4.1, step 2: |M_0^(1/2) A' x|^2 per field, and |x|^2.
 // ---------------------------------------------------------------------------
+struct LamCoef {
+    int K;
+    double c[4], d[4];   // c divided by h
+    double alpha[3];
+};
+
+// (D_i' u)[r] = sum_s c_s (u[r-s] - u[r-1+s]) - i alpha_i sum_s d_s (u[r-s] + u[r-1+s]) along axis i
+__device__ __forceinline__ C128 lam_dadj(const LamCoef& w, const C128* u, int N, int x, int y, int z, int axis) {
+    C128 diff = mk<C128>(0, 0), avg = mk<C128>(0, 0);
+    for (int s = 1; s <= w.K; ++s) {
+        int xa = x, ya = y, za = z, xb = x, yb = y, zb = z;
+        if (axis == 0) { xa = (x - s + 4 * N) % N; xb = (x + s - 1) % N; }
+        else if (axis == 1) { ya = (y - s + 4 * N) % N; yb = (y + s - 1) % N; }
+        else { za = (z - s + 4 * N) % N; zb = (z + s - 1) % N; }
+        const C128 a = u[((size_t)za * N + ya) * N + xa], b = u[((size_t)zb * N + yb) * N + xb];
+        diff = cadd(diff, cscale(csub(a, b), w.c[s - 1]));
+        avg = cadd(avg, cscale(cadd(a, b), w.d[s - 1]));
+    }
+    const double al = w.alpha[axis];
+    return mk<C128>(diff.x + al * avg.y, diff.y - al * avg.x);
+}
+
 __global__ __launch_bounds__(256) void lambda_re_kernel(const C128* __restrict__ X, const double* __restrict__ mu,
-                                                        int N, C128 cp0, C128 cp1, C128 cp2, C128 cm0, C128 cm1,
-                                                        C128 cm2, int nb, double* __restrict__ part) {
+                                                        int N, LamCoef w, int nb, double* __restrict__ part) {
     const int band = blockIdx.y;
     const size_t NN = (size_t)N * N, N3 = NN * N;
     const C128* v = X + (size_t)band * 3 * N3;
     double a = 0.0, b = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < N3; i += (size_t)gridDim.x * 256) {
         const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / NN);
-        const size_t ixm = i - x + (x == 0 ? N - 1 : x - 1);
-        const size_t iym = i + ((y == 0 ? N - 1 : y - 1) - y) * (size_t)N;
-        const size_t izm = i + ((z == 0 ? N - 1 : z - 1) - z) * NN;
         const C128 v1 = v[i], v2 = v[N3 + i], v3 = v[2 * N3 + i];
-        // (D_i' u)[r] = u[r-1] conj(cp_i) + u[r] conj(cm_i)
-        C128 e1 = csub(cadd(cmulc(cp2, v[N3 + izm]), cmulc(cm2, v2)), cadd(cmulc(cp1, v[2 * N3 + iym]), cmulc(cm1, v3)));
-        C128 e2 = csub(cadd(cmulc(cp0, v[2 * N3 + ixm]), cmulc(cm0, v3)), cadd(cmulc(cp2, v[izm]), cmulc(cm2, v1)));
-        C128 e3 = csub(cadd(cmulc(cp1, v[iym]), cmulc(cm1, v1)), cadd(cmulc(cp0, v[N3 + ixm]), cmulc(cm0, v2)));
+        const C128 e1 = csub(lam_dadj(w, v + N3, N, x, y, z, 2), lam_dadj(w, v + 2 * N3, N, x, y, z, 1));
+        const C128 e2 = csub(lam_dadj(w, v + 2 * N3, N, x, y, z, 0), lam_dadj(w, v, N, x, y, z, 2));
+        const C128 e3 = csub(lam_dadj(w, v, N, x, y, z, 1), lam_dadj(w, v + N3, N, x, y, z, 0));
         a += mu[i] * cabs2(e1) + mu[N3 + i] * cabs2(e2) + mu[2 * N3 + i] * cabs2(e3);
         b += cabs2(v1) + cabs2(v2) + cabs2(v3);
     }
@@ -349,20 +366,24 @@ __global__ __launch_bounds__(256) void lambda_re_kernel(const C128* __restrict__
     __syncthreads();
     if (threadIdx.x < 2) {
         double s = 0.0;
-        for (int w = 0; w < 4; ++w) s += red[threadIdx.x][w];
+        for (int w2 = 0; w2 < 4; ++w2) s += red[threadIdx.x][w2];
         part[((size_t)blockIdx.x * nb + band) * 2 + threadIdx.x] = s;
     }
 }
 
 hipError_t launch_lambda_re(const OpParams& p, int nb, const void* X, const void* mu, double* partial, int nparts,
                             double* out, hipStream_t s) {
-    C128 cp[3], cm[3];
-    for (int i = 0; i < 3; ++i) {
-        cp[i] = mk<C128>(1.0 / p.h, 0.5 * p.k[i]);
-        cm[i] = mk<C128>(-1.0 / p.h, 0.5 * p.k[i]);
+    LamCoef w;
+    w.K = p.order / 2;
+    double c[4], d[4];
+    stencil_coefs(p.order, c, d);
+    for (int q = 0; q < 4; ++q) {
+        w.c[q] = c[q] / p.h;
+        w.d[q] = d[q];
     }
+    for (int i = 0; i < 3; ++i) w.alpha[i] = p.k[i];
     hipLaunchKernelGGL(lambda_re_kernel, dim3(nparts, nb), dim3(256), 0, s, (const C128*)X, (const double*)mu, p.N,
-                       cp[0], cp[1], cp[2], cm[0], cm[1], cm[2], nb, partial);
+                       w, nb, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_reduce(partial, nparts, 2 * nb, out, s);

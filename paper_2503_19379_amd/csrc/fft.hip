@@ -180,8 +180,30 @@ struct SolveArgs {
     cplx<R>* out;
     const cplx<R>* tw;
     R inv_h, half_k[3], gm1, gamma, shift, scale;
+    int K;             // stencil half-width (order 2K)
+    R c[4], d[4];      // Table FD_1D, c divided by h
+    R alpha[3];
     FieldList fl;
 };
+
+// Symbol of D_i at frequency p (theta = 2 pi p / N) for the 2K-point stencil:
+//   d(p) = sum_s c_s (e^{i s theta} - e^{i (1-s) theta}) + i alpha sum_s d_s (e^{i s theta} + e^{i (1-s) theta}),
+// with e^{i m theta} = conj(tw[m p mod N]).
+template <class R, int N>
+__device__ __forceinline__ cplx<R> symbol_2k(const cplx<R>* tw, int p, const SolveArgs<R>& a, int axis) {
+    using T = cplx<R>;
+    T diff = mk<T>(0, 0), avg = mk<T>(0, 0);
+    for (int s = 1; s <= a.K; ++s) {
+        T e1 = tw[(p * s) % N];
+        T e0 = tw[((p * (1 - s)) % N + N) % N];
+        e1.y = -e1.y;
+        e0.y = -e0.y;
+        diff = cadd(diff, cscale(csub(e1, e0), a.c[s - 1]));
+        avg = cadd(avg, cscale(cadd(e1, e0), a.d[s - 1]));
+    }
+    const R al = a.alpha[axis];
+    return mk<T>(diff.x - al * avg.y, diff.y + al * avg.x);
+}
 
 // Kernel 2: DFT along z, 3 x 3 symbol solve, inverse DFT along z, for XC
 // consecutive x positions of one y row of one band.
@@ -215,9 +237,16 @@ __global__ __launch_bounds__(FFT_NT) void fft_zsolve_kernel(SolveArgs<R> a) {
         // e^{i theta} = conj(tw[p])
         T ex = tw[px], ey = tw[y], ez = tw[pz];
         ex.y = -ex.y; ey.y = -ey.y; ez.y = -ez.y;
-        T d1 = mk<T>((ex.x - (R)1) * a.inv_h - a.half_k[0] * ex.y, ex.y * a.inv_h + a.half_k[0] * ((R)1 + ex.x));
-        T d2 = mk<T>((ey.x - (R)1) * a.inv_h - a.half_k[1] * ey.y, ey.y * a.inv_h + a.half_k[1] * ((R)1 + ey.x));
-        T d3 = mk<T>((ez.x - (R)1) * a.inv_h - a.half_k[2] * ez.y, ez.y * a.inv_h + a.half_k[2] * ((R)1 + ez.x));
+        T d1, d2, d3;
+        if (a.K == 1) {
+            d1 = mk<T>((ex.x - (R)1) * a.inv_h - a.half_k[0] * ex.y, ex.y * a.inv_h + a.half_k[0] * ((R)1 + ex.x));
+            d2 = mk<T>((ey.x - (R)1) * a.inv_h - a.half_k[1] * ey.y, ey.y * a.inv_h + a.half_k[1] * ((R)1 + ey.x));
+            d3 = mk<T>((ez.x - (R)1) * a.inv_h - a.half_k[2] * ez.y, ez.y * a.inv_h + a.half_k[2] * ((R)1 + ez.x));
+        } else {
+            d1 = symbol_2k<R, N>(tw, px, a, 0);
+            d2 = symbol_2k<R, N>(tw, y, a, 1);
+            d3 = symbol_2k<R, N>(tw, pz, a, 2);
+        }
         const R s = cabs2(d1) + cabs2(d2) + cabs2(d3);
         T r1 = buf[i], r2 = buf[N * XC + i], r3 = buf[2 * N * XC + i];
         T dr = cmul(d1, r1);
@@ -286,6 +315,16 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
     a.shift = (R)p.shift;
     a.scale = (R)(1.0 / ((double)N * N * N));
     a.fl = fl;
+    a.K = p.order / 2;
+    {
+        double c[4], d[4];
+        stencil_coefs(p.order, c, d);
+        for (int q = 0; q < 4; ++q) {
+            a.c[q] = (R)(c[q] / p.h);
+            a.d[q] = (R)d[q];
+        }
+        for (int i = 0; i < 3; ++i) a.alpha[i] = (R)p.k[i];
+    }
     switch (pick_xc(N)) {
         case 16: if constexpr (N % 16 == 0) e = zsolve_launch<R, N, 16>(a, nb, s); break;
         case 8: if constexpr (N % 8 == 0) e = zsolve_launch<R, N, 8>(a, nb, s); break;
@@ -299,7 +338,7 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
     return hipGetLastError();
 }
 
-#define MFD_FFT_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(100) X(120) X(128)
+#define MFD_FFT_SIZES(X) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(100) X(120) X(128)
 
 bool fft_supported(int N, int real_bytes) {
     switch (N) {

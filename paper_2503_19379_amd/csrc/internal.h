@@ -10,7 +10,13 @@ struct OpParams {
     double L, h;
     double k[3];
     double gamma, shift;
+    int order = 2;             // stencil order 2K (Table FD_1D)
+    void* wtmp = nullptr;      // orders > 2: scratch for wtmp_bands bands of 4 FP64 complex fields
+    int wtmp_bands = 0;
 };
+
+// Table FD_1D coefficients (c_s, d_s), s = 1..order/2, zero-padded to 4 (wide.hip).
+void stencil_coefs(int order, double c[4], double d[4]);
 
 // Which fields of a block a launch processes: field b of the launch is field
 // idx[b] of the block when a list is given (at most 32), else field b.
@@ -24,6 +30,12 @@ struct FieldList {
 template <class R>
 hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
                           const FieldList& fl = FieldList());
+
+// Orders > 2: the same operator in two passes through p.wtmp (wide.hip); R
+// arithmetic, S storage.
+template <class R, class S>
+hipError_t launch_wide(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
+                       const FieldList& fl);
 
 // Same operator with FP64 arithmetic on FP32-stored fields (c64 in, c64 out).
 hipError_t launch_stencil_f64_s32(const OpParams& p, int nb, const void* X, void* Y, const void* mu64,

@@ -1,0 +1,165 @@
+// Higher-order MFD operator (orders 2K = 4, 6, 8; Section 4.1.3, eq. (2kfdm),
+// Table FD_1D): the compensated operator w = A M_0 A' v + gamma B'B v + c v
+// with every one-dimensional difference and midpoint value replaced by its
+// 2K-point symmetric stencil.  Along axis i, periodic:
+//   (D_i u)[r]  = (1/h) sum_s c_s (u[r+s] - u[r+1-s]) + i alpha_i sum_s d_s (u[r+s] + u[r+1-s])
+//   (D_i' u)[r] = (1/h) sum_s c_s (u[r-s] - u[r-1+s]) - i alpha_i sum_s d_s (u[r-s] + u[r-1+s])
+// (D_i' is the adjoint of D_i), assembled as in eq. (discrete_2nd_block):
+//   e = A'v : e1 = D3'v2 - D2'v3, e2 = D1'v3 - D3'v1, e3 = D2'v1 - D1'v2;  e <- mu e
+//   q = B v = D1 v1 + D2 v2 + D3 v3
+//   w1 = D2 e3 - D3 e2, w2 = D3 e1 - D1 e3, w3 = D1 e2 - D2 e1;  w_i += gamma D_i' q;  w += c v.
+// Two passes over the block: pass 1 writes e and q of each band to a scratch
+// buffer, pass 2 forms w.  One thread per cell; neighbours along y and z come
+// through the caches.
+#include "common.h"
+#include "internal.h"
+
+namespace mfd {
+
+// Table FD_1D.  The table prints c_1 = 25/64 for K = 3; consistency of the
+// derivative stencil (sum_s (2s - 1) c_s = 1) requires 75/64.
+static const double kC[4][4] = {{1.0, 0, 0, 0},
+                                {9.0 / 8.0, -1.0 / 24.0, 0, 0},
+                                {75.0 / 64.0, -25.0 / 384.0, 3.0 / 640.0, 0},
+                                {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0}};
+static const double kD[4][4] = {{0.5, 0, 0, 0},
+                                {9.0 / 16.0, -1.0 / 16.0, 0, 0},
+                                {75.0 / 128.0, -25.0 / 256.0, 3.0 / 256.0, 0},
+                                {1225.0 / 2048.0, -245.0 / 2048.0, 49.0 / 2048.0, -5.0 / 2048.0}};
+
+void stencil_coefs(int order, double c[4], double d[4]) {
+    const int K = order / 2;
+    for (int s = 0; s < 4; ++s) {
+        c[s] = (K >= 1 && K <= 4) ? kC[K - 1][s] : 0.0;
+        d[s] = (K >= 1 && K <= 4) ? kD[K - 1][s] : 0.0;
+    }
+}
+
+template <class R>
+struct WideCoef {
+    int K;
+    R c[4], d[4];   // c already divided by h
+    R alpha[3];
+};
+
+// u: one component field [z][y][x]; (x, y, z) the cell; axis 0 = x, 1 = y, 2 = z
+template <class R, class T>
+__device__ __forceinline__ cplx<R> ld_shift(const T* u, int N, int x, int y, int z, int axis, int off) {
+    if (axis == 0) x = (x + off + 4 * N) % N;
+    else if (axis == 1) y = (y + off + 4 * N) % N;
+    else z = (z + off + 4 * N) % N;
+    const T v = u[((size_t)z * N + y) * N + x];
+    return mk<cplx<R>>(v.x, v.y);
+}
+
+template <class R, class T>
+__device__ __forceinline__ cplx<R> Dfwd(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
+    cplx<R> diff = mk<cplx<R>>(0, 0), avg = mk<cplx<R>>(0, 0);
+    for (int s = 1; s <= w.K; ++s) {
+        const cplx<R> a = ld_shift<R>(u, N, x, y, z, axis, s), b = ld_shift<R>(u, N, x, y, z, axis, 1 - s);
+        diff = cadd(diff, cscale(csub(a, b), w.c[s - 1]));
+        avg = cadd(avg, cscale(cadd(a, b), w.d[s - 1]));
+    }
+    const R al = w.alpha[axis];
+    return mk<cplx<R>>(diff.x - al * avg.y, diff.y + al * avg.x);   // diff + i alpha avg
+}
+
+template <class R, class T>
+__device__ __forceinline__ cplx<R> Dadj(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
+    cplx<R> diff = mk<cplx<R>>(0, 0), avg = mk<cplx<R>>(0, 0);
+    for (int s = 1; s <= w.K; ++s) {
+        const cplx<R> a = ld_shift<R>(u, N, x, y, z, axis, -s), b = ld_shift<R>(u, N, x, y, z, axis, s - 1);
+        diff = cadd(diff, cscale(csub(a, b), w.c[s - 1]));
+        avg = cadd(avg, cscale(cadd(a, b), w.d[s - 1]));
+    }
+    const R al = w.alpha[axis];
+    return mk<cplx<R>>(diff.x + al * avg.y, diff.y - al * avg.x);   // diff - i alpha avg
+}
+
+// pass 1: T[b] = [mu_1 e1, mu_2 e2, mu_3 e3, q] of field fl(b0 + b)
+template <class R, class S>
+__global__ __launch_bounds__(256) void wide_pass1_kernel(const cplx<S>* __restrict__ X, cplx<R>* __restrict__ T,
+                                                         const R* __restrict__ mu, int N, int b0, int nb,
+                                                         WideCoef<R> w, FieldList fl) {
+    const size_t N3 = (size_t)N * N * N;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= N3 || b >= nb) return;
+    const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((size_t)N * N));
+    const cplx<S>* v = X + (size_t)fl(b0 + b) * 3 * N3;
+    const cplx<S>*v1 = v, *v2 = v + N3, *v3 = v + 2 * N3;
+    const cplx<R> e1 = csub(Dadj(w, v2, N, x, y, z, 2), Dadj(w, v3, N, x, y, z, 1));
+    const cplx<R> e2 = csub(Dadj(w, v3, N, x, y, z, 0), Dadj(w, v1, N, x, y, z, 2));
+    const cplx<R> e3 = csub(Dadj(w, v1, N, x, y, z, 1), Dadj(w, v2, N, x, y, z, 0));
+    const cplx<R> q = cadd(cadd(Dfwd(w, v1, N, x, y, z, 0), Dfwd(w, v2, N, x, y, z, 1)), Dfwd(w, v3, N, x, y, z, 2));
+    cplx<R>* t = T + (size_t)b * 4 * N3;
+    t[i] = cscale(e1, mu[i]);
+    t[N3 + i] = cscale(e2, mu[N3 + i]);
+    t[2 * N3 + i] = cscale(e3, mu[2 * N3 + i]);
+    t[3 * N3 + i] = q;
+}
+
+// pass 2: Y = A e + gamma B' q + shift X
+template <class R, class S>
+__global__ __launch_bounds__(256) void wide_pass2_kernel(const cplx<S>* __restrict__ X, const cplx<R>* __restrict__ T,
+                                                         cplx<S>* __restrict__ Y, int N, int b0, int nb,
+                                                         WideCoef<R> w, R gamma, R shift, FieldList fl) {
+    const size_t N3 = (size_t)N * N * N;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= N3 || b >= nb) return;
+    const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((size_t)N * N));
+    const cplx<R>* t = T + (size_t)b * 4 * N3;
+    const cplx<R>*e1 = t, *e2 = t + N3, *e3 = t + 2 * N3, *q = t + 3 * N3;
+    const size_t f = (size_t)fl(b0 + b) * 3 * N3;
+    const cplx<S>* v = X + f;
+    cplx<S>* out = Y + f;
+    cplx<R> w1 = csub(Dfwd(w, e3, N, x, y, z, 1), Dfwd(w, e2, N, x, y, z, 2));
+    cplx<R> w2 = csub(Dfwd(w, e1, N, x, y, z, 2), Dfwd(w, e3, N, x, y, z, 0));
+    cplx<R> w3 = csub(Dfwd(w, e2, N, x, y, z, 0), Dfwd(w, e1, N, x, y, z, 1));
+    w1 = cadd(w1, cscale(Dadj(w, q, N, x, y, z, 0), gamma));
+    w2 = cadd(w2, cscale(Dadj(w, q, N, x, y, z, 1), gamma));
+    w3 = cadd(w3, cscale(Dadj(w, q, N, x, y, z, 2), gamma));
+    const cplx<S> a1 = v[i], a2 = v[N3 + i], a3 = v[2 * N3 + i];
+    out[i] = mk<cplx<S>>(w1.x + shift * (R)a1.x, w1.y + shift * (R)a1.y);
+    out[N3 + i] = mk<cplx<S>>(w2.x + shift * (R)a2.x, w2.y + shift * (R)a2.y);
+    out[2 * N3 + i] = mk<cplx<S>>(w3.x + shift * (R)a3.x, w3.y + shift * (R)a3.y);
+}
+
+template <class R, class S>
+hipError_t launch_wide(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
+                       const FieldList& fl) {
+    if (!p.wtmp || p.wtmp_bands < 1) return hipErrorInvalidValue;
+    WideCoef<R> w;
+    w.K = p.order / 2;
+    double c[4], d[4];
+    stencil_coefs(p.order, c, d);
+    for (int q = 0; q < 4; ++q) {
+        w.c[q] = (R)(c[q] / p.h);
+        w.d[q] = (R)d[q];
+    }
+    for (int a = 0; a < 3; ++a) w.alpha[a] = (R)p.k[a];
+    const size_t N3 = (size_t)p.N * p.N * p.N;
+    const unsigned gx = (unsigned)((N3 + 255) / 256);
+    cplx<R>* T = (cplx<R>*)p.wtmp;
+    for (int b0 = 0; b0 < nb; b0 += p.wtmp_bands) {
+        const int nc = std::min(nb - b0, p.wtmp_bands);
+        hipLaunchKernelGGL((wide_pass1_kernel<R, S>), dim3(gx, nc), dim3(256), 0, s, (const cplx<S>*)X, T,
+                           (const R*)mu, p.N, b0, nc, w, fl);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((wide_pass2_kernel<R, S>), dim3(gx, nc), dim3(256), 0, s, (const cplx<S>*)X,
+                           (const cplx<R>*)T, (cplx<S>*)Y, p.N, b0, nc, w, (R)p.gamma, (R)p.shift, fl);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t launch_wide<float, float>(const OpParams&, int, const void*, void*, const void*, hipStream_t,
+                                              const FieldList&);
+template hipError_t launch_wide<double, double>(const OpParams&, int, const void*, void*, const void*, hipStream_t,
+                                                const FieldList&);
+template hipError_t launch_wide<double, float>(const OpParams&, int, const void*, void*, const void*, hipStream_t,
+                                               const FieldList&);
+
+}  // namespace mfd
