@@ -86,6 +86,9 @@ typedef struct {
                                  training pair (default 30; 0 = the untrained network, which
                                  proposes the previous step's combination unchanged) */
     float learn_rate;         /* warm_start 2: Adam learning rate (default 1e-3) */
+    int autotune;             /* 1 (default): on the first call for a context and block shape, time
+                                 candidate launch shapes of the Gram, update, stencil and FFT kernels
+                                 and keep the fastest (see mfd_tuning); 0: built-in shapes */
 } mfd_opts;
 
 typedef struct {
@@ -185,6 +188,11 @@ void mfd_destroy(mfd_ctx* ctx);
 
 const char* mfd_strerror(int status);
 const char* mfd_last_error(void);
+
+/* Launch shapes the autotuner chose for ctx: out[0] Gram workgroups, out[1]
+ * update workgroups, out[2] stencil workgroup target, out[3] FFT z-pass x run.
+ * Returns 1 when tuned, 0 when not yet (out holds zeros), MFD_EINVAL on NULL. */
+int mfd_tuning(const mfd_ctx* ctx, int* out);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start: the network's kernels.  A small multilayer perceptron

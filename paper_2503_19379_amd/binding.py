@@ -32,7 +32,7 @@ class mfd_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("precision", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("seed", ctypes.c_ulonglong), ("max_gamma_doublings", ctypes.c_int), ("guard", ctypes.c_int),
                 ("streams", ctypes.c_int), ("x0", ctypes.c_void_p), ("stall_window", ctypes.c_int),
-                ("learn_steps", ctypes.c_int), ("learn_rate", ctypes.c_float)]
+                ("learn_steps", ctypes.c_int), ("learn_rate", ctypes.c_float), ("autotune", ctypes.c_int)]
 
 
 class mfd_kstats(ctypes.Structure):
@@ -86,6 +86,7 @@ def lib():
         L.mfd_mlp_destroy.argtypes = [vp]
         L.mfd_mlp_destroy.restype = None
         L.mfd_warm_target.argtypes = [ctypes.c_longlong, i, vp, vp, vp, vp, vp, vp]
+        L.mfd_tuning.argtypes = [vp, ctypes.POINTER(i)]
         _lib = L
     return _lib
 
@@ -314,3 +315,13 @@ def mfd_warm_target(Xa, Xb, Xc, C, Rinv=None, stream=None):
     mb, n = Xa.shape
     _check(lib().mfd_warm_target(n, mb, _dev(Xa), _dev(Xb), _dev(Xc), _dev(C),
                                  _dev(Rinv) if Rinv is not None else None, _stream(stream)))
+
+
+def mfd_tuning(ctx: Context):
+    """(tuned, dict of the launch shapes the autotuner chose for ctx)."""
+    out = (ctypes.c_int * 4)()
+    r = lib().mfd_tuning(ctx.handle, out)
+    if r < 0:
+        _check(r)
+    return bool(r), dict(gram_workgroups=out[0], update_workgroups=out[1], stencil_workgroups=out[2],
+                         fft_x_run=out[3])

@@ -118,6 +118,7 @@ struct Ws {
     double* cout = nullptr;
     double* host = nullptr;    // pinned: theta | norms | info | column sums
     int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
+    int stencil_wgs = 2048, fft_xc = 0;
     WarmStart* warm = nullptr; // learned warm start (warm_start = 2), allocated on first use
     void* wtmp = nullptr;      // orders > 2: operator scratch of this workspace's stream
     Prof prof;
@@ -130,6 +131,9 @@ struct mfd_ctx {
     int device = 0;
     void* wtmp = nullptr;      // orders > 2: operator scratch for the ABI calls
     int wtmp_bands = 0;
+    // launch shapes chosen by the autotuner for one block shape (mb, precision)
+    int tune_mb = 0, tune_mixed = -1;
+    int tune[4] = {0, 0, 0, 0};   // Gram workgroups, update workgroups, stencil workgroups, FFT x run
     double gamma_override = 0.0;
     double* mu64 = nullptr;
     float* mu32 = nullptr;
@@ -225,16 +229,19 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
     w->n = n;
     w->nparts_upd = (int)std::min<size_t>(1024, (n + 255) / 256);
     w->nparts_gram = gram_mfma_parts(n);
+    // buffers sized for the largest launch shapes the autotuner tries
+    const int max_upd = (int)std::max<size_t>(w->nparts_upd, std::min<size_t>(2048, (n + 31) / 32));
+    const int max_gram = (int)std::max<size_t>(w->nparts_gram, std::min<size_t>(1024, (n + 31) / 32));
     w->nparts_col = (int)std::min<size_t>(256, (n + 255) / 256);
     const size_t K = 3 * (size_t)mb;
     hipError_t e;
     auto chk = [&](hipError_t r) { e = r; return r == hipSuccess; };
     if (!(chk(hipStreamCreate(&w->stream)) && chk(hipMalloc(&w->V, n * 6 * mb * sizeof(double2))) &&
           chk(hipMalloc(&w->U, n * 6 * mb * sizeof(double2))) &&
-          chk(hipMalloc(&w->gpart, std::max((size_t)w->nparts_gram * K * 2 * K,
-                                            gram_mfma_part_elems((int)K, w->nparts_gram)) * sizeof(double2))) &&
+          chk(hipMalloc(&w->gpart, std::max((size_t)max_gram * K * 2 * K,
+                                            gram_mfma_part_elems((int)K, max_gram)) * sizeof(double2))) &&
           chk(hipMalloc(&w->G, K * 2 * K * sizeof(double2))) && chk(hipMalloc(&w->C, K * mb * sizeof(double2))) &&
-          chk(hipMalloc(&w->npart, (size_t)w->nparts_upd * 2 * mb * sizeof(double))) &&
+          chk(hipMalloc(&w->npart, (size_t)std::max(max_upd, 1024) * 2 * mb * sizeof(double))) &&
           chk(hipMalloc(&w->norms, 2 * mb * sizeof(double))) && chk(hipMalloc(&w->theta, mb * sizeof(double))) &&
           chk(hipMalloc(&w->info, 16 * sizeof(int))) &&
           chk(hipMalloc(&w->cpart, (size_t)std::max(w->nparts_col, 1024) * 2 * mb * sizeof(double))) &&
@@ -391,7 +398,8 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         if (mixed) HIPCHK(launch_stencil_f64_s32(p, mb, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s));
         else HIPCHK(launch_stencil<double>(p, mb, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s));
     }
-    std::vector<int> act, act_prev, pact;
+    std::vector<int> act, pact;
+    bool have_p = false;
     if (union_start)
         for (int j = 0; j < mb; ++j) act.push_back(j);
     RRArgs ra;
@@ -420,10 +428,11 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     };
     for (;; ++it) {
         const int rb = mixed ? 8 : 16;   // bytes per complex of the W/AW blocks
-        // P columns still valid: bands active now whose P' the last update wrote
+        // P columns: every update writes P' of every band, so each active band
+        // has one from the second iteration on (zero after the first, which the
+        // Rayleigh-Ritz step leaves out)
         pact.clear();
-        for (int b : act)
-            if (std::find(act_prev.begin(), act_prev.end(), b) != act_prev.end()) pact.push_back(b);
+        if (have_p) pact = act;
         BasisMap bm = make_basis(mb, act, pact, mixed);
         const int na = (int)act.size(), np = (int)pact.size();
         if (it > 0 && na > 0) {
@@ -467,13 +476,11 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         HIPCHK(launch_update_mfma(V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, bm, w.C, w.theta,
                                   w.nparts_upd, w.npart, w.norms, s));
         // reads X, AX (FP64) and the W, P, AW, AP of the basis; writes X', AX'
-        // (FP64), R' for every band and P', AP' for the active ones
-        w.prof.end(e1, 4,
-                   (double)n * (2 * mb * 16.0 + 2 * (bm.na + np) * rb + 2 * mb * 16.0 + mb * rb + 2 * bm.na * rb),
-                   s);
+        // (FP64) and R', P', AP' of every band
+        w.prof.end(e1, 4, (double)n * (2 * mb * 16.0 + 2 * (bm.na + np) * rb + 2 * mb * 16.0 + 3 * mb * rb), s);
         std::swap(V, U);
         if (mixed) std::swap(V32, U32);
-        act_prev = act;   // the update wrote P', AP' of these bands
+        have_p = true;   // the update wrote P', AP' of every band
         HIPCHK(hipMemcpyAsync(hth, w.theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
         int* hinfo = (int*)(w.host + 3 * mb);
@@ -526,7 +533,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         if (mixed && stall_window > 0 && it - best_it >= stall_window) {
             mixed = false;
             out.fp64_fallback = true;
-            act_prev.clear();   // no P in FP64 storage yet
+            have_p = false;   // no P in FP64 storage yet
             HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
             HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), col(V, n, mb), false, n, n, mb, w.theta,
                                    w.nparts_col, w.npart, w.norms, s));
@@ -592,6 +599,8 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
     auto t0 = std::chrono::steady_clock::now();
     OpParams p = params(c, k);
     p.wtmp = w.wtmp;
+    p.stencil_wgs = w.stencil_wgs;
+    p.fft_xc = w.fft_xc;
     const double scale = std::pow(2.0 * M_PI / c->L, 2);
     KResult kr;
     int doublings = 0, total_iters = 0, nspur = 0, discarded = 0, fp64_fallback = 0;
@@ -759,6 +768,98 @@ void run_segment(Segment* sg) {
     }
 }
 
+// Autotuner: launch shapes of the Gram, update, stencil and FFT kernels for
+// this grid and block shape, each the fastest of a few candidates timed with
+// HIP events on the workspace's stream (full basis, random data).  Run once
+// per context and block shape, before concurrent work starts.
+int autotune(mfd_ctx* c, Ws& w, const double* k) {
+    const size_t n = w.n;
+    const int mb = w.mb;
+    hipStream_t s = w.stream;
+    OpParams p = params(c, k);
+    p.wtmp = w.wtmp;
+    HIPCHK(launch_fill_random(w.V, n * 6 * mb, 12345, s));
+    if (w.mixed) {
+        HIPCHK(launch_convert(w.V, w.V32, n * 6 * mb, true, s));
+    }
+    std::vector<int> all(mb);
+    for (int j = 0; j < mb; ++j) all[j] = j;
+    const BasisMap bm = make_basis(mb, all, all, w.mixed);
+    HIPCHK(hipMemsetAsync(w.theta, 0, mb * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(w.C, 0, (size_t)3 * mb * mb * sizeof(double2), s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto timeit = [&](auto&& launch) -> double {
+        if (launch() != hipSuccess) return HUGE_VAL;   // also the warm-up
+        float best = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess || launch() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess)
+                return HUGE_VAL;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, ms);
+        }
+        return best;
+    };
+    float2* V32 = w.mixed ? w.V32 : nullptr;
+    float2* U32 = w.mixed ? w.U32 : nullptr;
+    int best_gram = w.nparts_gram, best_upd = w.nparts_upd, best_wgs = 2048, best_xc = 0;
+    double tb = HUGE_VAL;
+    for (int np : {128, 256, 512, 1024}) {
+        if ((size_t)np * 32 > n + 31 && np != w.nparts_gram) continue;
+        const double t = timeit([&] { return launch_gram_mfma(w.V, V32, n, n, bm, np, w.gpart, w.G, s); });
+        if (t < tb) { tb = t; best_gram = np; }
+    }
+    tb = HUGE_VAL;
+    for (int np : {256, 512, 1024, 2048}) {
+        if ((size_t)np * 32 > n + 31 && np != w.nparts_upd) continue;
+        const double t = timeit([&] {
+            return launch_update_mfma(w.V, V32, w.U, U32, n, n, bm, w.C, w.theta, np, w.npart, w.norms, s);
+        });
+        if (t < tb) { tb = t; best_upd = np; }
+    }
+    tb = HUGE_VAL;
+    for (int wg : {512, 1024, 2048, 4096}) {
+        OpParams q = p;
+        q.stencil_wgs = wg;
+        const double t = timeit([&] {
+            return w.mixed ? launch_stencil_f64_s32(q, mb, w.V32 + n * mb, w.V32 + n * 4 * mb, c->mu64, s)
+                           : launch_stencil<double>(q, mb, col(w.V, n, mb), col(w.V, n, 4 * mb), c->mu64, s);
+        });
+        if (t < tb) { tb = t; best_wgs = wg; }
+    }
+    tb = HUGE_VAL;
+    for (int xc : {4, 8, 16}) {
+        if (c->N % xc) continue;
+        OpParams q = p;
+        q.fft_xc = xc;
+        const double t = timeit([&] {
+            return w.mixed ? launch_precond<float>(q, mb, w.V32 + n * mb, w.V32 + n * mb, c->tw32, s)
+                           : launch_precond<double>(q, mb, col(w.V, n, mb), col(w.V, n, mb), c->tw64, s);
+        });
+        if (t < tb) { tb = t; best_xc = xc; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tune_mb = mb;
+    c->tune_mixed = w.mixed ? 1 : 0;
+    c->tune[0] = best_gram;
+    c->tune[1] = best_upd;
+    c->tune[2] = best_wgs;
+    c->tune[3] = best_xc;
+    return MFD_OK;
+}
+
+void apply_tune(const mfd_ctx* c, Ws& w) {
+    if (c->tune_mb != w.mb || c->tune_mixed != (w.mixed ? 1 : 0)) return;
+    w.nparts_gram = c->tune[0];
+    w.nparts_upd = c->tune[1];
+    w.stencil_wgs = c->tune[2];
+    w.fft_xc = c->tune[3];
+}
+
 // Run segments on their workspaces, one host thread each; collect timing.
 int run_segments(std::vector<Segment>& segs) {
     std::vector<std::thread> th;
@@ -812,6 +913,13 @@ void mfd_default_opts(mfd_opts* o) {
     o->stall_window = 40;
     o->learn_steps = 30;
     o->learn_rate = 1e-3f;
+    o->autotune = 1;
+}
+
+int mfd_tuning(const mfd_ctx* ctx, int* out) {
+    if (!ctx || !out) return fail(MFD_EINVAL, "NULL argument");
+    for (int i = 0; i < 4; ++i) out[i] = ctx->tune[i];
+    return ctx->tune_mb > 0 ? 1 : 0;
 }
 
 int mfd_supported_n(int N) {
@@ -963,6 +1071,9 @@ int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol, 
     HIPCHK(hipEventRecord(ready, (hipStream_t)stream));
     for (int i = 0; i < nseg; ++i) HIPCHK(hipStreamWaitEvent(ctx->ws[i]->stream, ready, 0));
     hipEventDestroy(ready);
+    if (o.autotune && (ctx->tune_mb != mb || ctx->tune_mixed != (o.precision == 1 ? 1 : 0)))
+        if ((st = autotune(ctx, *ctx->ws[0], kpts))) return st;
+    for (int i = 0; i < nseg; ++i) apply_tune(ctx, *ctx->ws[i]);
     std::vector<Segment> segs(nseg);
     for (int i = 0; i < nseg; ++i) {
         Segment& sg = segs[i];
@@ -1008,6 +1119,9 @@ int mfd_bands_batch(int ncrys, mfd_ctx* const* ctxs, const int* nk, const double
         int st = ensure_ws(ctxs[c], mb, o.precision == 1, 1);
         if (st) { hipEventDestroy(ready); return st; }
         HIPCHK(hipStreamWaitEvent(ctxs[c]->ws[0]->stream, ready, 0));
+        if (o.autotune && (ctxs[c]->tune_mb != mb || ctxs[c]->tune_mixed != (o.precision == 1 ? 1 : 0)))
+            if ((st = autotune(ctxs[c], *ctxs[c]->ws[0], kpts[c]))) { hipEventDestroy(ready); return st; }
+        apply_tune(ctxs[c], *ctxs[c]->ws[0]);
         Segment& sg = segs[c];
         sg.ctx = ctxs[c];
         sg.ws = ctxs[c]->ws[0];

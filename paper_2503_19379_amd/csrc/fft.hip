@@ -325,7 +325,8 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
         }
         for (int i = 0; i < 3; ++i) a.alpha[i] = (R)p.k[i];
     }
-    switch (pick_xc(N)) {
+    const int xc = (p.fft_xc > 0 && N % p.fft_xc == 0 && p.fft_xc <= 16) ? p.fft_xc : pick_xc(N);
+    switch (xc) {
         case 16: if constexpr (N % 16 == 0) e = zsolve_launch<R, N, 16>(a, nb, s); break;
         case 8: if constexpr (N % 8 == 0) e = zsolve_launch<R, N, 8>(a, nb, s); break;
         case 4: if constexpr (N % 4 == 0) e = zsolve_launch<R, N, 4>(a, nb, s); break;

@@ -251,16 +251,17 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
     const int K = bm.K;
     const int KP = (K + 3) / 4 * 4;
     const int C2 = 2 * K;
-    double2* Cs = reinterpret_cast<double2*>(smem_raw);      // [KP][MP]
-    double2* slab = Cs + KP * MP;                             // [C2][UP_RBP], column-major
-    double2* xo = slab + C2 * UP_RBP;                         // [2][MP][UP_RBP]: X', AX'
-    double* red = reinterpret_cast<double*>(xo + 2 * MP * UP_RBP);   // [8][2][MP]
+    double2* Cs = reinterpret_cast<double2*>(smem_raw);      // [KP][mb]
+    double2* slab = Cs + KP * mb;                             // [C2][UP_RBP], column-major
+    double2* xo = slab + C2 * UP_RBP;                         // [2][mb][UP_RBP]: X', AX'
+    double2* po = xo + 2 * mb * UP_RBP;                       // [2][mb][UP_RBP]: P', AP'
+    double* red = reinterpret_cast<double*>(po + 2 * mb * UP_RBP);   // [8][2][MP]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int strip = wave & 1, chain = wave >> 1;
-    for (int e = tid; e < KP * MP; e += 256) {
-        const int k = e / MP, j = e % MP;
-        Cs[e] = (k < K && j < mb) ? Cg[k * mb + j] : mk<double2>(0.0, 0.0);
+    for (int e = tid; e < KP * mb; e += 256) {
+        const int k = e / mb;
+        Cs[e] = (k < K) ? Cg[e] : mk<double2>(0.0, 0.0);
     }
     const int li = lane & 15, lk = lane >> 4;
     // R phase mapping: row = tid % 32, columns jg, jg + 8, ...
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                 const double2 sv = (k < ke) ? arow[k * UP_RBP] : mk<double2>(0.0, 0.0);
 #pragma unroll
                 for (int J = 0; J < MJ; ++J) {
-                    const double2 c = (k < ke) ? Cs[k * MP + 16 * J + li] : mk<double2>(0.0, 0.0);
+                    const double2 c = (k < ke && 16 * J + li < mb) ? Cs[k * mb + 16 * J + li] : mk<double2>(0.0, 0.0);
                     acc[J][0] = mfma64(sv.x, c.x, acc[J][0]);
                     acc[J][1] = mfma64(sv.y, c.y, acc[J][1]);
                     acc[J][2] = mfma64(sv.x + sv.y, c.x + c.y, acc[J][2]);
@@ -342,16 +343,9 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                     const int rl = 16 * strip + lk + 4 * r;
                     const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
                     const double2 v = mk<double2>(t1 - t2, t3 - t1 - t2);
-                    if (pass == 0) {
-                        // P' (AP') of an active band: into this wave's rows of that
-                        // band's W (AW) column of the slab, which pass 0 has finished
-                        // reading and the other strip never touches; stored
-                        // row-contiguously with X' below
-                        const int t = (j < mb) ? bm.tpos[j] : -1;
-                        if (t >= 0) slab[(chain * K + mb + t) * UP_RBP + rl] = v;
-                    } else {
-                        xo[(chain * MP + j) * UP_RBP + rl] = v;
-                    }
+                    if (j >= mb) continue;
+                    if (pass == 0) po[(chain * mb + j) * UP_RBP + rl] = v;   // P' (AP'), stored with X' below
+                    else xo[(chain * mb + j) * UP_RBP + rl] = v;
                 }
             }
         }
@@ -364,7 +358,7 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                 const int j = jg + 8 * c;
                 if (j < mb) {
                     const double2 x = xo[j * UP_RBP + rrow];
-                    const double2 ax = xo[(MP + j) * UP_RBP + rrow];
+                    const double2 ax = xo[(mb + j) * UP_RBP + rrow];
                     const double2 res = mk<double2>(ax.x - th[c] * x.x, ax.y - th[c] * x.y);
                     U[(size_t)j * ld + row] = x;
                     U[(size_t)(3 * mb + j) * ld + row] = ax;
@@ -374,14 +368,13 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
                     nx[c] += cabs2(x);
                 }
             }
-            // P', AP' of the active bands (same thread mapping over the na staged columns)
+            // P', AP' of every band
 #pragma unroll
             for (int c = 0; c < NJ; ++c) {
-                const int t = jg + 8 * c;
-                if (t < bm.na) {
-                    const int j = bm.act[t];
-                    const double2 pn = slab[(mb + t) * UP_RBP + rrow];
-                    const double2 apn = slab[(K + mb + t) * UP_RBP + rrow];
+                const int j = jg + 8 * c;
+                if (j < mb) {
+                    const double2 pn = po[j * UP_RBP + rrow];
+                    const double2 apn = po[(mb + j) * UP_RBP + rrow];
                     if (U32) {
                         U32[(size_t)(2 * mb + j) * ld + row] = make_float2((float)pn.x, (float)pn.y);
                         U32[(size_t)(5 * mb + j) * ld + row] = make_float2((float)apn.x, (float)apn.y);
@@ -423,7 +416,8 @@ static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, 
     const int K = bm.K;
     const int KP = (K + 3) / 4 * 4;
     if (UP_RB * 2 * K > UP_PF * 256) return hipErrorInvalidValue;
-    const size_t lds = ((size_t)KP * MP + (size_t)UP_RBP * 2 * K + 2 * UP_RBP * MP) * sizeof(double2) +
+    const int mb = bm.mb;
+    const size_t lds = ((size_t)KP * mb + (size_t)UP_RBP * 2 * K + 4 * (size_t)UP_RBP * mb) * sizeof(double2) +
                        (size_t)8 * 2 * MP * sizeof(double);
     auto kern = update_mfma_kernel<MJ>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -14,8 +14,7 @@ int gram_parts(size_t n);
 hipError_t launch_update(const void* V, void* U, size_t ld, size_t n, int mb, const void* C, const double* theta,
                          int nparts, double* npart, double* norms, hipStream_t s);
 // The basis of one Rayleigh-Ritz step: X (mb columns), the W columns of the
-// na unconverged bands and the np P columns still valid for them, K = mb + na
-// + np, with the images AX, AW, AP at basis columns K..2K.  V holds
+// na unconverged bands and the np P columns of those bands, K = mb + na + np, with the images AX, AW, AP at basis columns K..2K.  V holds
 // [X | W | P | AX | AW | AP], mb columns each, in band order.
 struct BasisMap {
     int mb, K, na;
@@ -32,10 +31,8 @@ hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n,
                             void* part, void* G, hipStream_t s);
 int gram_mfma_parts(size_t n);
 size_t gram_mfma_part_elems(int K, int nparts);
-// U = [X' | R' | P' | AX' | - | AP'] from the K x mb coefficients C: X', AX'
-// and R' for every band, P' and AP' for the na active bands (their columns of
-// the other bands are left as they are).  U32 (or null): FP32 outputs R', P',
-// AP' (mixed precision).
+// U = [X' | R' | P' | AX' | - | AP'] from the K x mb coefficients C, every
+// band.  U32 (or null): FP32 outputs R', P', AP' (mixed precision).
 hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
                               const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
                               double* norms, hipStream_t s);

@@ -226,7 +226,7 @@ hipError_t launch_stencil_rs(const OpParams& p, int nb, const void* X, void* Y, 
     // z chunks: enough workgroups to fill 256 CUs several times over, chunks
     // of at least 8 planes (each chunk re-reads two halo planes).
     int zc = p.N;
-    while (zc % 2 == 0 && zc >= 16 && (size_t)a.nyt * (p.N / zc) * nb < 2048) zc /= 2;
+    while (zc % 2 == 0 && zc >= 16 && (size_t)a.nyt * (p.N / zc) * nb < (size_t)p.stencil_wgs) zc /= 2;
     a.zc = zc;
     a.nzc = p.N / zc;
     for (int i = 0; i < 3; ++i) {

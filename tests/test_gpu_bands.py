@@ -154,3 +154,24 @@ def test_mixed_precision_fp64_fallback(B):
         assert np.allclose(ev[i], lam, rtol=1e-7, atol=1e-9), (k, ev[i], lam)
     _, st0, _ = B.mfd_bands(ctx, kp, m, 1e-8, B.default_opts(precision=1, streams=1, stall_window=0))
     assert all(s["fp64_fallback"] == 0 for s in st0)
+
+
+def test_autotune_changes_launch_shapes_not_results(B):
+    """The autotuner picks each launch shape from its candidates; the bands
+    agree with the built-in shapes'."""
+    N, m = 24, 6
+    eps = workloads.eps_diamond(N)
+    kp = workloads.kpath("GXMGR", 6)
+    c0 = B.mfd_build(N, 1.0, 2, eps)
+    e0, s0, st0 = B.mfd_bands(c0, kp, m, 1e-9, B.default_opts(autotune=0, streams=2))
+    assert st0 == 0 and B.mfd_tuning(c0)[0] is False
+    c1 = B.mfd_build(N, 1.0, 2, eps)
+    e1, s1, st1 = B.mfd_bands(c1, kp, m, 1e-9, B.default_opts(autotune=1, streams=2))
+    assert st1 == 0
+    tuned, t = B.mfd_tuning(c1)
+    assert tuned
+    assert t["gram_workgroups"] in (128, 256, 512, 1024)
+    assert t["update_workgroups"] in (256, 512, 1024, 2048)
+    assert t["stencil_workgroups"] in (512, 1024, 2048, 4096)
+    assert t["fft_x_run"] in (4, 8)
+    assert np.allclose(e0, e1, rtol=1e-8, atol=1e-9)
