@@ -28,8 +28,7 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 // tile set; gram_reduce_kernel adds the partials in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int GM_KS = 32;       // rows per LDS slab
-constexpr int GM_MAXT = 3;      // tiles per wave; one wave per GM_MAXT tiles, up to 16 waves
-constexpr int GM_PF = 12;       // prefetch registers (complex) per thread
+constexpr int GM_PF = 16;       // prefetch registers (complex) per thread
 
 struct GramTiles {
     int n;                      // number of tiles
@@ -50,50 +49,53 @@ __device__ __forceinline__ double2 widen(double2 raw, bool f32) {
     return mk<double2>((double)v.x, (double)v.y);
 }
 
-// The next slab is loaded into registers while the current one is consumed
-// from LDS by the matrix cores.
-__global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restrict__ V, const float2* __restrict__ V32,
-                                                         size_t ld, size_t n, BasisMap bm, size_t rows_per,
-                                                         GramTiles tl, double2* __restrict__ part) {
-    const int K = bm.K;
+// One wave per 16-column block g of S.  Block g is the A operand of exactly
+// T + 1 tiles (T = ceil(K / 16)): the G_S tiles (g, b), b >= g, and the G_A
+// tiles (g, a), a <= g, so the wave loads its A fragment once per 4 rows and
+// reuses it for all of them.  The next slab is loaded into registers while the
+// current one is consumed from LDS by the matrix cores.
+template <int T>
+__global__ __launch_bounds__(64 * T) void gram_mfma_kernel(const double2* __restrict__ V,
+                                                            const float2* __restrict__ V32, size_t ld, size_t n,
+                                                            BasisMap bm, size_t rows_per,
+                                                            double2* __restrict__ part) {
+    constexpr int NT = 64 * T;
+    constexpr int TG = T + 1;   // tiles per wave
     extern __shared__ unsigned char smem_raw[];
     double2* slab = reinterpret_cast<double2*>(smem_raw);   // [GM_KS][2K]
+    const int K = bm.K;
     const int C2 = 2 * K;
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int nwaves = nthr >> 6;
+    const int lane = tid & 63, g = tid >> 6;
     const size_t r0 = (size_t)blockIdx.x * rows_per;
     const size_t r1 = min(n, r0 + rows_per);
-    const int my_n = (tl.n - wave + nwaves - 1) / nwaves;   // tiles wave, wave + nwaves, ...
-    const int nel = GM_KS * C2;
-    d4 acc[GM_MAXT][3];
+    d4 acc[TG][3];
 #pragma unroll
-    for (int t = 0; t < GM_MAXT; ++t)
+    for (int t = 0; t < TG; ++t)
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[t][q] = d4{0.0, 0.0, 0.0, 0.0};
     const int li = lane & 15, lk = lane >> 4;
-    // per-tile operand offsets in a slab row
-    int oa[GM_MAXT], ob[GM_MAXT];
-    bool va[GM_MAXT], vb[GM_MAXT];
+    // A operand: column 16 g + li of S; B operands: S columns 16 b + li (b = g..T-1),
+    // then AS columns 16 a + li (a = 0..g)
+    const int ia = 16 * g + li;
+    const bool va = ia < K;
+    int ob[TG];
+    bool vb[TG];
 #pragma unroll
-    for (int t = 0; t < GM_MAXT; ++t) {
-        const int ti = min(wave + nwaves * t, tl.n - 1);
-        const int i = tl.ti[ti] * 16 + li, j = tl.tj[ti] * 16 + li;
-        va[t] = i < K;
+    for (int t = 0; t < TG; ++t) {
+        const int j = (t < T - g) ? 16 * (g + t) + li : 16 * (t - (T - g)) + li;
+        const bool as = t >= T - g;
         vb[t] = j < K;
-        oa[t] = va[t] ? i : 0;
-        ob[t] = vb[t] ? tl.half[ti] * K + j : 0;
+        ob[t] = vb[t] ? (as ? K + j : j) : 0;
     }
-    // element tid + q nthr of a slab: row tid % GM_KS (nthr is a multiple of
-    // GM_KS) and load ordinal tid / GM_KS + q nthr / GM_KS, the same in every
-    // slab: resolve the columns once
+    // element tid + q NT of a slab: row tid % GM_KS and load ordinal
+    // tid / GM_KS + q NT / GM_KS, the same in every slab: resolve the columns once
     const int srow = tid % GM_KS;
     int scol[GM_PF], vcol[GM_PF];
     unsigned f32m = 0, okm = 0;
 #pragma unroll
     for (int q = 0; q < GM_PF; ++q) {
-        const int o = tid / GM_KS + q * (nthr / GM_KS);
+        const int o = tid / GM_KS + q * (NT / GM_KS);
         scol[q] = vcol[q] = 0;
         if (o < C2) {
             scol[q] = bm.lc[o];
@@ -102,7 +104,6 @@ __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restric
             if (V32 && col_is_f32(vcol[q], bm.mb)) f32m |= 1u << q;
         }
     }
-    (void)nel;
     double2 pf[GM_PF];
     auto prefetch = [&](size_t s0) {
         const bool inb = s0 + srow < r1;
@@ -125,25 +126,24 @@ __global__ __launch_bounds__(448) void gram_mfma_kernel(const double2* __restric
         if (s0 + GM_KS < r1) prefetch(s0 + GM_KS);
 #pragma unroll
         for (int k0 = 0; k0 < GM_KS; k0 += 4) {
-            const double2* srow = slab + (k0 + lk) * C2;
+            const double2* srow_p = slab + (k0 + lk) * C2;
+            const double2 a = va ? srow_p[ia] : mk<double2>(0.0, 0.0);
+            const double amd = a.x - a.y;
 #pragma unroll
-            for (int t = 0; t < GM_MAXT; ++t) {
-                if (t >= my_n) break;
-                const double2 a = va[t] ? srow[oa[t]] : mk<double2>(0.0, 0.0);
-                const double2 b = vb[t] ? srow[ob[t]] : mk<double2>(0.0, 0.0);
+            for (int t = 0; t < TG; ++t) {
+                const double2 b = vb[t] ? srow_p[ob[t]] : mk<double2>(0.0, 0.0);
                 acc[t][0] = mfma64(a.x, b.x, acc[t][0]);
                 acc[t][1] = mfma64(a.y, b.y, acc[t][1]);
-                acc[t][2] = mfma64(a.x - a.y, b.x + b.y, acc[t][2]);
+                acc[t][2] = mfma64(amd, b.x + b.y, acc[t][2]);
             }
         }
         __syncthreads();
     }
-    // partial tiles: part[w][tile][16][16]
-    double2* out = part + (size_t)blockIdx.x * tl.n * 256;
+    // partial tiles: part[w][tile][16][16], tiles of wave g at g TG .. g TG + T
+    double2* out = part + (size_t)blockIdx.x * (T * TG) * 256;
 #pragma unroll
-    for (int t = 0; t < GM_MAXT; ++t) {
-        if (t >= my_n) break;
-        const int ti = wave + nwaves * t;
+    for (int t = 0; t < TG; ++t) {
+        const int ti = g * TG + t;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = lk + 4 * r, colj = li;
@@ -174,19 +174,26 @@ __global__ void gram_scatter_kernel(const double2* __restrict__ sum, int K, Gram
     if (mirror) G[(size_t)j * 2 * K + off + i] = mk<double2>(v.x, -v.y);
 }
 
+// Tiles in the order the waves produce them: for block g of S, the G_S tiles
+// (g, b), b >= g, then the G_A tiles (g, a), a <= g.
 static GramTiles make_tiles(int K) {
     GramTiles tl;
     tl.n = 0;
     const int T = (K + 15) / 16;
-    for (int h = 0; h < 2; ++h)
-        for (int a = 0; a < T; ++a)
-            for (int b = a; b < T; ++b) {
-                // G_S: upper tiles (a, b); G_A: lower tiles (b, a)
-                tl.ti[tl.n] = (short)(h == 0 ? a : b);
-                tl.tj[tl.n] = (short)(h == 0 ? b : a);
-                tl.half[tl.n] = (unsigned char)h;
-                ++tl.n;
-            }
+    for (int g = 0; g < T; ++g) {
+        for (int b = g; b < T; ++b) {
+            tl.ti[tl.n] = (short)g;
+            tl.tj[tl.n] = (short)b;
+            tl.half[tl.n] = 0;
+            ++tl.n;
+        }
+        for (int a = 0; a <= g; ++a) {
+            tl.ti[tl.n] = (short)g;
+            tl.tj[tl.n] = (short)a;
+            tl.half[tl.n] = 1;
+            ++tl.n;
+        }
+    }
     return tl;
 }
 
@@ -197,25 +204,37 @@ size_t gram_mfma_part_elems(int K, int nparts) {
     return (size_t)(nparts + 1) * T * (T + 1) * 256;   // partials + their sum
 }
 
+template <int T>
+static hipError_t gram_t(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nw,
+                         size_t rows_per, void* part, hipStream_t s) {
+    const size_t lds = (size_t)GM_KS * 2 * bm.K * sizeof(double2);
+    auto kern = gram_mfma_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nw), dim3(64 * T), lds, s, (const double2*)V, (const float2*)V32, ld, n, bm,
+                       rows_per, (double2*)part);
+    return hipGetLastError();
+}
+
 hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nparts,
                             void* part, void* G, hipStream_t s) {
     const int K = bm.K;
+    if (K < 1 || K > 64) return hipErrorInvalidValue;
+    const int T = (K + 15) / 16;
+    // the slab of GM_KS x 2K elements must fit the prefetch registers of 64 T threads
+    if (GM_KS * 2 * K > GM_PF * 64 * T) return hipErrorInvalidValue;
     GramTiles tl = make_tiles(K);
-    const int nwaves_t = (tl.n + GM_MAXT - 1) / GM_MAXT;
-    if (K > 64) return hipErrorInvalidValue;
-    const int need = (int)((GM_KS * 2 * K + GM_PF * 64 - 1) / (GM_PF * 64));
-    const int nwaves = std::max(nwaves_t, need);
-    if (nwaves > 7) return hipErrorInvalidValue;
     const size_t rows_per = ((n + nparts - 1) / nparts + GM_KS - 1) / GM_KS * GM_KS;
     const int nw = (int)((n + rows_per - 1) / rows_per);
-    const size_t lds = (size_t)GM_KS * 2 * K * sizeof(double2);
-    hipError_t e = hipFuncSetAttribute((const void*)gram_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e;
+    switch (T) {
+        case 1: e = gram_t<1>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+        case 2: e = gram_t<2>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+        case 3: e = gram_t<3>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+        default: e = gram_t<4>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+    }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gram_mfma_kernel, dim3(nw), dim3(64 * nwaves), lds, s, (const double2*)V, (const float2*)V32,
-                       ld, n, bm, rows_per, tl, (double2*)part);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // sum the partial tiles (in place into the first part's slot after the last), then scatter
+    // sum the partial tiles (into the slot after the last part), then scatter
     double2* sum = (double2*)part + (size_t)nw * tl.n * 256;
     if ((e = launch_reduce((const double*)part, nw, tl.n * 256 * 2, (double*)sum, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(gram_scatter_kernel, dim3((tl.n * 256 + 255) / 256), dim3(256), 0, s, (const double2*)sum, K, tl,
