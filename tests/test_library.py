@@ -41,3 +41,24 @@ def test_host_only_calls():
     # argument validation happens before any device work
     h = ctypes.c_void_p()
     assert L.mfd_build(8, 1.0, 2, None, None, ctypes.byref(h)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_side_argument_errors():
+    """Argument checks that return before any device call."""
+    from paper_2503_19379_amd import binding as b
+    L = b.lib()
+    h = ctypes.c_void_p()
+    assert L.mfd_mlp_create(0, 8, 1, 4, 2, 1, 0, ctypes.byref(h)) == -1
+    assert L.mfd_mlp_create(8, 0, 1, 4, 2, 1, 0, ctypes.byref(h)) == -1
+    assert L.mfd_mlp_create(8, 8, 1, 4, 0, 1, 0, ctypes.byref(h)) == -1
+    assert L.mfd_tuning(None, None) == -1
+    eps = (ctypes.c_double * 512)(*([1.0] * 512))
+    dp = ctypes.cast(eps, ctypes.POINTER(ctypes.c_double))
+    assert L.mfd_build(8, 1.0, 3, dp, None, ctypes.byref(h)) == -6      # order 3: unsupported
+    assert L.mfd_build(8, 1.0, 10, dp, None, ctypes.byref(h)) == -6
+    assert L.mfd_build(7, 1.0, 2, dp, None, ctypes.byref(h)) == -6      # no FFT plan for N = 7
+    eps[5] = -1.0
+    assert L.mfd_build(8, 1.0, 2, dp, None, ctypes.byref(h)) == -1      # eps must be > 0
+    o = b.default_opts()
+    assert o.autotune == 1 and o.stall_window == 40 and o.learn_steps == 30
