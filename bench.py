@@ -314,6 +314,7 @@ def main():
         "converged_kpoints": ok,
         "total_kpoints": len(iters),
         "variants": variants,
+        "tuning": B.mfd_tuning(ctx)[1],
     }
     if not args.no_cpu_baseline:
         kidx = min(16, len(kpts) - 1)

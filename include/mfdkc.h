@@ -189,8 +189,9 @@ void mfd_destroy(mfd_ctx* ctx);
 const char* mfd_strerror(int status);
 const char* mfd_last_error(void);
 
-/* Launch shapes the autotuner chose for ctx: out[0] Gram workgroups, out[1]
- * update workgroups, out[2] stencil workgroup target, out[3] FFT z-pass x run.
+/* Launch shapes the autotuner chose for ctx (out: 5 ints): out[0] Gram
+ * workgroups, out[1] update workgroups, out[2] stencil workgroup target,
+ * out[3] FFT z-pass x run, out[4] update rows per workgroup block (16 or 32).
  * Returns 1 when tuned, 0 when not yet (out holds zeros), MFD_EINVAL on NULL. */
 int mfd_tuning(const mfd_ctx* ctx, int* out);
 

@@ -319,9 +319,9 @@ def mfd_warm_target(Xa, Xb, Xc, C, Rinv=None, stream=None):
 
 def mfd_tuning(ctx: Context):
     """(tuned, dict of the launch shapes the autotuner chose for ctx)."""
-    out = (ctypes.c_int * 4)()
+    out = (ctypes.c_int * 5)()
     r = lib().mfd_tuning(ctx.handle, out)
     if r < 0:
         _check(r)
     return bool(r), dict(gram_workgroups=out[0], update_workgroups=out[1], stencil_workgroups=out[2],
-                         fft_x_run=out[3])
+                         fft_x_run=out[3], update_rows=out[4])

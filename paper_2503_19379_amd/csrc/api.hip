@@ -118,7 +118,8 @@ struct Ws {
     double* cout = nullptr;
     double* host = nullptr;    // pinned: theta | norms | info | column sums
     int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
-    int stencil_wgs = 2048, fft_xc = 0;
+    int cap_upd = 0, cap_gram = 0; // workgroups the npart / gpart buffers hold partials for
+    int stencil_wgs = 2048, fft_xc = 0, upd_rows = 32;
     WarmStart* warm = nullptr; // learned warm start (warm_start = 2), allocated on first use
     void* wtmp = nullptr;      // orders > 2: operator scratch of this workspace's stream
     Prof prof;
@@ -133,7 +134,8 @@ struct mfd_ctx {
     int wtmp_bands = 0;
     // launch shapes chosen by the autotuner for one block shape (mb, precision)
     int tune_mb = 0, tune_mixed = -1;
-    int tune[4] = {0, 0, 0, 0};   // Gram workgroups, update workgroups, stencil workgroups, FFT x run
+    int tune[5] = {0, 0, 0, 0, 0};   // Gram workgroups, update workgroups, stencil workgroups, FFT x run,
+                                     // update rows per block
     double gamma_override = 0.0;
     double* mu64 = nullptr;
     float* mu32 = nullptr;
@@ -230,8 +232,11 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
     w->nparts_upd = (int)std::min<size_t>(1024, (n + 255) / 256);
     w->nparts_gram = gram_mfma_parts(n);
     // buffers sized for the largest launch shapes the autotuner tries
-    const int max_upd = (int)std::max<size_t>(w->nparts_upd, std::min<size_t>(2048, (n + 31) / 32));
+    // (update: down to 16 rows per block, at most 2048 workgroups; Gram: at most 1024)
+    const int max_upd = (int)std::max<size_t>(w->nparts_upd, std::min<size_t>(2048, (n + 15) / 16));
     const int max_gram = (int)std::max<size_t>(w->nparts_gram, std::min<size_t>(1024, (n + 31) / 32));
+    w->cap_upd = std::max(max_upd, 1024);
+    w->cap_gram = max_gram;
     w->nparts_col = (int)std::min<size_t>(256, (n + 255) / 256);
     const size_t K = 3 * (size_t)mb;
     hipError_t e;
@@ -241,7 +246,7 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
           chk(hipMalloc(&w->gpart, std::max((size_t)max_gram * K * 2 * K,
                                             gram_mfma_part_elems((int)K, max_gram)) * sizeof(double2))) &&
           chk(hipMalloc(&w->G, K * 2 * K * sizeof(double2))) && chk(hipMalloc(&w->C, K * mb * sizeof(double2))) &&
-          chk(hipMalloc(&w->npart, (size_t)std::max(max_upd, 1024) * 2 * mb * sizeof(double))) &&
+          chk(hipMalloc(&w->npart, (size_t)w->cap_upd * 2 * mb * sizeof(double))) &&
           chk(hipMalloc(&w->norms, 2 * mb * sizeof(double))) && chk(hipMalloc(&w->theta, mb * sizeof(double))) &&
           chk(hipMalloc(&w->info, 16 * sizeof(int))) &&
           chk(hipMalloc(&w->cpart, (size_t)std::max(w->nparts_col, 1024) * 2 * mb * sizeof(double))) &&
@@ -474,7 +479,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         w.prof.end(e1, 3, 0.0, s);
         e1 = w.prof.begin(s);
         HIPCHK(launch_update_mfma(V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, bm, w.C, w.theta,
-                                  w.nparts_upd, w.npart, w.norms, s));
+                                  w.nparts_upd, w.npart, w.norms, s, w.upd_rows));
         // reads X, AX (FP64) and the W, P, AW, AP of the basis; writes X', AX'
         // (FP64) and R', P', AP' of every band
         w.prof.end(e1, 4, (double)n * (2 * mb * 16.0 + 2 * (bm.na + np) * rb + 2 * mb * 16.0 + 3 * mb * rb), s);
@@ -805,21 +810,23 @@ int autotune(mfd_ctx* c, Ws& w, const double* k) {
     };
     float2* V32 = w.mixed ? w.V32 : nullptr;
     float2* U32 = w.mixed ? w.U32 : nullptr;
-    int best_gram = w.nparts_gram, best_upd = w.nparts_upd, best_wgs = 2048, best_xc = 0;
+    int best_gram = w.nparts_gram, best_upd = w.nparts_upd, best_wgs = 2048, best_xc = 0, best_rows = 32;
     double tb = HUGE_VAL;
     for (int np : {128, 256, 512, 1024}) {
-        if ((size_t)np * 32 > n + 31 && np != w.nparts_gram) continue;
+        if (((size_t)np * 32 > n + 31 && np != w.nparts_gram) || np > w.cap_gram) continue;
         const double t = timeit([&] { return launch_gram_mfma(w.V, V32, n, n, bm, np, w.gpart, w.G, s); });
         if (t < tb) { tb = t; best_gram = np; }
     }
     tb = HUGE_VAL;
-    for (int np : {256, 512, 1024, 2048}) {
-        if ((size_t)np * 32 > n + 31 && np != w.nparts_upd) continue;
-        const double t = timeit([&] {
-            return launch_update_mfma(w.V, V32, w.U, U32, n, n, bm, w.C, w.theta, np, w.npart, w.norms, s);
-        });
-        if (t < tb) { tb = t; best_upd = np; }
-    }
+    for (int rows : {32, 16})
+        for (int np : {256, 512, 1024, 2048}) {
+            if (((size_t)np * rows > n + rows - 1 && np != w.nparts_upd) || np > w.cap_upd) continue;
+            const double t = timeit([&] {
+                return launch_update_mfma(w.V, V32, w.U, U32, n, n, bm, w.C, w.theta, np, w.npart, w.norms, s,
+                                          rows);
+            });
+            if (t < tb) { tb = t; best_upd = np; best_rows = rows; }
+        }
     tb = HUGE_VAL;
     for (int wg : {512, 1024, 2048, 4096}) {
         OpParams q = p;
@@ -849,15 +856,18 @@ int autotune(mfd_ctx* c, Ws& w, const double* k) {
     c->tune[1] = best_upd;
     c->tune[2] = best_wgs;
     c->tune[3] = best_xc;
+    c->tune[4] = best_rows;
     return MFD_OK;
 }
 
 void apply_tune(const mfd_ctx* c, Ws& w) {
     if (c->tune_mb != w.mb || c->tune_mixed != (w.mixed ? 1 : 0)) return;
+    if (c->tune[0] > w.cap_gram || c->tune[1] > w.cap_upd) return;
     w.nparts_gram = c->tune[0];
     w.nparts_upd = c->tune[1];
     w.stencil_wgs = c->tune[2];
     w.fft_xc = c->tune[3];
+    w.upd_rows = c->tune[4];
 }
 
 // Run segments on their workspaces, one host thread each; collect timing.
@@ -918,7 +928,7 @@ void mfd_default_opts(mfd_opts* o) {
 
 int mfd_tuning(const mfd_ctx* ctx, int* out) {
     if (!ctx || !out) return fail(MFD_EINVAL, "NULL argument");
-    for (int i = 0; i < 4; ++i) out[i] = ctx->tune[i];
+    for (int i = 0; i < 5; ++i) out[i] = ctx->tune[i];
     return ctx->tune_mb > 0 ? 1 : 0;
 }
 

@@ -28,7 +28,7 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 // tile set; gram_reduce_kernel adds the partials in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int GM_KS = 32;       // rows per LDS slab
-constexpr int GM_PF = 16;       // prefetch registers (complex) per thread
+constexpr int GM_PF = 8;        // prefetch registers (complex) per thread
 
 struct GramTiles {
     int n;                      // number of tiles
@@ -55,18 +55,18 @@ __device__ __forceinline__ double2 widen(double2 raw, bool f32) {
 // reuses it for all of them.  The next slab is loaded into registers while the
 // current one is consumed from LDS by the matrix cores.
 template <int T>
-__global__ __launch_bounds__(64 * T) void gram_mfma_kernel(const double2* __restrict__ V,
-                                                            const float2* __restrict__ V32, size_t ld, size_t n,
-                                                            BasisMap bm, size_t rows_per,
-                                                            double2* __restrict__ part) {
-    constexpr int NT = 64 * T;
-    constexpr int TG = T + 1;   // tiles per wave
+__global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __restrict__ V,
+                                                             const float2* __restrict__ V32, size_t ld, size_t n,
+                                                             BasisMap bm, size_t rows_per,
+                                                             double2* __restrict__ part) {
+    constexpr int NT = 128 * T;   // two waves per block of S, each taking every other 4 rows
+    constexpr int TG = T + 1;     // tiles per wave
     extern __shared__ unsigned char smem_raw[];
     double2* slab = reinterpret_cast<double2*>(smem_raw);   // [GM_KS][2K]
     const int K = bm.K;
     const int C2 = 2 * K;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, g = tid >> 6;
+    const int lane = tid & 63, g = (tid >> 6) >> 1, sub = (tid >> 6) & 1;
     const size_t r0 = (size_t)blockIdx.x * rows_per;
     const size_t r1 = min(n, r0 + rows_per);
     d4 acc[TG][3];
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(64 * T) void gram_mfma_kernel(const double2* __rest
         __syncthreads();
         if (s0 + GM_KS < r1) prefetch(s0 + GM_KS);
 #pragma unroll
-        for (int k0 = 0; k0 < GM_KS; k0 += 4) {
+        for (int k0 = 4 * sub; k0 < GM_KS; k0 += 8) {
             const double2* srow_p = slab + (k0 + lk) * C2;
             const double2 a = va ? srow_p[ia] : mk<double2>(0.0, 0.0);
             const double amd = a.x - a.y;
@@ -139,8 +139,8 @@ __global__ __launch_bounds__(64 * T) void gram_mfma_kernel(const double2* __rest
         }
         __syncthreads();
     }
-    // partial tiles: part[w][tile][16][16], tiles of wave g at g TG .. g TG + T
-    double2* out = part + (size_t)blockIdx.x * (T * TG) * 256;
+    // partial tiles: part[2 w + sub][tile][16][16], tiles of block g at g TG .. g TG + T
+    double2* out = part + (size_t)(2 * blockIdx.x + sub) * (T * TG) * 256;
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         const int ti = g * TG + t;
@@ -201,7 +201,7 @@ int gram_mfma_parts(size_t n) { return (int)std::min<size_t>(512, (n + 1023) / 1
 
 size_t gram_mfma_part_elems(int K, int nparts) {
     const int T = (K + 15) / 16;
-    return (size_t)(nparts + 1) * T * (T + 1) * 256;   // partials + their sum
+    return (size_t)(2 * nparts + 1) * T * (T + 1) * 256;   // two partial sets per workgroup + their sum
 }
 
 template <int T>
@@ -211,7 +211,7 @@ static hipError_t gram_t(const void* V, const void* V32, size_t ld, size_t n, co
     auto kern = gram_mfma_kernel<T>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nw), dim3(64 * T), lds, s, (const double2*)V, (const float2*)V32, ld, n, bm,
+    hipLaunchKernelGGL(kern, dim3(nw), dim3(128 * T), lds, s, (const double2*)V, (const float2*)V32, ld, n, bm,
                        rows_per, (double2*)part);
     return hipGetLastError();
 }
@@ -221,8 +221,8 @@ hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n,
     const int K = bm.K;
     if (K < 1 || K > 64) return hipErrorInvalidValue;
     const int T = (K + 15) / 16;
-    // the slab of GM_KS x 2K elements must fit the prefetch registers of 64 T threads
-    if (GM_KS * 2 * K > GM_PF * 64 * T) return hipErrorInvalidValue;
+    // the slab of GM_KS x 2K elements must fit the prefetch registers of 128 T threads
+    if (GM_KS * 2 * K > GM_PF * 128 * T) return hipErrorInvalidValue;
     GramTiles tl = make_tiles(K);
     const size_t rows_per = ((n + nparts - 1) / nparts + GM_KS - 1) / GM_KS * GM_KS;
     const int nw = (int)((n + rows_per - 1) / rows_per);
@@ -234,9 +234,9 @@ hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n,
         default: e = gram_t<4>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
     }
     if (e != hipSuccess) return e;
-    // sum the partial tiles (into the slot after the last part), then scatter
-    double2* sum = (double2*)part + (size_t)nw * tl.n * 256;
-    if ((e = launch_reduce((const double*)part, nw, tl.n * 256 * 2, (double*)sum, s)) != hipSuccess) return e;
+    // sum the 2 nw partial tile sets (into the slot after the last), then scatter
+    double2* sum = (double2*)part + (size_t)2 * nw * tl.n * 256;
+    if ((e = launch_reduce((const double*)part, 2 * nw, tl.n * 256 * 2, (double*)sum, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(gram_scatter_kernel, dim3((tl.n * 256 + 255) / 256), dim3(256), 0, s, (const double2*)sum, K, tl,
                        (double2*)G);
     return hipGetLastError();
@@ -249,22 +249,28 @@ hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n,
 // Output U = [X' | R' | P' | AX' | - | AP'].  Each wave owns 16-row strips;
 // the coefficients sit in LDS as MFMA B fragments.
 // ---------------------------------------------------------------------------
-constexpr int UP_RB = 32;       // rows per block
-constexpr int UP_RBP = 33;      // padded column stride of the LDS blocks (conflict-free fragment reads)
+// RB rows per block (16 or 32): RB / 16 strips of 16 rows, one wave per
+// (strip, chain), 128 RB / 16 threads; the LDS blocks have column stride RB + 1
+// (conflict-free fragment reads).  The 16-row form needs about half the LDS,
+// so two workgroups can share a CU.
 constexpr int UP_PF = 16;       // prefetch registers (complex) per thread
 
-// 256 threads = 4 waves: wave w computes rows 16 (w & 1) .. of the block for
-// chain w >> 1 (0: S -> P', X'; 1: AS -> AP', AX').  X' and AX' meet in LDS,
-// where R' = AX' - X' theta and the column norms are formed and written out
-// row-contiguously.
-template <int MJ>   // mb <= 16 MJ
-__global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restrict__ V, const float2* __restrict__ V32,
-                                                          double2* __restrict__ U, float2* __restrict__ U32,
-                                                          size_t ld, size_t n, BasisMap bm,
-                                                          const double2* __restrict__ Cg,
-                                                          const double* __restrict__ theta,
-                                                          double* __restrict__ npart) {
+// Wave w computes rows 16 (w % NS) .. of the block for chain w / NS (0: S ->
+// P', X'; 1: AS -> AP', AX').  X' and AX' meet in LDS, where R' = AX' - X' theta
+// and the column norms are formed and written out row-contiguously.
+template <int MJ, int RB>   // mb <= 16 MJ
+__global__ __launch_bounds__(8 * RB) void update_mfma_kernel(const double2* __restrict__ V,
+                                                             const float2* __restrict__ V32,
+                                                             double2* __restrict__ U, float2* __restrict__ U32,
+                                                             size_t ld, size_t n, BasisMap bm,
+                                                             const double2* __restrict__ Cg,
+                                                             const double* __restrict__ theta,
+                                                             double* __restrict__ npart) {
     constexpr int MP = 16 * MJ;
+    constexpr int NS = RB / 16;          // strips
+    constexpr int NTH = 128 * NS;        // threads
+    constexpr int UP_RB = RB;
+    constexpr int UP_RBP = RB + 1;
     extern __shared__ unsigned char smem_raw[];
     const int mb = bm.mb;
     const int K = bm.K;
@@ -277,14 +283,14 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
     double* red = reinterpret_cast<double*>(po + 2 * mb * UP_RBP);   // [8][2][MP]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int strip = wave & 1, chain = wave >> 1;
-    for (int e = tid; e < KP * mb; e += 256) {
+    const int strip = wave % NS, chain = wave / NS;
+    for (int e = tid; e < KP * mb; e += NTH) {
         const int k = e / mb;
         Cs[e] = (k < K) ? Cg[e] : mk<double2>(0.0, 0.0);
     }
     const int li = lane & 15, lk = lane >> 4;
-    // R phase mapping: row = tid % 32, columns jg, jg + 8, ...
-    const int rrow = tid & 31, jg = tid >> 5;
+    // R phase mapping: row = tid % RB, columns jg, jg + 8, ... (NTH / RB = 8 groups)
+    const int rrow = tid % RB, jg = tid / RB;
     constexpr int NJ = MP / 8;
     double th[NJ], nr[NJ], nx[NJ];
 #pragma unroll
@@ -295,14 +301,14 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
     }
     const int nel = UP_RB * C2;
     const size_t nblk = (n + UP_RB - 1) / UP_RB;
-    // element tid + 256 q of a block: row tid % UP_RB and load ordinal
-    // tid / UP_RB + q 256 / UP_RB, the same in every block: resolve the columns once
+    // element tid + NTH q of a block: row tid % UP_RB and load ordinal
+    // tid / UP_RB + q NTH / UP_RB, the same in every block: resolve the columns once
     const int srow = tid % UP_RB;
     int scol[UP_PF], vcol[UP_PF];
     unsigned f32m = 0, okm = 0;
 #pragma unroll
     for (int q = 0; q < UP_PF; ++q) {
-        const int o = tid / UP_RB + q * (256 / UP_RB);
+        const int o = tid / UP_RB + q * (NTH / UP_RB);
         scol[q] = vcol[q] = 0;
         if (o < C2) {
             scol[q] = bm.lc[o];
@@ -406,13 +412,13 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
         }
         __syncthreads();
     }
-    // column sums over the 32 threads of each column group
+    // column sums over the RB threads of each column group
 #pragma unroll
     for (int c = 0; c < NJ; ++c) {
         double a = nr[c], b = nx[c];
-        for (int o = 16; o > 0; o >>= 1) {
-            a += __shfl_down(a, o, 32);
-            b += __shfl_down(b, o, 32);
+        for (int o = RB / 2; o > 0; o >>= 1) {
+            a += __shfl_down(a, o, RB);
+            b += __shfl_down(b, o, RB);
         }
         if (rrow == 0) {
             red[(c * 8 + jg) * 2 + 0] = a;
@@ -427,32 +433,38 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const double2* __restr
     }
 }
 
-template <int MJ>
+template <int MJ, int RB>
 static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
                             const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
                             hipStream_t s) {
     constexpr int MP = 16 * MJ;
+    constexpr int NTH = 8 * RB;
     const int K = bm.K;
     const int KP = (K + 3) / 4 * 4;
-    if (UP_RB * 2 * K > UP_PF * 256) return hipErrorInvalidValue;
+    if (RB * 2 * K > UP_PF * NTH) return hipErrorInvalidValue;
     const int mb = bm.mb;
-    const size_t lds = ((size_t)KP * mb + (size_t)UP_RBP * 2 * K + 4 * (size_t)UP_RBP * mb) * sizeof(double2) +
+    const size_t lds = ((size_t)KP * mb + (size_t)(RB + 1) * 2 * K + 4 * (size_t)(RB + 1) * mb) * sizeof(double2) +
                        (size_t)8 * 2 * MP * sizeof(double);
-    auto kern = update_mfma_kernel<MJ>;
+    auto kern = update_mfma_kernel<MJ, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nparts), dim3(256), lds, s, (const double2*)V, (const float2*)V32, (double2*)U,
+    hipLaunchKernelGGL(kern, dim3(nparts), dim3(NTH), lds, s, (const double2*)V, (const float2*)V32, (double2*)U,
                        (float2*)U32, ld, n, bm, (const double2*)C, theta, npart);
     return hipGetLastError();
 }
 
 hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
                               const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
-                              double* norms, hipStream_t s) {
+                              double* norms, hipStream_t s, int rows) {
     const int mb = bm.mb;
     hipError_t e;
-    if (mb <= 16) e = update_mj<1>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s);
-    else if (mb <= 32) e = update_mj<2>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s);
+    const bool r16 = rows == 16;
+    if (mb <= 16)
+        e = r16 ? update_mj<1, 16>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
+                : update_mj<1, 32>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s);
+    else if (mb <= 32)
+        e = r16 ? update_mj<2, 16>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
+                : update_mj<2, 32>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s);
     else return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
     return launch_reduce(npart, nparts, 2 * mb, norms, s);

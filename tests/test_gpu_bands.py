@@ -174,4 +174,5 @@ def test_autotune_changes_launch_shapes_not_results(B):
     assert t["update_workgroups"] in (256, 512, 1024, 2048)
     assert t["stencil_workgroups"] in (512, 1024, 2048, 4096)
     assert t["fft_x_run"] in (4, 8)
+    assert t["update_rows"] in (16, 32)
     assert np.allclose(e0, e1, rtol=1e-8, atol=1e-9)
