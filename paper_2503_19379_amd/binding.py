@@ -87,6 +87,7 @@ def lib():
         L.mfd_mlp_destroy.restype = None
         L.mfd_warm_target.argtypes = [ctypes.c_longlong, i, vp, vp, vp, vp, vp, vp]
         L.mfd_tuning.argtypes = [vp, ctypes.POINTER(i)]
+        L.mfd_set_tuning.argtypes = [vp, ctypes.POINTER(i)]
         _lib = L
     return _lib
 
@@ -325,3 +326,16 @@ def mfd_tuning(ctx: Context):
         _check(r)
     return bool(r), dict(gram_workgroups=out[0], update_workgroups=out[1], stencil_workgroups=out[2],
                          fft_x_run=out[3], update_rows=out[4])
+
+
+_TUNING_KEYS = ("gram_workgroups", "update_workgroups", "stencil_workgroups", "fft_x_run", "update_rows")
+
+
+def mfd_set_tuning(ctx: Context, shapes):
+    """Pin the launch shapes (a dict with mfd_tuning's keys) for every later
+    solve on ctx; None clears the pin."""
+    if shapes is None:
+        _check(lib().mfd_set_tuning(ctx.handle, None))
+        return
+    arr = (ctypes.c_int * 5)(*[int(shapes[k]) for k in _TUNING_KEYS])
+    _check(lib().mfd_set_tuning(ctx.handle, arr))

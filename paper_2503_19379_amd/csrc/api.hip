@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 #include <atomic>
+#include <initializer_list>
 #include <thread>
 
 #include "../../include/mfdkc.h"
@@ -119,7 +120,7 @@ struct Ws {
     double* host = nullptr;    // pinned: theta | norms | info | column sums
     int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
     int cap_upd = 0, cap_gram = 0; // workgroups the npart / gpart buffers hold partials for
-    int stencil_wgs = 2048, fft_xc = 0, upd_rows = 32;
+    int stencil_wgs = 2048, fft_xc = 0, upd_rows = 0;   // upd_rows 0: one wave per 16-row strip
     WarmStart* warm = nullptr; // learned warm start (warm_start = 2), allocated on first use
     void* wtmp = nullptr;      // orders > 2: operator scratch of this workspace's stream
     Prof prof;
@@ -133,7 +134,7 @@ struct mfd_ctx {
     void* wtmp = nullptr;      // orders > 2: operator scratch for the ABI calls
     int wtmp_bands = 0;
     // launch shapes chosen by the autotuner for one block shape (mb, precision)
-    int tune_mb = 0, tune_mixed = -1;
+    int tune_mb = 0, tune_mixed = -1;   // tune_mb: 0 untuned, -1 pinned by mfd_set_tuning
     int tune[5] = {0, 0, 0, 0, 0};   // Gram workgroups, update workgroups, stencil workgroups, FFT x run,
                                      // update rows per block
     double gamma_override = 0.0;
@@ -810,7 +811,7 @@ int autotune(mfd_ctx* c, Ws& w, const double* k) {
     };
     float2* V32 = w.mixed ? w.V32 : nullptr;
     float2* U32 = w.mixed ? w.U32 : nullptr;
-    int best_gram = w.nparts_gram, best_upd = w.nparts_upd, best_wgs = 2048, best_xc = 0, best_rows = 32;
+    int best_gram = w.nparts_gram, best_upd = w.nparts_upd, best_wgs = 2048, best_xc = 0, best_rows = 0;
     double tb = HUGE_VAL;
     for (int np : {128, 256, 512, 1024}) {
         if (((size_t)np * 32 > n + 31 && np != w.nparts_gram) || np > w.cap_gram) continue;
@@ -818,9 +819,10 @@ int autotune(mfd_ctx* c, Ws& w, const double* k) {
         if (t < tb) { tb = t; best_gram = np; }
     }
     tb = HUGE_VAL;
-    for (int rows : {32, 16})
+    for (int rows : {0, 32, 16})   // 0: one wave per 16-row strip, 4 per workgroup
         for (int np : {256, 512, 1024, 2048}) {
-            if (((size_t)np * rows > n + rows - 1 && np != w.nparts_upd) || np > w.cap_upd) continue;
+            const size_t rows_wg = rows ? (size_t)rows : 64;
+            if (((size_t)np * rows_wg > n + rows_wg - 1 && np != w.nparts_upd) || np > w.cap_upd) continue;
             const double t = timeit([&] {
                 return launch_update_mfma(w.V, V32, w.U, U32, n, n, bm, w.C, w.theta, np, w.npart, w.norms, s,
                                           rows);
@@ -861,10 +863,11 @@ int autotune(mfd_ctx* c, Ws& w, const double* k) {
 }
 
 void apply_tune(const mfd_ctx* c, Ws& w) {
-    if (c->tune_mb != w.mb || c->tune_mixed != (w.mixed ? 1 : 0)) return;
-    if (c->tune[0] > w.cap_gram || c->tune[1] > w.cap_upd) return;
-    w.nparts_gram = c->tune[0];
-    w.nparts_upd = c->tune[1];
+    if (c->tune_mb == 0) return;
+    if (c->tune_mb > 0 && (c->tune_mb != w.mb || c->tune_mixed != (w.mixed ? 1 : 0))) return;
+    // workgroup counts beyond what the partial buffers hold keep the built-in ones
+    if (c->tune[0] <= w.cap_gram) w.nparts_gram = c->tune[0];
+    if (c->tune[1] <= w.cap_upd) w.nparts_upd = c->tune[1];
     w.stencil_wgs = c->tune[2];
     w.fft_xc = c->tune[3];
     w.upd_rows = c->tune[4];
@@ -929,7 +932,32 @@ void mfd_default_opts(mfd_opts* o) {
 int mfd_tuning(const mfd_ctx* ctx, int* out) {
     if (!ctx || !out) return fail(MFD_EINVAL, "NULL argument");
     for (int i = 0; i < 5; ++i) out[i] = ctx->tune[i];
-    return ctx->tune_mb > 0 ? 1 : 0;
+    return ctx->tune_mb != 0 ? 1 : 0;
+}
+
+int mfd_set_tuning(mfd_ctx* ctx, const int* in) {
+    if (!ctx) return fail(MFD_EINVAL, "ctx is NULL");
+    if (!in) {
+        ctx->tune_mb = 0;
+        ctx->tune_mixed = -1;
+        for (int i = 0; i < 5; ++i) ctx->tune[i] = 0;
+        return MFD_OK;
+    }
+    auto one_of = [](int v, std::initializer_list<int> set) {
+        for (int x : set)
+            if (v == x) return true;
+        return false;
+    };
+    if (!one_of(in[0], {128, 256, 512, 1024})) return fail(MFD_EINVAL, "Gram workgroups not a candidate");
+    if (!one_of(in[1], {256, 512, 1024, 2048})) return fail(MFD_EINVAL, "update workgroups not a candidate");
+    if (!one_of(in[2], {512, 1024, 2048, 4096})) return fail(MFD_EINVAL, "stencil workgroups not a candidate");
+    if (!one_of(in[3], {0, 4, 8, 16}) || (in[3] && ctx->N % in[3]))
+        return fail(MFD_EINVAL, "FFT x run must be 0, or 4, 8 or 16 dividing N");
+    if (!one_of(in[4], {0, 16, 32})) return fail(MFD_EINVAL, "update form must be 0, 16 or 32");
+    for (int i = 0; i < 5; ++i) ctx->tune[i] = in[i];
+    ctx->tune_mb = -1;
+    ctx->tune_mixed = -1;
+    return MFD_OK;
 }
 
 int mfd_supported_n(int N) {
@@ -1081,7 +1109,7 @@ int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol, 
     HIPCHK(hipEventRecord(ready, (hipStream_t)stream));
     for (int i = 0; i < nseg; ++i) HIPCHK(hipStreamWaitEvent(ctx->ws[i]->stream, ready, 0));
     hipEventDestroy(ready);
-    if (o.autotune && (ctx->tune_mb != mb || ctx->tune_mixed != (o.precision == 1 ? 1 : 0)))
+    if (o.autotune && ctx->tune_mb >= 0 && (ctx->tune_mb != mb || ctx->tune_mixed != (o.precision == 1 ? 1 : 0)))
         if ((st = autotune(ctx, *ctx->ws[0], kpts))) return st;
     for (int i = 0; i < nseg; ++i) apply_tune(ctx, *ctx->ws[i]);
     std::vector<Segment> segs(nseg);
@@ -1129,7 +1157,8 @@ int mfd_bands_batch(int ncrys, mfd_ctx* const* ctxs, const int* nk, const double
         int st = ensure_ws(ctxs[c], mb, o.precision == 1, 1);
         if (st) { hipEventDestroy(ready); return st; }
         HIPCHK(hipStreamWaitEvent(ctxs[c]->ws[0]->stream, ready, 0));
-        if (o.autotune && (ctxs[c]->tune_mb != mb || ctxs[c]->tune_mixed != (o.precision == 1 ? 1 : 0)))
+        if (o.autotune && ctxs[c]->tune_mb >= 0 &&
+            (ctxs[c]->tune_mb != mb || ctxs[c]->tune_mixed != (o.precision == 1 ? 1 : 0)))
             if ((st = autotune(ctxs[c], *ctxs[c]->ws[0], kpts[c]))) { hipEventDestroy(ready); return st; }
         apply_tune(ctxs[c], *ctxs[c]->ws[0]);
         Segment& sg = segs[c];

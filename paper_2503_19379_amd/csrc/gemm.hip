@@ -12,6 +12,8 @@
 #include "common.h"
 #include "solver.h"
 
+#include <type_traits>
+
 namespace mfd {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -453,19 +455,225 @@ static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The same update with one wave per 16-row strip and no LDS staging of S.
+// The product runs transposed, U^T = C^T S^T: the A operand is a 16-column
+// block of C^T (LDS, zero-padded), the B operand 4 basis columns x 16 rows of
+// S, loaded from HBM straight into registers.  The accumulator tile then holds
+// output column 16 J + lk + 4 r, row li in lane (li, lk), so every store
+// writes 16 consecutive rows (256 bytes in FP64) of 4 columns, and X' and AX'
+// of a row meet in the same lane: R' and the column norms need no exchange.
+// A wave runs the S chain (P', then X') and the AS chain (AP', then AX') of its
+// strip; waves share only C, theta and the column map, so no barrier stands
+// between strips and the other waves of the SIMD cover a wave's load latency.
+// KS0 and KS1 are the k-steps of the two passes (4 basis columns each), at
+// least ceil((K - mb) / 4) over the W and P columns and ceil(mb / 4) over X;
+// steps past the basis run on zero fragments, so the code has no branch
+// between the loads and the matrix products.
+// ---------------------------------------------------------------------------
+template <int MJ, int KS0, int KS1, bool MIX>
+__global__ __launch_bounds__(256, 2) void update_wave_kernel(const double2* __restrict__ V,
+                                                             const float2* __restrict__ V32,
+                                                             double2* __restrict__ U, float2* __restrict__ U32,
+                                                             size_t ld, size_t n, BasisMap bm,
+                                                             const double2* __restrict__ Cg,
+                                                             const double* __restrict__ theta,
+                                                             double* __restrict__ npart) {
+    constexpr int MP = 16 * MJ;
+    // in mixed precision the pass over W and P (AW and AP) reads FP32 columns, the pass over X (AX) FP64
+    using T0 = typename std::conditional<MIX, float2, double2>::type;
+    extern __shared__ unsigned char smem_raw[];
+    const int mb = bm.mb;
+    const int K = bm.K;
+    const int KR = max(mb + 4 * KS0, 4 * KS1);                // rows of Cs the two passes read
+    double2* Cs = reinterpret_cast<double2*>(smem_raw);       // [KR][MP], zero outside K x mb
+    double* th = reinterpret_cast<double*>(Cs + (size_t)KR * MP);   // [MP]
+    double* red = th + MP;                                    // [4 waves][2][MP]
+    double2* xw = reinterpret_cast<double2*>(red + 8 * MP);  // [4 waves][4 MJ][64 lanes]: X' of the S chain
+    int* vmap = reinterpret_cast<int*>(xw + 4 * 4 * MJ * 64); // [2K]: basis column -> V column
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int e = tid; e < KR * MP; e += 256) {
+        const int k = e / MP, j = e % MP;
+        Cs[e] = (k < K && j < mb) ? Cg[(size_t)k * mb + j] : mk<double2>(0.0, 0.0);
+    }
+    for (int q = tid; q < 2 * K; q += 256) vmap[bm.lc[q]] = bm.pc[q];
+    for (int j = tid; j < MP; j += 256) th[j] = j < mb ? theta[j] : 0.0;
+    for (int e = tid; e < 8 * MP; e += 256) red[e] = 0.0;
+    __syncthreads();
+    double* wred = red + wave * 2 * MP;   // this wave's running sums of |R'|^2 and |X'|^2 per column
+    const size_t nstrip = (n + 15) / 16;
+    const size_t nwaves = (size_t)gridDim.x * 4;
+    for (size_t st = (size_t)blockIdx.x * 4 + wave; st < nstrip; st += nwaves) {
+        const size_t row = st * 16 + li;
+        const bool rok = row < n;
+        const size_t rowc = rok ? row : n - 1;   // masked lanes load a valid element and discard it
+        double2* xs = xw + (size_t)wave * 4 * MJ * 64 + lane;   // this lane's X' slots, stride 64
+#pragma unroll 1
+        for (int ch = 0; ch < 2; ++ch) {
+            // B fragments of the chain, lane (li, lk): pass 0 S[row][mb + 4 s + lk], pass 1 S[row][4 s + lk]
+            T0 F0[KS0];
+            double2 F1[KS1];
+            unsigned okm = 0;
+#pragma unroll
+            for (int s = 0; s < KS0; ++s) {
+                const int kk = mb + 4 * s + lk;
+                const bool ok = rok && kk < K;
+                const size_t o = (size_t)vmap[ch * K + min(kk, K - 1)] * ld + rowc;
+                if constexpr (MIX) F0[s] = V32[o];
+                else F0[s] = V[o];
+                okm |= (unsigned)ok << s;
+            }
+#pragma unroll
+            for (int s = 0; s < KS1; ++s) {
+                const int kk = 4 * s + lk;
+                const bool ok = rok && kk < mb;
+                F1[s] = V[(size_t)(ch * 3 * mb + min(kk, mb - 1)) * ld + rowc];   // X and AX are never permuted
+                okm |= (unsigned)ok << (KS0 + s);
+            }
+            d4 acc[MJ][3];
+#pragma unroll
+            for (int J = 0; J < MJ; ++J)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) acc[J][q] = d4{0.0, 0.0, 0.0, 0.0};
+            // C is the same for every strip; an opaque zero offset keeps its LDS
+            // reads inside the loop rather than hoisted into 6 registers per
+            // fragment for the whole kernel
+            int zo;
+            asm volatile("s_mov_b32 %0, 0" : "=s"(zo));
+            const double2* Cz = Cs + zo;
+            auto step = [&](double br, double bi, int kr) {
+                const double bs = br + bi;
+#pragma unroll
+                for (int J = 0; J < MJ; ++J) {
+                    const double2 a = Cz[kr * MP + 16 * J + li];
+                    acc[J][0] = mfma64(a.x, br, acc[J][0]);
+                    acc[J][1] = mfma64(a.y, bi, acc[J][1]);
+                    acc[J][2] = mfma64(a.x + a.y, bs, acc[J][2]);
+                }
+            };
+#pragma unroll
+            for (int s = 0; s < KS0; ++s) {
+                const bool ok = (okm >> s) & 1u;
+                step(ok ? (double)F0[s].x : 0.0, ok ? (double)F0[s].y : 0.0, mb + 4 * s + lk);
+            }
+            // P' (S chain) or AP' (AS chain) of every band
+#pragma unroll
+            for (int J = 0; J < MJ; ++J)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = 16 * J + lk + 4 * r;
+                    if (!rok || j >= mb) continue;
+                    const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
+                    const size_t o = (size_t)((ch ? 5 : 2) * mb + j) * ld + row;
+                    if constexpr (MIX) U32[o] = make_float2((float)(t1 - t2), (float)(t3 - t1 - t2));
+                    else U[o] = mk<double2>(t1 - t2, t3 - t1 - t2);
+                }
+#pragma unroll
+            for (int s = 0; s < KS1; ++s) {
+                const bool ok = (okm >> (KS0 + s)) & 1u;
+                step(ok ? F1[s].x : 0.0, ok ? F1[s].y : 0.0, 4 * s + lk);
+            }
+            if (ch == 0) {
+#pragma unroll
+                for (int J = 0; J < MJ; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
+                        xs[(J * 4 + r) * 64] = mk<double2>(t1 - t2, t3 - t1 - t2);
+                    }
+            } else {
+                // X', AX', R' = AX' - X' theta; column norms (sums over the 16 rows
+                // li, added in strip order to the wave's running sums)
+#pragma unroll
+                for (int J = 0; J < MJ; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = 16 * J + lk + 4 * r;
+                        double nr = 0.0, nx = 0.0;
+                        if (rok && j < mb) {
+                            const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
+                            const double2 ax = mk<double2>(t1 - t2, t3 - t1 - t2);
+                            const double2 x = xs[(J * 4 + r) * 64];
+                            const double tj = th[j];
+                            const double2 res = mk<double2>(ax.x - tj * x.x, ax.y - tj * x.y);
+                            U[(size_t)j * ld + row] = x;
+                            U[(size_t)(3 * mb + j) * ld + row] = ax;
+                            const size_t o = (size_t)(mb + j) * ld + row;
+                            if constexpr (MIX) U32[o] = make_float2((float)res.x, (float)res.y);
+                            else U[o] = res;
+                            nr = cabs2(res);
+                            nx = cabs2(x);
+                        }
+                        for (int o = 8; o > 0; o >>= 1) {
+                            nr += __shfl_down(nr, o, 16);
+                            nx += __shfl_down(nx, o, 16);
+                        }
+                        if (li == 0) {
+                            wred[j] += nr;
+                            wred[MP + j] += nx;
+                        }
+                    }
+            }
+        }
+    }
+    // sums over the 4 waves in order
+    __syncthreads();
+    if (tid < 2 * mb) {
+        const int which = tid / mb, j = tid % mb;
+        double t = 0.0;
+        for (int w = 0; w < 4; ++w) t += red[(w * 2 + which) * MP + j];
+        npart[(size_t)blockIdx.x * 2 * mb + tid] = t;
+    }
+}
+
+template <int MJ, int KS0, int KS1>
+static hipError_t update_wave(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
+                              const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
+                              hipStream_t s) {
+    constexpr int MP = 16 * MJ;
+    const int K = bm.K, mb = bm.mb;
+    if (mb > MP || (K - mb + 3) / 4 > KS0 || (mb + 3) / 4 > KS1 || 2 * K > 128 || !n) return hipErrorInvalidValue;
+    if ((V32 == nullptr) != (U32 == nullptr)) return hipErrorInvalidValue;
+    const size_t lds = (size_t)std::max(mb + 4 * KS0, 4 * KS1) * MP * sizeof(double2) +
+                       (size_t)9 * MP * sizeof(double) + (size_t)4 * 4 * MJ * 64 * sizeof(double2) +
+                       (size_t)2 * K * sizeof(int);
+    auto launch = [&](auto kern) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(nparts), dim3(256), lds, s, (const double2*)V, (const float2*)V32,
+                           (double2*)U, (float2*)U32, ld, n, bm, (const double2*)C, theta, npart);
+        return hipGetLastError();
+    };
+    return V32 ? launch(update_wave_kernel<MJ, KS0, KS1, true>) : launch(update_wave_kernel<MJ, KS0, KS1, false>);
+}
+
 hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
                               const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
                               double* norms, hipStream_t s, int rows) {
     const int mb = bm.mb;
+    const int nk0 = (bm.K - mb + 3) / 4;   // k-steps over the W and P columns
     hipError_t e;
-    const bool r16 = rows == 16;
-    if (mb <= 16)
-        e = r16 ? update_mj<1, 16>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
-                : update_mj<1, 32>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s);
-    else if (mb <= 32)
-        e = r16 ? update_mj<2, 16>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
-                : update_mj<2, 32>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s);
-    else return hipErrorInvalidValue;
+#define UPW(MJ, KS0, KS1) update_wave<MJ, KS0, KS1>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
+#define UPB(MJ, RB) update_mj<MJ, RB>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
+    if (mb < 1 || mb > 21) return hipErrorInvalidValue;
+    if (rows == 0 && mb <= 16)
+        e = nk0 <= 2 ? UPW(1, 2, 4) : nk0 <= 4 ? UPW(1, 4, 4) : nk0 <= 6 ? UPW(1, 6, 4) : UPW(1, 8, 4);
+    else if (rows == 0 && mb <= 20)
+        e = nk0 <= 2   ? UPW(2, 2, 5)
+            : nk0 <= 4 ? UPW(2, 4, 5)
+            : nk0 <= 6 ? UPW(2, 6, 5)
+            : nk0 <= 8 ? UPW(2, 8, 5)
+                       : UPW(2, 10, 5);
+    else if (rows == 0)
+        e = nk0 <= 4 ? UPW(2, 4, 6) : nk0 <= 8 ? UPW(2, 8, 6) : UPW(2, 11, 6);
+    else if (mb <= 16)
+        e = rows == 16 ? UPB(1, 16) : UPB(1, 32);
+    else
+        e = rows == 16 ? UPB(2, 16) : UPB(2, 32);
+#undef UPW
+#undef UPB
     if (e != hipSuccess) return e;
     return launch_reduce(npart, nparts, 2 * mb, norms, s);
 }

@@ -33,10 +33,10 @@ int gram_mfma_parts(size_t n);
 size_t gram_mfma_part_elems(int K, int nparts);
 // U = [X' | R' | P' | AX' | - | AP'] from the K x mb coefficients C, every
 // band.  U32 (or null): FP32 outputs R', P', AP' (mixed precision).
-// rows: rows per workgroup block, 16 or 32.
+// rows: 0 one wave per 16-row strip; 16 or 32 rows per workgroup block.
 hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
                               const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
-                              double* norms, hipStream_t s, int rows = 32);
+                              double* norms, hipStream_t s, int rows = 0);
 // R = AX - X theta written to W (FP32 if R32), column norms |R|^2, |X|^2 (blas.hip).
 hipError_t launch_residual(const void* X, const void* AX, void* R, bool r32, size_t ld, size_t n, int mb,
                            const double* theta, int nparts, double* npart, double* norms, hipStream_t s);

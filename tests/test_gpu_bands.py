@@ -1,6 +1,8 @@
 """GPU band solve (LOBPCG + FFT preconditioner + Alg 4.1) against the oracle:
 closed form (eps = 1), dense eigendecomposition (tiny grids) and the oracle's
 LOBPCG."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -174,5 +176,39 @@ def test_autotune_changes_launch_shapes_not_results(B):
     assert t["update_workgroups"] in (256, 512, 1024, 2048)
     assert t["stencil_workgroups"] in (512, 1024, 2048, 4096)
     assert t["fft_x_run"] in (4, 8)
-    assert t["update_rows"] in (16, 32)
+    assert t["update_rows"] in (0, 16, 32)
     assert np.allclose(e0, e1, rtol=1e-8, atol=1e-9)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_bands_n10(m):
+    k = workloads.kpath("GXMGR", 8)[3]
+    lam, _, _ = olob.solve_bands(workloads.eps_diamond(10), 1.0, k, m, tol=1e-10)
+    return lam
+
+
+@pytest.mark.parametrize("form", [0, 16, 32])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_update_forms_agree(B, form, precision):
+    """The three forms of the block update (one wave per 16-row strip, 16- or
+    32-row workgroup blocks) give the same bands, all within the oracle's;
+    mb = 18 exercises the two-tile column blocks, a ragged last strip
+    (n = 3 * 10^3 = 3000 rows) the row masks."""
+    N, m = 10, 16
+    eps = workloads.eps_diamond(N)
+    k = workloads.kpath("GXMGR", 8)[3]
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    B.mfd_set_tuning(ctx, dict(gram_workgroups=256, update_workgroups=256, stencil_workgroups=2048,
+                               fft_x_run=0, update_rows=form))
+    assert B.mfd_tuning(ctx) == (True, dict(gram_workgroups=256, update_workgroups=256,
+                                            stencil_workgroups=2048, fft_x_run=0, update_rows=form))
+    tol = 1e-8 if precision else 1e-10
+    ev, st, status = B.mfd_bands(ctx, [k], m, tol, B.default_opts(precision=precision, streams=1))
+    assert status == 0, st
+    lam = _oracle_bands_n10(m)
+    assert np.allclose(ev[0], lam, rtol=1e-7 if precision else 1e-9), (form, ev[0], lam)
+    with pytest.raises(B.MfdError):
+        B.mfd_set_tuning(ctx, dict(gram_workgroups=256, update_workgroups=256, stencil_workgroups=2048,
+                                   fft_x_run=0, update_rows=8))
+    B.mfd_set_tuning(ctx, None)
+    assert B.mfd_tuning(ctx)[0] is False

@@ -53,6 +53,7 @@ def test_host_side_argument_errors():
     assert L.mfd_mlp_create(8, 0, 1, 4, 2, 1, 0, ctypes.byref(h)) == -1
     assert L.mfd_mlp_create(8, 8, 1, 4, 0, 1, 0, ctypes.byref(h)) == -1
     assert L.mfd_tuning(None, None) == -1
+    assert L.mfd_set_tuning(None, None) == -1
     eps = (ctypes.c_double * 512)(*([1.0] * 512))
     dp = ctypes.cast(eps, ctypes.POINTER(ctypes.c_double))
     assert L.mfd_build(8, 1.0, 3, dp, None, ctypes.byref(h)) == -6      # order 3: unsupported
