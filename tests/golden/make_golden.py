@@ -41,7 +41,8 @@ def make(name):
     eps = workloads.crystal_eps(cfg["eps"], N)
     kp = workloads.kpath(cfg["path"], cfg["nk"])
     lines = [f"# {name}: oracle band energies (eq. (Ker_comp) after Alg 4.1), FP64 LOBPCG with the FFT",
-             f"# preconditioner (Section 5), relative residual <= {tol:g}, seeded random start (seed 0).",
+             f"# preconditioner (Section 5), iteration tolerance {tol:g} (each row's fresh residual",
+             f"# max_rel_resid is at most {2 * tol:g}), seeded random start (seed 0).",
              f"# N = {N}, L = 1, {cfg['nk']} k-points on {cfg['path']}, m = {m}; written by",
              f"# `python -m tests.golden.make_golden {name}` (calls only oracle/ and the input generators).",
              "# columns: k_index kx ky kz gamma max_rel_resid lambda_1 ... lambda_m"]
