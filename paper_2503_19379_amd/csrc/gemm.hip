@@ -54,8 +54,11 @@ __device__ __forceinline__ double2 widen(double2 raw, bool f32) {
 // One wave per 16-column block g of S.  Block g is the A operand of exactly
 // T + 1 tiles (T = ceil(K / 16)): the G_S tiles (g, b), b >= g, and the G_A
 // tiles (g, a), a <= g, so the wave loads its A fragment once per 4 rows and
-// reuses it for all of them.  The next slab is loaded into registers while the
-// current one is consumed from LDS by the matrix cores.
+// reuses it for all of them.  Two LDS slabs alternate: the next slab is
+// loaded into registers and written to the free slab while the current one is
+// consumed by the matrix cores, with one barrier per slab.  The two waves of a
+// block (alternate 4-row steps) add their tiles through LDS at the end, so a
+// workgroup writes one partial tile set.
 template <int T>
 __global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __restrict__ V,
                                                              const float2* __restrict__ V32, size_t ld, size_t n,
@@ -64,9 +67,10 @@ __global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __res
     constexpr int NT = 128 * T;   // two waves per block of S, each taking every other 4 rows
     constexpr int TG = T + 1;     // tiles per wave
     extern __shared__ unsigned char smem_raw[];
-    double2* slab = reinterpret_cast<double2*>(smem_raw);   // [GM_KS][2K]
+    double2* slabs = reinterpret_cast<double2*>(smem_raw);   // [2][GM_KS][2K]
     const int K = bm.K;
     const int C2 = 2 * K;
+    const int SL = GM_KS * C2;
     const int tid = threadIdx.x;
     const int lane = tid & 63, g = (tid >> 6) >> 1, sub = (tid >> 6) & 1;
     const size_t r0 = (size_t)blockIdx.x * rows_per;
@@ -119,13 +123,19 @@ __global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __res
             }
         }
     };
-    prefetch(r0);
-    for (size_t s0 = r0; s0 < r1; s0 += GM_KS) {
+    auto fill = [&](double2* slab) {
 #pragma unroll
         for (int q = 0; q < GM_PF; ++q)
             if ((okm >> q) & 1u) slab[srow * C2 + scol[q]] = widen(pf[q], (f32m >> q) & 1u);
-        __syncthreads();
-        if (s0 + GM_KS < r1) prefetch(s0 + GM_KS);
+    };
+    prefetch(r0);
+    fill(slabs);
+    __syncthreads();
+    int buf = 0;
+    for (size_t s0 = r0; s0 < r1; s0 += GM_KS) {
+        const bool more = s0 + GM_KS < r1;
+        if (more) prefetch(s0 + GM_KS);
+        const double2* slab = slabs + buf * SL;
 #pragma unroll
         for (int k0 = 4 * sub; k0 < GM_KS; k0 += 8) {
             const double2* srow_p = slab + (k0 + lk) * C2;
@@ -139,18 +149,35 @@ __global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __res
                 acc[t][2] = mfma64(amd, b.x + b.y, acc[t][2]);
             }
         }
+        // the free slab was last read before the previous barrier
+        if (more) fill(slabs + (buf ^ 1) * SL);
         __syncthreads();
+        buf ^= 1;
     }
-    // partial tiles: part[2 w + sub][tile][16][16], tiles of block g at g TG .. g TG + T
-    double2* out = part + (size_t)(2 * blockIdx.x + sub) * (T * TG) * 256;
+    // sub 1 hands its tiles to sub 0 through LDS (the slabs are free after the
+    // last barrier); partial tiles part[w][tile][16][16], tiles of block g at g TG .. g TG + T
+    double2* xch = slabs;   // [T TG][4][64]
+    if (sub == 1) {
 #pragma unroll
-    for (int t = 0; t < TG; ++t) {
-        const int ti = g * TG + t;
+        for (int t = 0; t < TG; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = lk + 4 * r, colj = li;
-            const double t1 = acc[t][0][r], t2 = acc[t][1][r], t3 = acc[t][2][r];
-            out[(size_t)ti * 256 + row * 16 + colj] = mk<double2>(t1 + t2, t3 - t1 + t2);
+            for (int r = 0; r < 4; ++r) {
+                const double t1 = acc[t][0][r], t2 = acc[t][1][r], t3 = acc[t][2][r];
+                xch[((g * TG + t) * 4 + r) * 64 + lane] = mk<double2>(t1 + t2, t3 - t1 + t2);
+            }
+    }
+    __syncthreads();
+    if (sub == 0) {
+        double2* out = part + (size_t)blockIdx.x * (T * TG) * 256;
+#pragma unroll
+        for (int t = 0; t < TG; ++t) {
+            const int ti = g * TG + t;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double t1 = acc[t][0][r], t2 = acc[t][1][r], t3 = acc[t][2][r];
+                const double2 o = xch[((g * TG + t) * 4 + r) * 64 + lane];
+                out[(size_t)ti * 256 + (lk + 4 * r) * 16 + li] = mk<double2>(t1 + t2 + o.x, t3 - t1 + t2 + o.y);
+            }
         }
     }
 }
@@ -203,13 +230,14 @@ int gram_mfma_parts(size_t n) { return (int)std::min<size_t>(512, (n + 1023) / 1
 
 size_t gram_mfma_part_elems(int K, int nparts) {
     const int T = (K + 15) / 16;
-    return (size_t)(2 * nparts + 1) * T * (T + 1) * 256;   // two partial sets per workgroup + their sum
+    return (size_t)(nparts + 1) * T * (T + 1) * 256;   // one partial set per workgroup + their sum
 }
 
 template <int T>
 static hipError_t gram_t(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nw,
                          size_t rows_per, void* part, hipStream_t s) {
-    const size_t lds = (size_t)GM_KS * 2 * bm.K * sizeof(double2);
+    // two slabs, or the tile exchange at the end if larger
+    const size_t lds = std::max((size_t)2 * GM_KS * 2 * bm.K, (size_t)T * (T + 1) * 4 * 64) * sizeof(double2);
     auto kern = gram_mfma_kernel<T>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -236,9 +264,9 @@ hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n,
         default: e = gram_t<4>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
     }
     if (e != hipSuccess) return e;
-    // sum the 2 nw partial tile sets (into the slot after the last), then scatter
-    double2* sum = (double2*)part + (size_t)2 * nw * tl.n * 256;
-    if ((e = launch_reduce((const double*)part, 2 * nw, tl.n * 256 * 2, (double*)sum, s)) != hipSuccess) return e;
+    // sum the nw partial tile sets (into the slot after the last), then scatter
+    double2* sum = (double2*)part + (size_t)nw * tl.n * 256;
+    if ((e = launch_reduce((const double*)part, nw, tl.n * 256 * 2, (double*)sum, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(gram_scatter_kernel, dim3((tl.n * 256 + 255) / 256), dim3(256), 0, s, (const double2*)sum, K, tl,
                        (double2*)G);
     return hipGetLastError();

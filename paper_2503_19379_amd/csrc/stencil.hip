@@ -12,8 +12,9 @@
 //   w = A e : w1 = D2 e3 - D3 e2,  w2 = D3 e1 - D1 e3,  w3 = D1 e2 - D2 e1
 //   q = B v = D1 v1 + D2 v2 + D3 v3,   w_i += gamma D_i' q.
 //
-// Kernel design (HBM-bound: v is read once, w written once, mu read once per
-// band).  A workgroup owns an x-y tile of N x TY cells plus one halo row on
+// Kernel design (HBM-bound: v is read once, w written once, mu read from HBM
+// about once per launch, since the bands of a tile run side by side and share
+// it in L2).  A workgroup owns an x-y tile of N x TY cells plus one halo row on
 // each side in y (x is a full periodic row, so x neighbours never leave the
 // tile) and marches through a chunk of z planes.  Each thread owns one (x, y)
 // column and keeps its z history in registers; in-plane neighbours travel
@@ -54,11 +55,13 @@ __global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R, S> a) {
 
     const int tx = threadIdx.x;
     const int ty = threadIdx.y;
+    // band fastest, then y tile, then z chunk: the bands of one tile run side
+    // by side on one XCD and share its mu planes and halo rows in L2
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int ytile = bid % a.nyt;
-    const int rest = bid / a.nyt;
-    const int zch = rest % a.nzc;
-    const int band = rest / a.nzc;
+    const int band = bid % a.nb;
+    const int rest = bid / a.nb;
+    const int ytile = rest % a.nyt;
+    const int zch = rest / a.nyt;
 
     const int y0 = ytile * TY;
     const int yg = (y0 - 1 + ty + N) % N;
