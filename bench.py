@@ -160,6 +160,11 @@ def main():
         print("bench.py runs on one GPU: this build has no multi-GPU path "
               "(k-points would shard across GPUs with no exchange between them)", file=sys.stderr)
         sys.exit(2)
+    # One hardware queue per concurrent k-path segment: with fewer, segments
+    # share a queue and one segment's one-workgroup Rayleigh-Ritz step holds up
+    # the other's kernels.  HIP reads this when it initialises, below.
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < args.streams:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.streams, 32))
     import torch
     from paper_2503_19379_amd import binding as B
     from paper_2503_19379_amd import workloads
@@ -301,7 +306,8 @@ def main():
                                f"({n} unknowns), {nk} k-points on {cfg['path']}, {m} bands, tol {args.tol:g}, "
                                f"{args.precision}, {args.streams} concurrent k-path segments",
                    "N": N, "nbands": m, "nk": nk, "tol": args.tol, "precision": args.precision,
-                   "warm_start": args.warm, "guard": args.guard, "streams": args.streams},
+                   "warm_start": args.warm, "guard": args.guard, "streams": args.streams,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "roofline_source": "HIP events recorded around each launch on its own stream during the timed steps "
                            "(concurrent k-path segments overlap); kernels_isolated: the same from a "
                            f"single-stream pass over {min(args.roofline_nk, nk)} k-points after the timed steps",

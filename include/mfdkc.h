@@ -76,7 +76,9 @@ typedef struct {
                                  compensation modes that Alg 4.1 flags and discards */
     int streams;              /* k-path segments (mfd_bands) or crystals (mfd_bands_batch) solved
                                  concurrently, each on its own stream and host thread (default 4,
-                                 at most 16) */
+                                 at most 16).  The streams run side by side only with as many
+                                 hardware queues: set GPU_MAX_HW_QUEUES >= streams before the
+                                 process first uses HIP (HIP's default is 4) */
     const void* x0;           /* optional device c128 start block [nbands][3][N][N][N] for the first
                                  k-point (NULL: random) */
     int stall_window;         /* precision 1: iterations without a halving of the largest
