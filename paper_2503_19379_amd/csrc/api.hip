@@ -509,13 +509,15 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
                          "rr-ticks %d %d %d %d %d Kk %d\n", (void*)&w, it, rmax, nact, hinfo[0], hinfo[1], hinfo[3], hth[0],
                          hth[nreq - 1], hinfo[4], hinfo[5], hinfo[6], hinfo[7], hinfo[8], hinfo[9]);
         }
-        // Mixed precision: the tracked AX = [AX AW AP] C drifts from A X by the
-        // FP32 rounding of AW and AP; recompute AX with the FP64 operator to
-        // confirm convergence, and every 15 iterations.
-        if (mixed && it > 0 && (conv || it - last_refresh >= 15)) {
+        // The tracked AX = [AX AW AP] C drifts from A X (in mixed precision by
+        // the FP32 rounding of AW and AP, every 15 iterations recomputed with
+        // the FP64 operator).  Convergence is confirmed with a fresh A X in
+        // every mode, the FP64 fallback included; if the fresh residuals miss
+        // the target, the iteration goes on from the refreshed state.
+        if (it > 0 && it != last_refresh && (conv || (mixed && it - last_refresh >= 15))) {
             HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
-            HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), V32 + n * mb, true, n, n, mb, w.theta,
-                                   w.nparts_col, w.npart, w.norms, s));
+            HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), mixed ? (void*)(V32 + n * mb) : col(V, n, mb),
+                                   mixed, n, n, mb, w.theta, w.nparts_col, w.npart, w.norms, s));
             HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             conv = residuals(&rmax);

@@ -485,12 +485,16 @@ static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, 
 
 // ---------------------------------------------------------------------------
 // The same update with one wave per 16-row strip and no LDS staging of S.
-// The product runs transposed, U^T = C^T S^T: the A operand is a 16-column
-// block of C^T (LDS, zero-padded), the B operand 4 basis columns x 16 rows of
-// S, loaded from HBM straight into registers.  The accumulator tile then holds
-// output column 16 J + lk + 4 r, row li in lane (li, lk), so every store
-// writes 16 consecutive rows (256 bytes in FP64) of 4 columns, and X' and AX'
-// of a row meet in the same lane: R' and the column norms need no exchange.
+// The product runs transposed, U^T = C^T S^T: the A operand is the first 16
+// columns of C^T (LDS), the B operand 4 basis columns x 16 rows of S, loaded
+// from HBM straight into registers.  The accumulator tile then holds output
+// column lk + 4 r, row li in lane (li, lk), so every store writes 16
+// consecutive rows (256 bytes in FP64) of 4 columns, and X' and AX' of a row
+// meet in the same lane: R' and the column norms need no exchange.
+// Bands 16 .. mb-1 (at most NT of them) would fill a second 16-column tile
+// mostly with zeros; they run instead as FP64 vector FMAs on the fragments
+// already in registers (lane (li, lk) adds its own basis columns for row li)
+// and are summed over the 4 lanes of a row with two shuffles.
 // A wave runs the S chain (P', then X') and the AS chain (AP', then AX') of its
 // strip; waves share only C, theta and the column map, so no barrier stands
 // between strips and the other waves of the SIMD cover a wave's load latency.
@@ -499,7 +503,7 @@ static hipError_t update_mj(const void* V, const void* V32, void* U, void* U32, 
 // steps past the basis run on zero fragments, so the code has no branch
 // between the loads and the matrix products.
 // ---------------------------------------------------------------------------
-template <int MJ, int KS0, int KS1, bool MIX>
+template <int KS0, int KS1, int NT, bool MIX>
 __global__ __launch_bounds__(256, 2) void update_wave_kernel(const double2* __restrict__ V,
                                                              const float2* __restrict__ V32,
                                                              double2* __restrict__ U, float2* __restrict__ U32,
@@ -507,165 +511,201 @@ __global__ __launch_bounds__(256, 2) void update_wave_kernel(const double2* __re
                                                              const double2* __restrict__ Cg,
                                                              const double* __restrict__ theta,
                                                              double* __restrict__ npart) {
-    constexpr int MP = 16 * MJ;
+    constexpr int CW = 16 + ((NT + 1) & ~1);   // columns of C kept in LDS (zero past mb); even, so
+                                               // the double2 arrays after th and red stay 16-byte aligned
+    constexpr int NX = 4 + NT;                 // X' slots per lane
     // in mixed precision the pass over W and P (AW and AP) reads FP32 columns, the pass over X (AX) FP64
     using T0 = typename std::conditional<MIX, float2, double2>::type;
     extern __shared__ unsigned char smem_raw[];
     const int mb = bm.mb;
     const int K = bm.K;
     const int KR = max(mb + 4 * KS0, 4 * KS1);                // rows of Cs the two passes read
-    double2* Cs = reinterpret_cast<double2*>(smem_raw);       // [KR][MP], zero outside K x mb
-    double* th = reinterpret_cast<double*>(Cs + (size_t)KR * MP);   // [MP]
-    double* red = th + MP;                                    // [4 waves][2][MP]
-    double2* xw = reinterpret_cast<double2*>(red + 8 * MP);  // [4 waves][4 MJ][64 lanes]: X' of the S chain
-    int* vmap = reinterpret_cast<int*>(xw + 4 * 4 * MJ * 64); // [2K]: basis column -> V column
+    double2* Cs = reinterpret_cast<double2*>(smem_raw);       // [KR][CW], zero outside K x mb
+    double* th = reinterpret_cast<double*>(Cs + (size_t)KR * CW);   // [CW]
+    double* red = th + CW;                                    // [4 waves][2][CW]
+    double2* xw = reinterpret_cast<double2*>(red + 8 * CW);   // [4 waves][NX][64 lanes]: X' of the S chain
+    int* vmap = reinterpret_cast<int*>(xw + 4 * NX * 64);     // [2K]: basis column -> V column
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    for (int e = tid; e < KR * MP; e += 256) {
-        const int k = e / MP, j = e % MP;
+    for (int e = tid; e < KR * CW; e += 256) {
+        const int k = e / CW, j = e % CW;
         Cs[e] = (k < K && j < mb) ? Cg[(size_t)k * mb + j] : mk<double2>(0.0, 0.0);
     }
     for (int q = tid; q < 2 * K; q += 256) vmap[bm.lc[q]] = bm.pc[q];
-    for (int j = tid; j < MP; j += 256) th[j] = j < mb ? theta[j] : 0.0;
-    for (int e = tid; e < 8 * MP; e += 256) red[e] = 0.0;
+    for (int j = tid; j < CW; j += 256) th[j] = j < mb ? theta[j] : 0.0;
+    for (int e = tid; e < 8 * CW; e += 256) red[e] = 0.0;
     __syncthreads();
-    double* wred = red + wave * 2 * MP;   // this wave's running sums of |R'|^2 and |X'|^2 per column
+    double* wred = red + wave * 2 * CW;   // this wave's running sums of |R'|^2 and |X'|^2 per column
+    double2* xs = xw + (size_t)wave * NX * 64 + lane;   // this lane's X' slots, stride 64
     const size_t nstrip = (n + 15) / 16;
     const size_t nwaves = (size_t)gridDim.x * 4;
-    for (size_t st = (size_t)blockIdx.x * 4 + wave; st < nstrip; st += nwaves) {
+    // sum over the 4 lanes of a row (lk = 0..3), result in all of them
+    auto rowsum = [](double v) {
+        v += __shfl_xor(v, 16);
+        return v + __shfl_xor(v, 32);
+    };
+    // B fragments of one chain of one strip, lane (li, lk): pass 0
+    // S[row][mb + 4 s + lk], pass 1 S[row][4 s + lk]; okm flags the lanes and
+    // steps that hold a basis column of a row < n
+    struct Frag {
+        T0 f0[KS0];
+        double2 f1[KS1];
+        unsigned okm;
+    };
+    auto load = [&](Frag& F, size_t st, int ch) {   // issued, not waited for
         const size_t row = st * 16 + li;
         const bool rok = row < n;
         const size_t rowc = rok ? row : n - 1;   // masked lanes load a valid element and discard it
-        double2* xs = xw + (size_t)wave * 4 * MJ * 64 + lane;   // this lane's X' slots, stride 64
-#pragma unroll 1
-        for (int ch = 0; ch < 2; ++ch) {
-            // B fragments of the chain, lane (li, lk): pass 0 S[row][mb + 4 s + lk], pass 1 S[row][4 s + lk]
-            T0 F0[KS0];
-            double2 F1[KS1];
-            unsigned okm = 0;
+        F.okm = 0;
 #pragma unroll
-            for (int s = 0; s < KS0; ++s) {
-                const int kk = mb + 4 * s + lk;
-                const bool ok = rok && kk < K;
-                const size_t o = (size_t)vmap[ch * K + min(kk, K - 1)] * ld + rowc;
-                if constexpr (MIX) F0[s] = V32[o];
-                else F0[s] = V[o];
-                okm |= (unsigned)ok << s;
-            }
-#pragma unroll
-            for (int s = 0; s < KS1; ++s) {
-                const int kk = 4 * s + lk;
-                const bool ok = rok && kk < mb;
-                F1[s] = V[(size_t)(ch * 3 * mb + min(kk, mb - 1)) * ld + rowc];   // X and AX are never permuted
-                okm |= (unsigned)ok << (KS0 + s);
-            }
-            d4 acc[MJ][3];
-#pragma unroll
-            for (int J = 0; J < MJ; ++J)
-#pragma unroll
-                for (int q = 0; q < 3; ++q) acc[J][q] = d4{0.0, 0.0, 0.0, 0.0};
-            // C is the same for every strip; an opaque zero offset keeps its LDS
-            // reads inside the loop rather than hoisted into 6 registers per
-            // fragment for the whole kernel
-            int zo;
-            asm volatile("s_mov_b32 %0, 0" : "=s"(zo));
-            const double2* Cz = Cs + zo;
-            auto step = [&](double br, double bi, int kr) {
-                const double bs = br + bi;
-#pragma unroll
-                for (int J = 0; J < MJ; ++J) {
-                    const double2 a = Cz[kr * MP + 16 * J + li];
-                    acc[J][0] = mfma64(a.x, br, acc[J][0]);
-                    acc[J][1] = mfma64(a.y, bi, acc[J][1]);
-                    acc[J][2] = mfma64(a.x + a.y, bs, acc[J][2]);
-                }
-            };
-#pragma unroll
-            for (int s = 0; s < KS0; ++s) {
-                const bool ok = (okm >> s) & 1u;
-                step(ok ? (double)F0[s].x : 0.0, ok ? (double)F0[s].y : 0.0, mb + 4 * s + lk);
-            }
-            // P' (S chain) or AP' (AS chain) of every band
-#pragma unroll
-            for (int J = 0; J < MJ; ++J)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = 16 * J + lk + 4 * r;
-                    if (!rok || j >= mb) continue;
-                    const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
-                    const size_t o = (size_t)((ch ? 5 : 2) * mb + j) * ld + row;
-                    if constexpr (MIX) U32[o] = make_float2((float)(t1 - t2), (float)(t3 - t1 - t2));
-                    else U[o] = mk<double2>(t1 - t2, t3 - t1 - t2);
-                }
-#pragma unroll
-            for (int s = 0; s < KS1; ++s) {
-                const bool ok = (okm >> (KS0 + s)) & 1u;
-                step(ok ? F1[s].x : 0.0, ok ? F1[s].y : 0.0, 4 * s + lk);
-            }
-            if (ch == 0) {
-#pragma unroll
-                for (int J = 0; J < MJ; ++J)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
-                        xs[(J * 4 + r) * 64] = mk<double2>(t1 - t2, t3 - t1 - t2);
-                    }
-            } else {
-                // X', AX', R' = AX' - X' theta; column norms (sums over the 16 rows
-                // li, added in strip order to the wave's running sums)
-#pragma unroll
-                for (int J = 0; J < MJ; ++J)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int j = 16 * J + lk + 4 * r;
-                        double nr = 0.0, nx = 0.0;
-                        if (rok && j < mb) {
-                            const double t1 = acc[J][0][r], t2 = acc[J][1][r], t3 = acc[J][2][r];
-                            const double2 ax = mk<double2>(t1 - t2, t3 - t1 - t2);
-                            const double2 x = xs[(J * 4 + r) * 64];
-                            const double tj = th[j];
-                            const double2 res = mk<double2>(ax.x - tj * x.x, ax.y - tj * x.y);
-                            U[(size_t)j * ld + row] = x;
-                            U[(size_t)(3 * mb + j) * ld + row] = ax;
-                            const size_t o = (size_t)(mb + j) * ld + row;
-                            if constexpr (MIX) U32[o] = make_float2((float)res.x, (float)res.y);
-                            else U[o] = res;
-                            nr = cabs2(res);
-                            nx = cabs2(x);
-                        }
-                        for (int o = 8; o > 0; o >>= 1) {
-                            nr += __shfl_down(nr, o, 16);
-                            nx += __shfl_down(nx, o, 16);
-                        }
-                        if (li == 0) {
-                            wred[j] += nr;
-                            wred[MP + j] += nx;
-                        }
-                    }
-            }
+        for (int s = 0; s < KS0; ++s) {
+            const int kk = mb + 4 * s + lk;
+            const size_t o = (size_t)vmap[ch * K + min(kk, K - 1)] * ld + rowc;
+            if constexpr (MIX) F.f0[s] = V32[o];
+            else F.f0[s] = V[o];
+            F.okm |= (unsigned)(rok && kk < K) << s;
         }
+#pragma unroll
+        for (int s = 0; s < KS1; ++s) {
+            const int kk = 4 * s + lk;
+            F.f1[s] = V[(size_t)(ch * 3 * mb + min(kk, mb - 1)) * ld + rowc];   // X and AX are never permuted
+            F.okm |= (unsigned)(rok && kk < mb) << (KS0 + s);
+        }
+    };
+    // one chain of one strip: ch 0 (S) writes P' and keeps X' in LDS, ch 1 (AS)
+    // writes AP', then X', AX', R' and adds the column norms
+    auto chain = [&](const Frag& F, size_t st, int ch) {
+        const size_t row = st * 16 + li;
+        const bool rok = row < n;
+        d4 acc[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+        double tre[NT > 0 ? NT : 1], tim[NT > 0 ? NT : 1];   // tail bands: this lane's partial sums
+#pragma unroll
+        for (int c = 0; c < NT; ++c) tre[c] = tim[c] = 0.0;
+        // C is the same for every strip; an opaque zero offset keeps its LDS
+        // reads here rather than hoisted into registers for the whole kernel
+        int zo;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(zo));
+        const double2* Cz = Cs + zo;
+        auto step = [&](double br, double bi, int kr) {
+            // keep each step's LDS reads in place: hoisted together they
+            // would hold every step's C values in registers at once
+            __builtin_amdgcn_sched_barrier(0);
+            const double2 a = Cz[kr * CW + li];
+            acc[0] = mfma64(a.x, br, acc[0]);
+            acc[1] = mfma64(a.y, bi, acc[1]);
+            acc[2] = mfma64(a.x + a.y, br + bi, acc[2]);
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const double2 t = Cz[kr * CW + 16 + c];
+                tre[c] = fma(br, t.x, fma(-bi, t.y, tre[c]));
+                tim[c] = fma(br, t.y, fma(bi, t.x, tim[c]));
+                // the sums are due here: deferred to their use, the FMAs
+                // would keep every step's C values live (no instruction)
+                asm volatile("" : "+v"(tre[c]), "+v"(tim[c]));
+            }
+        };
+#pragma unroll
+        for (int s = 0; s < KS0; ++s) {
+            const bool ok = (F.okm >> s) & 1u;
+            step(ok ? (double)F.f0[s].x : 0.0, ok ? (double)F.f0[s].y : 0.0, mb + 4 * s + lk);
+        }
+        // P' (S chain) or AP' (AS chain) of every band
+        auto put = [&](int j, double re, double im) {   // column (ch ? 5 : 2) mb + j, row
+            const size_t o = (size_t)((ch ? 5 : 2) * mb + j) * ld + row;
+            if constexpr (MIX) U32[o] = make_float2((float)re, (float)im);
+            else U[o] = mk<double2>(re, im);
+        };
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = lk + 4 * r;
+            if (rok && j < mb) put(j, acc[0][r] - acc[1][r], acc[2][r] - acc[0][r] - acc[1][r]);
+        }
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const double re = rowsum(tre[c]), im = rowsum(tim[c]);
+            if (rok && 16 + c < mb && lk == (c & 3)) put(16 + c, re, im);
+        }
+#pragma unroll
+        for (int s = 0; s < KS1; ++s) {
+            const bool ok = (F.okm >> (KS0 + s)) & 1u;
+            step(ok ? F.f1[s].x : 0.0, ok ? F.f1[s].y : 0.0, 4 * s + lk);
+        }
+        if (ch == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                xs[r * 64] = mk<double2>(acc[0][r] - acc[1][r], acc[2][r] - acc[0][r] - acc[1][r]);
+#pragma unroll
+            for (int c = 0; c < NT; ++c) xs[(4 + c) * 64] = mk<double2>(rowsum(tre[c]), rowsum(tim[c]));
+            return;
+        }
+        // X', AX', R' = AX' - X' theta; column norms (sums over the 16 rows li,
+        // added in strip order to the wave's running sums)
+        auto finish = [&](int j, double2 x, double2 ax, bool mine) {
+            double nr = 0.0, nx = 0.0;
+            if (mine && rok && j < mb) {
+                const double tj = th[j];
+                const double2 res = mk<double2>(ax.x - tj * x.x, ax.y - tj * x.y);
+                U[(size_t)j * ld + row] = x;
+                U[(size_t)(3 * mb + j) * ld + row] = ax;
+                const size_t o = (size_t)(mb + j) * ld + row;
+                if constexpr (MIX) U32[o] = make_float2((float)res.x, (float)res.y);
+                else U[o] = res;
+                nr = cabs2(res);
+                nx = cabs2(x);
+            }
+            for (int o = 8; o > 0; o >>= 1) {
+                nr += __shfl_down(nr, o, 16);
+                nx += __shfl_down(nx, o, 16);
+            }
+            if (mine && li == 0) {
+                wred[j] += nr;
+                wred[CW + j] += nx;
+            }
+        };
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            finish(lk + 4 * r, xs[r * 64], mk<double2>(acc[0][r] - acc[1][r], acc[2][r] - acc[0][r] - acc[1][r]),
+                   true);
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+            finish(16 + c, xs[(4 + c) * 64], mk<double2>(rowsum(tre[c]), rowsum(tim[c])), lk == (c & 3));
+    };
+    // Software pipeline over the chains: the AS fragments of a strip load while
+    // its S chain runs, the next strip's S fragments while its AS chain runs,
+    // so each wave keeps one chain's loads in flight behind its matrix work.
+    // The last prefetch repeats the wave's last strip (in bounds, unused).
+    Frag FA, FB;
+    size_t st = (size_t)blockIdx.x * 4 + wave;
+    if (st < nstrip) load(FA, st, 0);
+    for (; st < nstrip; st += nwaves) {
+        load(FB, st, 1);
+        chain(FA, st, 0);
+        load(FA, st + nwaves < nstrip ? st + nwaves : st, 0);
+        chain(FB, st, 1);
     }
     // sums over the 4 waves in order
     __syncthreads();
     if (tid < 2 * mb) {
         const int which = tid / mb, j = tid % mb;
         double t = 0.0;
-        for (int w = 0; w < 4; ++w) t += red[(w * 2 + which) * MP + j];
+        for (int w = 0; w < 4; ++w) t += red[(w * 2 + which) * CW + j];
         npart[(size_t)blockIdx.x * 2 * mb + tid] = t;
     }
 }
 
-template <int MJ, int KS0, int KS1>
+template <int KS0, int KS1, int NT>
 static hipError_t update_wave(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
                               const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
                               hipStream_t s) {
-    constexpr int MP = 16 * MJ;
+    constexpr int CW = 16 + ((NT + 1) & ~1), NX = 4 + NT;   // as in the kernel
     const int K = bm.K, mb = bm.mb;
-    if (mb > MP || (K - mb + 3) / 4 > KS0 || (mb + 3) / 4 > KS1 || 2 * K > 128 || !n) return hipErrorInvalidValue;
+    if (mb > CW || (K - mb + 3) / 4 > KS0 || (mb + 3) / 4 > KS1 || 2 * K > 128 || !n) return hipErrorInvalidValue;
     if ((V32 == nullptr) != (U32 == nullptr)) return hipErrorInvalidValue;
-    const size_t lds = (size_t)std::max(mb + 4 * KS0, 4 * KS1) * MP * sizeof(double2) +
-                       (size_t)9 * MP * sizeof(double) + (size_t)4 * 4 * MJ * 64 * sizeof(double2) +
+    const size_t lds = (size_t)std::max(mb + 4 * KS0, 4 * KS1) * CW * sizeof(double2) +
+                       (size_t)9 * CW * sizeof(double) + (size_t)4 * NX * 64 * sizeof(double2) +
                        (size_t)2 * K * sizeof(int);
     auto launch = [&](auto kern) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -674,7 +714,7 @@ static hipError_t update_wave(const void* V, const void* V32, void* U, void* U32
                            (double2*)U, (float2*)U32, ld, n, bm, (const double2*)C, theta, npart);
         return hipGetLastError();
     };
-    return V32 ? launch(update_wave_kernel<MJ, KS0, KS1, true>) : launch(update_wave_kernel<MJ, KS0, KS1, false>);
+    return V32 ? launch(update_wave_kernel<KS0, KS1, NT, true>) : launch(update_wave_kernel<KS0, KS1, NT, false>);
 }
 
 hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
@@ -683,19 +723,19 @@ hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32
     const int mb = bm.mb;
     const int nk0 = (bm.K - mb + 3) / 4;   // k-steps over the W and P columns
     hipError_t e;
-#define UPW(MJ, KS0, KS1) update_wave<MJ, KS0, KS1>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
+#define UPW(KS0, KS1, NT) update_wave<KS0, KS1, NT>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
 #define UPB(MJ, RB) update_mj<MJ, RB>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
     if (mb < 1 || mb > 21) return hipErrorInvalidValue;
     if (rows == 0 && mb <= 16)
-        e = nk0 <= 2 ? UPW(1, 2, 4) : nk0 <= 4 ? UPW(1, 4, 4) : nk0 <= 6 ? UPW(1, 6, 4) : UPW(1, 8, 4);
+        e = nk0 <= 2 ? UPW(2, 4, 0) : nk0 <= 4 ? UPW(4, 4, 0) : nk0 <= 6 ? UPW(6, 4, 0) : UPW(8, 4, 0);
     else if (rows == 0 && mb <= 20)
-        e = nk0 <= 2   ? UPW(2, 2, 5)
-            : nk0 <= 4 ? UPW(2, 4, 5)
-            : nk0 <= 6 ? UPW(2, 6, 5)
-            : nk0 <= 8 ? UPW(2, 8, 5)
-                       : UPW(2, 10, 5);
+        e = nk0 <= 2   ? UPW(2, 5, 4)
+            : nk0 <= 4 ? UPW(4, 5, 4)
+            : nk0 <= 6 ? UPW(6, 5, 4)
+            : nk0 <= 8 ? UPW(8, 5, 4)
+                       : UPW(10, 5, 4);
     else if (rows == 0)
-        e = nk0 <= 4 ? UPW(2, 4, 6) : nk0 <= 8 ? UPW(2, 8, 6) : UPW(2, 11, 6);
+        e = nk0 <= 4 ? UPW(4, 6, 5) : nk0 <= 8 ? UPW(8, 6, 5) : UPW(11, 6, 5);
     else if (mb <= 16)
         e = rows == 16 ? UPB(1, 16) : UPB(1, 32);
     else
