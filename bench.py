@@ -311,7 +311,11 @@ def main():
         "roofline_source": "HIP events recorded around each launch on its own stream during the timed steps "
                            "(concurrent k-path segments overlap); kernels_isolated: the same from a "
                            f"single-stream pass over {min(args.roofline_nk, nk)} k-points after the timed steps",
-        "roofline": dict(rl[dom], kernel=dom) if dom else None,
+        # the timed region's durations include the wait for CUs that the other
+        # concurrent segments hold; the same kernel alone on the chip beside them
+        "roofline": dict(rl[dom], kernel=dom,
+                         single_stream={k: rl_iso[dom][k] for k in ("achieved", "frac", "avg_us")}
+                         if dom in rl_iso else None) if dom else None,
         "stencil": rl.get("stencil"),
         "kernels": rl,
         "kernels_isolated": rl_iso,
