@@ -40,8 +40,10 @@ struct StencilArgs {
     R gamma, shift;
 };
 
-template <class R, class S, int TY>
-__global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R, S> a) {
+// MAXT: the largest workgroup the instantiation serves (N (TY + 2) threads);
+// grids up to N = 64 use at most 640, which leaves each thread more registers.
+template <class R, class S, int TY, int MAXT>
+__global__ __launch_bounds__(MAXT) void stencil_kernel(StencilArgs<R, S> a) {
     using T = cplx<R>;
     using TS = cplx<S>;
     extern __shared__ unsigned char smem_raw[];
@@ -86,10 +88,25 @@ __global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R, S> a) {
     T qxy_c = zero;                              // in-plane part of q(t)
     T q_prev = zero;                             // q(t-1)
 
-    for (int t = z0 - 2; t < z1; ++t) {
-        const int zt1 = (t + 1 + 2 * N) % N;
-        const size_t off = (size_t)zt1 * NN + (size_t)yg * N + tx;
-        const TS sv0 = Xb[off], sv1 = Xb[N3 + off], sv2 = Xb[2 * N3 + off];
+    // v and mu of each plane are loaded two steps ahead, so that their HBM
+    // latency overlaps two planes' LDS work and barriers.  Two register sets
+    // alternate, A for the planes t + 1 with t - z0 even, B for the odd ones.
+    struct Plane {
+        TS v0, v1, v2;
+        R m0, m1, m2;
+    };
+    auto load_plane = [&](Plane& P, int t) {   // plane t + 1 (periodic)
+        const size_t o = (size_t)((t + 1 + 2 * N) % N) * NN + (size_t)yg * N + tx;
+        P.v0 = Xb[o];
+        P.v1 = Xb[N3 + o];
+        P.v2 = Xb[2 * N3 + o];
+        P.m0 = a.mu[o];
+        P.m1 = a.mu[N3 + o];
+        P.m2 = a.mu[2 * N3 + o];
+    };
+    auto step = [&](int t, const Plane& P) {
+        const TS sv0 = P.v0, sv1 = P.v1, sv2 = P.v2;
+        const R mu0 = P.m0, mu1 = P.m1, mu2 = P.m2;
         const T vn0 = mk<T>(sv0.x, sv0.y);
         const T vn1 = mk<T>(sv1.x, sv1.y);
         const T vn2 = mk<T>(sv2.x, sv2.y);
@@ -120,10 +137,9 @@ __global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R, S> a) {
             s = cadd(s, cmulc(cm2, vn0));
             s = csub(s, cmulc(cp1, v2xm));
             en2 = csub(s, cmulc(cm1, vn1));
-            const R* mup = a.mu + off;
-            en0 = cscale(en0, mup[0]);
-            en1 = cscale(en1, mup[N3]);
-            en2 = cscale(en2, mup[2 * N3]);
+            en0 = cscale(en0, mu0);
+            en1 = cscale(en1, mu1);
+            en2 = cscale(en2, mu2);
         }
         // in-plane part of q(t+1) and the full q(t) (needs the row above: ty <= TY)
         T qxy_n = zero, q_t = zero;
@@ -188,6 +204,17 @@ __global__ __launch_bounds__(1024) void stencil_kernel(StencilArgs<R, S> a) {
         ec0 = en0; ec1 = en1; ec2 = en2;
         qxy_c = qxy_n;
         q_prev = q_t;
+    };
+    Plane A, B;
+    load_plane(A, z0 - 2);
+    load_plane(B, z0 - 1);
+    for (int t = z0 - 2; t < z1; t += 2) {
+        step(t, A);
+        load_plane(A, t + 2 < z1 ? t + 2 : t);   // past the chunk: a repeated plane, unused
+        if (t + 1 < z1) {                        // uniform: zc + 2 planes, odd for odd N
+            step(t + 1, B);
+            load_plane(B, t + 3 < z1 ? t + 3 : t + 1);
+        }
     }
 }
 
@@ -202,7 +229,7 @@ static int stencil_ty(int N) {
 template <class R, class S, int TY>
 static hipError_t launch_ty(const StencilArgs<R, S>& a, hipStream_t s) {
     const size_t lds = (size_t)10 * (TY + 2) * a.N * sizeof(cplx<R>);
-    auto kern = stencil_kernel<R, S, TY>;
+    auto kern = a.N * (TY + 2) <= 640 ? stencil_kernel<R, S, TY, 640> : stencil_kernel<R, S, TY, 1024>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 block(a.N, TY + 2);
