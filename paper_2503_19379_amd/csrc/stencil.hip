@@ -211,7 +211,7 @@ __global__ __launch_bounds__(MAXT) void stencil_kernel(StencilArgs<R, S> a) {
     for (int t = z0 - 2; t < z1; t += 2) {
         step(t, A);
         load_plane(A, t + 2 < z1 ? t + 2 : t);   // past the chunk: a repeated plane, unused
-        if (t + 1 < z1) {                        // uniform: zc + 2 planes, odd for odd N
+        if (t + 1 < z1) {                        // uniform: zc + 2 planes, odd for odd zc (N = 100, 120)
             step(t + 1, B);
             load_plane(B, t + 3 < z1 ? t + 3 : t + 1);
         }

@@ -23,14 +23,15 @@ def B():
 KS = [np.array([0.7, -0.4, 1.3]), np.zeros(3), np.array([np.pi, np.pi, np.pi])]
 
 
-@pytest.mark.parametrize("N", [8, 12, 24, 32, 64])
+@pytest.mark.parametrize("N", [8, 12, 24, 32, 64, 100])
 @pytest.mark.parametrize("ki", [0, 1, 2])
 def test_op_apply_fp64(B, N, ki):
+    """N = 100: odd z chunks (the stencil's two-plane loop ends on a half step)."""
     rng = np.random.default_rng(100 + N + ki)
     L = 1.0
     k = KS[ki]
     eps = rand_eps(rng, N)
-    nb = 3 if N <= 32 else 2
+    nb = 3 if N <= 32 else 2 if N <= 64 else 1
     X = rand_block(rng, nb, N)
     ctx = B.mfd_build(N, L, 2, eps)
     g, c = B.mfd_gamma_shift(ctx, k)
@@ -43,12 +44,13 @@ def test_op_apply_fp64(B, N, ki):
     assert rel_err(Yd.cpu().numpy(), ref) < 1e-13
 
 
-@pytest.mark.parametrize("N", [16, 48])
+@pytest.mark.parametrize("N", [16, 48, 100, 128])
 def test_op_apply_fp32(B, N):
+    """N = 100: odd z chunks; N = 128: the 1024-thread stencil workgroups."""
     rng = np.random.default_rng(7 + N)
     L, k = 1.0, np.array([0.3, 0.2, -0.9]) * np.pi
     eps = rand_eps(rng, N)
-    X = rand_block(rng, 2, N)
+    X = rand_block(rng, 2 if N <= 48 else 1, N)
     ctx = B.mfd_build(N, L, 2, eps)
     g, c = B.mfd_gamma_shift(ctx, k)
     Xd = torch.from_numpy(X.astype(np.complex64)).cuda()
