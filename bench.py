@@ -316,7 +316,9 @@ def main():
         "roofline": dict(rl[dom], kernel=dom,
                          single_stream={k: rl_iso[dom][k] for k in ("achieved", "frac", "avg_us")}
                          if dom in rl_iso else None) if dom else None,
-        "stencil": rl.get("stencil"),
+        "stencil": dict(rl["stencil"],
+                        single_stream={k: rl_iso["stencil"][k] for k in ("achieved", "frac", "avg_us")}
+                        if "stencil" in rl_iso else None) if "stencil" in rl else None,
         "kernels": rl,
         "kernels_isolated": rl_iso,
         "iters_per_k": float(np.mean(iters)) if iters else None,
