@@ -49,7 +49,10 @@ extern "C" {
 
 typedef struct mfd_ctx mfd_ctx;
 
-typedef enum { MFD_C64 = 1, MFD_C128 = 2 } mfd_dtype;
+/* MFD_C64_F64 (mfd_op_apply only): MFD_C64 storage, FP64 arithmetic with
+ * the FP64 M_0, the form the mixed-precision solver applies to its
+ * FP32-stored blocks. */
+typedef enum { MFD_C64 = 1, MFD_C128 = 2, MFD_C64_F64 = 3 } mfd_dtype;
 
 typedef enum {
     MFD_OK = 0,
@@ -135,7 +138,8 @@ int mfd_gamma_shift(const mfd_ctx* ctx, const double k[3], double* gamma, double
 
 /* Y = op(k) X for nb fields (eq. (Ker_comp) plus the shift c(k)).
  * X, Y: device, [nb][3][N][N][N] interleaved complex of `dtype`; must not
- * overlap.  FP32 (MFD_C64) uses an FP32 copy of M_0. */
+ * overlap.  FP32 (MFD_C64) uses an FP32 copy of M_0; MFD_C64_F64 reads and
+ * writes FP32 and computes in FP64. */
 int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* X, void* Y,
                  void* stream);
 

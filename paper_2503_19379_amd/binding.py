@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmfdkc.so")
 
 MFD_C64 = 1
 MFD_C128 = 2
+MFD_C64_F64 = 3   # FP32 storage, FP64 arithmetic (mfd_op_apply)
 STATUS = {0: "MFD_OK", -1: "MFD_EINVAL", -2: "MFD_ENOMEM", -3: "MFD_EDEVICE", -4: "MFD_ENOTCONV",
           -5: "MFD_ESPURIOUS", -6: "MFD_EUNSUPPORTED"}
 
@@ -169,12 +170,18 @@ def mfd_gamma_shift(ctx: Context, k):
     return g.value, c.value
 
 
-def mfd_op_apply(ctx: Context, k, X, Y, stream=None):
-    """Y <- op(k) X (device tensors of shape (nb, 3, N, N, N))."""
+def mfd_op_apply(ctx: Context, k, X, Y, stream=None, fp64_arith: bool = False):
+    """Y <- op(k) X (device tensors of shape (nb, 3, N, N, N)).  fp64_arith
+    with complex64 tensors: FP32 storage, FP64 arithmetic (MFD_C64_F64)."""
     ka, kp = _k(k)
     if X.dtype != Y.dtype or X.shape != Y.shape:
         raise ValueError("X and Y must match in dtype and shape")
-    _check(lib().mfd_op_apply(ctx.handle, kp, int(X.shape[0]), _dtype(X), _dev(X), _dev(Y), _stream(stream)))
+    dt = _dtype(X)
+    if fp64_arith:
+        if dt != MFD_C64:
+            raise ValueError("fp64_arith applies to complex64 tensors")
+        dt = MFD_C64_F64
+    _check(lib().mfd_op_apply(ctx.handle, kp, int(X.shape[0]), dt, _dev(X), _dev(Y), _stream(stream)))
     return Y
 
 

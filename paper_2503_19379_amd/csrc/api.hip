@@ -1029,18 +1029,21 @@ int mfd_gamma_shift(const mfd_ctx* ctx, const double k[3], double* gamma, double
     return MFD_OK;
 }
 
-static int check_block(mfd_ctx* ctx, const double* k, int nb, int dtype, const void* X, const void* Y) {
+static int check_block(mfd_ctx* ctx, const double* k, int nb, int dtype, const void* X, const void* Y,
+                       bool allow_c64_f64 = false) {
     if (!ctx || !k || !X || !Y) return fail(MFD_EINVAL, "NULL argument");
     if (nb < 0) return fail(MFD_EINVAL, "nb < 0");
-    if (dtype != MFD_C64 && dtype != MFD_C128) return fail(MFD_EINVAL, "dtype must be MFD_C64 or MFD_C128");
+    if (dtype != MFD_C64 && dtype != MFD_C128 && !(allow_c64_f64 && dtype == MFD_C64_F64))
+        return fail(MFD_EINVAL, allow_c64_f64 ? "dtype must be MFD_C64, MFD_C128 or MFD_C64_F64"
+                                              : "dtype must be MFD_C64 or MFD_C128");
     if (!finite3(k)) return fail(MFD_EINVAL, "k must be finite");
     return MFD_OK;
 }
 
 int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* X, void* Y, void* stream) {
-    int st = check_block(ctx, k, nb, dtype, X, Y);
+    int st = check_block(ctx, k, nb, dtype, X, Y, true);
     if (st) return st;
-    const size_t bytes = ctx->n * nb * (dtype == MFD_C64 ? 8 : 16);
+    const size_t bytes = ctx->n * nb * (dtype == MFD_C128 ? 16 : 8);
     const char* x = (const char*)X;
     const char* y = (const char*)Y;
     if (nb > 0 && x < y + bytes && y < x + bytes) return fail(MFD_EINVAL, "X and Y overlap");
@@ -1048,6 +1051,7 @@ int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void*
     OpParams p = params(ctx, k);
     hipStream_t s = (hipStream_t)stream;
     if (dtype == MFD_C128) HIPCHK(launch_stencil<double>(p, nb, X, Y, ctx->mu64, s));
+    else if (dtype == MFD_C64_F64) HIPCHK(launch_stencil_f64_s32(p, nb, X, Y, ctx->mu64, s));
     else HIPCHK(launch_stencil<float>(p, nb, X, Y, ctx->mu32, s));
     return MFD_OK;
 }

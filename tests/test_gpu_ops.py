@@ -61,6 +61,30 @@ def test_op_apply_fp32(B, N):
     assert rel_err(Yd.cpu().numpy(), ref) < 2e-6
 
 
+@pytest.mark.parametrize("N", [16, 64, 100])
+@pytest.mark.parametrize("ki", [0, 1])
+def test_op_apply_fp32_storage_fp64_arith(B, N, ki):
+    """MFD_C64_F64, the operator the mixed-precision solver applies to its
+    FP32-stored blocks: FP64 arithmetic on FP32 inputs, so the only error is
+    the FP32 rounding of the output (2^-24 per component)."""
+    rng = np.random.default_rng(400 + N + ki)
+    L, k = 1.0, KS[ki]
+    eps = rand_eps(rng, N)
+    X = rand_block(rng, 2 if N <= 64 else 1, N).astype(np.complex64)
+    ctx = B.mfd_build(N, L, 2, eps)
+    g, c = B.mfd_gamma_shift(ctx, k)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    B.mfd_op_apply(ctx, k, Xd, Yd, fp64_arith=True)
+    torch.cuda.synchronize()
+    ref = mfd.apply_op(X.astype(np.complex128), mfd.mu_from_eps(eps), k, L / N, g, 2, c)
+    got = Yd.cpu().numpy().astype(np.complex128)
+    assert rel_err(got, ref) < 1e-7
+    # element-wise: the FP32 rounding of each output component, plus the FP64
+    # level of the operator (1e-12 of the largest entry, as in the FP64 test)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -23 * np.abs(ref) + 1e-12 * np.max(np.abs(ref)))
+
+
 @pytest.mark.parametrize("N", [8, 12, 20, 24, 32, 48, 64])
 @pytest.mark.parametrize("ki", [0, 1])
 def test_precond_fp64(B, N, ki):
