@@ -84,9 +84,10 @@ typedef struct {
                                  process first uses HIP (HIP's default is 4) */
     const void* x0;           /* optional device c128 start block [nbands][3][N][N][N] for the first
                                  k-point (NULL: random) */
-    int stall_window;         /* precision 1: iterations without a halving of the largest
-                                 residual after which the k-point continues in FP64 (default 40,
-                                 0 = never) */
+    int stall_window;         /* iterations without a halving of the largest residual after
+                                 which precision 1 continues the k-point in FP64 (default 40,
+                                 0 = never); FP64 restarts its conjugate directions from the
+                                 current vectors after max(stall_window, 40) such iterations */
     int learn_steps;          /* warm_start 2: Adam steps over the replay buffer after each new
                                  training pair (default 30; 0 = the untrained network, which
                                  proposes the previous step's combination unchanged) */
@@ -164,6 +165,9 @@ int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double
  * concurrently; inside a segment each k-point starts from the previous one's
  * vectors (warm_start = 1).
  * kpts: host nk x 3.  tol: relative residual target (see mfd_kstats).
+ * nbands + opts->guard <= 21 (the basis of 3 (nbands + guard) columns is
+ * at most 63, the size the one-workgroup Rayleigh-Ritz step holds in LDS);
+ * MFD_EUNSUPPORTED otherwise.  20 bands therefore take guard <= 1.
  * evals: host nk x nbands, ascending.  evecs: device c128
  * [nk][nbands][3][N][N][N] or NULL.  stats: host nk entries or NULL.
  * Returns MFD_ENOTCONV / MFD_ESPURIOUS after filling evals and stats. */
@@ -186,7 +190,9 @@ int mfd_bands_batch(int ncrys, mfd_ctx* const* ctxs, const int* nk, const double
  * array, by category: 0 stencil (mfd_op_apply kernel), 1 FFT preconditioner
  * (three kernels), 2 Gram product (+ partial-sum reduction), 3 Rayleigh-Ritz,
  * 4 block update (+ norm reduction), 5 unused.  ms: total event time, count:
- * launches, bytes: algorithmic HBM bytes (each block read or written once). */
+ * launches, bytes: algorithmic HBM bytes (each block read or written once);
+ * for the Gram product (category 2) its flops instead, 8 n K (K + 1) for the
+ * launch's basis of K columns (two Hermitian K x K products, upper halves). */
 int mfd_profile(mfd_ctx* ctx, int enable);
 int mfd_profile_read(mfd_ctx* ctx, double* ms, long long* count, double* bytes);
 

@@ -457,7 +457,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         }
         hipEvent_t e1 = w.prof.begin(s);
         HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s));
-        w.prof.end(e1, 2, (double)n * (2 * mb * 16.0 + 2 * (na + np) * rb), s);
+        w.prof.end(e1, 2, 8.0 * (double)n * bm.K * (bm.K + 1), s);   // flops, not bytes
         if (it == 0 && union_start) {
             const int Kb = bm.K;
             std::vector<double2> hG((size_t)Kb * 2 * Kb);
@@ -553,6 +553,22 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             best_it = it;
             if (trace) std::fprintf(stderr, "[%p] it %d: mixed precision stalled at %.3e, continuing in FP64\n",
                                     (void*)&w, it, rmax);
+        } else if (!mixed && stall_window > 0 && it - best_it >= std::max(stall_window, 40)) {
+            // FP64 stall (a nearly dependent search direction kept in the
+            // basis can hold the Rayleigh-Ritz step at a floor): restart the
+            // conjugate directions once from the current X, with fresh A X and
+            // R = A X - theta X; judged over at least 40 iterations, however
+            // short the window that sends mixed precision to FP64
+            have_p = false;
+            HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+            HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), col(V, n, mb), false, n, n, mb, w.theta,
+                                   w.nparts_col, w.npart, w.norms, s));
+            HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            active_set();
+            best = rmax;
+            best_it = it;
+            if (trace) std::fprintf(stderr, "[%p] it %d: stalled at %.3e, P restarted\n", (void*)&w, it, rmax);
         }
     }
     w.V32 = V32;

@@ -10,8 +10,10 @@
 //      (d = diag(Gs)^-1/2);
 //   2. Cholesky factor D Gs D = R^H R column by column; a column whose pivot
 //      (squared distance to the span of the previous columns) falls below a
-//      threshold is dropped, and if a P column does, all of P is dropped for
-//      this step (the conjugate direction is restarted);
+//      threshold is dropped, W and P columns alike; the other P columns keep
+//      their conjugate directions (restarting all of P whenever one column
+//      was nearly dependent could leave P out at every step, which reduces
+//      the iteration to preconditioned steepest descent);
 //   3. Z = R^-1 and H = Z^H (D Ga D) Z, the operator in an orthonormal basis;
 //   4. cyclic Jacobi on the Hermitian H with round-robin pairs: in a round
 //      every index is in one pair, and the two-sided update J^H H J is done
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
             const bool isP = idx[j] >= pbeg;
             const double piv = A[j * KE + j].x;
             const double thr = isP ? a.drop_p : a.drop_w;
-            if (!(piv > thr) || (isP && dropP)) {
+            if (!(piv > thr)) {
                 dropped[j] = 1;
                 if (isP) dropP = 1;
             } else {
@@ -126,9 +128,7 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
         }
         __syncthreads();
     }
-    // a restarted P drops every P column; isolate dropped columns
-    if (tid < Kk && dropP && idx[tid] >= pbeg) dropped[tid] = 1;
-    __syncthreads();
+    // isolate dropped columns
     for (int e = tid; e < KE * KE; e += RR_NT) {
         const int i = e / KE, l = e % KE;
         if (l < i) A[e] = mk<C128>(0.0, 0.0);

@@ -51,7 +51,7 @@ hipError_t launch_convert(const void* X, void* Y, size_t count, bool to_c64, hip
 //   G:      K x 2K row-major c128, [S^H S | S^H A S]
 //   theta:  mb doubles, the new Ritz values (out)
 //   C:      K x mb row-major c128 coefficients (out)
-//   info:   ints (out): [0] = columns kept, [1] = 1 if P was restarted,
+//   info:   ints (out): [0] = columns kept, [1] = 1 if a P column was dropped,
 //           [2] = active bands (nw), [3] = Jacobi sweeps, [4..8] phase ticks, [9] = kept
 struct RRArgs {
     const double2* G;

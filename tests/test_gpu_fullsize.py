@@ -53,3 +53,37 @@ def test_sphere_n32_fp64(B):
 
 def test_diamond_n64_mixed(B):
     _check(B, "diamond_n64", 1, 1e-7)
+
+
+def test_diamond_n96_20bands_mixed(B):
+    """The learned-warm-start workload's shape (diamond, N = 96, 2,654,208
+    unknowns, 20 bands, path Gamma-X-M-Gamma-R-X) in mixed precision with
+    guard = 1 (nbands + guard = 21, the library's limit), three consecutive
+    k-points (a warm-started chain).  The oracle cannot solve N = 96 within a
+    test, so it checks what holds at any size: its own FP64 operator, applied
+    to sampled returned eigenvectors, gives relative residuals <= 2e-8 and
+    Rayleigh quotients equal to the returned eigenvalues."""
+    from oracle import mfd
+    cfg = workloads.CONFIGS["diamond_n96"]
+    N, m = cfg["N"], cfg["nbands"]
+    kp = workloads.kpath(cfg["path"], cfg["nk"])[[30, 31, 32]]
+    eps = workloads.crystal_eps(cfg["eps"], N)
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    vecs = torch.empty((len(kp), m, 3, N, N, N), dtype=torch.complex128, device="cuda")
+    opts = B.default_opts(precision=1, warm_start=1, guard=1, streams=1, max_iter=500)
+    ev, st, status = B.mfd_bands(ctx, kp, m, 1e-8, opts, evecs=vecs)
+    assert status == 0, st
+    for i, s in enumerate(st):
+        assert s["max_rel_resid"] <= 1e-8 and s["spurious"] == 0, (i, s)
+    assert np.all(np.diff(ev, axis=1) >= -1e-12 * np.abs(ev).max())
+    mu = mfd.mu_from_eps(eps)
+    for i, k in enumerate(kp):
+        _, c = B.mfd_gamma_shift(ctx, k)
+        for j in (0, m - 1):
+            x = vecs[i, j].cpu().numpy()
+            y = mfd.apply_op(x[None], mu, k, 1.0 / N, st[i]["gamma"], 2, c)[0]
+            lam = ev[i, j] + c
+            res = np.linalg.norm(y - lam * x) / (abs(lam) * np.linalg.norm(x))
+            assert res <= 2e-8, (i, j, res)
+            rq = np.vdot(x, y).real / np.vdot(x, x).real
+            assert abs(rq - lam) <= 1e-10 * abs(lam), (i, j, rq, lam)
