@@ -23,11 +23,12 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 }
 
 // ---------------------------------------------------------------------------
-// Gram: for the K = 3mb basis columns S = V[:, :K] and AS = V[:, K:2K],
+// Gram: for the K basis columns S (K = mb + 2 na under soft locking, at most
+// 3 mb; the column map gives their places in V) and their images AS,
 //   G_S = S^H S, G_A = S^H AS (both Hermitian: only the 16x16 tiles of one
-//   triangle are formed; the reduction mirrors them).
+//   triangle are formed; gram_scatter_kernel mirrors them).
 // Workgroup w sums rows [w rows_per, (w+1) rows_per) into its own partial
-// tile set; gram_reduce_kernel adds the partials in a fixed order.
+// tile set; reduce_parts_kernel adds the partials in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int GM_KS = 32;       // rows per LDS slab
 constexpr int GM_PF = 8;        // prefetch registers (complex) per thread
