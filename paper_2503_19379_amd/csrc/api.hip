@@ -1169,8 +1169,11 @@ int mfd_bands_batch(int ncrys, mfd_ctx* const* ctxs, const int* nk, const double
         for (int d = 0; d < c; ++d)
             if (ctxs[d] == ctxs[c]) return fail(MFD_EINVAL, "a context appears twice in the batch");
     }
-    // crystals are taken in order by `streams` workers (largest grids first
-    // would balance better; the order is the caller's)
+    // crystals are taken in the caller's order by `streams` workers.  Largest
+    // grid first measured slower (32 crystals of N = 24..64 interleaved:
+    // 27 -> 16 k-points/s): the small solves are bound by their per-iteration
+    // host round trip, and run side by side with large ones their latency
+    // hides behind the large ones' kernels
     hipEvent_t ready;
     HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     HIPCHK(hipEventRecord(ready, (hipStream_t)stream));
