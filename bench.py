@@ -92,6 +92,10 @@ def measured_traffic(workload, precision):
     return out
 
 
+def batch_workers(args):
+    return min(2 * args.streams, 16)
+
+
 def batch_variant(B, args, torch, count):
     """Many crystals of uneven grids in one mfd_bands_batch call: 32 seeded
     random-field crystals (N = 24, 32, 48, 64 in turn), 8 k-points on
@@ -103,7 +107,8 @@ def batch_variant(B, args, torch, count):
     crystals = workloads.random_batch_crystals(cfg["ncrys"], cfg["Ns"])
     ctxs = [B.mfd_build(N, 1.0, 2, eps) for N, eps in crystals]
     kp = workloads.kpath(cfg["path"], cfg["nk"])
-    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=args.guard, max_iter=500, streams=args.streams)
+    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=args.guard, max_iter=500,
+                       streams=batch_workers(args))
     B.mfd_bands_batch(ctxs, [kp[:1]] * len(ctxs), cfg["nbands"], cfg["tol"], o)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -115,7 +120,7 @@ def batch_variant(B, args, torch, count):
         c.close()
     return {"value": ok / dt, "unit": "k-points/s", "steps": 1, "ms_per_step": dt * 1e3,
             "iters_per_k": float(np.mean(iters)), "converged_kpoints": ok, "total_kpoints": len(iters),
-            "max_rel_resid": maxres, "precision": "mixed", "warm_start": "prev",
+            "max_rel_resid": maxres, "precision": "mixed", "warm_start": "prev", "workers": o.streams,
             "workload": f"{cfg['ncrys']} random-field crystals (correlation length 0.15, 30% eps 13 in 1), "
                         f"N in {cfg['Ns']}, {cfg['nk']} k-points on {cfg['path']}, {cfg['nbands']} bands, "
                         f"tol {cfg['tol']:g}"}
@@ -163,8 +168,11 @@ def main():
     # One hardware queue per concurrent k-path segment: with fewer, segments
     # share a queue and one segment's one-workgroup Rayleigh-Ritz step holds up
     # the other's kernels.  HIP reads this when it initialises, below.
-    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < args.streams:
-        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.streams, 32))
+    # The batch variant's crystals run on twice as many workers (their small
+    # solves are bound by the host round trip of each iteration).
+    queues = max(args.streams, 0 if args.no_variants else batch_workers(args))
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(queues, 32))
     import torch
     from paper_2503_19379_amd import binding as B
     from paper_2503_19379_amd import workloads
