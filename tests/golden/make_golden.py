@@ -9,6 +9,7 @@ the seeded input generators are called.
 
     python -m tests.golden.make_golden sphere_n32     # about 10 minutes
     python -m tests.golden.make_golden diamond_n64    # about an hour
+    python -m tests.golden.make_golden random_batch_c0   # a few minutes
 """
 from __future__ import annotations
 
@@ -27,7 +28,19 @@ from paper_2503_19379_amd import workloads
 SAMPLES = {
     "sphere_n32": ((0, 5, 10, 15), 10, 1e-10),
     "diamond_n64": ((0, 16, 32, 48), 16, 1e-9),
+    # crystal 0 (N = 24, seed 0) of the 32-crystal random-field batch
+    "random_batch_c0": ((0, 3, 7), 12, 1e-10),
 }
+
+
+def workload(name):
+    """(N, eps, path, nk) of a sampled workload."""
+    if name == "random_batch_c0":
+        cfg = workloads.CONFIGS["random_batch"]
+        N, eps = workloads.random_batch_crystals(1, cfg["Ns"])[0]
+        return N, eps, cfg["path"], cfg["nk"]
+    cfg = workloads.CONFIGS[name]
+    return cfg["N"], workloads.crystal_eps(cfg["eps"], cfg["N"]), cfg["path"], cfg["nk"]
 
 
 def path(name):
@@ -35,15 +48,13 @@ def path(name):
 
 
 def make(name):
-    cfg = workloads.CONFIGS[name]
     kidx, m, tol = SAMPLES[name]
-    N = cfg["N"]
-    eps = workloads.crystal_eps(cfg["eps"], N)
-    kp = workloads.kpath(cfg["path"], cfg["nk"])
+    N, eps, path_, nk = workload(name)
+    kp = workloads.kpath(path_, nk)
     lines = [f"# {name}: oracle band energies (eq. (Ker_comp) after Alg 4.1), FP64 LOBPCG with the FFT",
              f"# preconditioner (Section 5), iteration tolerance {tol:g} (each row's fresh residual",
              f"# max_rel_resid is at most {2 * tol:g}), seeded random start (seed 0).",
-             f"# N = {N}, L = 1, {cfg['nk']} k-points on {cfg['path']}, m = {m}; written by",
+             f"# N = {N}, L = 1, {nk} k-points on {path_}, m = {m}; written by",
              f"# `python -m tests.golden.make_golden {name}` (calls only oracle/ and the input generators).",
              "# columns: k_index kx ky kz gamma max_rel_resid lambda_1 ... lambda_m"]
     for i in kidx:

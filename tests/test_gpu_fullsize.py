@@ -87,3 +87,32 @@ def test_diamond_n96_20bands_mixed(B):
             assert res <= 2e-8, (i, j, res)
             rq = np.vdot(x, y).real / np.vdot(x, x).real
             assert abs(rq - lam) <= 1e-10 * abs(lam), (i, j, rq, lam)
+
+
+def test_random_batch_mixed(B):
+    """The 32-crystal random-field batch (N = 24, 32, 48, 64 in turn, 8 k-points
+    on Gamma-X-M-Gamma-R, 12 bands, mixed precision) in one mfd_bands_batch
+    call, as the benchmark runs it: every k-point of every crystal reaches
+    1e-8, and crystal 0 (N = 24) matches the oracle's bands at the sampled
+    k-points (tests/golden/random_batch_c0_bands.txt)."""
+    if not os.path.exists(make_golden.path("random_batch_c0")):
+        pytest.skip("random_batch_c0 golden values not written")
+    cfg = workloads.CONFIGS["random_batch"]
+    crystals = workloads.random_batch_crystals(cfg["ncrys"], cfg["Ns"])
+    ctxs = [B.mfd_build(N, 1.0, 2, eps) for N, eps in crystals]
+    kp = workloads.kpath(cfg["path"], cfg["nk"])
+    m = cfg["nbands"]
+    opts = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, streams=8)
+    evs, sts, status = B.mfd_bands_batch(ctxs, [kp] * len(ctxs), m, 1e-8, opts)
+    assert status == 0
+    for c, st in enumerate(sts):
+        for i, s in enumerate(st):
+            assert s["max_rel_resid"] <= 1e-8 and s["spurious"] == 0, (c, i, s)
+    scale = (2 * np.pi) ** 2
+    for i, (k, gamma, lam) in make_golden.load("random_batch_c0").items():
+        assert np.allclose(kp[i], k, atol=1e-15)
+        assert sts[0][i]["gamma"] == pytest.approx(gamma, rel=1e-15)
+        err = np.abs(evs[0][i] - lam[:m])
+        assert np.all(err <= 1e-7 * np.abs(lam[:m]) + 1e-9 * scale), (i, evs[0][i], lam[:m], err)
+    for c in ctxs:
+        c.close()
