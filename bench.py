@@ -17,6 +17,8 @@ Also reported (same JSON line):
                   from HIP events recorded inside the library on the solve's
                   stream during the timed steps;
   stencil       - the same for the fused stencil (the metric's second part);
+  stencil_full_block - the fused stencil alone on a full 16-band block,
+                  timed with HIP events over back-to-back calls;
   cpu_baseline  - the FP64 CPU oracle timed on a bounded sample of the same
                   workload on this host.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -124,6 +126,38 @@ def batch_variant(B, args, torch, count):
             "workload": f"{cfg['ncrys']} random-field crystals (correlation length 0.15, 30% eps 13 in 1), "
                         f"N in {cfg['Ns']}, {cfg['nk']} k-points on {cfg['path']}, {cfg['nbands']} bands, "
                         f"tol {cfg['tol']:g}"}
+
+
+def stencil_direct(B, ctx, k, m, N, torch, reps=30):
+    """The fused stencil alone on a full block of m bands (no soft locking),
+    with nothing else on the chip: mean duration of `reps` back-to-back
+    mfd_op_apply calls between HIP events on the stream they launch on.
+    Algorithmic bytes per call: X read and Y written once (2 x 24 N^3 m bytes
+    of complex64) plus mu on the 3 N^3 edges once (FP32 copy: 12 N^3 bytes;
+    FP64: 24 N^3), the halos coming from LDS or cache."""
+    n3 = N ** 3
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((m, 3, N, N, N), dtype=torch.complex64, device="cuda", generator=g)
+    Y = torch.empty_like(X)
+    s = torch.cuda.Stream()
+    out = {}
+    for name, f64, mu_bytes in (("fp32", False, 12), ("fp32_storage_fp64_arith", True, 24)):
+        for _ in range(3):
+            B.mfd_op_apply(ctx, k, X, Y, stream=s.cuda_stream, fp64_arith=f64)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            B.mfd_op_apply(ctx, k, X, Y, stream=s.cuda_stream, fp64_arith=f64)
+        e1.record(s)
+        e1.synchronize()
+        avg_s = e0.elapsed_time(e1) * 1e-3 / reps
+        by = 48.0 * n3 * m + mu_bytes * n3
+        out[name] = {"achieved": by / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": by / avg_s / HBM_PEAK, "avg_us": avg_s * 1e6, "bytes_per_call": by,
+                     "nbands": m, "calls": reps}
+    del X, Y
+    torch.cuda.synchronize()
+    return out
 
 
 def cpu_baseline(eps, L, k, m, iters, gpu_iters_per_k):
@@ -329,6 +363,7 @@ def main():
         "stencil": dict(rl["stencil"],
                         single_stream={k: rl_iso["stencil"][k] for k in ("achieved", "frac", "avg_us")}
                         if "stencil" in rl_iso else None) if "stencil" in rl else None,
+        "stencil_full_block": stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch),
         "kernels": rl,
         "kernels_isolated": rl_iso,
         "iters_per_k": float(np.mean(iters)) if iters else None,
