@@ -11,7 +11,7 @@ struct OpParams {
     double k[3];
     double gamma, shift;
     int order = 2;             // stencil order 2K (Table FD_1D)
-    int stencil_wgs = 2048;    // order 2: z chunks are halved until this many workgroups
+    int stencil_wgs = 2048;    // order 2: z chunks until this many workgroups (N = 64: waves)
     int fft_xc = 0;            // x run of the z-pass of the FFT solve (0: the largest of 16, 8, 4, 2, 1 dividing N)
     void* wtmp = nullptr;      // orders > 2: scratch for wtmp_bands bands of 4 FP64 complex fields
     int wtmp_bands = 0;

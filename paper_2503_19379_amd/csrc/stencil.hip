@@ -12,11 +12,13 @@
 //   w = A e : w1 = D2 e3 - D3 e2,  w2 = D3 e1 - D1 e3,  w3 = D1 e2 - D2 e1
 //   q = B v = D1 v1 + D2 v2 + D3 v3,   w_i += gamma D_i' q.
 //
-// Kernel design (HBM-bound: v is read once, w written once, mu read from HBM
-// about once per launch, since the bands of a tile run side by side and share
-// it in L2).  A workgroup owns an x-y tile of N x TY cells plus one halo row on
-// each side in y (x is a full periodic row, so x neighbours never leave the
-// tile) and marches through a chunk of z planes.  Each thread owns one (x, y)
+// Two kernels, both HBM-bound in intent (v read once, w written once, mu read
+// from HBM about once per launch: the bands of a tile run side by side and
+// share it in L2): stencil_wave_kernel for N = 64 (below) and, for the other
+// grids, stencil_kernel.  In stencil_kernel a workgroup owns an x-y tile of
+// N x TY cells plus one halo row on each side in y (x is a full periodic row,
+// so x neighbours never leave the tile) and marches through a chunk of z
+// planes.  Each thread owns one (x, y)
 // column and keeps its z history in registers; in-plane neighbours travel
 // through LDS.  Intermediates e = mu A'v and q = Bv never touch HBM.  At step
 // t the plane v(t+1) is loaded and the thread forms e(t+1), the in-plane part
@@ -24,6 +26,7 @@
 // e(t), e(t+1), q(t-1), q(t).
 #include "common.h"
 #include "internal.h"
+#include <algorithm>
 
 namespace mfd {
 
@@ -37,6 +40,7 @@ struct StencilArgs {
     int N, nyt, nzc, zc, nb;
     FieldList fl;
     cplx<R> cp[3], cm[3];
+    cplx<R> gcp[3], gcm[3];   // gamma cp, gamma cm
     R gamma, shift;
 };
 
@@ -218,6 +222,216 @@ __global__ __launch_bounds__(MAXT) void stencil_kernel(StencilArgs<R, S> a) {
     }
 }
 
+// Barrier-free form for N = 64: one x row per wave, so x neighbours are
+// lanes of the same wave and come through ds_bpermute, and y neighbours are
+// registers: each lane owns a strip of WTY rows (plus the halo rows y0 - 1
+// and y0 + WTY, whose e and q it recomputes) and marches in z.  No LDS is
+// allocated and no wave waits for another, so the memory, FP64 and permute
+// work of different waves overlap on a CU.  State carried from plane t to
+// t + 1, per lane: v(t) on rows -1..WTY (storage precision), e(t) on rows
+// 0..WTY, q(t-1) on rows 0..WTY-1.  At most 168 VGPRs: 3 waves per SIMD.
+constexpr int WTY = 2;
+
+__device__ __forceinline__ float lane_get(int addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_get(int addr, double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <class C> __device__ __forceinline__ C lane_get(int addr, C v) {
+    v.x = lane_get(addr, v.x);
+    v.y = lane_get(addr, v.y);
+    return v;
+}
+// acc - a * b and acc - conj(a) * b, four FMAs each
+template <class T> __device__ __forceinline__ T cfms(T acc, T a, T b) {
+    acc.x = fma(-a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+template <class T> __device__ __forceinline__ T cfmsc(T acc, T a, T b) {
+    acc.x = fma(-a.x, b.x, acc.x); acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+
+// Grid: a.nyt workgroups of 4 waves (4 consecutive strips) per band and z
+// chunk, band next, z chunk slowest; a.nzc chunks of N / nzc planes, rounded.
+template <class R, class S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void stencil_wave_kernel(
+    StencilArgs<R, S> a) {
+    using T = cplx<R>;
+    using TS = cplx<S>;
+    constexpr int TY = WTY;
+    constexpr int N = 64;
+    const int x = threadIdx.x & 63;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = bid % a.nyt;
+    const int rest = bid / a.nyt;
+    const int band = rest % a.nb;
+    const int zch = rest / a.nb;
+    const int y0 = (grp * 4 + (int)(threadIdx.x >> 6)) * TY;
+    const int z0 = zch * N / a.nzc;
+    const int z1 = (zch + 1) * N / a.nzc;
+    constexpr unsigned NN = N * N;
+    constexpr unsigned N3 = NN * N;
+    const size_t fo = (size_t)a.fl(band) * 3 * N3;
+    const char* Xb = (const char*)(a.X + fo);     // per-lane offsets below stay 32-bit
+    char* Yb = (char*)(a.Y + fo);
+    const char* Mb = (const char*)a.mu;
+    const int am = ((x + N - 1) % N) * 4;         // ds_bpermute address of lane x - 1
+    const int ap = ((x + 1) % N) * 4;             // of lane x + 1
+    unsigned yo[TY + 2];                          // rows y0 - 1 .. y0 + TY (cell index in a plane)
+#pragma unroll
+    for (int r = 0; r < TY + 2; ++r) yo[r] = (unsigned)(((y0 - 1 + r + N) % N) * N + x);
+
+    const T cp1 = a.cp[0], cp2 = a.cp[1], cp3 = a.cp[2];
+    const T cm1 = a.cm[0], cm2 = a.cm[1], cm3 = a.cm[2];
+    const T gp1 = a.gcp[0], gp2 = a.gcp[1], gp3 = a.gcp[2];   // gamma cp, gamma cm
+    const T gm1 = a.gcm[0], gm2 = a.gcm[1], gm3 = a.gcm[2];
+    const R sh = a.shift;
+    auto up = [](TS s) { return mk<T>(s.x, s.y); };
+
+    struct Plane {
+        TS v[TY + 2][3];   // rows -1..TY
+        R m[TY + 1][3];    // rows 0..TY
+    };
+    auto load = [&](Plane& P, int z) {            // plane z, -1 <= z <= N
+        const unsigned zo = (unsigned)((z + N) % N) * NN;
+#pragma unroll
+        for (int r = 0; r < TY + 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                P.v[r][c] = *(const TS*)(Xb + (size_t)((c * N3 + zo + yo[r]) * (unsigned)sizeof(TS)));
+#pragma unroll
+        for (int r = 0; r < TY + 1; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                P.m[r][c] = *(const R*)(Mb + (size_t)((c * N3 + zo + yo[r + 1]) * (unsigned)sizeof(R)));
+    };
+
+    struct Vec3 {
+        T c[3];
+    };
+    TS vc[TY + 2][3];   // v(t)
+    Vec3 ec[TY + 1];    // e(t) = mu A'v(t)
+    T qp[TY];           // q(t-1) = B v(t-1)
+
+    auto e_row = [&](const Plane& P, int r) {     // e(t+1) on row r, 0 <= r <= TY
+        const T v0 = up(P.v[r + 1][0]), v1 = up(P.v[r + 1][1]), v2 = up(P.v[r + 1][2]);
+        const T v1ym = up(P.v[r][0]), v3ym = up(P.v[r][2]);
+        const T v2xm = lane_get(am, v1);
+        const T v3xm = lane_get(am, v2);
+        const T p0 = up(vc[r + 1][0]), p1 = up(vc[r + 1][1]);
+        Vec3 en;
+        // D3' v2 - D2' v3
+        T s = cmulc(cp3, p1);
+        s = cfmac(s, cm3, v1);
+        s = cfmsc(s, cp2, v3ym);
+        s = cfmsc(s, cm2, v2);
+        en.c[0] = cscale(s, P.m[r][0]);
+        // D1' v3 - D3' v1
+        s = cmulc(cp1, v3xm);
+        s = cfmac(s, cm1, v2);
+        s = cfmsc(s, cp3, p0);
+        s = cfmsc(s, cm3, v0);
+        en.c[1] = cscale(s, P.m[r][1]);
+        // D2' v1 - D1' v2
+        s = cmulc(cp2, v1ym);
+        s = cfmac(s, cm2, v0);
+        s = cfmsc(s, cp1, v2xm);
+        s = cfmsc(s, cm1, v1);
+        en.c[2] = cscale(s, P.m[r][2]);
+        return en;
+    };
+    auto q_row = [&](const Plane& P, int r) {     // q(t) on row r, -1 <= r < TY
+        const T c0 = up(vc[r + 1][0]), c1 = up(vc[r + 1][1]), c2 = up(vc[r + 1][2]);
+        const T c0xp = lane_get(ap, c0);
+        const T c1yp = up(vc[r + 2][1]);
+        const T n2 = up(P.v[r + 1][2]);
+        T s = cmul(cp1, c0xp);
+        s = cfma(s, cm1, c0);
+        s = cfma(s, cp2, c1yp);
+        s = cfma(s, cm2, c1);
+        s = cfma(s, cp3, n2);
+        return cfma(s, cm3, c2);
+    };
+    // One plane step: v(t+1) arrives in P; forms e(t+1), q(t) and, when
+    // `out`, writes w(t).  Rows are swept upwards and each row's state is
+    // replaced as soon as the rows below and above no longer need it:
+    // after row r, ec[r] holds e(t+1), qp[r] holds q(t) (the y - 1 term of
+    // row r + 1) and vc row r holds v(t+1).
+    auto step = [&](int t, const Plane& P, bool out) {
+        T qym = q_row(P, -1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vc[0][c] = P.v[0][c];
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            const Vec3 en = e_row(P, r);
+            const T qc = q_row(P, r);
+            if (out) {                            // w(t) on row r
+                const T qxm = lane_get(am, qc);
+                const T e2xp = lane_get(ap, ec[r].c[1]);
+                const T e3xp = lane_get(ap, ec[r].c[2]);
+                // w1 = D2 e3 - D3 e2 + gamma D1' q
+                T w0 = cmul(cp2, ec[r + 1].c[2]);
+                w0 = cfma(w0, cm2, ec[r].c[2]);
+                w0 = cfms(w0, cp3, en.c[1]);
+                w0 = cfms(w0, cm3, ec[r].c[1]);
+                w0 = cfmac(w0, gp1, qxm);
+                w0 = cfmac(w0, gm1, qc);
+                // w2 = D3 e1 - D1 e3 + gamma D2' q
+                T w1 = cmul(cp3, en.c[0]);
+                w1 = cfma(w1, cm3, ec[r].c[0]);
+                w1 = cfms(w1, cp1, e3xp);
+                w1 = cfms(w1, cm1, ec[r].c[2]);
+                w1 = cfmac(w1, gp2, qym);
+                w1 = cfmac(w1, gm2, qc);
+                // w3 = D1 e2 - D2 e1 + gamma D3' q
+                T w2 = cmul(cp1, e2xp);
+                w2 = cfma(w2, cm1, ec[r].c[1]);
+                w2 = cfms(w2, cp2, ec[r + 1].c[0]);
+                w2 = cfms(w2, cm2, ec[r].c[0]);
+                w2 = cfmac(w2, gp3, qp[r]);
+                w2 = cfmac(w2, gm3, qc);
+                if (sh != R(0)) {                 // uniform
+                    w0 = cadd(w0, cscale(up(vc[r + 1][0]), sh));
+                    w1 = cadd(w1, cscale(up(vc[r + 1][1]), sh));
+                    w2 = cadd(w2, cscale(up(vc[r + 1][2]), sh));
+                }
+                const unsigned o = (unsigned)t * NN + yo[r + 1];
+                *(TS*)(Yb + (size_t)(o * (unsigned)sizeof(TS))) = mk<TS>(w0.x, w0.y);
+                *(TS*)(Yb + (size_t)((N3 + o) * (unsigned)sizeof(TS))) = mk<TS>(w1.x, w1.y);
+                *(TS*)(Yb + (size_t)((2 * N3 + o) * (unsigned)sizeof(TS))) = mk<TS>(w2.x, w2.y);
+            }
+            ec[r] = en;
+            qp[r] = qc;
+            qym = qc;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vc[r + 1][c] = P.v[r + 1][c];
+        }
+        ec[TY] = e_row(P, TY);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vc[TY + 1][c] = P.v[TY + 1][c];
+    };
+
+    Plane P;
+    load(P, z0 - 1);
+#pragma unroll
+    for (int r = 0; r < TY + 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vc[r][c] = P.v[r][c];
+    load(P, z0);
+    step(z0 - 1, P, false);                       // e(z0), q(z0 - 1)
+    for (int t = z0; t < z1; ++t) {
+        load(P, t + 1);                           // t + 1 <= N: periodic
+        step(t, P, true);
+    }
+}
+
 // Tile height TY for grid size N: N * (TY + 2) <= 1024 threads, TY | N.
 static int stencil_ty(int N) {
     int best = 0;
@@ -235,6 +449,20 @@ static hipError_t launch_ty(const StencilArgs<R, S>& a, hipStream_t s) {
     dim3 block(a.N, TY + 2);
     dim3 grid(a.nyt * a.nzc * a.nb);
     hipLaunchKernelGGL(kern, grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+template <class R, class S>
+static hipError_t launch_wave(StencilArgs<R, S> a, int target, hipStream_t s) {
+    constexpr int N = 64, wpc = N * N / (64 * WTY);   // waves per band and z chunk
+    a.nyt = wpc / 4;
+    // z chunks (of at least 8 planes; each re-reads two halo planes) until
+    // the grid has `target` waves
+    const size_t per = (size_t)wpc * a.nb;
+    a.nzc = (int)std::min<size_t>(std::max<size_t>((target + per - 1) / per, 1), (size_t)N / 8);
+    a.zc = 0;
+    dim3 grid(a.nyt * a.nb * a.nzc);
+    hipLaunchKernelGGL((stencil_wave_kernel<R, S>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -262,9 +490,12 @@ hipError_t launch_stencil_rs(const OpParams& p, int nb, const void* X, void* Y, 
     for (int i = 0; i < 3; ++i) {
         a.cp[i] = mk<cplx<R>>(1.0 / p.h, 0.5 * p.k[i]);
         a.cm[i] = mk<cplx<R>>(-1.0 / p.h, 0.5 * p.k[i]);
+        a.gcp[i] = mk<cplx<R>>(p.gamma / p.h, 0.5 * p.gamma * p.k[i]);
+        a.gcm[i] = mk<cplx<R>>(-p.gamma / p.h, 0.5 * p.gamma * p.k[i]);
     }
     a.gamma = (R)p.gamma;
     a.shift = (R)p.shift;
+    if (p.N == 64) return launch_wave<R, S>(a, p.stencil_wgs, s);
     switch (TY) {
         case 8: return launch_ty<R, S, 8>(a, s);
         case 6: return launch_ty<R, S, 6>(a, s);
