@@ -112,6 +112,11 @@ typedef struct {
                                  of the residual in stall_window iterations) and the k-point was
                                  finished in FP64 from the current block */
     float ms;                 /* wall time of this k-point */
+    int rejected_steps;       /* Rayleigh-Ritz steps rejected: a step whose Ritz values are not the
+                                 Rayleigh quotients of its vectors under a fresh operator application
+                                 (a nearly dependent search direction amplified the rounding of its
+                                 Gram entries) is undone, A X recomputed and P restarted; mixed
+                                 precision then continues in FP64 (unless stall_window is 0) */
 } mfd_kstats;
 
 void mfd_default_opts(mfd_opts* opts);

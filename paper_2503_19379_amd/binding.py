@@ -39,7 +39,8 @@ class mfd_opts(ctypes.Structure):
 class mfd_kstats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("gamma_doublings", ctypes.c_int), ("gamma", ctypes.c_double),
                 ("max_rel_resid", ctypes.c_double), ("spurious", ctypes.c_int), ("discarded", ctypes.c_int),
-                ("used_fallback", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("ms", ctypes.c_float)]
+                ("used_fallback", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("ms", ctypes.c_float),
+                ("rejected_steps", ctypes.c_int)]
 
 
 _lib = None
@@ -249,7 +250,8 @@ def mfd_bands(ctx: Context, kpts, nbands: int, tol: float, opts: mfd_opts | None
 def _stats_list(st):
     return [dict(iters=s.iters, gamma_doublings=s.gamma_doublings, gamma=s.gamma,
                  max_rel_resid=s.max_rel_resid, spurious=s.spurious, discarded=s.discarded,
-                 used_fallback=s.used_fallback, fp64_fallback=s.fp64_fallback, ms=s.ms) for s in st]
+                 used_fallback=s.used_fallback, fp64_fallback=s.fp64_fallback, ms=s.ms,
+                 rejected_steps=s.rejected_steps) for s in st]
 
 
 def mfd_bands_batch(ctxs, kpts_list, nbands: int, tol: float, opts: mfd_opts | None = None, stream=None,

@@ -289,6 +289,7 @@ struct KResult {
     bool converged = false;
     bool fp64_fallback = false;
     bool proposal_used = false;
+    int rejected = 0;   // Rayleigh-Ritz steps rejected
     std::vector<double> theta, res;
 };
 
@@ -394,6 +395,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     float2* V32 = w.V32;
     float2* U32 = w.U32;
     out.fp64_fallback = false;
+    out.rejected = 0;
     out.proposal_used = false;
     // AX = op(X) (FP64); with a proposal, AW = op(W).  The basis holds the W
     // and P columns of unconverged bands only, so nothing needs clearing: a W
@@ -419,8 +421,10 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     double* hnorm = w.host + mb;
     static const bool trace = std::getenv("MFD_TRACE") != nullptr;
     const double N3 = (double)c->N * c->N * c->N;
-    int it = 0, last_refresh = 0, refreshes = 0, best_it = 0;
-    double best = HUGE_VAL;
+    int it = 0, last_refresh = 0, refreshes = 0, best_it = 0, rejected = 0;
+    bool rejected_last = false;
+    double best = HUGE_VAL, rprev = HUGE_VAL;
+    std::vector<double> th_prev(mb, 0.0);
     auto residuals = [&](double* rmax_out) {
         bool conv = true;
         double rmax = 0.0;
@@ -509,6 +513,77 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
                          "rr-ticks %d %d %d %d %d Kk %d\n", (void*)&w, it, rmax, nact, hinfo[0], hinfo[1], hinfo[3], hth[0],
                          hth[nreq - 1], hinfo[4], hinfo[5], hinfo[6], hinfo[7], hinfo[8], hinfo[9]);
         }
+        // Rayleigh-Ritz breakdown: a nearly dependent W or P column that the
+        // Cholesky pivots let through amplifies the rounding of its Gram
+        // entries (FP32-stored AW, AP; drift of the tracked AX, AP), and the
+        // step returns garbage.  A suspect step (a negative Ritz value, which
+        // the positive semidefinite operator cannot have, or a worst residual
+        // up more than 20 times, from the third iteration on) is checked with
+        // a fresh A X': a sound step's Ritz values are the Rayleigh quotients
+        // of its vectors (a residual can also jump when the subspace finds an
+        // eigenvalue the block had missed), a broken one's are not.  A broken
+        // step is rejected: the previous X, AX are still in the other buffer;
+        // AX is recomputed, R = A X - theta X with the previous theta, and the
+        // conjugate directions restart.  Mixed precision (unless its FP64
+        // fallback is off) continues in FP64, where the Gram entries of the
+        // search directions carry no FP32 rounding.  Two steps in a row are
+        // never rejected, so the iteration cannot loop.
+        bool suspect = !(rmax == rmax) || (it >= 3 && rmax > 20.0 * rprev && rmax > 1e-4);
+        for (int j = 0; j < mb; ++j) suspect |= !(hth[j] >= 0.0);
+        bool reject = false;
+        if (suspect && it > 0) {
+            double* rq = w.host + 5 * mb;
+            HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+            HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, nullptr, w.nparts_col, w.cpart, w.cout,
+                                   s));
+            HIPCHK(hipMemcpyAsync(rq, w.cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            double dev = 0.0, scale = 0.0;
+            for (int j = 0; j < mb; ++j) {
+                const double t = rq[2 * j + 1] / rq[2 * j];
+                dev = std::max(dev, std::fabs(t - hth[j]));
+                scale = std::max(scale, std::fabs(t));
+            }
+            reject = !(dev <= 1e-6 * scale) && !rejected_last;
+            if (trace) std::fprintf(stderr, "[%p] it %d: suspect step, Ritz values vs fresh Rayleigh quotients %.3e "
+                                    "(scale %.3e)%s\n", (void*)&w, it, dev, scale, reject ? ": rejected" : "");
+            if (!reject) {   // the fresh A X' stands in for the tracked one
+                HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb),
+                                       mixed ? (void*)(V32 + n * mb) : col(V, n, mb), mixed, n, n, mb, w.theta,
+                                       w.nparts_col, w.npart, w.norms, s));
+                HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                conv = residuals(&rmax);
+                active_set();
+                last_refresh = it;
+            }
+        }
+        rejected_last = reject;
+        if (reject) {
+            std::swap(V, U);
+            if (mixed) std::swap(V32, U32);
+            if (mixed && stall_window > 0) {
+                mixed = false;
+                out.fp64_fallback = true;
+                ra.drop_w = 1e-10;
+                ra.drop_p = 1e-8;
+                best_it = it;
+            }
+            std::memcpy(hth, th_prev.data(), mb * sizeof(double));
+            HIPCHK(hipMemcpyAsync(w.theta, hth, mb * sizeof(double), hipMemcpyHostToDevice, s));
+            HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+            HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), mixed ? (void*)(V32 + n * mb) : col(V, n, mb),
+                                   mixed, n, n, mb, w.theta, w.nparts_col, w.npart, w.norms, s));
+            HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            have_p = false;
+            conv = residuals(&rmax);
+            active_set();
+            last_refresh = it;
+            ++rejected;
+            if (trace) std::fprintf(stderr, "[%p] it %d: Rayleigh-Ritz step rejected (%s), P restarted: rmax %.3e\n",
+                                    (void*)&w, it, mixed ? "mixed" : "FP64", rmax);
+        }
         // The tracked AX = [AX AW AP] C drifts from A X (in mixed precision by
         // the FP32 rounding of AW and AP, every 15 iterations recomputed with
         // the FP64 operator).  Convergence is confirmed with a fresh A X in
@@ -570,7 +645,10 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             best_it = it;
             if (trace) std::fprintf(stderr, "[%p] it %d: stalled at %.3e, P restarted\n", (void*)&w, it, rmax);
         }
+        rprev = rmax;
+        std::memcpy(th_prev.data(), hth, mb * sizeof(double));
     }
+    out.rejected = rejected;
     w.V32 = V32;
     w.U32 = U32;
     w.V = V;
@@ -627,7 +705,7 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
     p.fft_xc = w.fft_xc;
     const double scale = std::pow(2.0 * M_PI / c->L, 2);
     KResult kr;
-    int doublings = 0, total_iters = 0, nspur = 0, discarded = 0, fp64_fallback = 0;
+    int doublings = 0, total_iters = 0, nspur = 0, discarded = 0, fp64_fallback = 0, rejected = 0;
     int nreq = nbands;
     std::vector<double> lam(mb), lre(mb);
     std::vector<int> sel;
@@ -638,6 +716,7 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
         if (st) return st;
         total_iters += kr.iters;
         fp64_fallback |= kr.fp64_fallback;
+        rejected += kr.rejected;
         for (int j = 0; j < mb; ++j) lam[j] = kr.theta[j] - p.shift;
         // Alg 4.1: recompute lambda_re = |M_0^(1/2) A'x|^2 / |x|^2; a band with
         // lambda - lambda_re visibly > 0 is a compensation (spurious) mode
@@ -697,6 +776,7 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
         ks.discarded = discarded;
         ks.used_fallback = 0;
         ks.fp64_fallback = fp64_fallback;
+        ks.rejected_steps = rejected;
         ks.ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     *converged = (maxres <= tol) ? (nspur ? 2 : 1) : 0;

@@ -63,3 +63,32 @@ def test_host_side_argument_errors():
     assert L.mfd_build(8, 1.0, 2, dp, None, ctypes.byref(h)) == -1      # eps must be > 0
     o = b.default_opts()
     assert o.autotune == 1 and o.stall_window == 40 and o.learn_steps == 30
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of mfd_opts and mfd_kstats have the C layout: every
+    field's offset and the struct sizes, from a C program compiled against
+    include/mfdkc.h."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    from paper_2503_19379_amd import binding as B
+    lines = []
+    for st in (B.mfd_opts, B.mfd_kstats):
+        cname = st.__name__
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mfdkc.h"\nint main(void) {\n    '
+                   + "\n    ".join(lines) + "\n    return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in (B.mfd_opts, B.mfd_kstats):
+        cname = st.__name__
+        assert got[(cname, "sizeof")] == ctypes.sizeof(st), cname
+        for f, _ in st._fields_:
+            assert got[(cname, f)] == getattr(st, f).offset, (cname, f)
