@@ -153,7 +153,9 @@ int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void*
  * preconditioner of Section 5.1 eq. (penalised_marix), solved as in Alg 5.1:
  * forward FFT along each axis, the 3 x 3 symbol solve at every frequency
  * (closed-form rank-one inverse: P_hat = s I + (gamma - 1) conj(d) d^T),
- * inverse FFT along each axis.  R and T may be the same buffer. */
+ * inverse FFT along each axis.  R and T may be the same buffer.
+ * The x-y plane pass holds a whole plane in LDS: MFD_C128 needs N <= 96
+ * (MFD_EUNSUPPORTED above), MFD_C64 every N that mfd_supported_n accepts. */
 int mfd_precond_solve(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* R, void* T,
                       void* stream);
 
@@ -173,6 +175,8 @@ int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double
  * nbands + opts->guard <= 21 (the basis of 3 (nbands + guard) columns is
  * at most 63, the size the one-workgroup Rayleigh-Ritz step holds in LDS);
  * MFD_EUNSUPPORTED otherwise.  20 bands therefore take guard <= 1.
+ * FP64 iterations on grids above N = 96 apply the preconditioner to an FP32
+ * copy of the search directions (the FP64 plane FFT does not fit in LDS). 
  * evals: host nk x nbands, ascending.  evecs: device c128
  * [nk][nbands][3][N][N][N] or NULL.  stats: host nk entries or NULL.
  * Returns MFD_ENOTCONV / MFD_ESPURIOUS after filling evals and stats. */

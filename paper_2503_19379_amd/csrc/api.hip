@@ -105,6 +105,7 @@ struct Ws {
     size_t n = 0;
     float2* V32 = nullptr;     // mixed precision: FP32 W, P, AW, AP (same column positions as V)
     float2* U32 = nullptr;
+    float2* stage32 = nullptr; // FP64 workspaces on grids without an FP64 FFT plan: W staged in FP32 (n x mb)
     hipStream_t stream = nullptr;
     double2* V = nullptr;      // n x 6mb: [X | W | P | AX | AW | AP]
     double2* U = nullptr;      // the next V
@@ -211,7 +212,7 @@ bool finite3(const double* k) { return std::isfinite(k[0]) && std::isfinite(k[1]
 void ws_free(Ws* w) {
     if (!w) return;
     hipFree(w->V); hipFree(w->U); hipFree(w->gpart); hipFree(w->G); hipFree(w->C);
-    hipFree(w->V32); hipFree(w->U32);
+    hipFree(w->V32); hipFree(w->U32); hipFree(w->stage32);
     hipFree(w->npart); hipFree(w->norms); hipFree(w->theta); hipFree(w->info);
     hipFree(w->cpart); hipFree(w->cout); hipFree(w->wtmp);
     if (w->host) hipHostFree(w->host);
@@ -255,6 +256,7 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
           chk(hipHostMalloc(&w->host, (8 * mb + 32) * sizeof(double), hipHostMallocDefault)) &&
           (!mixed || (chk(hipMalloc(&w->V32, n * 6 * mb * sizeof(float2))) &&
                       chk(hipMalloc(&w->U32, n * 6 * mb * sizeof(float2))))) &&
+          (mixed || fft_supported(c->N, 8) || chk(hipMalloc(&w->stage32, n * mb * sizeof(float2)))) &&
           (c->order == 2 || chk(hipMalloc(&w->wtmp, (size_t)c->wtmp_bands * 4 * (n / 3) * sizeof(double2)))))) {
         ws_free(w);
         return fail(e == hipErrorOutOfMemory ? MFD_ENOMEM : MFD_EDEVICE, hipGetErrorString(e));
@@ -292,6 +294,22 @@ struct KResult {
     int rejected = 0;   // Rayleigh-Ritz steps rejected
     std::vector<double> theta, res;
 };
+
+// W <- T W in place for the listed FP64 fields (field fl(t) at W + n fl(t)).
+// Grids whose FP64 plane FFT does not fit in LDS (N = 100, 120, 128) stage the
+// fields through FP32 in `stage` (same field positions): T only approximates
+// the operator's inverse, so its rounding slows LOBPCG at most slightly and
+// does not limit the accuracy the residual test certifies.
+hipError_t precond_fp64(const mfd_ctx* c, const OpParams& p, int na, double2* W, float2* stage, size_t n,
+                        const FieldList& fl, hipStream_t s) {
+    if (fft_supported(c->N, 8)) return launch_precond<double>(p, na, W, W, c->tw64, s, fl);
+    if (!stage) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < na && e == hipSuccess; ++t) e = launch_convert(W + n * fl(t), stage + n * fl(t), n, true, s);
+    if (e == hipSuccess) e = launch_precond<float>(p, na, stage, stage, c->tw32, s, fl);
+    for (int t = 0; t < na && e == hipSuccess; ++t) e = launch_convert(stage + n * fl(t), W + n * fl(t), n, false, s);
+    return e;
+}
 
 // LOBPCG at one k-point from the start block in V[:, :mb] (FP64).  Stops when
 // the lowest `nreq` columns have converged (or after max_iter iterations).
@@ -452,7 +470,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             for (int t = 0; t < na; ++t) fl.idx[t] = (unsigned char)act[t];
             hipEvent_t e0 = w.prof.begin(s);
             if (mixed) HIPCHK(launch_precond<float>(p, na, V32 + n * mb, V32 + n * mb, c->tw32, s, fl));
-            else HIPCHK(launch_precond<double>(p, na, col(V, n, mb), col(V, n, mb), c->tw64, s, fl));
+            else HIPCHK(precond_fp64(c, p, na, col(V, n, mb), w.mixed ? V32 + n * mb : w.stage32, n, fl, s));
             w.prof.end(e0, 1, N3 * 3 * rb * 2.0 * na, s);
             e0 = w.prof.begin(s);
             if (mixed) HIPCHK(launch_stencil_f64_s32(p, na, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s, fl));
@@ -943,8 +961,11 @@ int autotune(mfd_ctx* c, Ws& w, const double* k) {
         OpParams q = p;
         q.fft_xc = xc;
         const double t = timeit([&] {
-            return w.mixed ? launch_precond<float>(q, mb, w.V32 + n * mb, w.V32 + n * mb, c->tw32, s)
-                           : launch_precond<double>(q, mb, col(w.V, n, mb), col(w.V, n, mb), c->tw64, s);
+            if (w.mixed) return launch_precond<float>(q, mb, w.V32 + n * mb, w.V32 + n * mb, c->tw32, s);
+            FieldList fl;
+            fl.on = 1;
+            for (int t = 0; t < mb; ++t) fl.idx[t] = (unsigned char)t;
+            return precond_fp64(c, q, mb, col(w.V, n, mb), w.stage32, n, fl, s);
         });
         if (t < tb) { tb = t; best_xc = xc; }
     }

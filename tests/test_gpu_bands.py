@@ -158,6 +158,36 @@ def test_mixed_precision_fp64_fallback(B):
     assert all(s["fp64_fallback"] == 0 for s in st0)
 
 
+def test_large_grid_fp64_preconditioner_staged(B):
+    """N = 100: the FP64 plane FFT does not fit in LDS, so FP64 iterations
+    apply the preconditioner to an FP32 copy of W.  Homogeneous eps: the bands
+    are the oracle's closed-form spectrum."""
+    N, m = 100, 4
+    k = np.array([0.3, 0.2, 0.1]) * np.pi
+    ctx = B.mfd_build(N, 1.0, 2, np.ones((N, N, N)))
+    ev, st, status = B.mfd_bands(ctx, [k], m, 1e-9, B.default_opts(precision=0, streams=1, max_iter=300))
+    assert status == 0, st
+    assert st[0]["max_rel_resid"] <= 1e-9, st
+    phys, _ = mfd.closed_form_spectrum(N, 1.0, k, mfd.gamma_rule(N, 1.0, k))
+    assert np.allclose(ev[0], phys[:m], rtol=1e-9), (ev, phys[:m])
+
+
+def test_large_grid_mixed_fallback_to_staged_fp64(B):
+    """N = 100, diamond: a stall window of 2 sends the mixed solve to FP64,
+    whose preconditioner is staged through FP32 on this grid; the result
+    reaches 1e-8 (fresh FP64 operator) and agrees with the FP64 solve."""
+    N, m = 100, 4
+    k = workloads.kpath("GXMGR", 8)[2]
+    ctx = B.mfd_build(N, 1.0, 2, workloads.eps_diamond(N))
+    ev1, st1, status = B.mfd_bands(ctx, [k], m, 1e-8, B.default_opts(precision=1, streams=1, max_iter=400,
+                                                                      stall_window=2))
+    assert status == 0, st1
+    assert st1[0]["fp64_fallback"] == 1 and st1[0]["max_rel_resid"] <= 1e-8, st1
+    ev0, st0, status = B.mfd_bands(ctx, [k], m, 1e-8, B.default_opts(precision=0, streams=1, max_iter=400))
+    assert status == 0, st0
+    assert np.allclose(ev1[0], ev0[0], rtol=1e-7), (ev1, ev0)
+
+
 def test_autotune_changes_launch_shapes_not_results(B):
     """The autotuner picks each launch shape from its candidates; the bands
     agree with the built-in shapes'."""
