@@ -11,8 +11,10 @@ the previous k-point after it).  A k-point counts when every band's residual,
 recomputed with the FP64 operator, is <= 1e-8.
 
 Also reported (same JSON line):
-  variants      - one timed step each of the plain FP64 solve and of the
-                  learned warm start, on the same GPU;
+  variants      - one timed step each of the plain FP64 solve, of the
+                  learned warm start, of a 32-crystal batch and of the band
+                  structure and band-gap ratio of the curved-interface cubic
+                  cell (N = 120), on the same GPU;
   roofline      - the dominant kernel's achieved rate against its MI355X peak,
                   from HIP events recorded inside the library on the solve's
                   stream during the timed steps;
@@ -126,6 +128,35 @@ def batch_variant(B, args, torch, count):
             "workload": f"{cfg['ncrys']} random-field crystals (correlation length 0.15, 30% eps 13 in 1), "
                         f"N in {cfg['Ns']}, {cfg['nk']} k-points on {cfg['path']}, {cfg['nbands']} bands, "
                         f"tol {cfg['tol']:g}"}
+
+
+def band_gap_variant(B, args, torch):
+    """Section 6.2's curved-interface cubic cell (sphere 0.345 + three
+    cylinders 0.11, eps 13 in 1, M_0 set per edge) at N = 120: 10 bands along
+    Gamma-X-M-Gamma-R-X-M-R with every symmetry point, the paper's tolerance
+    1e-5, mixed precision, then the band-gap ratio.  One timed call after an
+    untimed one at the first k-point."""
+    from paper_2503_19379_amd import workloads
+    cfg = workloads.CONFIGS["sc_sphere_cyl"]
+    N = cfg["N"]
+    kp = workloads.kpath_vertices(cfg["path"], cfg["nk"])
+    ctx = B.mfd_build_mu(N, 1.0, 2, workloads.mu_sc_sphere_cylinders(N))
+    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, streams=args.streams)
+    B.mfd_bands(ctx, kp[:1], cfg["nbands"], cfg["tol"], o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ratio, below = B.mfd_gap_ratio(ev)
+    ctx.close()
+    ok = sum(1 for x in st if x["max_rel_resid"] <= cfg["tol"])
+    return {"value": ok / dt, "unit": "k-points/s", "steps": 1, "ms_per_step": dt * 1e3,
+            "iters_per_k": float(np.mean([x["iters"] for x in st])), "converged_kpoints": ok,
+            "total_kpoints": len(st), "gap_ratio": ratio, "gap_above_band": below,
+            "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"],
+            "workload": f"simple cubic sphere r 0.345 + 3 cylinders r 0.11, eps 13 in 1, M_0 per edge, N = {N}, "
+                        f"{len(kp)} k-points on {cfg['path']}, {cfg['nbands']} bands, tol {cfg['tol']:g}, mixed"}
 
 
 def stencil_direct(B, ctx, k, m, N, torch, reps=30):
@@ -298,6 +329,7 @@ def main():
                               "iters_per_k": float(np.mean(vit)), "converged_kpoints": vok,
                               "max_rel_resid": vres, "precision": prec, "warm_start": warm}
         variants["random_batch"] = batch_variant(B, args, torch, count)
+        variants["sc_sphere_cyl_gap"] = band_gap_variant(B, args, torch)
     n = 3 * N ** 3
 
     mb = m + args.guard

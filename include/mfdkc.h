@@ -133,6 +133,24 @@ void mfd_default_opts(mfd_opts* opts);
  * Errors: MFD_EINVAL, MFD_EUNSUPPORTED, MFD_ENOMEM, MFD_EDEVICE. */
 int mfd_build(int N, double L, int order, const double* eps_cells, void* stream, mfd_ctx** out);
 
+/* As mfd_build, with M_0 given directly: mu_edges (host, 3 N^3 doubles,
+ * [comp][z][y][x], finite and > 0) is the diagonal of M_0 on the edges, edge
+ * e_1 at ((x + 1/2) h, y h, z h), e_2 at (x h, (y + 1/2) h, z h), e_3 at
+ * (x h, y h, (z + 1/2) h).  Section 6.2 builds M_0 this way for its cubic
+ * lattices: eps_1^-1 on the edges inside the material, eps_0^-1 outside.
+ * Errors as mfd_build. */
+int mfd_build_mu(int N, double L, int order, const double* mu_edges, void* stream, mfd_ctx** out);
+
+/* Band-gap ratio of Section 6.2 from a computed band structure (host only):
+ * for each pair of consecutive bands j, j + 1 (1-based j), omega_low = the
+ * largest omega of band j over the nk k-points, omega_up = the smallest of
+ * band j + 1, ratio = (omega_up - omega_low) / ((omega_up + omega_low) / 2),
+ * with omega = sqrt(lambda) (lambda below zero, roundoff at Gamma, counts as
+ * zero).  Returns the largest ratio over the pairs in *ratio and its lower
+ * band j in *below; a ratio <= 0 means no gap.  evals: host nk x nbands (as
+ * mfd_bands writes it), finite; nk >= 1, nbands >= 2. */
+int mfd_gap_ratio(int nk, int nbands, const double* evals, double* ratio, int* below);
+
 /* 1 if this build has an FFT plan and stencil for grid size N, else 0. */
 int mfd_supported_n(int N);
 

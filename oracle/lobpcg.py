@@ -116,7 +116,7 @@ def spurious_flags(lam, lam_re, scale, rel=1e-4, abs_tol=1e-10):
 
 
 def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
-                maxiter=500, max_doublings=4, check=True, guard=2):
+                maxiter=500, max_doublings=4, check=True, guard=2, mu=None):
     """Lowest m physical eigenpairs of A M_0 A' + gamma B'B at Bloch vector k
     (eq. (Ker_comp)), following Alg 4.1: compute the lowest eigenpairs, recompute
     lambda_re = |M_0^(1/2) A'x|^2 / |x|^2, and treat a band with lambda_re !=
@@ -125,6 +125,9 @@ def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
     among the m + guard, gamma is doubled and the solve repeated.
 
     eps: cell permittivity (N, N, N); k: Cartesian Bloch vector (1/L units).
+    mu: M_0 on the edges (3, N, N, N) in place of the one eps gives
+    (Section 6.2 sets it per edge for its cubic lattices); eps then only
+    fixes N.
     X0: (m + guard, 3, N, N, N) start block (default: seeded complex Gaussian).
     Convergence: |A x - lambda x| <= tol (|lambda| + c) |x|, c the shift of
     ``mfd.shift_rule``.
@@ -135,7 +138,7 @@ def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
     h = L / N
     k = np.asarray(k, dtype=np.float64)
     mb = m + guard
-    mu = mfd.mu_from_eps(eps)
+    mu = mfd.mu_from_eps(eps) if mu is None else np.asarray(mu, dtype=np.float64)
     g = mfd.gamma_rule(N, L, k) if gamma is None else float(gamma)
     c = mfd.shift_rule(L, k)
     if X0 is None:

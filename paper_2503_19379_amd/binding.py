@@ -56,6 +56,8 @@ def lib():
         vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         dp = ctypes.POINTER(ctypes.c_double)
         L.mfd_build.argtypes = [i, d, i, dp, vp, ctypes.POINTER(vp)]
+        L.mfd_build_mu.argtypes = [i, d, i, dp, vp, ctypes.POINTER(vp)]
+        L.mfd_gap_ratio.argtypes = [i, i, dp, dp, ctypes.POINTER(i)]
         L.mfd_supported_n.argtypes = [i]
         L.mfd_set_gamma.argtypes = [vp, d]
         L.mfd_gamma_shift.argtypes = [vp, dp, dp, dp]
@@ -158,6 +160,30 @@ def mfd_build(N: int, L: float, order: int, eps, stream=None) -> Context:
     _check(lib().mfd_build(int(N), float(L), int(order), eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                            _stream(stream), ctypes.byref(h)))
     return Context(h, N, L)
+
+
+def mfd_build_mu(N: int, L: float, order: int, mu, stream=None) -> Context:
+    """A context from M_0 on the edges: mu of shape (3, N, N, N)."""
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64))
+    if mu.shape != (3, N, N, N):
+        raise ValueError("mu must have shape (3, N, N, N)")
+    h = ctypes.c_void_p()
+    _check(lib().mfd_build_mu(int(N), float(L), int(order), mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              _stream(stream), ctypes.byref(h)))
+    return Context(h, N, L)
+
+
+def mfd_gap_ratio(evals):
+    """(ratio, below) of the band structure evals (nk x nbands): the largest
+    gap ratio over consecutive band pairs and its lower band (1-based)."""
+    ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+    if ev.ndim != 2:
+        raise ValueError("evals must be nk x nbands")
+    r = ctypes.c_double()
+    b = ctypes.c_int()
+    _check(lib().mfd_gap_ratio(int(ev.shape[0]), int(ev.shape[1]), ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(r), ctypes.byref(b)))
+    return r.value, b.value
 
 
 def mfd_set_gamma(ctx: Context, gamma: float):

@@ -166,6 +166,12 @@ __global__ void mu_kernel(const double* __restrict__ eps, int N, double* __restr
     }
 }
 
+// M_0 given on the edges: the FP32 copy
+__global__ void mu_copy_kernel(const double* __restrict__ mu, size_t count, float* __restrict__ mu32) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        mu32[i] = (float)mu[i];
+}
+
 __global__ void twiddle_kernel(int N, double2* tw64, float2* tw32) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
@@ -1083,19 +1089,26 @@ int mfd_supported_n(int N) {
     return (N >= 4 && N <= 128 && fft_supported(N, 4)) ? 1 : 0;
 }
 
-int mfd_build(int N, double L, int order, const double* eps_cells, void* stream, mfd_ctx** out) {
+}  // extern "C"
+
+namespace {
+
+// A context from cell permittivities (mu_kernel forms M_0) or, when
+// `edges`, from M_0 itself on the 3 N^3 edges.
+int build_ctx(int N, double L, int order, const double* src, bool edges, void* stream, mfd_ctx** out) {
     if (!out) return fail(MFD_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!eps_cells) return fail(MFD_EINVAL, "eps_cells is NULL");
+    if (!src) return fail(MFD_EINVAL, edges ? "mu_edges is NULL" : "eps_cells is NULL");
     if (N < 4 || N > 128) return fail(MFD_EINVAL, "N must be in [4, 128]");
     if (!(L > 0.0) || !std::isfinite(L)) return fail(MFD_EINVAL, "L must be finite and > 0");
     if (order != 2 && order != 4 && order != 6 && order != 8)
         return fail(MFD_EUNSUPPORTED, "stencil order must be 2, 4, 6 or 8");
     if (!mfd_supported_n(N)) return fail(MFD_EUNSUPPORTED, "no FFT plan for this N");
     const size_t N3 = (size_t)N * N * N;
-    for (size_t i = 0; i < N3; ++i)
-        if (!std::isfinite(eps_cells[i]) || !(eps_cells[i] > 0.0))
-            return fail(MFD_EINVAL, "eps must be finite and > 0");
+    const size_t count = edges ? 3 * N3 : N3;
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(src[i]) || !(src[i] > 0.0))
+            return fail(MFD_EINVAL, edges ? "mu must be finite and > 0" : "eps must be finite and > 0");
     hipStream_t s = (hipStream_t)stream;
     mfd_ctx* c = new mfd_ctx();
     c->N = N;
@@ -1117,16 +1130,61 @@ int mfd_build(int N, double L, int order, const double* eps_cells, void* stream,
         (e = hipMalloc(&c->mu32, 3 * N3 * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&c->tw64, N * sizeof(double2))) != hipSuccess ||
         (e = hipMalloc(&c->tw32, N * sizeof(float2))) != hipSuccess ||
-        (e = hipMalloc(&eps_d, N3 * sizeof(double))) != hipSuccess)
+        (!edges && (e = hipMalloc(&eps_d, N3 * sizeof(double))) != hipSuccess))
         return cleanup(fail(MFD_ENOMEM, hipGetErrorString(e)));
-    if ((e = hipMemcpyAsync(eps_d, eps_cells, N3 * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
-        return cleanup(fail(MFD_EDEVICE, hipGetErrorString(e)));
-    hipLaunchKernelGGL(mu_kernel, dim3(1024), dim3(256), 0, s, eps_d, N, c->mu64, c->mu32);
+    if (edges) {
+        if ((e = hipMemcpyAsync(c->mu64, src, 3 * N3 * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return cleanup(fail(MFD_EDEVICE, hipGetErrorString(e)));
+        hipLaunchKernelGGL(mu_copy_kernel, dim3(1024), dim3(256), 0, s, c->mu64, 3 * N3, c->mu32);
+    } else {
+        if ((e = hipMemcpyAsync(eps_d, src, N3 * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return cleanup(fail(MFD_EDEVICE, hipGetErrorString(e)));
+        hipLaunchKernelGGL(mu_kernel, dim3(1024), dim3(256), 0, s, eps_d, N, c->mu64, c->mu32);
+    }
     hipLaunchKernelGGL(twiddle_kernel, dim3((N + 127) / 128), dim3(128), 0, s, N, (double2*)c->tw64, (float2*)c->tw32);
     if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
         return cleanup(fail(MFD_EDEVICE, hipGetErrorString(e)));
     hipFree(eps_d);
     *out = c;
+    return MFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfd_build(int N, double L, int order, const double* eps_cells, void* stream, mfd_ctx** out) {
+    return build_ctx(N, L, order, eps_cells, false, stream, out);
+}
+
+int mfd_build_mu(int N, double L, int order, const double* mu_edges, void* stream, mfd_ctx** out) {
+    return build_ctx(N, L, order, mu_edges, true, stream, out);
+}
+
+int mfd_gap_ratio(int nk, int nbands, const double* evals, double* ratio, int* below) {
+    if (!evals || !ratio || !below) return fail(MFD_EINVAL, "NULL argument");
+    if (nk < 1 || nbands < 2) return fail(MFD_EINVAL, "need nk >= 1 and nbands >= 2");
+    for (long long i = 0; i < (long long)nk * nbands; ++i)
+        if (!std::isfinite(evals[i])) return fail(MFD_EINVAL, "evals must be finite");
+    // omega = sqrt(lambda) in the units of lambda (the ratio is scale free);
+    // the zero bands at Gamma can come out as roundoff below zero
+    auto omega = [&](int i, int j) { return std::sqrt(std::max(evals[(size_t)i * nbands + j], 0.0)); };
+    double best = -HUGE_VAL;
+    int band = 0;
+    for (int j = 0; j + 1 < nbands; ++j) {
+        double low = -HUGE_VAL, up = HUGE_VAL;
+        for (int i = 0; i < nk; ++i) {
+            low = std::max(low, omega(i, j));
+            up = std::min(up, omega(i, j + 1));
+        }
+        const double r = (up - low) / (0.5 * (up + low));
+        if (r > best) {
+            best = r;
+            band = j + 1;
+        }
+    }
+    *ratio = best;
+    *below = band;
     return MFD_OK;
 }
 

@@ -1,0 +1,117 @@
+"""Band-gap ratio (Section 6.2): the oracle's definition against values fixed
+by hand and by the free-photon spectrum, the library's host routine against
+the oracle, and the edge sampling of the simple cubic sphere + cylinders
+cell (no GPU needed)."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bandgap, mfd
+from paper_2503_19379_amd import workloads
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2503_19379_amd",
+                   "libmfdkc.so")
+
+
+def test_ratio_by_hand():
+    """omega = sqrt(lambda): band 1 reaches 2 at most, band 2 starts at 3, so
+    the ratio is (3 - 2) / 2.5; band 2 and band 3 overlap."""
+    ev = np.array([[1.0, 9.0, 12.0], [4.0, 16.0, 13.0]])
+    r = bandgap.gap_ratios(ev)
+    assert r[0] == pytest.approx(0.4, rel=1e-15)
+    assert r[1] < 0
+    assert bandgap.gap_ratio(ev) == (pytest.approx(0.4, rel=1e-15), 1)
+
+
+def test_ratio_is_scale_free_and_clamps_roundoff():
+    rng = np.random.default_rng(3)
+    ev = np.sort(rng.uniform(0.0, 50.0, (7, 6)), axis=1)
+    assert np.allclose(bandgap.gap_ratios(ev), bandgap.gap_ratios(17.5 * ev), rtol=1e-13)
+    ev2 = ev.copy()
+    ev2[0, 0] = -1e-12   # a zero band at Gamma
+    ev3 = ev.copy()
+    ev3[0, 0] = 0.0
+    assert np.array_equal(bandgap.gap_ratios(ev2), bandgap.gap_ratios(ev3))
+
+
+def test_ratio_brute_force():
+    rng = np.random.default_rng(5)
+    ev = rng.uniform(0.0, 30.0, (9, 5))
+    r = bandgap.gap_ratios(ev)
+    for j in range(4):
+        low = max(np.sqrt(ev[i, j]) for i in range(9))
+        up = min(np.sqrt(ev[i, j + 1]) for i in range(9))
+        assert r[j] == pytest.approx((up - low) / ((up + low) / 2), rel=1e-14)
+
+
+def test_free_photons_have_no_gap():
+    """eps = 1: the physical spectrum of the discrete operator (its closed
+    form) along the simple cubic path has no complete gap among the lowest
+    ten bands."""
+    N = 16
+    kp = workloads.kpath_vertices("GXMGRXMR", 24)
+    ev = []
+    for k in kp:
+        g = mfd.gamma_rule(N, 1.0, k)
+        phys, _ = mfd.closed_form_spectrum(N, 1.0, k, g)
+        ev.append(phys[:10])
+    assert np.all(bandgap.gap_ratios(np.array(ev)) <= 0)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_gap_ratio_matches_oracle():
+    lib = ctypes.CDLL(LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.mfd_gap_ratio.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_int)]
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        nk, nb = int(rng.integers(1, 12)), int(rng.integers(2, 12))
+        ev = np.ascontiguousarray(np.sort(rng.uniform(-1e-12, 40.0, (nk, nb)), axis=1))
+        if trial % 3 == 0:   # open a gap above band nb // 2
+            ev[:, nb // 2:] += 25.0
+        r, b = ctypes.c_double(), ctypes.c_int()
+        assert lib.mfd_gap_ratio(nk, nb, ev.ctypes.data_as(dp), ctypes.byref(r), ctypes.byref(b)) == 0
+        ro, bo = bandgap.gap_ratio(ev)
+        assert r.value == pytest.approx(ro, rel=1e-13, abs=1e-15) and b.value == bo
+    r, b = ctypes.c_double(), ctypes.c_int()
+    one = np.ones((3, 1))
+    assert lib.mfd_gap_ratio(3, 1, one.ctypes.data_as(dp), ctypes.byref(r), ctypes.byref(b)) < 0
+    bad = np.array([[1.0, np.nan]])
+    assert lib.mfd_gap_ratio(1, 2, bad.ctypes.data_as(dp), ctypes.byref(r), ctypes.byref(b)) < 0
+
+
+def test_sc_sphere_cylinder_edges():
+    """Edge midpoints of the Section 6.2 cell: each edge's entry by hand at a
+    few points, the three components related by the cell's axis symmetry,
+    and the material fraction close to the solid's volume."""
+    N = 40
+    mu = workloads.mu_sc_sphere_cylinders(N)
+    hi, lo = 1.0 / 13.0, 1.0
+    h = 1.0 / N
+    # e_1 at ((x + 1/2) h, y h, z h): the centre region is material, a corner is not
+    assert mu[0, N // 2, N // 2, N // 2] == hi
+    assert mu[0, 0, 0, 0] == lo
+    # on the x-axis cylinder (y = z = 1/2) at x = 0.05: inside the cylinder
+    assert mu[0, N // 2, N // 2, 1] == hi
+    # just outside the cylinder radius 0.11 at x near 0: y = 1/2 + 0.125
+    assert mu[0, N // 2, N // 2 + 5, 1] == lo
+    # the cell is invariant under permutations of the axes: e_1 at (x, y, z)
+    # equals e_2 at the point with x and y swapped, and e_3 with x and z swapped
+    assert np.array_equal(mu[0], np.transpose(mu[1], (0, 2, 1)))
+    assert np.array_equal(mu[0], np.transpose(mu[2], (2, 1, 0)))
+    frac = (mu == hi).mean()
+    rs, rc = 0.345, 0.11
+    lens = 2.0 * np.sqrt(rs ** 2 - rc ** 2)   # cylinder length inside the sphere, roughly
+    vol = 4.0 / 3.0 * np.pi * rs ** 3 + 3.0 * np.pi * rc ** 2 * (1.0 - lens)
+    assert abs(frac - vol) < 0.02
+
+
+def test_kpath_vertices_hits_every_vertex():
+    kp = workloads.kpath_vertices("GXMGRXMR", 40)
+    pts = workloads.sc_points()
+    for c in "GXMR":
+        assert np.any(np.all(np.abs(kp - np.array(pts[c])) < 1e-14, axis=1)), c
+    d = np.linalg.norm(np.diff(kp, axis=0), axis=1)
+    assert np.all(d > 0) and d.max() < 2.5 * d.min()

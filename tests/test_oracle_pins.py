@@ -407,3 +407,23 @@ def test_k_symmetry():
     e2 = np.linalg.eigvalsh(mfd.dense_matrix(eps, L, -k, g))[:6]
     e3 = np.linalg.eigvalsh(mfd.dense_matrix(eps, L, k[[2, 0, 1]], g))[:6]
     assert np.allclose(e1, e2, rtol=1e-11) and np.allclose(e1, e3, rtol=1e-11)
+
+
+def test_bragg_stack_converges_to_exact_dispersion():
+    """eps 13 for x < 1/2 and 1 above (interfaces on cell faces): at the zone
+    edge along x the oracle's two lowest frequencies (each twice, one per
+    polarisation) approach the exact ones of the one-dimensional stack at
+    second order in h."""
+    from tests.exact import bragg_omegas
+    k = np.array([np.pi, 0.0, 0.0])
+    lam = bragg_omegas(np.pi, 2) ** 2
+    errs = []
+    for N in (8, 16):
+        eps = np.ones((N, N, N))
+        eps[:, :, : N // 2] = 13.0
+        ev, _, info = lobpcg.solve_bands(eps, 1.0, k, 4, tol=1e-9)
+        assert np.allclose(ev[0::2], ev[1::2], rtol=1e-8)
+        errs.append(np.abs(ev[0::2] - lam) / lam)
+    assert np.all(errs[1] < 0.02)
+    rate = np.log2(errs[0] / errs[1])
+    assert np.all((rate > 1.7) & (rate < 2.3)), (errs, rate)
