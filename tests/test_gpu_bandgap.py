@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 from oracle import bandgap, lobpcg as olob, mfd
 from paper_2503_19379_amd import workloads
-from tests.exact import bragg_omegas
+from tests.exact import bragg_omegas, layered_spectrum
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +34,22 @@ def test_bragg_stack_exact_dispersion(B, kx):
     lam = bragg_omegas(kx, 2) ** 2
     assert np.allclose(ev[0], np.repeat(lam, 2), rtol=2e-3), (ev[0], lam)
     assert abs(ev[0][0] - ev[0][1]) <= 1e-9 * ev[0][0] and abs(ev[0][2] - ev[0][3]) <= 1e-9 * ev[0][2]
+
+
+def test_layered_stack_oblique_exact_dispersion(B):
+    """The same stack with a wavevector along the layers, k = (0, pi/2, 0):
+    a TE wave (E tangential to the interfaces), a TM wave (E with a component
+    normal to them) and the first folded ones, against the exact transfer-
+    matrix relations.  N = 64, FP64."""
+    N = 64
+    eps = np.ones((N, N, N))
+    eps[:, :, : N // 2] = 13.0
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    k = (0.0, 0.5 * np.pi, 0.0)
+    ev, st, status = B.mfd_bands(ctx, [k], 4, 1e-10, B.default_opts(precision=0, streams=1))
+    assert status == 0, st
+    lam = layered_spectrum(k[0], k[1], 4)
+    assert np.allclose(ev[0], lam, rtol=3e-3), (ev[0], lam)
 
 
 def test_build_mu_matches_oracle(B):

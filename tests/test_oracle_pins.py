@@ -427,3 +427,21 @@ def test_bragg_stack_converges_to_exact_dispersion():
     assert np.all(errs[1] < 0.02)
     rate = np.log2(errs[0] / errs[1])
     assert np.all((rate > 1.7) & (rate < 2.3)), (errs, rate)
+
+
+def test_layered_stack_oblique_converges_to_exact_dispersion():
+    """Wavevector along the layers, k = (0, pi/2, 0): the TE wave and the TM
+    wave, whose field crosses the interfaces, reach the exact transfer-matrix
+    frequencies at second order in h."""
+    from tests.exact import layered_spectrum
+    k = np.array([0.0, 0.5 * np.pi, 0.0])
+    lam = layered_spectrum(k[0], k[1], 2)
+    errs = []
+    for N in (8, 16):
+        eps = np.ones((N, N, N))
+        eps[:, :, : N // 2] = 13.0
+        ev, _, _ = lobpcg.solve_bands(eps, 1.0, k, 2, tol=1e-9)
+        errs.append(np.abs(ev - lam) / lam)
+    assert np.all(errs[1] < 0.03), errs
+    rate = np.log2(errs[0] / errs[1])
+    assert np.all((rate > 1.6) & (rate < 2.4)), (errs, rate)
