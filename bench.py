@@ -18,9 +18,10 @@ Also reported (same JSON line):
   roofline      - the dominant kernel's achieved rate against its MI355X peak,
                   from HIP events recorded inside the library on the solve's
                   stream during the timed steps;
-  stencil       - the same for the fused stencil (the metric's second part);
-  stencil_full_block - the fused stencil alone on a full 16-band block,
-                  timed with HIP events over back-to-back calls;
+  stencil       - the metric's second part: the fused stencil alone on a
+                  full 16-band FP32 block (HIP events over back-to-back
+                  calls), with the FP64-arithmetic form and the solver's own
+                  launches beside it;
   cpu_baseline  - the FP64 CPU oracle timed on a bounded sample of the same
                   workload on this host.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -60,8 +61,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--profile-only", action="store_true", help="one short step, no JSON (for rocprofv3)")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="only the full-block stencil timing (for rocprofv3); prints its JSON object")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="with --profile-only: also run a plain 1 GiB read + 1 GiB write elementwise copy, "
+                    help="with --profile-only or --stencil-only: also run a plain 1 GiB read + 1 GiB write copy, "
                          "the reference for scaling the HBM byte counters")
     ap.add_argument("--verbose", action="store_true", help="per-k statistics on stderr")
     return ap.parse_args()
@@ -157,6 +160,18 @@ def band_gap_variant(B, args, torch):
             "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"],
             "workload": f"simple cubic sphere r 0.345 + 3 cylinders r 0.11, eps 13 in 1, M_0 per edge, N = {N}, "
                         f"{len(kp)} k-points on {cfg['path']}, {cfg['nbands']} bands, tol {cfg['tol']:g}, mixed"}
+
+
+def stencil_object(direct, timed, single):
+    out = dict(direct["fp32"], form="fp32 storage and arithmetic, full 16-band block, 30 back-to-back calls")
+    out["fp32_storage_fp64_arith"] = direct["fp32_storage_fp64_arith"]
+    if timed is not None:
+        out["in_solve"] = {
+            "timed_region": {k: timed[k] for k in ("achieved", "frac", "avg_us", "launches", "traffic")},
+            "single_stream": {k: single[k] for k in ("achieved", "frac", "avg_us")} if single else None,
+            "note": "soft-locked launches (about 10 active bands) in FP64 arithmetic; the timed region's "
+                    "durations include the wait for CUs held by the concurrent segments"}
+    return out
 
 
 def stencil_direct(B, ctx, k, m, N, torch, reps=30):
@@ -269,15 +284,23 @@ def main():
                     ok += 1
         return ok, iters, maxres
 
+    def copy_calibration():
+        x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+
+    if args.stencil_only:
+        print(json.dumps(stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch)))
+        if args.copy_calib:
+            copy_calibration()
+        return
     if args.profile_only:
         step()
         torch.cuda.synchronize()
         if args.copy_calib:
-            x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
-            y = torch.empty_like(x)
-            torch.cuda.synchronize()
-            torch.mul(x, 1.0, out=y)
-            torch.cuda.synchronize()
+            copy_calibration()
         return
     for _ in range(args.warmup):
         step()
@@ -392,10 +415,12 @@ def main():
         "roofline": dict(rl[dom], kernel=dom,
                          single_stream={k: rl_iso[dom][k] for k in ("achieved", "frac", "avg_us")}
                          if dom in rl_iso else None) if dom else None,
-        "stencil": dict(rl["stencil"],
-                        single_stream={k: rl_iso["stencil"][k] for k in ("achieved", "frac", "avg_us")}
-                        if "stencil" in rl_iso else None) if "stencil" in rl else None,
-        "stencil_full_block": stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch),
+        # the metric's second part: the fused stencil on a full block of the
+        # workload's 16 bands in FP32 (one call: 204.5 MB at N = 64), alone on
+        # the chip; beside it the FP64-arithmetic form the solver applies to
+        # its FP32 W, and the solver's own soft-locked launches
+        "stencil": stencil_object(stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch),
+                                  rl.get("stencil"), rl_iso.get("stencil")),
         "kernels": rl,
         "kernels_isolated": rl_iso,
         "iters_per_k": float(np.mean(iters)) if iters else None,
