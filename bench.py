@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--nk", type=int, default=0, help="k-points per step (0: the workload's path)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--guard", type=int, default=2)
-    ap.add_argument("--streams", type=int, default=8, help="k-path segments solved concurrently")
+    ap.add_argument("--streams", type=int, default=12, help="k-path segments solved concurrently")
     ap.add_argument("--warm", default="prev", choices=["prev", "learned"],
                     help="start block after a segment's first k-point: previous k, or the learned proposal")
     ap.add_argument("--no-variants", action="store_true",
