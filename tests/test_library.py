@@ -61,6 +61,15 @@ def test_host_side_argument_errors():
     assert L.mfd_build(7, 1.0, 2, dp, None, ctypes.byref(h)) == -6      # no FFT plan for N = 7
     eps[5] = -1.0
     assert L.mfd_build(8, 1.0, 2, dp, None, ctypes.byref(h)) == -1      # eps must be > 0
+    mu = (ctypes.c_double * 1536)(*([1.0] * 1536))                       # 3 N^3 edges at N = 8
+    mp = ctypes.cast(mu, ctypes.POINTER(ctypes.c_double))
+    assert L.mfd_build_mu(8, 1.0, 2, None, None, ctypes.byref(h)) == -1  # NULL mu
+    assert L.mfd_build_mu(7, 1.0, 2, mp, None, ctypes.byref(h)) == -6    # no FFT plan for N = 7
+    assert L.mfd_build_mu(8, 0.0, 2, mp, None, ctypes.byref(h)) == -1    # L must be > 0
+    mu[1500] = 0.0                                                       # an e_3 entry
+    assert L.mfd_build_mu(8, 1.0, 2, mp, None, ctypes.byref(h)) == -1    # mu must be > 0
+    mu[1500] = float("nan")
+    assert L.mfd_build_mu(8, 1.0, 2, mp, None, ctypes.byref(h)) == -1
     o = b.default_opts()
     assert o.autotune == 1 and o.stall_window == 40 and o.learn_steps == 30
 
