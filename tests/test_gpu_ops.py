@@ -85,6 +85,35 @@ def test_op_apply_fp32_storage_fp64_arith(B, N, ki):
     assert np.all(np.abs(got - ref) <= 2.0 ** -23 * np.abs(ref) + 1e-12 * np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("nb,dtype", [(11, "f64"), (11, "f64s32"), (16, "f32")])
+def test_op_apply_n64_uneven_z_chunks(B, nb, dtype):
+    """N = 64 stencil on wider blocks: 11 fields make 352 waves per z chunk,
+    so the default target of 2048 waves cuts z into 6 chunks of 10 or 11
+    planes (uneven); 16 fields in FP32 are the benchmark's full block.
+    Against the FP64 oracle, element-wise as in the tests above."""
+    N = 64
+    rng = np.random.default_rng(900 + nb)
+    L, k = 1.0, np.array([0.7, -0.4, 1.3])
+    eps = rand_eps(rng, N)
+    X = rand_block(rng, nb, N)
+    if dtype != "f64":
+        X = X.astype(np.complex64)
+    ctx = B.mfd_build(N, L, 2, eps)
+    g, c = B.mfd_gamma_shift(ctx, k)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    B.mfd_op_apply(ctx, k, Xd, Yd, fp64_arith=(dtype == "f64s32"))
+    torch.cuda.synchronize()
+    ref = mfd.apply_op(X.astype(np.complex128), mfd.mu_from_eps(eps), k, L / N, g, 2, c)
+    got = Yd.cpu().numpy().astype(np.complex128)
+    if dtype == "f64":
+        assert rel_err(got, ref) < 1e-13
+    elif dtype == "f64s32":
+        assert np.all(np.abs(got - ref) <= 2.0 ** -23 * np.abs(ref) + 1e-12 * np.max(np.abs(ref)))
+    else:
+        assert rel_err(got, ref) < 2e-6
+
+
 @pytest.mark.parametrize("N", [8, 12, 20, 24, 32, 48, 64])
 @pytest.mark.parametrize("ki", [0, 1])
 def test_precond_fp64(B, N, ki):
