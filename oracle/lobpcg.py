@@ -19,6 +19,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
+from . import lattice as lat
 from . import mfd
 
 
@@ -116,7 +117,7 @@ def spurious_flags(lam, lam_re, scale, rel=1e-4, abs_tol=1e-10):
 
 
 def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
-                maxiter=500, max_doublings=4, check=True, guard=2, mu=None):
+                maxiter=500, max_doublings=4, check=True, guard=2, mu=None, lattice=None):
     """Lowest m physical eigenpairs of A M_0 A' + gamma B'B at Bloch vector k
     (eq. (Ker_comp)), following Alg 4.1: compute the lowest eigenpairs, recompute
     lambda_re = |M_0^(1/2) A'x|^2 / |x|^2, and treat a band with lambda_re !=
@@ -128,6 +129,9 @@ def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
     mu: M_0 on the edges (3, N, N, N) in place of the one eps gives
     (Section 6.2 sets it per edge for its cubic lattices); eps then only
     fixes N.
+    lattice: 3 x 3 matrix whose columns are the lattice vectors (Section 2's
+    coordinate change, Section 4.2's D^_i; ``oracle.lattice``); L is then
+    ignored and |det A|^(1/3) takes its place in the penalty and shift rules.
     X0: (m + guard, 3, N, N, N) start block (default: seeded complex Gaussian).
     Convergence: |A x - lambda x| <= tol (|lambda| + c) |x|, c the shift of
     ``mfd.shift_rule``.
@@ -135,6 +139,8 @@ def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
     eps = np.asarray(eps, dtype=np.float64)
     N = eps.shape[0]
     n = 3 * N ** 3
+    if lattice is not None:
+        L = lat.cell_length(lattice)
     h = L / N
     k = np.asarray(k, dtype=np.float64)
     mb = m + guard
@@ -149,10 +155,15 @@ def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
     total_iters = 0
     nreq = m
     while True:
-        Pinv = np.linalg.inv(mfd.precond_matrices(N, L, k, g, order, c))
+        if lattice is None:
+            Pinv = np.linalg.inv(mfd.precond_matrices(N, L, k, g, order, c))
+        else:
+            Pinv = np.linalg.inv(lat.precond_matrices(N, lattice, k, g, order, c))
 
         def apply_A(Y, g=g):
             V = Y.T.reshape(-1, 3, N, N, N)
+            if lattice is not None:
+                return lat.apply_op(V, mu, k, lattice, g, order, c).reshape(-1, n).T
             return mfd.apply_op(V, mu, k, h, g, order, c).reshape(-1, n).T
 
         def apply_T(R, g=g, Pinv=Pinv):
@@ -163,7 +174,10 @@ def solve_bands(eps, L, k, m, tol=1e-10, order=2, gamma=None, X0=None, seed=0,
         total_iters += info["iters"]
         lam = th - c
         Xb = X.T.reshape(mb, 3, N, N, N)
-        lam_re = np.array([mfd.lambda_re(x, mu, k, h, order) for x in Xb])
+        if lattice is None:
+            lam_re = np.array([mfd.lambda_re(x, mu, k, h, order) for x in Xb])
+        else:
+            lam_re = np.array([lat.lambda_re(x, mu, k, lattice, order) for x in Xb])
         spur = spurious_flags(lam, lam_re, (2 * np.pi / L) ** 2) if check else np.zeros(mb, bool)
         phys = np.flatnonzero(~spur)
         if len(phys) >= m:
