@@ -141,6 +141,25 @@ int mfd_build(int N, double L, int order, const double* eps_cells, void* stream,
  * Errors as mfd_build. */
 int mfd_build_mu(int N, double L, int order, const double* mu_edges, void* stream, mfd_ctx** out);
 
+/* As mfd_build, on a general lattice (Section 2, eq. (coordinate_change);
+ * Section 4.2, "Matrix representation on general lattices").
+ * lattice: host, 9 doubles, row-major 3 x 3 matrix A whose columns are the
+ *    primitive vectors a_1, a_2, a_3 (Cartesian; lattice[3 r + c] = component r
+ *    of a_{c+1}), linearly independent.  The grid is the unit cube of
+ *    y = A^-1 x with N cells per axis; eps_cells ([z][y][x] as for mfd_build)
+ *    holds the permittivity of the cell centred at y = ((x+1/2), (y+1/2),
+ *    (z+1/2)) / N.  Every derivative becomes D^_i = sum_j b_ji K_j + i L_i with
+ *    b = A^-1, K_j the difference along grid axis j and L_i the unchanged
+ *    average along grid axis i (alpha = the Cartesian k).
+ * Wave vectors passed to the other calls stay Cartesian (units 1/length of A).
+ * The penalty and shift rules use L = |det A|^(1/3) in place of the cell side.
+ * Every order uses the two-pass operator (scratch owned by the context, as
+ * for orders > 2).
+ * Errors: MFD_EINVAL also for a NULL, non-finite or singular lattice; others
+ * as mfd_build. */
+int mfd_build_lattice(int N, const double* lattice, int order, const double* eps_cells, void* stream,
+                      mfd_ctx** out);
+
 /* Band-gap ratio of Section 6.2 from a computed band structure (host only):
  * for each pair of consecutive bands j, j + 1 (1-based j), omega_low = the
  * largest omega of band j over the nk k-points, omega_up = the smallest of

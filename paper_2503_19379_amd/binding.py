@@ -57,6 +57,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.mfd_build.argtypes = [i, d, i, dp, vp, ctypes.POINTER(vp)]
         L.mfd_build_mu.argtypes = [i, d, i, dp, vp, ctypes.POINTER(vp)]
+        L.mfd_build_lattice.argtypes = [i, dp, i, dp, vp, ctypes.POINTER(vp)]
         L.mfd_gap_ratio.argtypes = [i, i, dp, dp, ctypes.POINTER(i)]
         L.mfd_supported_n.argtypes = [i]
         L.mfd_set_gamma.argtypes = [vp, d]
@@ -171,6 +172,22 @@ def mfd_build_mu(N: int, L: float, order: int, mu, stream=None) -> Context:
     _check(lib().mfd_build_mu(int(N), float(L), int(order), mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                               _stream(stream), ctypes.byref(h)))
     return Context(h, N, L)
+
+
+def mfd_build_lattice(N: int, lattice, order: int, eps, stream=None) -> Context:
+    """A context on a general lattice: ``lattice`` is the 3 x 3 matrix whose
+    columns are the primitive vectors, eps of shape (N, N, N) on the unit-cube
+    grid of y = lattice^-1 x."""
+    A = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64))
+    if A.shape != (3, 3):
+        raise ValueError("lattice must be 3 x 3")
+    eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
+    if eps.shape != (N, N, N):
+        raise ValueError("eps must have shape (N, N, N)")
+    h = ctypes.c_void_p()
+    dptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().mfd_build_lattice(int(N), dptr(A), int(order), dptr(eps), _stream(stream), ctypes.byref(h)))
+    return Context(h, N, float(abs(np.linalg.det(A))) ** (1.0 / 3.0))
 
 
 def mfd_gap_ratio(evals):

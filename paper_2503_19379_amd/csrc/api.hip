@@ -123,7 +123,7 @@ struct Ws {
     int cap_upd = 0, cap_gram = 0; // workgroups the npart / gpart buffers hold partials for
     int stencil_wgs = 2048, fft_xc = 0, upd_rows = 0;   // upd_rows 0: one wave per 16-row strip
     WarmStart* warm = nullptr; // learned warm start (warm_start = 2), allocated on first use
-    void* wtmp = nullptr;      // orders > 2: operator scratch of this workspace's stream
+    void* wtmp = nullptr;      // two-pass operator: scratch of this workspace's stream
     Prof prof;
 };
 
@@ -132,8 +132,10 @@ struct mfd_ctx {
     double L = 1.0, h = 1.0;
     int order = 2;
     int device = 0;
-    void* wtmp = nullptr;      // orders > 2: operator scratch for the ABI calls
+    void* wtmp = nullptr;      // two-pass operator: scratch for the ABI calls
     int wtmp_bands = 0;
+    int lattice = 0;           // general lattice: B[i][j] = N (A^-1)_ji (Section 4.2)
+    double B[3][3] = {};
     // launch shapes chosen by the autotuner for one block shape (mb, precision)
     int tune_mb = 0, tune_mixed = -1;   // tune_mb: 0 untuned, -1 pinned by mfd_set_tuning
     int tune[5] = {0, 0, 0, 0, 0};   // Gram workgroups, update workgroups, stencil workgroups, FFT x run,
@@ -203,6 +205,9 @@ OpParams params(const mfd_ctx* ctx, const double k[3]) {
     p.order = ctx->order;
     p.wtmp = ctx->wtmp;
     p.wtmp_bands = ctx->wtmp_bands;
+    p.lattice = ctx->lattice;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) p.B[i][j] = ctx->B[i][j];
     return p;
 }
 
@@ -263,7 +268,8 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
           (!mixed || (chk(hipMalloc(&w->V32, n * 6 * mb * sizeof(float2))) &&
                       chk(hipMalloc(&w->U32, n * 6 * mb * sizeof(float2))))) &&
           (mixed || fft_supported(c->N, 8) || chk(hipMalloc(&w->stage32, n * mb * sizeof(float2)))) &&
-          (c->order == 2 || chk(hipMalloc(&w->wtmp, (size_t)c->wtmp_bands * 4 * (n / 3) * sizeof(double2)))))) {
+          ((c->order == 2 && !c->lattice) ||
+           chk(hipMalloc(&w->wtmp, (size_t)c->wtmp_bands * 4 * (n / 3) * sizeof(double2)))))) {
         ws_free(w);
         return fail(e == hipErrorOutOfMemory ? MFD_ENOMEM : MFD_EDEVICE, hipGetErrorString(e));
     }
@@ -1094,8 +1100,10 @@ int mfd_supported_n(int N) {
 namespace {
 
 // A context from cell permittivities (mu_kernel forms M_0) or, when
-// `edges`, from M_0 itself on the 3 N^3 edges.
-int build_ctx(int N, double L, int order, const double* src, bool edges, void* stream, mfd_ctx** out) {
+// `edges`, from M_0 itself on the 3 N^3 edges.  `lat` (nullable): row-major
+// 3 x 3 matrix whose columns are the lattice vectors; L is then |det|^(1/3).
+int build_ctx(int N, double L, int order, const double* src, bool edges, void* stream, mfd_ctx** out,
+              const double* lat = nullptr) {
     if (!out) return fail(MFD_EINVAL, "out is NULL");
     *out = nullptr;
     if (!src) return fail(MFD_EINVAL, edges ? "mu_edges is NULL" : "eps_cells is NULL");
@@ -1104,6 +1112,30 @@ int build_ctx(int N, double L, int order, const double* src, bool edges, void* s
     if (order != 2 && order != 4 && order != 6 && order != 8)
         return fail(MFD_EUNSUPPORTED, "stencil order must be 2, 4, 6 or 8");
     if (!mfd_supported_n(N)) return fail(MFD_EUNSUPPORTED, "no FFT plan for this N");
+    double Bl[3][3] = {};
+    if (lat) {
+        double scale = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            if (!std::isfinite(lat[i])) return fail(MFD_EINVAL, "lattice vectors must be finite");
+            scale = std::max(scale, std::fabs(lat[i]));
+        }
+        auto a = [&](int r, int c) { return lat[3 * r + c]; };
+        const double det = a(0, 0) * (a(1, 1) * a(2, 2) - a(1, 2) * a(2, 1)) -
+                           a(0, 1) * (a(1, 0) * a(2, 2) - a(1, 2) * a(2, 0)) +
+                           a(0, 2) * (a(1, 0) * a(2, 1) - a(1, 1) * a(2, 0));
+        if (!(std::fabs(det) > 1e-12 * scale * scale * scale))
+            return fail(MFD_EINVAL, "lattice vectors are linearly dependent");
+        // inverse by cofactors: inv[r][c] = cof[c][r] / det
+        double inv[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+                inv[r][c] = (a(r1, c1) * a(r2, c2) - a(r1, c2) * a(r2, c1)) / det;
+            }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Bl[i][j] = N * inv[j][i];
+        L = std::cbrt(std::fabs(det));
+    }
     const size_t N3 = (size_t)N * N * N;
     const size_t count = edges ? 3 * N3 : N3;
     for (size_t i = 0; i < count; ++i)
@@ -1116,6 +1148,9 @@ int build_ctx(int N, double L, int order, const double* src, bool edges, void* s
     c->h = L / N;
     c->order = order;
     c->n = 3 * N3;
+    c->lattice = lat ? 1 : 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) c->B[i][j] = Bl[i][j];
     hipGetDevice(&c->device);
     double* eps_d = nullptr;
     auto cleanup = [&](int st) {
@@ -1124,8 +1159,9 @@ int build_ctx(int N, double L, int order, const double* src, bool edges, void* s
         return st;
     };
     hipError_t e;
-    if (order > 2) c->wtmp_bands = wide_bands(N);
-    if ((order > 2 && (e = hipMalloc(&c->wtmp, (size_t)c->wtmp_bands * 4 * N3 * sizeof(double2))) != hipSuccess) ||
+    const bool wide = order > 2 || lat;
+    if (wide) c->wtmp_bands = wide_bands(N);
+    if ((wide && (e = hipMalloc(&c->wtmp, (size_t)c->wtmp_bands * 4 * N3 * sizeof(double2))) != hipSuccess) ||
         (e = hipMalloc(&c->mu64, 3 * N3 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->mu32, 3 * N3 * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&c->tw64, N * sizeof(double2))) != hipSuccess ||
@@ -1159,6 +1195,15 @@ int mfd_build(int N, double L, int order, const double* eps_cells, void* stream,
 
 int mfd_build_mu(int N, double L, int order, const double* mu_edges, void* stream, mfd_ctx** out) {
     return build_ctx(N, L, order, mu_edges, true, stream, out);
+}
+
+int mfd_build_lattice(int N, const double* lattice, int order, const double* eps_cells, void* stream,
+                      mfd_ctx** out) {
+    if (!lattice) {
+        if (out) *out = nullptr;
+        return fail(MFD_EINVAL, "lattice is NULL");
+    }
+    return build_ctx(N, 1.0, order, eps_cells, false, stream, out, lattice);
 }
 
 int mfd_gap_ratio(int nk, int nbands, const double* evals, double* ratio, int* below) {

@@ -321,22 +321,32 @@ hipError_t launch_residual(const void* X, const void* AX, void* R, bool r32, siz
 // ---------------------------------------------------------------------------
 struct LamCoef {
     int K;
-    double c[4], d[4];   // c divided by h
+    double c[4], d[4];   // unit-step stencil
+    double B[3][3];      // B[i][j]: weight of the difference along grid axis j in D_i
     double alpha[3];
 };
 
-// (D_i' u)[r] = sum_s c_s (u[r-s] - u[r-1+s]) - i alpha_i sum_s d_s (u[r-s] + u[r-1+s]) along axis i
+__device__ __forceinline__ C128 lam_at(const C128* u, int N, int x, int y, int z, int axis, int off) {
+    if (axis == 0) x = (x + off + 4 * N) % N;
+    else if (axis == 1) y = (y + off + 4 * N) % N;
+    else z = (z + off + 4 * N) % N;
+    return u[((size_t)z * N + y) * N + x];
+}
+
+// (D_i' u)[r] = sum_j B_ij sum_s c_s (u[r - s e_j] - u[r + (s-1) e_j])
+//               - i alpha_i sum_s d_s (u[r - s e_i] + u[r + (s-1) e_i])
 __device__ __forceinline__ C128 lam_dadj(const LamCoef& w, const C128* u, int N, int x, int y, int z, int axis) {
     C128 diff = mk<C128>(0, 0), avg = mk<C128>(0, 0);
-    for (int s = 1; s <= w.K; ++s) {
-        int xa = x, ya = y, za = z, xb = x, yb = y, zb = z;
-        if (axis == 0) { xa = (x - s + 4 * N) % N; xb = (x + s - 1) % N; }
-        else if (axis == 1) { ya = (y - s + 4 * N) % N; yb = (y + s - 1) % N; }
-        else { za = (z - s + 4 * N) % N; zb = (z + s - 1) % N; }
-        const C128 a = u[((size_t)za * N + ya) * N + xa], b = u[((size_t)zb * N + yb) * N + xb];
-        diff = cadd(diff, cscale(csub(a, b), w.c[s - 1]));
-        avg = cadd(avg, cscale(cadd(a, b), w.d[s - 1]));
+    for (int j = 0; j < 3; ++j) {
+        const double bj = w.B[axis][j];
+        if (bj == 0.0) continue;
+        C128 dj = mk<C128>(0, 0);
+        for (int s = 1; s <= w.K; ++s)
+            dj = cadd(dj, cscale(csub(lam_at(u, N, x, y, z, j, -s), lam_at(u, N, x, y, z, j, s - 1)), w.c[s - 1]));
+        diff = cadd(diff, cscale(dj, bj));
     }
+    for (int s = 1; s <= w.K; ++s)
+        avg = cadd(avg, cscale(cadd(lam_at(u, N, x, y, z, axis, -s), lam_at(u, N, x, y, z, axis, s - 1)), w.d[s - 1]));
     const double al = w.alpha[axis];
     return mk<C128>(diff.x + al * avg.y, diff.y - al * avg.x);
 }
@@ -378,10 +388,13 @@ hipError_t launch_lambda_re(const OpParams& p, int nb, const void* X, const void
     double c[4], d[4];
     stencil_coefs(p.order, c, d);
     for (int q = 0; q < 4; ++q) {
-        w.c[q] = c[q] / p.h;
+        w.c[q] = c[q];
         w.d[q] = d[q];
     }
-    for (int i = 0; i < 3; ++i) w.alpha[i] = p.k[i];
+    for (int i = 0; i < 3; ++i) {
+        w.alpha[i] = p.k[i];
+        for (int j = 0; j < 3; ++j) w.B[i][j] = diff_weight(p, i, j);
+    }
     hipLaunchKernelGGL(lambda_re_kernel, dim3(nparts, nb), dim3(256), 0, s, (const C128*)X, (const double*)mu, p.N,
                        w, nb, partial);
     hipError_t e = hipGetLastError();

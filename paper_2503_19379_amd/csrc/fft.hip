@@ -8,6 +8,11 @@
 //   d_i(p) = (e^{i theta} - 1) / h + i alpha_i (1 + e^{i theta}) / 2,
 // and by Cor 4.4 (A A' + B'B = diag(L, L, L)) the 3 x 3 symbol of P is
 //   P_hat(p) = s I + (gamma - 1) conj(d) d^T,   s = |d_1|^2 + |d_2|^2 + |d_3|^2.
+// On a general lattice (Section 4.2) every D^_i = sum_j b_ji K_j + i L_i is
+// still a polynomial in the grid shifts, so the same 3 x 3 form holds with
+//   d_i(p) = sum_j B_ij kappa(p_j) + i alpha_i lambda(p_i),
+// kappa and lambda the unit-step difference and average symbols along one
+// axis and B_ij = N (A^-1)_ji.
 // Alg 5.1 inverts a scalar diagonal; here the per-frequency block is rank-one
 // plus a multiple of I, so its inverse is closed form (Sherman-Morrison):
 //   t_hat = ( r_hat - (gamma - 1) conj(d) (d^T r_hat) / (gamma s + c) ) / (s + c).
@@ -183,6 +188,9 @@ struct SolveArgs {
     int K;             // stencil half-width (order 2K)
     R c[4], d[4];      // Table FD_1D, c divided by h
     R alpha[3];
+    int lattice;       // general lattice: d_i from B and the unit-step symbols
+    R cu[4];           // Table FD_1D c, unit step
+    R B[3][3];         // B[i][j]: weight of the difference along grid axis j in D_i
     FieldList fl;
 };
 
@@ -203,6 +211,24 @@ __device__ __forceinline__ cplx<R> symbol_2k(const cplx<R>* tw, int p, const Sol
     }
     const R al = a.alpha[axis];
     return mk<T>(diff.x - al * avg.y, diff.y + al * avg.x);
+}
+
+// Unit-step symbols along one axis at frequency p:
+//   kap = sum_s c_s (e^{i s theta} - e^{i (1-s) theta}),  lam = sum_s d_s (e^{i s theta} + e^{i (1-s) theta}).
+template <class R, int N>
+__device__ __forceinline__ void symbol_parts(const cplx<R>* tw, int p, const SolveArgs<R>& a, cplx<R>& kap,
+                                             cplx<R>& lam) {
+    using T = cplx<R>;
+    kap = mk<T>(0, 0);
+    lam = mk<T>(0, 0);
+    for (int s = 1; s <= a.K; ++s) {
+        T e1 = tw[(p * s) % N];
+        T e0 = tw[((p * (1 - s)) % N + N) % N];
+        e1.y = -e1.y;
+        e0.y = -e0.y;
+        kap = cadd(kap, cscale(csub(e1, e0), a.cu[s - 1]));
+        lam = cadd(lam, cscale(cadd(e1, e0), a.d[s - 1]));
+    }
 }
 
 // Kernel 2: DFT along z, 3 x 3 symbol solve, inverse DFT along z, for XC
@@ -238,7 +264,21 @@ __global__ __launch_bounds__(FFT_NT) void fft_zsolve_kernel(SolveArgs<R> a) {
         T ex = tw[px], ey = tw[y], ez = tw[pz];
         ex.y = -ex.y; ey.y = -ey.y; ez.y = -ez.y;
         T d1, d2, d3;
-        if (a.K == 1) {
+        if (a.lattice) {
+            T kp[3], lm[3], dd[3];
+            symbol_parts<R, N>(tw, px, a, kp[0], lm[0]);
+            symbol_parts<R, N>(tw, y, a, kp[1], lm[1]);
+            symbol_parts<R, N>(tw, pz, a, kp[2], lm[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dd[c] = mk<T>(-a.alpha[c] * lm[c].y, a.alpha[c] * lm[c].x);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dd[c] = cadd(dd[c], cscale(kp[j], a.B[c][j]));
+            }
+            d1 = dd[0];
+            d2 = dd[1];
+            d3 = dd[2];
+        } else if (a.K == 1) {
             d1 = mk<T>((ex.x - (R)1) * a.inv_h - a.half_k[0] * ex.y, ex.y * a.inv_h + a.half_k[0] * ((R)1 + ex.x));
             d2 = mk<T>((ey.x - (R)1) * a.inv_h - a.half_k[1] * ey.y, ey.y * a.inv_h + a.half_k[1] * ((R)1 + ey.x));
             d3 = mk<T>((ez.x - (R)1) * a.inv_h - a.half_k[2] * ez.y, ez.y * a.inv_h + a.half_k[2] * ((R)1 + ez.x));
@@ -321,9 +361,14 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
         stencil_coefs(p.order, c, d);
         for (int q = 0; q < 4; ++q) {
             a.c[q] = (R)(c[q] / p.h);
+            a.cu[q] = (R)c[q];
             a.d[q] = (R)d[q];
         }
-        for (int i = 0; i < 3; ++i) a.alpha[i] = (R)p.k[i];
+        for (int i = 0; i < 3; ++i) {
+            a.alpha[i] = (R)p.k[i];
+            for (int j = 0; j < 3; ++j) a.B[i][j] = (R)diff_weight(p, i, j);
+        }
+        a.lattice = p.lattice;
     }
     const int xc = (p.fft_xc > 0 && N % p.fft_xc == 0 && p.fft_xc <= 16) ? p.fft_xc : pick_xc(N);
     switch (xc) {

@@ -13,9 +13,23 @@ struct OpParams {
     int order = 2;             // stencil order 2K (Table FD_1D)
     int stencil_wgs = 2048;    // order 2: z chunks until this many workgroups (N = 64: waves)
     int fft_xc = 0;            // x run of the z-pass of the FFT solve (0: the largest of 16, 8, 4, 2, 1 dividing N)
-    void* wtmp = nullptr;      // orders > 2: scratch for wtmp_bands bands of 4 FP64 complex fields
+    void* wtmp = nullptr;      // two-pass operator: scratch for wtmp_bands bands of 4 FP64 complex fields
     int wtmp_bands = 0;
+    // General lattice (Section 4.2, eq. (coordinate_change)): the grid is the
+    // unit cube of y = A^-1 x and D^_i = sum_j b_ji K_j + i L_i.  B[i][j] =
+    // N b_ji weighs the unit-step difference along grid axis j in D^_i.
+    int lattice = 0;
+    double B[3][3] = {};
 };
+
+// Weight of the unit-step difference along grid axis j in D_i: B[i][j] on a
+// general lattice, 1/h on the diagonal of a cubic one.
+inline double diff_weight(const OpParams& p, int i, int j) {
+    return p.lattice ? p.B[i][j] : (i == j ? 1.0 / p.h : 0.0);
+}
+
+// Orders > 2 and general lattices use the two-pass operator.
+inline bool two_pass(const OpParams& p) { return p.order > 2 || p.lattice; }
 
 // Table FD_1D coefficients (c_s, d_s), s = 1..order/2, zero-padded to 4 (wide.hip).
 void stencil_coefs(int order, double c[4], double d[4]);
@@ -33,8 +47,8 @@ template <class R>
 hipError_t launch_stencil(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
                           const FieldList& fl = FieldList());
 
-// Orders > 2: the same operator in two passes through p.wtmp (wide.hip); R
-// arithmetic, S storage.
+// Orders > 2 and general lattices: the same operator in two passes through
+// p.wtmp (wide.hip); R arithmetic, S storage.
 template <class R, class S>
 hipError_t launch_wide(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
                        const FieldList& fl);

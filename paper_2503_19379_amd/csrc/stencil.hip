@@ -470,7 +470,7 @@ template <class R, class S>
 hipError_t launch_stencil_rs(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
                              const FieldList& fl) {
     if (fl.on && nb > 32) return hipErrorInvalidValue;
-    if (p.order > 2) return launch_wide<R, S>(p, nb, X, Y, mu, s, fl);
+    if (two_pass(p)) return launch_wide<R, S>(p, nb, X, Y, mu, s, fl);
     StencilArgs<R, S> a;
     a.fl = fl;
     a.X = (const cplx<S>*)X;

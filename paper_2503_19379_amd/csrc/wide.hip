@@ -1,10 +1,16 @@
-// Higher-order MFD operator (orders 2K = 4, 6, 8; Section 4.1.3, eq. (2kfdm),
-// Table FD_1D): the compensated operator w = A M_0 A' v + gamma B'B v + c v
-// with every one-dimensional difference and midpoint value replaced by its
-// 2K-point symmetric stencil.  Along axis i, periodic:
-//   (D_i u)[r]  = (1/h) sum_s c_s (u[r+s] - u[r+1-s]) + i alpha_i sum_s d_s (u[r+s] + u[r+1-s])
-//   (D_i' u)[r] = (1/h) sum_s c_s (u[r-s] - u[r-1+s]) - i alpha_i sum_s d_s (u[r-s] + u[r-1+s])
-// (D_i' is the adjoint of D_i), assembled as in eq. (discrete_2nd_block):
+// Two-pass MFD operator: orders 2K = 4, 6, 8 (Section 4.1.3, eq. (2kfdm),
+// Table FD_1D) and general lattices (Section 4.2).  It forms the compensated
+// operator w = A M_0 A' + gamma B'B v + c v with every one-dimensional
+// difference and midpoint value replaced by its 2K-point symmetric stencil.
+// With the unit-step difference and average along grid axis j, periodic,
+//   (K_j u)[r]  = sum_s c_s (u[r+s] - u[r+1-s]),   (L_j u)[r]  = sum_s d_s (u[r+s] + u[r+1-s]),
+//   (K_j' u)[r] = sum_s c_s (u[r-s] - u[r-1+s]),   (L_j' u)[r] = sum_s d_s (u[r-s] + u[r-1+s]),
+// the derivative of Cartesian axis i is
+//   D_i  = sum_j B_ij K_j  + i alpha_i L_i,   D_i' = sum_j B_ij K_j' - i alpha_i L_i'
+// (D_i' the adjoint of D_i).  B = I / h on a cubic cell; on the lattice of A
+// the grid is the unit cube of y = A^-1 x and B_ij = N (A^-1)_ji, while the
+// average stays along grid axis i.  The operator is assembled as in eq.
+// (discrete_2nd_block):
 //   e = A'v : e1 = D3'v2 - D2'v3, e2 = D1'v3 - D3'v1, e3 = D2'v1 - D1'v2;  e <- mu e
 //   q = B v = D1 v1 + D2 v2 + D3 v3
 //   w1 = D2 e3 - D3 e2, w2 = D3 e1 - D1 e3, w3 = D1 e2 - D2 e1;  w_i += gamma D_i' q;  w += c v.
@@ -38,7 +44,8 @@ void stencil_coefs(int order, double c[4], double d[4]) {
 template <class R>
 struct WideCoef {
     int K;
-    R c[4], d[4];   // c already divided by h
+    R c[4], d[4];   // unit-step stencil
+    R B[3][3];      // B[i][j]: weight of the difference along grid axis j in D_i
     R alpha[3];
 };
 
@@ -52,28 +59,37 @@ __device__ __forceinline__ cplx<R> ld_shift(const T* u, int N, int x, int y, int
     return mk<cplx<R>>(v.x, v.y);
 }
 
-template <class R, class T>
-__device__ __forceinline__ cplx<R> Dfwd(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
+// sum_j B[axis][j] sum_s c_s (u[r + sg s e_j] - u[r + sg (1 - s) e_j]) + i sg alpha_axis
+//   sum_s d_s (u[r + sg s e_axis] + u[r + sg (1 - s) e_axis]); sg = +1 gives D, sg = -1 gives D'.
+template <int SG, class R, class T>
+__device__ __forceinline__ cplx<R> Dapply(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
     cplx<R> diff = mk<cplx<R>>(0, 0), avg = mk<cplx<R>>(0, 0);
+    for (int j = 0; j < 3; ++j) {
+        const R bj = w.B[axis][j];
+        if (bj == (R)0) continue;
+        cplx<R> dj = mk<cplx<R>>(0, 0);
+        for (int s = 1; s <= w.K; ++s) {
+            const cplx<R> a = ld_shift<R>(u, N, x, y, z, j, SG * s), b = ld_shift<R>(u, N, x, y, z, j, SG * (1 - s));
+            dj = cadd(dj, cscale(csub(a, b), w.c[s - 1]));
+        }
+        diff = cadd(diff, cscale(dj, bj));
+    }
     for (int s = 1; s <= w.K; ++s) {
-        const cplx<R> a = ld_shift<R>(u, N, x, y, z, axis, s), b = ld_shift<R>(u, N, x, y, z, axis, 1 - s);
-        diff = cadd(diff, cscale(csub(a, b), w.c[s - 1]));
+        const cplx<R> a = ld_shift<R>(u, N, x, y, z, axis, SG * s), b = ld_shift<R>(u, N, x, y, z, axis, SG * (1 - s));
         avg = cadd(avg, cscale(cadd(a, b), w.d[s - 1]));
     }
-    const R al = w.alpha[axis];
-    return mk<cplx<R>>(diff.x - al * avg.y, diff.y + al * avg.x);   // diff + i alpha avg
+    const R al = SG * w.alpha[axis];
+    return mk<cplx<R>>(diff.x - al * avg.y, diff.y + al * avg.x);   // diff + i sg alpha avg
+}
+
+template <class R, class T>
+__device__ __forceinline__ cplx<R> Dfwd(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
+    return Dapply<1>(w, u, N, x, y, z, axis);
 }
 
 template <class R, class T>
 __device__ __forceinline__ cplx<R> Dadj(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
-    cplx<R> diff = mk<cplx<R>>(0, 0), avg = mk<cplx<R>>(0, 0);
-    for (int s = 1; s <= w.K; ++s) {
-        const cplx<R> a = ld_shift<R>(u, N, x, y, z, axis, -s), b = ld_shift<R>(u, N, x, y, z, axis, s - 1);
-        diff = cadd(diff, cscale(csub(a, b), w.c[s - 1]));
-        avg = cadd(avg, cscale(cadd(a, b), w.d[s - 1]));
-    }
-    const R al = w.alpha[axis];
-    return mk<cplx<R>>(diff.x + al * avg.y, diff.y - al * avg.x);   // diff - i alpha avg
+    return Dapply<-1>(w, u, N, x, y, z, axis);
 }
 
 // pass 1: T[b] = [mu_1 e1, mu_2 e2, mu_3 e3, q] of field fl(b0 + b)
@@ -135,10 +151,13 @@ hipError_t launch_wide(const OpParams& p, int nb, const void* X, void* Y, const 
     double c[4], d[4];
     stencil_coefs(p.order, c, d);
     for (int q = 0; q < 4; ++q) {
-        w.c[q] = (R)(c[q] / p.h);
+        w.c[q] = (R)c[q];
         w.d[q] = (R)d[q];
     }
-    for (int a = 0; a < 3; ++a) w.alpha[a] = (R)p.k[a];
+    for (int a = 0; a < 3; ++a) {
+        w.alpha[a] = (R)p.k[a];
+        for (int j = 0; j < 3; ++j) w.B[a][j] = (R)diff_weight(p, a, j);
+    }
     const size_t N3 = (size_t)p.N * p.N * p.N;
     const unsigned gx = (unsigned)((N3 + 255) / 256);
     cplx<R>* T = (cplx<R>*)p.wtmp;

@@ -70,6 +70,21 @@ def test_host_side_argument_errors():
     assert L.mfd_build_mu(8, 1.0, 2, mp, None, ctypes.byref(h)) == -1    # mu must be > 0
     mu[1500] = float("nan")
     assert L.mfd_build_mu(8, 1.0, 2, mp, None, ctypes.byref(h)) == -1
+    # general lattice: NULL, singular and non-finite lattice matrices
+    eps = (ctypes.c_double * 512)(*([1.0] * 512))
+    ep = ctypes.cast(eps, ctypes.POINTER(ctypes.c_double))
+    bcc = (ctypes.c_double * 9)(-0.5, 0.5, 0.5, 0.5, -0.5, 0.5, 0.5, 0.5, -0.5)
+    lp = ctypes.cast(bcc, ctypes.POINTER(ctypes.c_double))
+    assert L.mfd_build_lattice(8, None, 2, ep, None, ctypes.byref(h)) == -1
+    assert L.mfd_build_lattice(8, lp, 2, None, None, ctypes.byref(h)) == -1
+    assert L.mfd_build_lattice(7, lp, 2, ep, None, ctypes.byref(h)) == -6
+    assert L.mfd_build_lattice(8, lp, 3, ep, None, ctypes.byref(h)) == -6
+    sing = (ctypes.c_double * 9)(1.0, 2.0, 0.0, 2.0, 4.0, 0.0, 3.0, 6.0, 1.0)   # a_2 = 2 a_1
+    assert L.mfd_build_lattice(8, ctypes.cast(sing, ctypes.POINTER(ctypes.c_double)), 2, ep, None,
+                               ctypes.byref(h)) == -1
+    bcc[4] = float("inf")
+    assert L.mfd_build_lattice(8, lp, 2, ep, None, ctypes.byref(h)) == -1
+    assert h.value is None
     o = b.default_opts()
     assert o.autotune == 1 and o.stall_window == 40 and o.learn_steps == 30
 
