@@ -151,7 +151,7 @@ def band_gap_variant(B, args, torch):
     ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], o)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ratio, below = B.mfd_gap_ratio(ev)
+    ratio, below = B.mfd_gap_ratio(ev, kp)
     ctx.close()
     ok = sum(1 for x in st if x["max_rel_resid"] <= cfg["tol"])
     return {"value": ok / dt, "unit": "k-points/s", "steps": 1, "ms_per_step": dt * 1e3,

@@ -160,6 +160,12 @@ int mfd_build_mu(int N, double L, int order, const double* mu_edges, void* strea
 int mfd_build_lattice(int N, const double* lattice, int order, const double* eps_cells, void* stream,
                       mfd_ctx** out);
 
+/* As mfd_build_lattice, with M_0 given on the edges of the unit-cube grid
+ * (mu_edges as for mfd_build_mu, edge e_1 at y = ((x + 1/2), y, z) / N and so
+ * on).  Section 6.3 sets M_0 this way for its BCC and FCC cells. */
+int mfd_build_lattice_mu(int N, const double* lattice, int order, const double* mu_edges, void* stream,
+                         mfd_ctx** out);
+
 /* Band-gap ratio of Section 6.2 from a computed band structure (host only):
  * for each pair of consecutive bands j, j + 1 (1-based j), omega_low = the
  * largest omega of band j over the nk k-points, omega_up = the smallest of
@@ -167,8 +173,17 @@ int mfd_build_lattice(int N, const double* lattice, int order, const double* eps
  * with omega = sqrt(lambda) (lambda below zero, roundoff at Gamma, counts as
  * zero).  Returns the largest ratio over the pairs in *ratio and its lower
  * band j in *below; a ratio <= 0 means no gap.  evals: host nk x nbands (as
- * mfd_bands writes it), finite; nk >= 1, nbands >= 2. */
-int mfd_gap_ratio(int nk, int nbands, const double* evals, double* ratio, int* below);
+ * mfd_bands writes it), finite; nk >= 1, nbands >= 2.
+ * kpts: host nk x 3 (the k-points of evals), or NULL.  At k = 0 mfd_bands
+ * returns the three constant fields as bands 1-3; two of them continue the
+ * two lowest bands as k -> 0 and the third is a static mode through which no
+ * band passes.  With kpts given, a row with k exactly 0 skips that third
+ * zero: its band j >= 3 is the returned value j + 1, and it has no value for
+ * the last band.  With NULL, every row is taken as returned.
+ * Errors: MFD_EINVAL for NULL outputs, bad sizes, non-finite values, or when
+ * no pair gives a ratio (a lone k = 0 row with nbands = 3: 0/0 for bands
+ * 1-2, no value of band 3). */
+int mfd_gap_ratio(int nk, int nbands, const double* kpts, const double* evals, double* ratio, int* below);
 
 /* 1 if this build has an FFT plan and stencil for grid size N, else 0. */
 int mfd_supported_n(int N);

@@ -58,7 +58,8 @@ def lib():
         L.mfd_build.argtypes = [i, d, i, dp, vp, ctypes.POINTER(vp)]
         L.mfd_build_mu.argtypes = [i, d, i, dp, vp, ctypes.POINTER(vp)]
         L.mfd_build_lattice.argtypes = [i, dp, i, dp, vp, ctypes.POINTER(vp)]
-        L.mfd_gap_ratio.argtypes = [i, i, dp, dp, ctypes.POINTER(i)]
+        L.mfd_build_lattice_mu.argtypes = [i, dp, i, dp, vp, ctypes.POINTER(vp)]
+        L.mfd_gap_ratio.argtypes = [i, i, dp, dp, dp, ctypes.POINTER(i)]
         L.mfd_supported_n.argtypes = [i]
         L.mfd_set_gamma.argtypes = [vp, d]
         L.mfd_gamma_shift.argtypes = [vp, dp, dp, dp]
@@ -190,16 +191,39 @@ def mfd_build_lattice(N: int, lattice, order: int, eps, stream=None) -> Context:
     return Context(h, N, float(abs(np.linalg.det(A))) ** (1.0 / 3.0))
 
 
-def mfd_gap_ratio(evals):
+def mfd_build_lattice_mu(N: int, lattice, order: int, mu, stream=None) -> Context:
+    """A context on a general lattice from M_0 on the edges: mu of shape
+    (3, N, N, N) on the unit-cube grid of y = lattice^-1 x."""
+    A = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64))
+    if A.shape != (3, 3):
+        raise ValueError("lattice must be 3 x 3")
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64))
+    if mu.shape != (3, N, N, N):
+        raise ValueError("mu must have shape (3, N, N, N)")
+    h = ctypes.c_void_p()
+    dptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().mfd_build_lattice_mu(int(N), dptr(A), int(order), dptr(mu), _stream(stream), ctypes.byref(h)))
+    return Context(h, N, float(abs(np.linalg.det(A))) ** (1.0 / 3.0))
+
+
+def mfd_gap_ratio(evals, kpts=None):
     """(ratio, below) of the band structure evals (nk x nbands): the largest
-    gap ratio over consecutive band pairs and its lower band (1-based)."""
+    gap ratio over consecutive band pairs and its lower band (1-based).
+    kpts (nk x 3): the k-points of evals; a k = 0 row then skips the static
+    third zero band."""
     ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
     if ev.ndim != 2:
         raise ValueError("evals must be nk x nbands")
+    kp = None
+    if kpts is not None:
+        kp = np.ascontiguousarray(np.asarray(kpts, dtype=np.float64).reshape(-1, 3))
+        if kp.shape[0] != ev.shape[0]:
+            raise ValueError("kpts must have one row per row of evals")
+    dptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     r = ctypes.c_double()
     b = ctypes.c_int()
-    _check(lib().mfd_gap_ratio(int(ev.shape[0]), int(ev.shape[1]), ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                               ctypes.byref(r), ctypes.byref(b)))
+    _check(lib().mfd_gap_ratio(int(ev.shape[0]), int(ev.shape[1]), dptr(kp), dptr(ev), ctypes.byref(r),
+                               ctypes.byref(b)))
     return r.value, b.value
 
 

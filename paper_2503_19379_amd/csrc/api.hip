@@ -1206,28 +1206,50 @@ int mfd_build_lattice(int N, const double* lattice, int order, const double* eps
     return build_ctx(N, 1.0, order, eps_cells, false, stream, out, lattice);
 }
 
-int mfd_gap_ratio(int nk, int nbands, const double* evals, double* ratio, int* below) {
+int mfd_build_lattice_mu(int N, const double* lattice, int order, const double* mu_edges, void* stream,
+                         mfd_ctx** out) {
+    if (!lattice) {
+        if (out) *out = nullptr;
+        return fail(MFD_EINVAL, "lattice is NULL");
+    }
+    return build_ctx(N, 1.0, order, mu_edges, true, stream, out, lattice);
+}
+
+int mfd_gap_ratio(int nk, int nbands, const double* kpts, const double* evals, double* ratio, int* below) {
     if (!evals || !ratio || !below) return fail(MFD_EINVAL, "NULL argument");
     if (nk < 1 || nbands < 2) return fail(MFD_EINVAL, "need nk >= 1 and nbands >= 2");
     for (long long i = 0; i < (long long)nk * nbands; ++i)
         if (!std::isfinite(evals[i])) return fail(MFD_EINVAL, "evals must be finite");
+    if (kpts)
+        for (long long i = 0; i < 3LL * nk; ++i)
+            if (!std::isfinite(kpts[i])) return fail(MFD_EINVAL, "kpts must be finite");
+    // At k = 0 the returned bands 1-3 are the three constant fields; only two
+    // of them continue bands as k -> 0, the third (along the direction of
+    // approach) is static, so band b >= 3 of a k = 0 row is column b.
+    auto col = [&](int i, int j) {
+        const bool gamma = kpts && kpts[3 * i] == 0.0 && kpts[3 * i + 1] == 0.0 && kpts[3 * i + 2] == 0.0;
+        return (gamma && j >= 2) ? j + 1 : j;
+    };
     // omega = sqrt(lambda) in the units of lambda (the ratio is scale free);
     // the zero bands at Gamma can come out as roundoff below zero
-    auto omega = [&](int i, int j) { return std::sqrt(std::max(evals[(size_t)i * nbands + j], 0.0)); };
+    auto omega = [&](int i, int c) { return std::sqrt(std::max(evals[(size_t)i * nbands + c], 0.0)); };
     double best = -HUGE_VAL;
     int band = 0;
     for (int j = 0; j + 1 < nbands; ++j) {
         double low = -HUGE_VAL, up = HUGE_VAL;
         for (int i = 0; i < nk; ++i) {
-            low = std::max(low, omega(i, j));
-            up = std::min(up, omega(i, j + 1));
+            const int c0 = col(i, j), c1 = col(i, j + 1);
+            if (c0 < nbands) low = std::max(low, omega(i, c0));
+            if (c1 < nbands) up = std::min(up, omega(i, c1));
         }
+        if (low == -HUGE_VAL || up == HUGE_VAL) continue;   // only k = 0 rows, which lack band j + 1
         const double r = (up - low) / (0.5 * (up + low));
         if (r > best) {
             best = r;
             band = j + 1;
         }
     }
+    if (band == 0) return fail(MFD_EINVAL, "no band pair gives a ratio");
     *ratio = best;
     *below = band;
     return MFD_OK;

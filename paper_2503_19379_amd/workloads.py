@@ -109,11 +109,30 @@ def kpath(labels: str, n: int, L: float = 1.0) -> np.ndarray:
     return out
 
 
-def kpath_vertices(labels: str, n: int, L: float = 1.0) -> np.ndarray:
-    """About n k-points along the polyline through the named points, each
-    segment sampled in proportion to its length with its end points included
-    (band extrema sit at the symmetry points).  Shape (n', 3)."""
-    pts = sc_points(L)
+def bcc_points(l: float = 1.0) -> dict:
+    """Symmetry points of the BCC Brillouin zone (Section 6, lattice constant
+    l): H'(0, 0, 2 pi/l) is "h", Gamma "G", P, N and H."""
+    p = np.pi / l
+    return {"h": (0.0, 0.0, 2 * p), "G": (0.0, 0.0, 0.0), "P": (p, p, p), "N": (p, 0.0, p),
+            "H": (0.0, 2 * p, 0.0)}
+
+
+def lattice_vectors(kind: str, l: float = 1.0) -> np.ndarray:
+    """Primitive vectors of eq. (translation_vecs) as the columns of a 3 x 3
+    matrix: "sc", "fcc" or "bcc" with lattice constant l."""
+    h = 0.5 * l
+    cols = {"sc": [(l, 0, 0), (0, l, 0), (0, 0, l)],
+            "fcc": [(0, h, h), (h, 0, h), (h, h, 0)],
+            "bcc": [(-h, h, h), (h, -h, h), (h, h, -h)]}[kind]
+    return np.array(cols, dtype=np.float64).T
+
+
+def kpath_vertices(labels: str, n: int, L: float = 1.0, points: dict | None = None) -> np.ndarray:
+    """About n k-points along the polyline through the named points (simple
+    cubic ones unless ``points`` is given), each segment sampled in
+    proportion to its length with its end points included (band extrema sit
+    at the symmetry points).  Shape (n', 3)."""
+    pts = sc_points(L) if points is None else points
     P = np.array([pts[c] for c in labels], dtype=np.float64)
     seg = np.linalg.norm(np.diff(P, axis=0), axis=1)
     out = []
@@ -155,6 +174,34 @@ def mu_sc_sphere_cylinders(N: int, L: float = 1.0, r_sphere: float = 0.345, r_cy
     return mu
 
 
+def mu_bcc_gyroid(N: int, l: float = 1.0, t: float = 1.1, eps_in: float = 16.0,
+                  eps_out: float = 1.0) -> np.ndarray:
+    """M_0 on the edges of the unit-cube grid of the BCC primitive cell for
+    the single gyroid of Section 6.3: material where
+    g = sin(2 pi x/l) cos(2 pi y/l) + sin(2 pi y/l) cos(2 pi z/l) + sin(2 pi z/l) cos(2 pi x/l) > t,
+    eps_in / eps_out = 16.  g is invariant under the BCC translations, so it
+    is periodic on the cell.  Edge e_1[z, y, x] sits at y = ((x + 1/2), y, z) / N
+    in cell coordinates (e_2, e_3 likewise), mapped to Cartesian by the BCC
+    vectors; an edge takes eps_in^-1 when its midpoint is in the material.
+    Shape (3, N, N, N)."""
+    A = lattice_vectors("bcc", l)
+    i = np.arange(N) / N
+    half = i + 0.5 / N
+    mu = np.empty((3, N, N, N))
+    w = 2 * np.pi / l
+    for comp in range(3):
+        ax = [i, i, i]
+        ax[comp] = half
+        Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        cx = A[0, 0] * X + A[0, 1] * Y + A[0, 2] * Z
+        cy = A[1, 0] * X + A[1, 1] * Y + A[1, 2] * Z
+        cz = A[2, 0] * X + A[2, 1] * Y + A[2, 2] * Z
+        g = (np.sin(w * cx) * np.cos(w * cy) + np.sin(w * cy) * np.cos(w * cz)
+             + np.sin(w * cz) * np.cos(w * cx))
+        mu[comp] = np.where(g > t, 1.0 / eps_in, 1.0 / eps_out)
+    return mu
+
+
 def start_block(m: int, N: int, seed: int) -> np.ndarray:
     """Seeded complex Gaussian start block, shape (m, 3, N, N, N), complex128
     (real and imaginary parts independent standard normals)."""
@@ -181,6 +228,12 @@ CONFIGS = {
     # the paper's grid is N = 150, beyond this build's FFT plans
     "sc_sphere_cyl": dict(N=120, mu="sc_sphere_cyl", path="GXMGRXMR", nk=40, nbands=10, tol=1e-5,
                           precision="mixed", gap_ratio_paper=0.14019, N_paper=150),
+    # BCC single gyroid (Section 6.3, Table time_comp_bc): first 10 bands at
+    # k = (pi, pi, pi)/l, N = 100 and 120, relative residual 1e-5
+    "bcc_gyroid": dict(Ns=(100, 120), lattice="bcc", mu="bcc_gyroid", k=(np.pi, np.pi, np.pi), nbands=10,
+                       tol=1e-5, precision="mixed", steps_paper={100: 70, 120: 65},
+                       gpu_s_paper={100: 40.55, 120: 54.92}, path="hGPNH", nk=40, gap_ratio_paper=0.31745,
+                       N_paper=150),
     # diamond at N = 96, learned warm start
     "diamond_n96": dict(N=96, eps="diamond", path="GXMGRX", nk=100, nbands=20, tol=1e-8,
                         precision="mixed"),

@@ -25,6 +25,24 @@ def test_ratio_by_hand():
     assert bandgap.gap_ratio(ev) == (pytest.approx(0.4, rel=1e-15), 1)
 
 
+def test_gamma_row_skips_the_static_zero_band():
+    """At k = 0 the solver returns three zero bands; with the k-points given
+    the third is skipped.  Here omega at Gamma becomes (0, 0, 3, 4, -) and at
+    the other point (1, 2, sqrt 10, sqrt 12, sqrt 20): pair 2-3 has low 2 and
+    up 3, ratio 0.4; pair 4-5 takes band 5 from the second row only.  Taken
+    as returned, band 3 reaches 0 at Gamma and the 2-3 gap closes."""
+    ev = np.array([[0.0, 0.0, 0.0, 9.0, 16.0], [1.0, 4.0, 10.0, 12.0, 20.0]])
+    kp = np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0]])
+    r = bandgap.gap_ratios(ev, kp)
+    assert r[1] == pytest.approx(0.4, rel=1e-15)
+    assert r[3] == pytest.approx((np.sqrt(20) - 4) / ((np.sqrt(20) + 4) / 2), rel=1e-14)
+    assert bandgap.gap_ratio(ev, kp) == (pytest.approx(0.4, rel=1e-15), 2)
+    assert bandgap.gap_ratios(ev)[1] < 0
+    # a k-point that is only near Gamma keeps its row
+    kp2 = np.array([[1e-9, 0.0, 0.0], [0.1, 0.0, 0.0]])
+    assert np.array_equal(bandgap.gap_ratios(ev, kp2), bandgap.gap_ratios(ev))
+
+
 def test_ratio_is_scale_free_and_clamps_roundoff():
     rng = np.random.default_rng(3)
     ev = np.sort(rng.uniform(0.0, 50.0, (7, 6)), axis=1)
@@ -49,7 +67,8 @@ def test_ratio_brute_force():
 def test_free_photons_have_no_gap():
     """eps = 1: the physical spectrum of the discrete operator (its closed
     form) along the simple cubic path has no complete gap among the lowest
-    ten bands."""
+    ten bands.  The closed form's physical part holds two zeros at Gamma, not
+    the solver's three, so its rows are taken as they are."""
     N = 16
     kp = workloads.kpath_vertices("GXMGRXMR", 24)
     ev = []
@@ -64,22 +83,32 @@ def test_free_photons_have_no_gap():
 def test_library_gap_ratio_matches_oracle():
     lib = ctypes.CDLL(LIB)
     dp = ctypes.POINTER(ctypes.c_double)
-    lib.mfd_gap_ratio.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_int)]
+    lib.mfd_gap_ratio.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
     rng = np.random.default_rng(11)
-    for trial in range(20):
-        nk, nb = int(rng.integers(1, 12)), int(rng.integers(2, 12))
+    for trial in range(30):
+        nk, nb = int(rng.integers(1, 12)), int(rng.integers(3, 12))
         ev = np.ascontiguousarray(np.sort(rng.uniform(-1e-12, 40.0, (nk, nb)), axis=1))
         if trial % 3 == 0:   # open a gap above band nb // 2
             ev[:, nb // 2:] += 25.0
-        r, b = ctypes.c_double(), ctypes.c_int()
-        assert lib.mfd_gap_ratio(nk, nb, ev.ctypes.data_as(dp), ctypes.byref(r), ctypes.byref(b)) == 0
-        ro, bo = bandgap.gap_ratio(ev)
-        assert r.value == pytest.approx(ro, rel=1e-13, abs=1e-15) and b.value == bo
+        kp = np.ascontiguousarray(rng.uniform(-1, 1, (nk, 3)))
+        kp[rng.random(nk) < 0.3] = 0.0
+        if nk == 1:
+            kp[0] = 0.5
+        ev[np.all(kp == 0.0, axis=1), :3] = rng.uniform(-1e-12, 1e-12, 3)
+        for with_k in (False, True):
+            r, b = ctypes.c_double(), ctypes.c_int()
+            assert lib.mfd_gap_ratio(nk, nb, kp.ctypes.data_as(dp) if with_k else None, ev.ctypes.data_as(dp),
+                                     ctypes.byref(r), ctypes.byref(b)) == 0
+            ro, bo = bandgap.gap_ratio(ev, kp if with_k else None)
+            assert r.value == pytest.approx(ro, rel=1e-13, abs=1e-15) and b.value == bo
     r, b = ctypes.c_double(), ctypes.c_int()
     one = np.ones((3, 1))
-    assert lib.mfd_gap_ratio(3, 1, one.ctypes.data_as(dp), ctypes.byref(r), ctypes.byref(b)) < 0
+    assert lib.mfd_gap_ratio(3, 1, None, one.ctypes.data_as(dp), ctypes.byref(r), ctypes.byref(b)) < 0
     bad = np.array([[1.0, np.nan]])
-    assert lib.mfd_gap_ratio(1, 2, bad.ctypes.data_as(dp), ctypes.byref(r), ctypes.byref(b)) < 0
+    assert lib.mfd_gap_ratio(1, 2, None, bad.ctypes.data_as(dp), ctypes.byref(r), ctypes.byref(b)) < 0
+    z3 = np.zeros((1, 3))   # a lone Gamma row with three bands: 0/0 for bands 1-2, no band 3
+    assert lib.mfd_gap_ratio(1, 3, z3.ctypes.data_as(dp), np.zeros((1, 3)).ctypes.data_as(dp),
+                             ctypes.byref(r), ctypes.byref(b)) < 0
 
 
 def test_sc_sphere_cylinder_edges():

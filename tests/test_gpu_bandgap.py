@@ -85,8 +85,11 @@ def test_build_mu_equals_build_eps(B):
 def test_band_gap_driver(B):
     """The sphere + cylinders cell at N = 64, mixed precision, the paper's
     LOBPCG tolerance 1e-5, 10 bands along Gamma-X-M-Gamma-R-X-M-R with every
-    symmetry point included: every k-point converges and the library's gap
-    ratio is the oracle's for the same band structure."""
+    symmetry point included: every k-point converges, the library's gap ratio
+    is the oracle's for the same band structure, and with the static zero
+    mode at Gamma skipped the gap opens between bands 5 and 6 at the paper's
+    0.14019 (N = 150) within 0.004.  Taken as returned (third zero band
+    counted at Gamma) bands 5 and 6 overlap."""
     cfg = workloads.CONFIGS["sc_sphere_cyl"]
     N = 64
     kp = workloads.kpath_vertices(cfg["path"], cfg["nk"])
@@ -95,8 +98,47 @@ def test_band_gap_driver(B):
                                  B.default_opts(precision=1, warm_start=1, guard=2, streams=8, max_iter=500))
     assert status == 0, st
     assert all(s["max_rel_resid"] <= cfg["tol"] for s in st)
-    r, below = B.mfd_gap_ratio(ev)
-    ro, bo = bandgap.gap_ratio(ev)
+    r, below = B.mfd_gap_ratio(ev, kp)
+    ro, bo = bandgap.gap_ratio(ev, kp)
     assert r == pytest.approx(ro, rel=1e-12) and below == bo
-    print(f"N = {N}: largest gap ratio {r:.5f} above band {below} (the paper prints {cfg['gap_ratio_paper']} "
+    r0, _ = B.mfd_gap_ratio(ev)
+    print(f"N = {N}: largest gap ratio {r:.5f} above band {below}, {r0:.5f} with the static mode counted "
+          f"(the paper prints {cfg['gap_ratio_paper']} at N = {cfg['N_paper']})")
+    assert below == 5 and abs(r - cfg["gap_ratio_paper"]) < 0.004
+    assert r0 < 0
+
+
+def test_gamma_row_minus_the_static_mode_is_the_physical_spectrum(B):
+    """eps = 1 at k = 0: the solver's three zero bands are the two transverse
+    zeros of the closed-form physical spectrum plus one static mode; without
+    the third, the row is the physical spectrum."""
+    N, m = 12, 9
+    ctx = B.mfd_build(N, 1.0, 2, np.ones((N, N, N)))
+    ev, st, status = B.mfd_bands(ctx, [np.zeros(3)], m, 1e-10, B.default_opts(precision=0, streams=1))
+    assert status == 0, st
+    assert np.abs(ev[0][:3]).max() < 1e-9
+    phys, _ = mfd.closed_form_spectrum(N, 1.0, np.zeros(3), st[0]["gamma"])
+    row = np.concatenate([ev[0][:2], ev[0][3:]])
+    assert np.allclose(row, phys[: m - 1], rtol=1e-9, atol=1e-9), (row, phys[: m - 1])
+
+
+def test_bcc_gyroid_band_gap(B):
+    """Section 6.3's single gyroid on the BCC lattice (eps 16 in 1, M_0 per
+    edge) at N = 64, 10 bands on H'-Gamma-P-N-H with every symmetry point,
+    tol 1e-5, mixed precision: the gap opens between bands 2 and 3 and its
+    ratio approaches the paper's 0.31745 (N = 150) from below as N grows
+    (0.3122 at N = 100, 0.3150 at N = 120)."""
+    cfg = workloads.CONFIGS["bcc_gyroid"]
+    N = 64
+    kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.bcc_points())
+    ctx = B.mfd_build_lattice_mu(N, workloads.lattice_vectors("bcc"), 2, workloads.mu_bcc_gyroid(N))
+    ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"],
+                                 B.default_opts(precision=1, warm_start=1, guard=2, streams=8, max_iter=500))
+    assert status == 0, st
+    assert all(s["max_rel_resid"] <= cfg["tol"] for s in st)
+    r, below = B.mfd_gap_ratio(ev, kp)
+    ro, bo = bandgap.gap_ratio(ev, kp)
+    assert r == pytest.approx(ro, rel=1e-12) and below == bo
+    print(f"N = {N}: gyroid gap ratio {r:.5f} above band {below} (the paper prints {cfg['gap_ratio_paper']} "
           f"at N = {cfg['N_paper']})")
+    assert below == 2 and 0.28 < r < cfg["gap_ratio_paper"]
