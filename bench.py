@@ -63,8 +63,11 @@ def parse():
     ap.add_argument("--profile-only", action="store_true", help="one short step, no JSON (for rocprofv3)")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only the full-block stencil timing (for rocprofv3); prints its JSON object")
+    ap.add_argument("--lattice-only", action="store_true",
+                    help="only the two-pass operator timing on the BCC gyroid at N = 120 (for rocprofv3); "
+                         "prints its JSON object")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="with --profile-only or --stencil-only: also run a plain 1 GiB read + 1 GiB write copy, "
+                    help="with --profile-only, --stencil-only or --lattice-only: also run a plain 1 GiB read + 1 GiB write copy, "
                          "the reference for scaling the HBM byte counters")
     ap.add_argument("--verbose", action="store_true", help="per-k statistics on stderr")
     return ap.parse_args()
@@ -160,6 +163,91 @@ def band_gap_variant(B, args, torch):
             "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"],
             "workload": f"simple cubic sphere r 0.345 + 3 cylinders r 0.11, eps 13 in 1, M_0 per edge, N = {N}, "
                         f"{len(kp)} k-points on {cfg['path']}, {cfg['nbands']} bands, tol {cfg['tol']:g}, mixed"}
+
+
+def lattice_op_direct(B, ctx, k, m, N, torch, reps=20):
+    """The two-pass general-lattice operator alone on a block of m FP32-stored
+    bands, FP64 arithmetic as the mixed solve applies it: mean duration of
+    `reps` back-to-back mfd_op_apply calls between HIP events on their
+    stream.  Algorithmic bytes per call: per band and cell, X read by both
+    passes (2 x 24 B), the FP64 scratch e and q written and read once
+    (2 x 64 B) and Y written (24 B), plus mu (24 B per cell) once."""
+    n3 = N ** 3
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((m, 3, N, N, N), dtype=torch.complex64, device="cuda", generator=g)
+    Y = torch.empty_like(X)
+    s = torch.cuda.Stream()
+    for _ in range(3):
+        B.mfd_op_apply(ctx, k, X, Y, stream=s.cuda_stream, fp64_arith=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        B.mfd_op_apply(ctx, k, X, Y, stream=s.cuda_stream, fp64_arith=True)
+    e1.record(s)
+    e1.synchronize()
+    avg_s = e0.elapsed_time(e1) * 1e-3 / reps
+    by = (48.0 + 128.0 + 24.0) * n3 * m + 24.0 * n3
+    del X, Y
+    torch.cuda.synchronize()
+    return {"achieved": by / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": by / avg_s / HBM_PEAK,
+            "avg_us": avg_s * 1e6, "bytes_per_call": by, "nbands": m, "N": N, "calls": reps,
+            "form": "FP32 storage, FP64 arithmetic, two passes through FP64 scratch"}
+
+
+def lattice_only(B, torch):
+    """The BCC gyroid context at N = 120 and the two-pass operator timing
+    alone (for rocprofv3)."""
+    from paper_2503_19379_amd import workloads
+    cfg = workloads.CONFIGS["bcc_gyroid"]
+    N = cfg["Ns"][-1]
+    ctx = B.mfd_build_lattice_mu(N, workloads.lattice_vectors("bcc"), 2, workloads.mu_bcc_gyroid(N))
+    out = lattice_op_direct(B, ctx, np.array(cfg["k"]), cfg["nbands"] + 2, N, torch)
+    ctx.close()
+    return out
+
+
+def gyroid_variant(B, args, torch):
+    """Section 6.3's BCC single gyroid (eps 16 in 1, M_0 per edge, general
+    lattice operator).  (1) Table time_comp_bc's workload: the first 10
+    bands at k = (pi, pi, pi)/l to the paper's tolerance 1e-5 from a random
+    start, N = 100 and 120, one timed solve after an untimed one; the paper's
+    steps and its A100 seconds are carried beside for context.  (2) The band
+    structure on H'-Gamma-P-N-H at N = 120 and its gap ratio.  (3) The
+    two-pass operator alone on a 12-band block at N = 120
+    (lattice_op_direct)."""
+    from paper_2503_19379_amd import workloads
+    cfg = workloads.CONFIGS["bcc_gyroid"]
+    A = workloads.lattice_vectors("bcc")
+    kP = np.array([cfg["k"]])
+    out = {"workload": "BCC single gyroid g > 1.1, eps 16 in 1, M_0 per edge, general-lattice operator, "
+                       f"{cfg['nbands']} bands, tol {cfg['tol']:g}, mixed precision"}
+    for N in cfg["Ns"]:
+        ctx = B.mfd_build_lattice_mu(N, A, 2, workloads.mu_bcc_gyroid(N))
+        o = B.default_opts(precision=1, warm_start=0, seed=0, guard=2, max_iter=500, streams=1)
+        B.mfd_bands(ctx, kP, cfg["nbands"], cfg["tol"], o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, st, status = B.mfd_bands(ctx, kP, cfg["nbands"], cfg["tol"], o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"P_N{N}"] = {"value": 1.0 / dt, "unit": "k-points/s", "ms": dt * 1e3, "iters": st[0]["iters"],
+                          "max_rel_resid": st[0]["max_rel_resid"], "status": status,
+                          "paper_steps": cfg["steps_paper"][N], "paper_a100_s": cfg["gpu_s_paper"][N]}
+        if N == cfg["Ns"][-1]:
+            kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.bcc_points())
+            o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, streams=args.streams)
+            t0 = time.perf_counter()
+            ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ratio, below = B.mfd_gap_ratio(ev, kp)
+            ok = sum(1 for x in st if x["max_rel_resid"] <= cfg["tol"])
+            out[f"path_N{N}"] = {"value": ok / dt, "unit": "k-points/s", "ms": dt * 1e3, "kpoints": len(kp),
+                                 "converged_kpoints": ok, "gap_ratio": ratio, "gap_above_band": below,
+                                 "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"]}
+            out["two_pass_operator"] = lattice_op_direct(B, ctx, kP[0], cfg["nbands"] + 2, N, torch)
+        ctx.close()
+    return out
 
 
 def stencil_object(direct, timed, single):
@@ -291,6 +379,11 @@ def main():
         torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
 
+    if args.lattice_only:
+        print(json.dumps(lattice_only(B, torch)))
+        if args.copy_calib:
+            copy_calibration()
+        return
     if args.stencil_only:
         print(json.dumps(stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch)))
         if args.copy_calib:
@@ -353,6 +446,7 @@ def main():
                               "max_rel_resid": vres, "precision": prec, "warm_start": warm}
         variants["random_batch"] = batch_variant(B, args, torch, count)
         variants["sc_sphere_cyl_gap"] = band_gap_variant(B, args, torch)
+        variants["bcc_gyroid"] = gyroid_variant(B, args, torch)
     n = 3 * N ** 3
 
     mb = m + args.guard

@@ -49,32 +49,43 @@ struct WideCoef {
     R alpha[3];
 };
 
-// u: one component field [z][y][x]; (x, y, z) the cell; axis 0 = x, 1 = y, 2 = z
+// u: one component field [z][y][x]; (x, y, z) the cell; axis 0 = x, 1 = y, 2 = z.
+// |off| <= K <= 4 <= N, so one conditional wrap keeps the index periodic;
+// N^3 <= 128^3 fits a 32-bit index.
+__device__ __forceinline__ int wrap(int c, int N) {
+    c += (c < 0) ? N : 0;
+    return c - ((c >= N) ? N : 0);
+}
+
 template <class R, class T>
 __device__ __forceinline__ cplx<R> ld_shift(const T* u, int N, int x, int y, int z, int axis, int off) {
-    if (axis == 0) x = (x + off + 4 * N) % N;
-    else if (axis == 1) y = (y + off + 4 * N) % N;
-    else z = (z + off + 4 * N) % N;
-    const T v = u[((size_t)z * N + y) * N + x];
+    if (axis == 0) x = wrap(x + off, N);
+    else if (axis == 1) y = wrap(y + off, N);
+    else z = wrap(z + off, N);
+    const T v = u[(z * N + y) * N + x];
     return mk<cplx<R>>(v.x, v.y);
 }
 
 // sum_j B[axis][j] sum_s c_s (u[r + sg s e_j] - u[r + sg (1 - s) e_j]) + i sg alpha_axis
 //   sum_s d_s (u[r + sg s e_axis] + u[r + sg (1 - s) e_axis]); sg = +1 gives D, sg = -1 gives D'.
-template <int SG, class R, class T>
+// KC = 1: order 2 with every loop unrolled (the neighbour loads of a cell are
+// then shared between the D_i that use them); KC = 0: K from w.
+template <int SG, int KC, class R, class T>
 __device__ __forceinline__ cplx<R> Dapply(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
+    const int K = KC ? KC : w.K;
     cplx<R> diff = mk<cplx<R>>(0, 0), avg = mk<cplx<R>>(0, 0);
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
         const R bj = w.B[axis][j];
         if (bj == (R)0) continue;
         cplx<R> dj = mk<cplx<R>>(0, 0);
-        for (int s = 1; s <= w.K; ++s) {
+        for (int s = 1; s <= K; ++s) {
             const cplx<R> a = ld_shift<R>(u, N, x, y, z, j, SG * s), b = ld_shift<R>(u, N, x, y, z, j, SG * (1 - s));
             dj = cadd(dj, cscale(csub(a, b), w.c[s - 1]));
         }
         diff = cadd(diff, cscale(dj, bj));
     }
-    for (int s = 1; s <= w.K; ++s) {
+    for (int s = 1; s <= K; ++s) {
         const cplx<R> a = ld_shift<R>(u, N, x, y, z, axis, SG * s), b = ld_shift<R>(u, N, x, y, z, axis, SG * (1 - s));
         avg = cadd(avg, cscale(cadd(a, b), w.d[s - 1]));
     }
@@ -82,32 +93,32 @@ __device__ __forceinline__ cplx<R> Dapply(const WideCoef<R>& w, const T* u, int 
     return mk<cplx<R>>(diff.x - al * avg.y, diff.y + al * avg.x);   // diff + i sg alpha avg
 }
 
-template <class R, class T>
+template <int KC, class R, class T>
 __device__ __forceinline__ cplx<R> Dfwd(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
-    return Dapply<1>(w, u, N, x, y, z, axis);
+    return Dapply<1, KC>(w, u, N, x, y, z, axis);
 }
 
-template <class R, class T>
+template <int KC, class R, class T>
 __device__ __forceinline__ cplx<R> Dadj(const WideCoef<R>& w, const T* u, int N, int x, int y, int z, int axis) {
-    return Dapply<-1>(w, u, N, x, y, z, axis);
+    return Dapply<-1, KC>(w, u, N, x, y, z, axis);
 }
 
 // pass 1: T[b] = [mu_1 e1, mu_2 e2, mu_3 e3, q] of field fl(b0 + b)
-template <class R, class S>
+template <class R, class S, int KC>
 __global__ __launch_bounds__(256) void wide_pass1_kernel(const cplx<S>* __restrict__ X, cplx<R>* __restrict__ T,
                                                          const R* __restrict__ mu, int N, int b0, int nb,
                                                          WideCoef<R> w, FieldList fl) {
-    const size_t N3 = (size_t)N * N * N;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N3 = N * N * N;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= N3 || b >= nb) return;
-    const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((size_t)N * N));
+    const int x = i % N, y = (i / N) % N, z = i / (N * N);
     const cplx<S>* v = X + (size_t)fl(b0 + b) * 3 * N3;
     const cplx<S>*v1 = v, *v2 = v + N3, *v3 = v + 2 * N3;
-    const cplx<R> e1 = csub(Dadj(w, v2, N, x, y, z, 2), Dadj(w, v3, N, x, y, z, 1));
-    const cplx<R> e2 = csub(Dadj(w, v3, N, x, y, z, 0), Dadj(w, v1, N, x, y, z, 2));
-    const cplx<R> e3 = csub(Dadj(w, v1, N, x, y, z, 1), Dadj(w, v2, N, x, y, z, 0));
-    const cplx<R> q = cadd(cadd(Dfwd(w, v1, N, x, y, z, 0), Dfwd(w, v2, N, x, y, z, 1)), Dfwd(w, v3, N, x, y, z, 2));
+    const cplx<R> e1 = csub(Dadj<KC>(w, v2, N, x, y, z, 2), Dadj<KC>(w, v3, N, x, y, z, 1));
+    const cplx<R> e2 = csub(Dadj<KC>(w, v3, N, x, y, z, 0), Dadj<KC>(w, v1, N, x, y, z, 2));
+    const cplx<R> e3 = csub(Dadj<KC>(w, v1, N, x, y, z, 1), Dadj<KC>(w, v2, N, x, y, z, 0));
+    const cplx<R> q = cadd(cadd(Dfwd<KC>(w, v1, N, x, y, z, 0), Dfwd<KC>(w, v2, N, x, y, z, 1)), Dfwd<KC>(w, v3, N, x, y, z, 2));
     cplx<R>* t = T + (size_t)b * 4 * N3;
     t[i] = cscale(e1, mu[i]);
     t[N3 + i] = cscale(e2, mu[N3 + i]);
@@ -116,26 +127,26 @@ __global__ __launch_bounds__(256) void wide_pass1_kernel(const cplx<S>* __restri
 }
 
 // pass 2: Y = A e + gamma B' q + shift X
-template <class R, class S>
+template <class R, class S, int KC>
 __global__ __launch_bounds__(256) void wide_pass2_kernel(const cplx<S>* __restrict__ X, const cplx<R>* __restrict__ T,
                                                          cplx<S>* __restrict__ Y, int N, int b0, int nb,
                                                          WideCoef<R> w, R gamma, R shift, FieldList fl) {
-    const size_t N3 = (size_t)N * N * N;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N3 = N * N * N;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= N3 || b >= nb) return;
-    const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((size_t)N * N));
+    const int x = i % N, y = (i / N) % N, z = i / (N * N);
     const cplx<R>* t = T + (size_t)b * 4 * N3;
     const cplx<R>*e1 = t, *e2 = t + N3, *e3 = t + 2 * N3, *q = t + 3 * N3;
     const size_t f = (size_t)fl(b0 + b) * 3 * N3;
     const cplx<S>* v = X + f;
     cplx<S>* out = Y + f;
-    cplx<R> w1 = csub(Dfwd(w, e3, N, x, y, z, 1), Dfwd(w, e2, N, x, y, z, 2));
-    cplx<R> w2 = csub(Dfwd(w, e1, N, x, y, z, 2), Dfwd(w, e3, N, x, y, z, 0));
-    cplx<R> w3 = csub(Dfwd(w, e2, N, x, y, z, 0), Dfwd(w, e1, N, x, y, z, 1));
-    w1 = cadd(w1, cscale(Dadj(w, q, N, x, y, z, 0), gamma));
-    w2 = cadd(w2, cscale(Dadj(w, q, N, x, y, z, 1), gamma));
-    w3 = cadd(w3, cscale(Dadj(w, q, N, x, y, z, 2), gamma));
+    cplx<R> w1 = csub(Dfwd<KC>(w, e3, N, x, y, z, 1), Dfwd<KC>(w, e2, N, x, y, z, 2));
+    cplx<R> w2 = csub(Dfwd<KC>(w, e1, N, x, y, z, 2), Dfwd<KC>(w, e3, N, x, y, z, 0));
+    cplx<R> w3 = csub(Dfwd<KC>(w, e2, N, x, y, z, 0), Dfwd<KC>(w, e1, N, x, y, z, 1));
+    w1 = cadd(w1, cscale(Dadj<KC>(w, q, N, x, y, z, 0), gamma));
+    w2 = cadd(w2, cscale(Dadj<KC>(w, q, N, x, y, z, 1), gamma));
+    w3 = cadd(w3, cscale(Dadj<KC>(w, q, N, x, y, z, 2), gamma));
     const cplx<S> a1 = v[i], a2 = v[N3 + i], a3 = v[2 * N3 + i];
     out[i] = mk<cplx<S>>(w1.x + shift * (R)a1.x, w1.y + shift * (R)a1.y);
     out[N3 + i] = mk<cplx<S>>(w2.x + shift * (R)a2.x, w2.y + shift * (R)a2.y);
@@ -161,14 +172,16 @@ hipError_t launch_wide(const OpParams& p, int nb, const void* X, void* Y, const 
     const size_t N3 = (size_t)p.N * p.N * p.N;
     const unsigned gx = (unsigned)((N3 + 255) / 256);
     cplx<R>* T = (cplx<R>*)p.wtmp;
+    auto k1 = (w.K == 1) ? wide_pass1_kernel<R, S, 1> : wide_pass1_kernel<R, S, 0>;
+    auto k2 = (w.K == 1) ? wide_pass2_kernel<R, S, 1> : wide_pass2_kernel<R, S, 0>;
     for (int b0 = 0; b0 < nb; b0 += p.wtmp_bands) {
         const int nc = std::min(nb - b0, p.wtmp_bands);
-        hipLaunchKernelGGL((wide_pass1_kernel<R, S>), dim3(gx, nc), dim3(256), 0, s, (const cplx<S>*)X, T,
-                           (const R*)mu, p.N, b0, nc, w, fl);
+        hipLaunchKernelGGL(k1, dim3(gx, nc), dim3(256), 0, s, (const cplx<S>*)X, T, (const R*)mu, p.N, b0, nc, w,
+                           fl);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((wide_pass2_kernel<R, S>), dim3(gx, nc), dim3(256), 0, s, (const cplx<S>*)X,
-                           (const cplx<R>*)T, (cplx<S>*)Y, p.N, b0, nc, w, (R)p.gamma, (R)p.shift, fl);
+        hipLaunchKernelGGL(k2, dim3(gx, nc), dim3(256), 0, s, (const cplx<S>*)X, (const cplx<R>*)T, (cplx<S>*)Y,
+                           p.N, b0, nc, w, (R)p.gamma, (R)p.shift, fl);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
