@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--stencil-only", action="store_true",
                     help="only the full-block stencil timing (for rocprofv3); prints its JSON object")
     ap.add_argument("--lattice-only", action="store_true",
-                    help="only the two-pass operator timing on the BCC gyroid at N = 120 (for rocprofv3); "
+                    help="only the general-lattice operator timing on the BCC gyroid at N = 120 (for rocprofv3); "
                          "prints its JSON object")
     ap.add_argument("--copy-calib", action="store_true",
                     help="with --profile-only, --stencil-only or --lattice-only: also run a plain 1 GiB read + 1 GiB write copy, "
@@ -166,12 +166,12 @@ def band_gap_variant(B, args, torch):
 
 
 def lattice_op_direct(B, ctx, k, m, N, torch, reps=20):
-    """The two-pass general-lattice operator alone on a block of m FP32-stored
-    bands, FP64 arithmetic as the mixed solve applies it: mean duration of
-    `reps` back-to-back mfd_op_apply calls between HIP events on their
-    stream.  Algorithmic bytes per call: per band and cell, X read by both
-    passes (2 x 24 B), the FP64 scratch e and q written and read once
-    (2 x 64 B) and Y written (24 B), plus mu (24 B per cell) once."""
+    """The general-lattice operator alone (the fused z-marching kernel at
+    order 2) on a block of m FP32-stored bands, FP64 arithmetic as the mixed
+    solve applies it: mean duration of `reps` back-to-back mfd_op_apply calls
+    between HIP events on their stream.  Algorithmic bytes per call: X read
+    and Y written once (2 x 24 B per cell and band) plus mu (24 B per cell)
+    once; the halo ring and neighbour planes come from LDS."""
     n3 = N ** 3
     g = torch.Generator(device="cuda").manual_seed(0)
     X = torch.randn((m, 3, N, N, N), dtype=torch.complex64, device="cuda", generator=g)
@@ -186,16 +186,16 @@ def lattice_op_direct(B, ctx, k, m, N, torch, reps=20):
     e1.record(s)
     e1.synchronize()
     avg_s = e0.elapsed_time(e1) * 1e-3 / reps
-    by = (48.0 + 128.0 + 24.0) * n3 * m + 24.0 * n3
+    by = 48.0 * n3 * m + 24.0 * n3
     del X, Y
     torch.cuda.synchronize()
     return {"achieved": by / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": by / avg_s / HBM_PEAK,
             "avg_us": avg_s * 1e6, "bytes_per_call": by, "nbands": m, "N": N, "calls": reps,
-            "form": "FP32 storage, FP64 arithmetic, two passes through FP64 scratch"}
+            "form": "FP32 storage, FP64 arithmetic, one z-marching pass (lattice_fused_kernel)"}
 
 
 def lattice_only(B, torch):
-    """The BCC gyroid context at N = 120 and the two-pass operator timing
+    """The BCC gyroid context at N = 120 and the lattice operator timing
     alone (for rocprofv3)."""
     from paper_2503_19379_amd import workloads
     cfg = workloads.CONFIGS["bcc_gyroid"]
@@ -213,7 +213,7 @@ def gyroid_variant(B, args, torch):
     start, N = 100 and 120, one timed solve after an untimed one; the paper's
     steps and its A100 seconds are carried beside for context.  (2) The band
     structure on H'-Gamma-P-N-H at N = 120 and its gap ratio.  (3) The
-    two-pass operator alone on a 12-band block at N = 120
+    lattice operator alone on a 12-band block at N = 120
     (lattice_op_direct)."""
     from paper_2503_19379_amd import workloads
     cfg = workloads.CONFIGS["bcc_gyroid"]
@@ -245,7 +245,7 @@ def gyroid_variant(B, args, torch):
             out[f"path_N{N}"] = {"value": ok / dt, "unit": "k-points/s", "ms": dt * 1e3, "kpoints": len(kp),
                                  "converged_kpoints": ok, "gap_ratio": ratio, "gap_above_band": below,
                                  "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"]}
-            out["two_pass_operator"] = lattice_op_direct(B, ctx, kP[0], cfg["nbands"] + 2, N, torch)
+            out["lattice_operator"] = lattice_op_direct(B, ctx, kP[0], cfg["nbands"] + 2, N, torch)
         ctx.close()
     return out
 

@@ -53,6 +53,12 @@ template <class R, class S>
 hipError_t launch_wide(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
                        const FieldList& fl);
 
+// General lattice, order 2: the same operator in one z-marching pass with
+// v, e and q tiles in LDS (lattice.hip); launch_wide calls it.
+template <class R, class S>
+hipError_t launch_lattice(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
+                          const FieldList& fl);
+
 // Same operator with FP64 arithmetic on FP32-stored fields (c64 in, c64 out).
 hipError_t launch_stencil_f64_s32(const OpParams& p, int nb, const void* X, void* Y, const void* mu64,
                                   hipStream_t s, const FieldList& fl = FieldList());

@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void wide_pass2_kernel(const cplx<S>* __restri
 template <class R, class S>
 hipError_t launch_wide(const OpParams& p, int nb, const void* X, void* Y, const void* mu, hipStream_t s,
                        const FieldList& fl) {
+    if (p.lattice && p.order == 2) return launch_lattice<R, S>(p, nb, X, Y, mu, s, fl);
     if (!p.wtmp || p.wtmp_bands < 1) return hipErrorInvalidValue;
     WideCoef<R> w;
     w.K = p.order / 2;
