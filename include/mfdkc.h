@@ -153,8 +153,8 @@ int mfd_build_mu(int N, double L, int order, const double* mu_edges, void* strea
  *    average along grid axis i (alpha = the Cartesian k).
  * Wave vectors passed to the other calls stay Cartesian (units 1/length of A).
  * The penalty and shift rules use L = |det A|^(1/3) in place of the cell side.
- * Every order uses the two-pass operator (scratch owned by the context, as
- * for orders > 2).
+ * Order 2 uses a fused single-pass kernel (z-marching tiles in LDS); orders
+ * 4-8 the two-pass operator (scratch owned by the context).
  * Errors: MFD_EINVAL also for a NULL, non-finite or singular lattice; others
  * as mfd_build. */
 int mfd_build_lattice(int N, const double* lattice, int order, const double* eps_cells, void* stream,

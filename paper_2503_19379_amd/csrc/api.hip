@@ -268,8 +268,7 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
           (!mixed || (chk(hipMalloc(&w->V32, n * 6 * mb * sizeof(float2))) &&
                       chk(hipMalloc(&w->U32, n * 6 * mb * sizeof(float2))))) &&
           (mixed || fft_supported(c->N, 8) || chk(hipMalloc(&w->stage32, n * mb * sizeof(float2)))) &&
-          ((c->order == 2 && !c->lattice) ||
-           chk(hipMalloc(&w->wtmp, (size_t)c->wtmp_bands * 4 * (n / 3) * sizeof(double2)))))) {
+          (c->order == 2 || chk(hipMalloc(&w->wtmp, (size_t)c->wtmp_bands * 4 * (n / 3) * sizeof(double2)))))) {
         ws_free(w);
         return fail(e == hipErrorOutOfMemory ? MFD_ENOMEM : MFD_EDEVICE, hipGetErrorString(e));
     }
@@ -1159,7 +1158,7 @@ int build_ctx(int N, double L, int order, const double* src, bool edges, void* s
         return st;
     };
     hipError_t e;
-    const bool wide = order > 2 || lat;
+    const bool wide = order > 2;   // order 2 (cubic or lattice) needs no operator scratch
     if (wide) c->wtmp_bands = wide_bands(N);
     if ((wide && (e = hipMalloc(&c->wtmp, (size_t)c->wtmp_bands * 4 * N3 * sizeof(double2))) != hipSuccess) ||
         (e = hipMalloc(&c->mu64, 3 * N3 * sizeof(double))) != hipSuccess ||
