@@ -134,3 +134,51 @@ def test_bands_random_fcc_vs_oracle(B, precision):
         assert info["converged"]
         assert np.allclose(ev[i], lam, rtol=1e-7 if precision else 1e-9), (i, ev[i], lam)
         assert st[i]["max_rel_resid"] <= (1e-8 if precision else 1e-10)
+
+
+def test_cubic_cell_through_the_lattice_path_matches_the_cubic_context(B):
+    """A = L I through mfd_build_lattice (the z-marching lattice kernel and
+    the lattice FFT symbols) against mfd_build (the fused cubic stencil and
+    its closed-form symbols): two independent kernels, one operator."""
+    rng = np.random.default_rng(21)
+    N, L = 24, 1.3
+    k = np.array([0.8, -0.3, 1.9])
+    eps = rand_eps(rng, N)
+    cl = B.mfd_build_lattice(N, L * np.eye(3), 2, eps)
+    cc = B.mfd_build(N, L, 2, eps)
+    assert B.mfd_gamma_shift(cl, k) == pytest.approx(B.mfd_gamma_shift(cc, k), rel=1e-14)
+    X = torch.from_numpy(rand_block(rng, 4, N)).cuda()
+    Ya, Yb, Ta, Tb = (torch.empty_like(X) for _ in range(4))
+    B.mfd_op_apply(cl, k, X, Ya)
+    B.mfd_op_apply(cc, k, X, Yb)
+    B.mfd_precond_solve(cl, k, X, Ta)
+    B.mfd_precond_solve(cc, k, X, Tb)
+    torch.cuda.synchronize()
+    assert rel_err(Ya.cpu().numpy(), Yb.cpu().numpy()) < 1e-13
+    assert rel_err(Ta.cpu().numpy(), Tb.cpu().numpy()) < 1e-13
+    ea, sa, _ = B.mfd_bands(cl, [k], 6, 1e-10, B.default_opts(precision=0, streams=1))
+    eb, sb, _ = B.mfd_bands(cc, [k], 6, 1e-10, B.default_opts(precision=0, streams=1))
+    assert np.allclose(ea, eb, rtol=1e-9)
+
+
+def test_fused_lattice_kernel_ragged_tiles_and_uneven_chunks(B):
+    """N = 100 (tiles of 16 leave a ragged 4-cell edge), 5 FP32-stored bands
+    with FP64 arithmetic: 7 x 7 tiles x 5 bands call for 9 z chunks of 11 or
+    12 planes.  Against the oracle on the same FP32 inputs; the only
+    difference is the final rounding to FP32."""
+    rng = np.random.default_rng(22)
+    N, k = 100, np.array([1.1, 0.4, -0.7])
+    A = LATTICES["bcc"]
+    eps = rand_eps(rng, N)
+    ctx = B.mfd_build_lattice(N, A, 2, eps)
+    g, c = B.mfd_gamma_shift(ctx, k)
+    X = rand_block(rng, 5, N).astype(np.complex64)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    B.mfd_op_apply(ctx, k, Xd, Yd, fp64_arith=True)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy()
+    mu = mfd.mu_from_eps(eps)
+    for b in range(5):
+        ref = lat.apply_op(X[b].astype(np.complex128), mu, k, A, g, 2, c)
+        assert rel_err(Y[b], ref) < 1e-7, b
