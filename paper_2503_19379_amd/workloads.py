@@ -117,6 +117,16 @@ def bcc_points(l: float = 1.0) -> dict:
             "H": (0.0, 2 * p, 0.0)}
 
 
+def fcc_points(l: float = 1.0) -> dict:
+    """Symmetry points of the FCC Brillouin zone (Section 6, lattice constant
+    l): X, U, L, Gamma ("G"), W, K.  The paper prints U as (pi/2l, 0, pi/2l),
+    which is not on the zone boundary; U here is the usual (pi/2l, 2 pi/l,
+    pi/2l), the end of the X-U edge."""
+    p = np.pi / l
+    return {"X": (0.0, 2 * p, 0.0), "U": (0.5 * p, 2 * p, 0.5 * p), "L": (p, p, p), "G": (0.0, 0.0, 0.0),
+            "W": (p, 2 * p, 0.0), "K": (1.5 * p, 1.5 * p, 0.0)}
+
+
 def lattice_vectors(kind: str, l: float = 1.0) -> np.ndarray:
     """Primitive vectors of eq. (translation_vecs) as the columns of a 3 x 3
     matrix: "sc", "fcc" or "bcc" with lattice constant l."""
@@ -202,6 +212,48 @@ def mu_bcc_gyroid(N: int, l: float = 1.0, t: float = 1.1, eps_in: float = 16.0,
     return mu
 
 
+def mu_fcc_diamond(N: int, l: float = 1.0, r: float = 0.12, b: float = 0.11, eps_in: float = 13.0,
+                   eps_out: float = 1.0) -> np.ndarray:
+    """M_0 on the edges of the unit-cube grid of the FCC primitive cell for the
+    sp3 diamond structure of Section 6.3: dielectric spheres of radius r l at
+    the two basis sites 0 and (l/4)(1, 1, 1) of every lattice point, joined
+    along the four nearest-neighbour bonds by prolate spheroids whose foci
+    are the two sphere centres.  The paper's minor axis b l is read as the
+    spheroid's minor radius (semi-minor axis), so the semi-major axis is
+    sqrt((sqrt(3) l/8)^2 + (b l)^2); with b l as the full minor axis the cell
+    has half the gap the paper reports.  eps_in / eps_out = 13.  An edge
+    takes eps_in^-1 when its midpoint (mapped to Cartesian by the FCC
+    vectors) is in the material.  Shape (3, N, N, N)."""
+    A = lattice_vectors("fcc", l)
+    q = 0.25 * l
+    bonds = q * np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
+    semi = np.sqrt((0.5 * np.linalg.norm(bonds[0])) ** 2 + (b * l) ** 2)
+    n = np.arange(-1, 2)
+    T = np.stack(np.meshgrid(n, n, n, indexing="ij"), -1).reshape(-1, 3) @ A.T   # 27 lattice images
+    sites = np.concatenate([T, T + bonds[0]])
+    i = np.arange(N) / N
+    half = i + 0.5 / N
+    mu = np.empty((3, N, N, N))
+    for comp in range(3):
+        ax = [i, i, i]
+        ax[comp] = half
+        Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1) @ A.T
+        inside = np.zeros(P.shape[0], dtype=bool)
+        for c0 in range(0, P.shape[0], 1 << 16):
+            p = P[c0:c0 + (1 << 16)]
+            ins = np.zeros(p.shape[0], dtype=bool)
+            for s_ in sites:
+                ins |= np.sum((p - s_) ** 2, axis=1) <= (r * l) ** 2
+            for t in T:
+                d0 = np.sqrt(np.sum((p - t) ** 2, axis=1))
+                for bd in bonds:
+                    ins |= d0 + np.sqrt(np.sum((p - t - bd) ** 2, axis=1)) <= 2 * semi
+            inside[c0:c0 + (1 << 16)] = ins
+        mu[comp] = np.where(inside.reshape(N, N, N), 1.0 / eps_in, 1.0 / eps_out)
+    return mu
+
+
 def start_block(m: int, N: int, seed: int) -> np.ndarray:
     """Seeded complex Gaussian start block, shape (m, 3, N, N, N), complex128
     (real and imaginary parts independent standard normals)."""
@@ -234,6 +286,9 @@ CONFIGS = {
                        tol=1e-5, precision="mixed", steps_paper={100: 70, 120: 65},
                        gpu_s_paper={100: 40.55, 120: 54.92}, path="hGPNH", nk=40, gap_ratio_paper=0.31745,
                        N_paper=150),
+    # FCC sp3 diamond of spheres and spheroids (Section 6.3): band gap
+    "fcc_diamond": dict(lattice="fcc", mu="fcc_diamond", path="XULGXWK", nk=40, nbands=10, tol=1e-5,
+                        precision="mixed", gap_ratio_paper=0.31182, N_paper=150),
     # diamond at N = 96, learned warm start
     "diamond_n96": dict(N=96, eps="diamond", path="GXMGRX", nk=100, nbands=20, tol=1e-8,
                         precision="mixed"),

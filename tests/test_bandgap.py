@@ -144,3 +144,22 @@ def test_kpath_vertices_hits_every_vertex():
         assert np.any(np.all(np.abs(kp - np.array(pts[c])) < 1e-14, axis=1)), c
     d = np.linalg.norm(np.diff(kp, axis=0), axis=1)
     assert np.all(d > 0) and d.max() < 2.5 * d.min()
+
+
+def test_fcc_diamond_edges_have_bond_centre_inversion():
+    """The diamond structure is symmetric under inversion through a bond
+    centre, (l/8)(1, 1, 1), which is y = (1/8, 1/8, 1/8) in cell coordinates
+    and maps the e_1 edge (i, j, k) to (N/4 - 1 - i, N/4 - j, N/4 - k)
+    (likewise for e_2, e_3).  Only edges within rounding of a surface may
+    differ."""
+    N = 32
+    mu = workloads.mu_fcc_diamond(N)
+    q = N // 4
+    i = np.arange(N)
+    for comp in range(3):
+        idx = [(q - i) % N] * 3
+        idx[comp] = (q - 1 - i) % N
+        inv = mu[comp][np.ix_(idx[2], idx[1], idx[0])]
+        assert np.mean(inv != mu[comp]) < 2e-3
+    frac = np.mean(mu < 1.0)
+    assert 0.15 < frac < 0.23        # spheres 5.8% of the cell, spheroids the rest

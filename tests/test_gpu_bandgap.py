@@ -142,3 +142,25 @@ def test_bcc_gyroid_band_gap(B):
     print(f"N = {N}: gyroid gap ratio {r:.5f} above band {below} (the paper prints {cfg['gap_ratio_paper']} "
           f"at N = {cfg['N_paper']})")
     assert below == 2 and 0.28 < r < cfg["gap_ratio_paper"]
+
+
+def test_fcc_diamond_band_gap(B):
+    """Section 6.3's FCC sp3 diamond (spheres r = 0.12 l joined by spheroids
+    of minor radius 0.11 l, eps 13 in 1, M_0 per edge) at N = 64, 10 bands
+    on X-U-L-Gamma-X-W-K with every symmetry point, tol 1e-5, mixed
+    precision: the gap opens between bands 2 and 3 at 0.309, close to the
+    paper's 0.31182 (N = 150); 0.31098 at N = 100."""
+    cfg = workloads.CONFIGS["fcc_diamond"]
+    N = 64
+    kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.fcc_points())
+    ctx = B.mfd_build_lattice_mu(N, workloads.lattice_vectors("fcc"), 2, workloads.mu_fcc_diamond(N))
+    ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"],
+                                 B.default_opts(precision=1, warm_start=1, guard=2, streams=8, max_iter=500))
+    assert status == 0, st
+    assert all(s["max_rel_resid"] <= cfg["tol"] for s in st)
+    r, below = B.mfd_gap_ratio(ev, kp)
+    ro, bo = bandgap.gap_ratio(ev, kp)
+    assert r == pytest.approx(ro, rel=1e-12) and below == bo
+    print(f"N = {N}: FCC diamond gap ratio {r:.5f} above band {below} (the paper prints "
+          f"{cfg['gap_ratio_paper']} at N = {cfg['N_paper']})")
+    assert below == 2 and abs(r - cfg["gap_ratio_paper"]) < 0.005
