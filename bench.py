@@ -250,6 +250,34 @@ def gyroid_variant(B, args, torch):
     return out
 
 
+def fcc_gap_variant(B, args, torch):
+    """Section 6.3's FCC sp3 diamond (spheres and bond spheroids, eps 13 in
+    1, M_0 per edge) at N = 100: 10 bands on X-U-L-Gamma-X-W-K with every
+    symmetry point, tol 1e-5, mixed precision, one timed call, then the
+    band-gap ratio."""
+    from paper_2503_19379_amd import workloads
+    cfg = workloads.CONFIGS["fcc_diamond"]
+    N = 100
+    kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.fcc_points())
+    ctx = B.mfd_build_lattice_mu(N, workloads.lattice_vectors("fcc"), 2, workloads.mu_fcc_diamond(N))
+    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, streams=args.streams)
+    B.mfd_bands(ctx, kp[:1], cfg["nbands"], cfg["tol"], o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ratio, below = B.mfd_gap_ratio(ev, kp)
+    ctx.close()
+    ok = sum(1 for x in st if x["max_rel_resid"] <= cfg["tol"])
+    return {"value": ok / dt, "unit": "k-points/s", "ms": dt * 1e3, "kpoints": len(kp), "converged_kpoints": ok,
+            "iters_per_k": float(np.mean([x["iters"] for x in st])), "gap_ratio": ratio, "gap_above_band": below,
+            "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"],
+            "workload": f"FCC sp3 diamond, spheres r 0.12 + bond spheroids of minor radius 0.11, eps 13 in 1, "
+                        f"M_0 per edge, N = {N}, {len(kp)} k-points on {cfg['path']}, {cfg['nbands']} bands, "
+                        f"tol {cfg['tol']:g}, mixed"}
+
+
 def stencil_object(direct, timed, single):
     out = dict(direct["fp32"], form="fp32 storage and arithmetic, full 16-band block, 30 back-to-back calls")
     out["fp32_storage_fp64_arith"] = direct["fp32_storage_fp64_arith"]
@@ -447,6 +475,7 @@ def main():
         variants["random_batch"] = batch_variant(B, args, torch, count)
         variants["sc_sphere_cyl_gap"] = band_gap_variant(B, args, torch)
         variants["bcc_gyroid"] = gyroid_variant(B, args, torch)
+        variants["fcc_diamond_gap"] = fcc_gap_variant(B, args, torch)
     n = 3 * N ** 3
 
     mb = m + args.guard
