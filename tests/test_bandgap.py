@@ -163,3 +163,29 @@ def test_fcc_diamond_edges_have_bond_centre_inversion():
         assert np.mean(inv != mu[comp]) < 2e-3
     frac = np.mean(mu < 1.0)
     assert 0.15 < frac < 0.23        # spheres 5.8% of the cell, spheroids the rest
+
+
+def test_bcc_gyroid_edges():
+    """Section 6.3's single gyroid: g is invariant under the three BCC
+    translations (so the cell is periodic), and each sampled edge equals
+    g > 1.1 evaluated by hand at its midpoint, mapped by the BCC vectors."""
+    A = workloads.lattice_vectors("bcc")
+
+    def g(p):
+        w = 2 * np.pi
+        return (np.sin(w * p[0]) * np.cos(w * p[1]) + np.sin(w * p[1]) * np.cos(w * p[2])
+                + np.sin(w * p[2]) * np.cos(w * p[0]))
+
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        p = rng.uniform(-1, 1, 3)
+        for c in range(3):
+            assert g(p + A[:, c]) == pytest.approx(g(p), abs=1e-12)
+    N = 20
+    mu = workloads.mu_bcc_gyroid(N)
+    for _ in range(200):
+        comp, z, y, x = int(rng.integers(3)), *(int(v) for v in rng.integers(0, N, 3))
+        yv = np.array([x, y, z], dtype=float) / N
+        yv[comp] += 0.5 / N
+        inside = g(A @ yv) > 1.1
+        assert mu[comp, z, y, x] == (1.0 / 16.0 if inside else 1.0)
