@@ -8,7 +8,7 @@
 //   (D^_i' u)(r) = sum_j B_ij (u(r - e_j) - u(r)) - i (alpha_i / 2) (u(r - e_i) + u(r)),
 //   e = M_0 A'v needs v at r and r - e_j;  q = B v needs v at r and r + e_j;
 //   w(r) needs e at r and r + e_j, q at r and r - e_j.
-// One workgroup owns a 16 x 16 tile of (x, y) for one band and marches up a
+// One workgroup owns a 16 x 14 tile of (x, y) for one band and marches up a
 // chunk of z.  Per plane it loads v(z + 1) with a one-cell halo into LDS,
 // forms e(z + 1) on the tile and one cell beyond on the +x and +y sides,
 // q(z) on the tile and one cell before on the -x and -y sides, then w(z).
@@ -21,7 +21,9 @@ namespace mfd {
 
 namespace {
 
-constexpr int LT_X = 16, LT_Y = 16, LT_NT = LT_X * LT_Y;
+// 16 x 14 tiles: the e and q regions (17 x 15 = 255 entries) then take one
+// pass of the 256 threads each, and w uses 224 of them
+constexpr int LT_X = 16, LT_Y = 14, LT_NT = 256;
 constexpr int LV_X = LT_X + 2, LV_Y = LT_Y + 2;   // v tile with a one-cell halo
 constexpr int LE_X = LT_X + 1, LE_Y = LT_Y + 1;   // e: tile + one cell beyond; q: one cell before
 
@@ -134,6 +136,7 @@ __global__ __launch_bounds__(LT_NT) void lattice_fused_kernel(LatArgs<R> a) {
     // w(z) on the tile: e(z) in E slot ec, e(z + 1) in en, q(z) in Q slot qc,
     // q(z - 1) in qp, v(z) in V slot vc
     auto make_w = [&](int ec, int en, int qc, int qp, int vc, int z) {
+        if (t >= LT_X * LT_Y) return;
         const int tlx = t % LT_X, tly = t / LT_X;
         C df[3][3];   // df[c][k] = D^_k e_c
 #pragma unroll

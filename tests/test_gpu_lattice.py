@@ -162,10 +162,10 @@ def test_cubic_cell_through_the_lattice_path_matches_the_cubic_context(B):
 
 
 def test_fused_lattice_kernel_ragged_tiles_and_uneven_chunks(B):
-    """N = 100 (tiles of 16 leave a ragged 4-cell edge), 5 FP32-stored bands
-    with FP64 arithmetic: 7 x 7 tiles x 5 bands call for 9 z chunks of 11 or
-    12 planes.  Against the oracle on the same FP32 inputs; the only
-    difference is the final rounding to FP32."""
+    """N = 100 (16 x 14 tiles leave ragged edges of 4 columns and 2 rows),
+    5 FP32-stored bands with FP64 arithmetic: 7 x 8 tiles x 5 bands call for
+    8 z chunks of 12 or 13 planes.  Against the oracle on the same FP32
+    inputs; the only difference is the final rounding to FP32."""
     rng = np.random.default_rng(22)
     N, k = 100, np.array([1.1, 0.4, -0.7])
     A = LATTICES["bcc"]
