@@ -8,7 +8,7 @@
 //   (D^_i' u)(r) = sum_j B_ij (u(r - e_j) - u(r)) - i (alpha_i / 2) (u(r - e_i) + u(r)),
 //   e = M_0 A'v needs v at r and r - e_j;  q = B v needs v at r and r + e_j;
 //   w(r) needs e at r and r + e_j, q at r and r - e_j.
-// One workgroup owns a 16 x 14 tile of (x, y) for one band and marches up a
+// One workgroup owns a 16 x 10 tile of (x, y) for one band and marches up a
 // chunk of z.  Per plane it loads v(z + 1) with a one-cell halo into LDS,
 // forms e(z + 1) on the tile and one cell beyond on the +x and +y sides,
 // q(z) on the tile and one cell before on the -x and -y sides, then w(z).
@@ -21,9 +21,10 @@ namespace mfd {
 
 namespace {
 
-// 16 x 14 tiles: the e and q regions (17 x 15 = 255 entries) then take one
-// pass of the 256 threads each, and w uses 224 of them
-constexpr int LT_X = 16, LT_Y = 14, LT_NT = 256;
+// 16 x 10 tiles: the e and q regions (17 x 11 = 187 entries) take one pass
+// of the 256 threads each, w uses 160 of them, and 34.4 KB of LDS (FP32
+// storage) lets 4 workgroups share a CU (16 x 14: 3, 16 x 8: 5 were slower)
+constexpr int LT_X = 16, LT_Y = 10, LT_NT = 256;
 constexpr int LV_X = LT_X + 2, LV_Y = LT_Y + 2;   // v tile with a one-cell halo
 constexpr int LE_X = LT_X + 1, LE_Y = LT_Y + 1;   // e: tile + one cell beyond; q: one cell before
 

@@ -162,10 +162,11 @@ def test_cubic_cell_through_the_lattice_path_matches_the_cubic_context(B):
 
 
 def test_fused_lattice_kernel_ragged_tiles_and_uneven_chunks(B):
-    """N = 100 (16 x 14 tiles leave ragged edges of 4 columns and 2 rows),
-    5 FP32-stored bands with FP64 arithmetic: 7 x 8 tiles x 5 bands call for
-    8 z chunks of 12 or 13 planes.  Against the oracle on the same FP32
-    inputs; the only difference is the final rounding to FP32."""
+    """N = 100 (16 x 10 tiles leave a ragged edge of 4 columns; N = 12 above
+    has ragged rows), 5 FP32-stored bands with FP64 arithmetic: 7 x 10 tiles
+    x 5 bands call for 6 z chunks of 16 or 17 planes.  Against the oracle on
+    the same FP32 inputs; the only difference is the final rounding to
+    FP32."""
     rng = np.random.default_rng(22)
     N, k = 100, np.array([1.1, 0.4, -0.7])
     A = LATTICES["bcc"]
