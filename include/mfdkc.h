@@ -83,7 +83,9 @@ typedef struct {
                                  hardware queues: set GPU_MAX_HW_QUEUES >= streams before the
                                  process first uses HIP (HIP's default is 4) */
     const void* x0;           /* optional device c128 start block [nbands][3][N][N][N] for the first
-                                 k-point (NULL: random) */
+                                 k-point (NULL: random); a column numerically dependent on the ones
+                                 before it (squared distance to their span below 1e-10 of its squared
+                                 norm, or a zero column) is replaced by seeded random values */
     int stall_window;         /* iterations without a halving of the largest residual after
                                  which precision 1 continues the k-point in FP64 (default 40,
                                  0 = never); FP64 restarts its conjugate directions from the

@@ -812,6 +812,47 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
     return MFD_OK;
 }
 
+// A caller's start block must span mb dimensions: a column whose squared
+// distance to the span of the columns before it is below 1e-10 of its squared
+// norm (a pivot of the Cholesky factor of X^H X) is replaced by seeded random
+// values.  Checked twice (a replacement is itself checked once more).
+int fix_dependent_start(Ws& w, uint64_t seed) {
+    const size_t n = w.n;
+    const int mb = w.mb;
+    hipStream_t s = w.stream;
+    std::vector<double2> G((size_t)mb * mb);
+    for (int pass = 0; pass < 2; ++pass) {
+        HIPCHK(launch_gram(w.V, n, n, mb, mb, gram_parts(n), w.gpart, w.G, s));
+        HIPCHK(hipMemcpyAsync(G.data(), w.G, G.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<double> Lr((size_t)mb * mb, 0.0), Li((size_t)mb * mb, 0.0);
+        std::vector<int> dep;
+        for (int j = 0; j < mb; ++j) {
+            const double gjj = G[(size_t)j * mb + j].x;
+            double d = gjj;
+            for (int k = 0; k < j; ++k) d -= Lr[j * mb + k] * Lr[j * mb + k] + Li[j * mb + k] * Li[j * mb + k];
+            if (!(d > 1e-10 * gjj) || !(gjj > 0.0)) {   // dependent (or zero, or not finite): row j of L stays 0
+                dep.push_back(j);
+                continue;
+            }
+            const double ljj = std::sqrt(d);
+            Lr[j * mb + j] = ljj;
+            for (int i = j + 1; i < mb; ++i) {
+                double sr = G[(size_t)i * mb + j].x, si = G[(size_t)i * mb + j].y;
+                for (int k = 0; k < j; ++k) {
+                    sr -= Lr[i * mb + k] * Lr[j * mb + k] + Li[i * mb + k] * Li[j * mb + k];
+                    si -= Li[i * mb + k] * Lr[j * mb + k] - Lr[i * mb + k] * Li[j * mb + k];
+                }
+                Lr[i * mb + j] = sr / ljj;
+                Li[i * mb + j] = si / ljj;
+            }
+        }
+        if (dep.empty()) return MFD_OK;
+        for (int j : dep) HIPCHK(launch_fill_random(col(w.V, n, j), n, seed + 7ull * (uint64_t)(pass + 1) + j, s));
+    }
+    return MFD_OK;
+}
+
 // A run of consecutive k-points on one workspace: random start at the first
 // (or the caller's block), warm start from the previous k-point afterwards.
 struct Segment {
@@ -872,6 +913,7 @@ void run_segment(Segment* sg) {
             if (e == hipSuccess && mb > sg->nbands)
                 e = launch_fill_random(col(w.V, n, sg->nbands), n * (mb - sg->nbands), seed_k + 17, w.stream);
             if (e != hipSuccess) st = fail(MFD_EDEVICE, hipGetErrorString(e));
+            else st = fix_dependent_start(w, seed_k + 101);
         } else if (!st && (ik == sg->k0 || !o.warm_start)) {
             hipError_t e = launch_fill_random(w.V, n * mb, seed_k, w.stream);
             if (e != hipSuccess) st = fail(MFD_EDEVICE, hipGetErrorString(e));
@@ -1270,6 +1312,15 @@ int mfd_gamma_shift(const mfd_ctx* ctx, const double k[3], double* gamma, double
     return MFD_OK;
 }
 
+// The direct operator and preconditioner calls take the launch shapes the
+// autotuner chose (or mfd_set_tuning pinned) for this context, so that they
+// run the kernel instances the band solve runs.
+static void tuned_shapes(const mfd_ctx* ctx, OpParams& p) {
+    if (ctx->tune_mb == 0) return;
+    p.stencil_wgs = ctx->tune[2];
+    p.fft_xc = ctx->tune[3];
+}
+
 static int check_block(mfd_ctx* ctx, const double* k, int nb, int dtype, const void* X, const void* Y,
                        bool allow_c64_f64 = false) {
     if (!ctx || !k || !X || !Y) return fail(MFD_EINVAL, "NULL argument");
@@ -1290,6 +1341,7 @@ int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void*
     if (nb > 0 && x < y + bytes && y < x + bytes) return fail(MFD_EINVAL, "X and Y overlap");
     if (nb == 0) return MFD_OK;
     OpParams p = params(ctx, k);
+    tuned_shapes(ctx, p);
     hipStream_t s = (hipStream_t)stream;
     if (dtype == MFD_C128) HIPCHK(launch_stencil<double>(p, nb, X, Y, ctx->mu64, s));
     else if (dtype == MFD_C64_F64) HIPCHK(launch_stencil_f64_s32(p, nb, X, Y, ctx->mu64, s));
@@ -1308,6 +1360,7 @@ int mfd_precond_solve(mfd_ctx* ctx, const double k[3], int nb, int dtype, const 
     if (!fft_supported(ctx->N, dtype == MFD_C64 ? 4 : 8))
         return fail(MFD_EUNSUPPORTED, "no FFT plan for this N and precision");
     OpParams p = params(ctx, k);
+    tuned_shapes(ctx, p);
     hipStream_t s = (hipStream_t)stream;
     if (dtype == MFD_C128) HIPCHK(launch_precond<double>(p, nb, R, T, ctx->tw64, s));
     else HIPCHK(launch_precond<float>(p, nb, R, T, ctx->tw32, s));

@@ -10,6 +10,7 @@ the seeded input generators are called.
     python -m tests.golden.make_golden sphere_n32     # about 10 minutes
     python -m tests.golden.make_golden diamond_n64    # about an hour
     python -m tests.golden.make_golden random_batch_c0   # a few minutes
+    python -m tests.golden.make_golden diamond_n96    # a few hours
 """
 from __future__ import annotations
 
@@ -28,6 +29,9 @@ from paper_2503_19379_amd import workloads
 SAMPLES = {
     "sphere_n32": ((0, 5, 10, 15), 10, 1e-10),
     "diamond_n64": ((0, 16, 32, 48), 16, 1e-9),
+    # the learned-warm-start workload (N = 96, 20 bands, path Gamma-X-M-Gamma-R-X):
+    # two k-points on Gamma-X, away from the residual floor next to Gamma
+    "diamond_n96": ((16, 24), 20, 1e-9),
     # crystal 0 (N = 24, seed 0) of the 32-crystal random-field batch
     "random_batch_c0": ((0, 3, 7), 12, 1e-10),
 }

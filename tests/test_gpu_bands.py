@@ -83,9 +83,9 @@ def test_sphere_n16_vs_oracle(B):
         lam, _, info = olob.solve_bands(eps, 1.0, k, m, tol=1e-10)
         if np.linalg.norm(k) == 0:
             assert np.all(np.abs(ev[i][:3]) < 1e-8)
-            assert np.allclose(ev[i][3:], lam[3:], rtol=1e-9)
+            assert np.allclose(ev[i][3:], lam[3:], rtol=1e-10)
         else:
-            assert np.allclose(ev[i], lam, rtol=1e-9), (i, ev[i], lam)
+            assert np.allclose(ev[i], lam, rtol=1e-10), (i, ev[i], lam)
 
 
 def test_stream_segments_match_single_stream(B):
@@ -118,7 +118,7 @@ def test_batch_uneven_grids(B):
     # and one crystal against the oracle
     N, eps = crystals[1]
     lam, _, info = olob.solve_bands(eps, 1.0, kp[1], 5, tol=1e-10)
-    assert np.allclose(evs[1][1], lam, rtol=1e-9)
+    assert np.allclose(evs[1][1], lam, rtol=1e-10)
 
 
 @pytest.mark.parametrize("N,kidx", [(16, (0, 2, 5, 7)), (24, (3,))])
@@ -169,7 +169,7 @@ def test_large_grid_fp64_preconditioner_staged(B):
     assert status == 0, st
     assert st[0]["max_rel_resid"] <= 1e-9, st
     phys, _ = mfd.closed_form_spectrum(N, 1.0, k, mfd.gamma_rule(N, 1.0, k))
-    assert np.allclose(ev[0], phys[:m], rtol=1e-9), (ev, phys[:m])
+    assert np.allclose(ev[0], phys[:m], rtol=1e-10), (ev, phys[:m])
 
 
 def test_large_grid_mixed_fallback_to_staged_fp64(B):
@@ -236,7 +236,7 @@ def test_update_forms_agree(B, form, precision):
     ev, st, status = B.mfd_bands(ctx, [k], m, tol, B.default_opts(precision=precision, streams=1))
     assert status == 0, st
     lam = _oracle_bands_n10(m)
-    assert np.allclose(ev[0], lam, rtol=1e-7 if precision else 1e-9), (form, ev[0], lam)
+    assert np.allclose(ev[0], lam, rtol=1e-7 if precision else 1e-10), (form, ev[0], lam)
     with pytest.raises(B.MfdError):
         B.mfd_set_tuning(ctx, dict(gram_workgroups=256, update_workgroups=256, stencil_workgroups=2048,
                                    fft_x_run=0, update_rows=8))

@@ -150,6 +150,32 @@ def test_precond_fp32(B, N):
     assert rel_err(Td.cpu().numpy(), ref) < 5e-6
 
 
+@pytest.mark.parametrize("N,xrun", [(64, 4), (64, 8), (64, 16), (100, 0), (120, 0)])
+def test_precond_fp32_solver_instances(B, N, xrun):
+    """Element-wise FP32 parity of the instances the solves run: N = 64 with
+    each z-pass x run the autotuner may pick (16 is the benchmark's), and the
+    radix-5 and radix-3 plans of N = 100 and 120 (band-gap workloads), on a
+    two-field block at a generic k and at k = 0 (shifted)."""
+    rng = np.random.default_rng(400 + N + xrun)
+    L = 1.0
+    ctx = B.mfd_build(N, L, 2, np.ones((N, N, N)))
+    if xrun:
+        B.mfd_set_tuning(ctx, dict(gram_workgroups=256, update_workgroups=512, stencil_workgroups=2048,
+                                   fft_x_run=xrun, update_rows=0))
+    for k in (np.array([0.5, -0.25, 0.1]) * np.pi, np.zeros(3)):
+        g, c = B.mfd_gamma_shift(ctx, k)
+        R = rand_block(rng, 2, N).astype(np.complex64)
+        Rd = torch.from_numpy(R).cuda()
+        Td = torch.empty_like(Rd)
+        B.mfd_precond_solve(ctx, k, Rd, Td)
+        torch.cuda.synchronize()
+        got = Td.cpu().numpy()
+        ref = mfd.precond_solve(R.astype(np.complex128), N, L, k, g, 2, c)
+        # element-wise, against the block's largest entry: FP32 FFTs of
+        # length N err by about log2 N unit roundoffs
+        assert rel_err(got, ref) < 5e-6, (N, xrun, k)
+
+
 def test_precond_inverts_operator_homogeneous(B):
     """eps = 1: P = the compensated operator, so precond(op(x)) = x."""
     N, L = 32, 1.0

@@ -110,7 +110,7 @@ def test_bands_order4_diamond_vs_oracle(B, precision):
     assert status == 0, st
     for i, k in enumerate(kp):
         lam, _, _ = olob.solve_bands(eps, 1.0, k, m, tol=1e-10, order=4)
-        assert np.allclose(ev[i], lam, rtol=1e-7 if precision else 1e-9), (i, ev[i], lam)
+        assert np.allclose(ev[i], lam, rtol=1e-7 if precision else 1e-10), (i, ev[i], lam)
 
 
 def _iso_cases():

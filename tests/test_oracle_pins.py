@@ -224,6 +224,38 @@ def test_kernel_dimensions(k):
         assert _count_zeros(ev, scale) == 3
 
 
+@pytest.mark.parametrize("k", [np.array([0.9, -0.4, 0.3]), np.zeros(3)])
+def test_lambda_re_on_random_eps(k):
+    """Alg 4.1's recompute on an inhomogeneous medium.  lambda_re(x) is the
+    Rayleigh quotient of A M_0 A' alone, so for any x (Section 4.5)
+        x^H (A M_0 A' + gamma B'B) x / |x|^2 - lambda_re(x) = gamma |Bx|^2 / |x|^2.
+    Both sides are taken from the dense Kronecker assembly (M_0 from eps
+    through the four-cell rule), independent of the np.roll operators; a
+    lambda_re that dropped M_0, or a wrong sign or axis in A', fails."""
+    rng = np.random.default_rng(21)
+    N, L = 4, 1.0
+    h = L / N
+    eps = _rand_eps(rng, N)
+    mu = mfd.mu_from_eps(eps)
+    g = mfd.gamma_rule(N, L, k)
+    M, AMA, BB = mfd.dense_matrix(eps, L, k, g, parts=True)
+    _, _, Bd = mfd.dense_operators(N, L, k)
+    for _ in range(3):
+        x = _rand_field(rng, (3, N, N, N))
+        xv = x.reshape(-1)
+        nrm = np.vdot(xv, xv).real
+        lre = mfd.lambda_re(x, mu, k, h)
+        rq = np.vdot(xv, M @ xv).real / nrm
+        comp = g * np.linalg.norm(Bd @ xv) ** 2 / nrm
+        assert abs(lre - np.vdot(xv, AMA @ xv).real / nrm) <= 1e-12 * rq
+        assert abs((rq - lre) - comp) <= 1e-12 * rq
+    # a physical eigenvector of the dense matrix: lambda_re = lambda (Prop 4.5)
+    ev, U = np.linalg.eigh(M)
+    j = 3 if np.linalg.norm(k) == 0 else 0
+    x = U[:, j].reshape(3, N, N, N)
+    assert abs(mfd.lambda_re(x, mu, k, h) - ev[j]) <= 1e-10 * ev[j]
+
+
 def test_prop32_spectrum_merge():
     """Prop 3.2: the spectrum of A M_0 A' + gamma B'B is the union of the
     nonzero spectra of A M_0 A' and gamma B'B (plus dim H zeros)."""
