@@ -11,17 +11,20 @@ the previous k-point after it).  A k-point counts when every band's residual,
 recomputed with the FP64 operator, is <= 1e-8.
 
 Also reported (same JSON line):
-  variants      - one timed step each of the plain FP64 solve, of the
-                  learned warm start, of a 32-crystal batch and of the band
-                  structure and band-gap ratio of the curved-interface cubic
-                  cell (N = 120), on the same GPU;
-  roofline      - the dominant kernel's achieved rate against its MI355X peak,
-                  from HIP events recorded inside the library on the solve's
-                  stream during the timed steps;
-  stencil       - the metric's second part: the fused stencil alone on a
-                  full 16-band FP32 block (HIP events over back-to-back
-                  calls), with the FP64-arithmetic form and the solver's own
-                  launches beside it;
+  roofline      - the dominant kernel (the largest share of the solve's
+                  kernel time among the kernels that occupy the whole chip)
+                  against its MI355X peak, from HIP events around each launch
+                  in a single-stream pass over the first k-points after the
+                  timed steps; roofline_check: the summed event time fits in
+                  that pass's wall time;
+  stencil       - the metric's second part: the fused stencil alone on full
+                  16-band blocks rotated over a working set above the
+                  Infinity Cache, FP32, FP32-storage/FP64-arithmetic and FP64;
+                  precond the same for the FFT preconditioner;
+  variants      - one timed step each of the plain FP64 solve, of a
+                  32-crystal batch, of the learned warm start at N = 96 (with
+                  the previous-k start and the untrained network beside it),
+                  and of the band structures of Section 6's cells;
   cpu_baseline  - the FP64 CPU oracle timed on a bounded sample of the same
                   workload on this host.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -59,8 +62,12 @@ def parse():
                     help="skip the one-step comparison runs (FP64 solve, learned warm start)")
     ap.add_argument("--roofline-nk", type=int, default=6, help="k-points of the single-stream timing pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--learned-streams", type=int, default=12,
+                    help="k-path segments of the learned-warm-start variant (N = 96, 100 k-points)")
     ap.add_argument("--profile-only", action="store_true", help="one short step, no JSON (for rocprofv3)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the single-stream pass the roofline object is taken from (for rocprofv3); "
+                         "prints its JSON object")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only the full-block stencil timing (for rocprofv3); prints its JSON object")
     ap.add_argument("--lattice-only", action="store_true",
@@ -74,6 +81,12 @@ def parse():
 
 
 COPY_BYTES = 1 << 30
+T_START = time.perf_counter()
+
+
+def progress(msg):
+    """One line on stderr per finished piece of work (the JSON line goes to stdout)."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 KERNEL_SOURCES = {"update": "gemm.hip", "gram": "gemm.hip", "stencil": "stencil.hip", "precond": "fft.hip"}
 
@@ -231,8 +244,7 @@ def gyroid_variant(B, args, torch):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[f"P_N{N}"] = {"value": 1.0 / dt, "unit": "k-points/s", "ms": dt * 1e3, "iters": st[0]["iters"],
-                          "max_rel_resid": st[0]["max_rel_resid"], "status": status,
-                          "paper_steps": cfg["steps_paper"][N], "paper_a100_s": cfg["gpu_s_paper"][N]}
+                          "max_rel_resid": st[0]["max_rel_resid"], "status": status}
         if N == cfg["Ns"][-1]:
             kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.bcc_points())
             o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, streams=args.streams)
@@ -250,109 +262,211 @@ def gyroid_variant(B, args, torch):
     return out
 
 
-def fcc_gap_variant(B, args, torch):
-    """Section 6.3's FCC sp3 diamond (spheres and bond spheroids, eps 13 in
-    1, M_0 per edge) at N = 100: 10 bands on X-U-L-Gamma-X-W-K with every
-    symmetry point, tol 1e-5, mixed precision, one timed call, then the
-    band-gap ratio."""
-    from paper_2503_19379_amd import workloads
-    cfg = workloads.CONFIGS["fcc_diamond"]
-    N = 100
-    kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.fcc_points())
-    ctx = B.mfd_build_lattice_mu(N, workloads.lattice_vectors("fcc"), 2, workloads.mu_fcc_diamond(N))
-    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, streams=args.streams)
-    B.mfd_bands(ctx, kp[:1], cfg["nbands"], cfg["tol"], o)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], o)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ratio, below = B.mfd_gap_ratio(ev, kp)
-    ctx.close()
-    ok = sum(1 for x in st if x["max_rel_resid"] <= cfg["tol"])
-    return {"value": ok / dt, "unit": "k-points/s", "ms": dt * 1e3, "kpoints": len(kp), "converged_kpoints": ok,
-            "iters_per_k": float(np.mean([x["iters"] for x in st])), "gap_ratio": ratio, "gap_above_band": below,
-            "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"],
-            "workload": f"FCC sp3 diamond, spheres r 0.12 + bond spheroids of minor radius 0.11, eps 13 in 1, "
-                        f"M_0 per edge, N = {N}, {len(kp)} k-points on {cfg['path']}, {cfg['nbands']} bands, "
-                        f"tol {cfg['tol']:g}, mixed"}
-
-
-def stencil_object(direct, timed, single):
-    out = dict(direct["fp32"], form="fp32 storage and arithmetic, full 16-band block, 30 back-to-back calls")
-    out["fp32_storage_fp64_arith"] = direct["fp32_storage_fp64_arith"]
-    if timed is not None:
-        out["in_solve"] = {
-            "timed_region": {k: timed[k] for k in ("achieved", "frac", "avg_us", "launches", "traffic")},
-            "single_stream": {k: single[k] for k in ("achieved", "frac", "avg_us")} if single else None,
-            "note": "soft-locked launches (about 10 active bands) in FP64 arithmetic; the timed region's "
-                    "durations include the wait for CUs held by the concurrent segments"}
-    return out
-
-
-def stencil_direct(B, ctx, k, m, N, torch, reps=30):
-    """The fused stencil alone on a full block of m bands (no soft locking),
-    with nothing else on the chip: mean duration of `reps` back-to-back
-    mfd_op_apply calls between HIP events on the stream they launch on.
-    Algorithmic bytes per call: X read and Y written once (2 x 24 N^3 m bytes
-    of complex64) plus mu on the 3 N^3 edges once (FP32 copy: 12 N^3 bytes;
-    FP64: 24 N^3), the halos coming from LDS or cache."""
-    n3 = N ** 3
+def _rotating_blocks(torch, m, N, dtype, count):
     g = torch.Generator(device="cuda").manual_seed(0)
-    X = torch.randn((m, 3, N, N, N), dtype=torch.complex64, device="cuda", generator=g)
-    Y = torch.empty_like(X)
+    return [torch.randn((m, 3, N, N, N), dtype=dtype, device="cuda", generator=g) for _ in range(count)]
+
+
+def _timed_calls(torch, s, calls, reps):
+    """Mean duration of `reps` passes over `calls` (back-to-back launches on
+    stream s) between HIP events recorded on s, after one untimed pass."""
+    for c in calls:
+        c()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        for c in calls:
+            c()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / (reps * len(calls))
+
+
+def stencil_direct(B, ctx, k, m, N, torch, min_ws=512e6, reps=10):
+    """The fused stencil alone on full blocks of m bands (no soft locking),
+    nothing else on the chip.  The calls rotate over enough distinct (X, Y)
+    block pairs that the working set is at least min_ws bytes (above the
+    256 MB Infinity Cache), so every call streams from HBM.  Algorithmic
+    bytes per call: X read and Y written once (2 x 24 N^3 m bytes in FP32
+    storage, 2 x 48 in FP64) plus M_0 once (FP32 copy 12 N^3, FP64 24 N^3);
+    the neighbour values come from registers, LDS or cache.  Three forms:
+    FP32 storage and arithmetic; FP32 storage with FP64 arithmetic (what the
+    mixed-precision solve applies to its search directions); FP64 (the FP64
+    solve)."""
+    n3 = N ** 3
     s = torch.cuda.Stream()
     out = {}
-    for name, f64, mu_bytes in (("fp32", False, 12), ("fp32_storage_fp64_arith", True, 24)):
-        for _ in range(3):
-            B.mfd_op_apply(ctx, k, X, Y, stream=s.cuda_stream, fp64_arith=f64)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(reps):
-            B.mfd_op_apply(ctx, k, X, Y, stream=s.cuda_stream, fp64_arith=f64)
-        e1.record(s)
-        e1.synchronize()
-        avg_s = e0.elapsed_time(e1) * 1e-3 / reps
-        by = 48.0 * n3 * m + mu_bytes * n3
+    for name, dtype, f64, by in (("fp32", torch.complex64, False, 48.0 * n3 * m + 12.0 * n3),
+                                 ("fp32_storage_fp64_arith", torch.complex64, True, 48.0 * n3 * m + 24.0 * n3),
+                                 ("fp64", torch.complex128, False, 96.0 * n3 * m + 24.0 * n3)):
+        per_pair = 2 * m * 3 * n3 * (8 if dtype == torch.complex64 else 16)
+        npair = max(2, int(np.ceil(min_ws / per_pair)))
+        X = _rotating_blocks(torch, m, N, dtype, npair)
+        Y = [torch.empty_like(x) for x in X]
+        calls = [(lambda x=x, y=y: B.mfd_op_apply(ctx, k, x, y, stream=s.cuda_stream, fp64_arith=f64))
+                 for x, y in zip(X, Y)]
+        avg_s = _timed_calls(torch, s, calls, reps)
         out[name] = {"achieved": by / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": by / avg_s / HBM_PEAK, "avg_us": avg_s * 1e6, "bytes_per_call": by,
-                     "nbands": m, "calls": reps}
-    del X, Y
-    torch.cuda.synchronize()
+                     "working_set_bytes": npair * per_pair + (24 if f64 or dtype == torch.complex128 else 12) * n3,
+                     "blocks_rotated": npair, "nbands": m, "N": N, "calls": reps * npair}
+        del X, Y, calls
+        torch.cuda.synchronize()
     return out
 
 
-def cpu_baseline(eps, L, k, m, iters, gpu_iters_per_k):
-    """Time the FP64 oracle for a few LOBPCG iterations at one k-point of the
-    same workload and scale by the GPU's iterations per k-point."""
+def precond_direct(B, ctx, k, m, N, torch, min_ws=512e6, reps=10):
+    """The FFT preconditioner alone on full FP32 blocks of m bands, in place,
+    rotating over enough distinct blocks for a working set of at least
+    min_ws bytes.  Algorithmic bytes: one read and one write of the block
+    (48 B per cell and band), the single-pass minimum; the design makes three
+    passes (x-y plane FFT, z FFT with the 3 x 3 solve, inverse plane FFT), so
+    the bytes it moves are three times that."""
+    n3 = N ** 3
+    s = torch.cuda.Stream()
+    per = m * 3 * n3 * 8
+    nblk = max(2, int(np.ceil(min_ws / per)))
+    X = _rotating_blocks(torch, m, N, torch.complex64, nblk)
+    calls = [(lambda x=x: B.mfd_precond_solve(ctx, k, x, x, stream=s.cuda_stream)) for x in X]
+    avg_s = _timed_calls(torch, s, calls, reps)
+    by = 48.0 * n3 * m
+    del X, calls
+    torch.cuda.synchronize()
+    return {"achieved": by / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": by / avg_s / HBM_PEAK,
+            "moved_three_pass_GBps": 3 * by / avg_s / 1e9, "moved_three_pass_frac": 3 * by / avg_s / HBM_PEAK,
+            "avg_us": avg_s * 1e6, "bytes_per_call": by, "working_set_bytes": nblk * per, "blocks_rotated": nblk,
+            "nbands": m, "N": N, "calls": reps * nblk, "form": "FP32, in place"}
+
+
+def learned_variant(B, args, torch):
+    """The learned-warm-start workload: diamond cell at N = 96 (2,654,208
+    unknowns), 100 k-points on Gamma-X-M-Gamma-R-X, 20 bands, mixed
+    precision, tol 1e-8.  Each k-path segment is solved with the previous-k
+    start, with the learned proposal (network trained along the path), and
+    with the untrained network (learn_steps = 0: the aligned-subspace
+    extrapolation it starts from).  One timed call each after an untimed one
+    that sizes the workspaces."""
+    from paper_2503_19379_amd import workloads
+    cfg = workloads.CONFIGS["diamond_n96"]
+    N, m = cfg["N"], cfg["nbands"]
+    kp = workloads.kpath(cfg["path"], cfg["nk"])
+    ctx = B.mfd_build(N, 1.0, 2, workloads.crystal_eps(cfg["eps"], N))
+    guard = max(0, min(args.guard, B.max_block() - m))
+    out = {"workload": f"diamond cell, N = {N} ({3 * N ** 3} unknowns), {len(kp)} k-points on {cfg['path']}, "
+                       f"{m} bands, tol {cfg['tol']:g}, mixed precision, guard {guard}, "
+                       f"{args.learned_streams} k-path segments"}
+    for name, warm, steps in (("previous_k", 1, 30), ("learned", 2, 30), ("untrained", 2, 0)):
+        o = B.default_opts(precision=1, warm_start=warm, learn_steps=steps, seed=0, guard=guard, max_iter=500,
+                           streams=args.learned_streams)
+        B.mfd_bands(ctx, kp[:args.learned_streams], m, cfg["tol"], o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, st, status = B.mfd_bands(ctx, kp, m, cfg["tol"], o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = sum(1 for x in st if x["max_rel_resid"] <= cfg["tol"] and x["spurious"] == 0)
+        out[name] = {"value": ok / dt, "unit": "k-points/s", "ms": dt * 1e3,
+                     "iters_per_k": float(np.mean([x["iters"] for x in st])),
+                     "iters_total": int(sum(x["iters"] for x in st)), "converged_kpoints": ok,
+                     "total_kpoints": len(st),
+                     "proposals_used": int(sum(1 for x in st if warm == 2 and not x["used_fallback"]))}
+    ctx.close()
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(eps, L, kpts, kidx, m, guard, gpu_iters_per_k):
+    """The FP64 oracle as it stands, on this host: at each k-index of kidx
+    (cold start, seed 0, the same block of m + guard columns), its LOBPCG is
+    timed for 1 and for 2 iterations; the difference is one iteration, the
+    rest the start-up (FFT symbol inverses, QR, first operator application).
+    Seconds per k-point = start-up + one iteration x the GPU run's mean
+    iterations per k-point.  FFTs run on os.cpu_count() threads, BLAS on its
+    own pool; both are recorded."""
     from oracle import lobpcg as olob
     from oracle import mfd as omfd
     from paper_2503_19379_amd import workloads
+    ncpu = os.cpu_count() or 1
+    omfd.FFT_WORKERS = ncpu
     N = eps.shape[0]
     n = 3 * N ** 3
     h = L / N
     mu = omfd.mu_from_eps(eps)
-    g = omfd.gamma_rule(N, L, k)
-    c = omfd.shift_rule(L, k)
-    X0 = workloads.start_block(m, N, 0).reshape(m, n).T
-    t0 = time.perf_counter()
-    Pinv = np.linalg.inv(omfd.precond_matrices(N, L, k, g, 2, c))
-    A = lambda X: omfd.apply_op(X.T.reshape(-1, 3, N, N, N), mu, k, h, g, 2, c).reshape(-1, n).T
-    T = lambda R: omfd.precond_solve(R.T.reshape(-1, 3, N, N, N), N, L, k, g, 2, c, Pinv=Pinv).reshape(-1, n).T
-    olob.lobpcg(A, T, X0, 1e-8, maxiter=iters)
-    dt = time.perf_counter() - t0
-    # lobpcg runs `iters` iterations plus the start-up and the final check
-    per_iter = dt / (iters + 2)
-    per_k = per_iter * gpu_iters_per_k
+    X0 = workloads.start_block(m + guard, N, 0).reshape(m + guard, n).T
+    per_iter, startup = [], []
+    t_all = time.perf_counter()
+    for ki in kidx:
+        k = kpts[ki]
+        g = omfd.gamma_rule(N, L, k)
+        c = omfd.shift_rule(L, k)
+        times = []
+        for iters in (1, 2):
+            t0 = time.perf_counter()
+            Pinv = np.linalg.inv(omfd.precond_matrices(N, L, k, g, 2, c))
+            A = lambda X: omfd.apply_op(X.T.reshape(-1, 3, N, N, N), mu, k, h, g, 2, c).reshape(-1, n).T
+            T = lambda R: omfd.precond_solve(R.T.reshape(-1, 3, N, N, N), N, L, k, g, 2, c,
+                                             Pinv=Pinv).reshape(-1, n).T
+            olob.lobpcg(A, T, X0, 1e-8, maxiter=iters)
+            times.append(time.perf_counter() - t0)
+        per_iter.append(max(times[1] - times[0], 0.0))
+        startup.append(times[0] - per_iter[-1])
+        progress(f"CPU oracle at k-index {ki}: {times[0]:.1f} s (1 iteration), {times[1]:.1f} s (2)")
+    wall = time.perf_counter() - t_all
+    s_per_k = float(np.mean(startup) + np.mean(per_iter) * gpu_iters_per_k)
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except ImportError:
-        cores = 1
-    return {"value": 1.0 / per_k, "unit": "k-points/s", "cores": cores, "kind": "oracle",
-            "sample": f"{iters} oracle LOBPCG iterations (+ start-up and final check, {dt:.1f} s) at one "
-                      f"k-point of the same workload, scaled to {gpu_iters_per_k:.1f} iterations per k-point "
-                      f"(the GPU run's mean)"}
+        blas = None
+    return {"value": 1.0 / s_per_k, "unit": "k-points/s", "cores": ncpu, "kind": "oracle",
+            "s_per_kpoint": s_per_k, "s_per_iteration": float(np.mean(per_iter)),
+            "startup_s": float(np.mean(startup)), "nproc": ncpu, "cpu_model": cpu_model(),
+            "fft_workers": ncpu, "blas_threads": blas,
+            "sample": f"oracle LOBPCG at k-indices {list(kidx)} of the same path (cold start, seed 0, "
+                      f"{m} + {guard} columns), 1 and 2 iterations each ({wall:.1f} s in all); seconds per "
+                      f"k-point = start-up + one iteration x {gpu_iters_per_k:.1f} (the GPU run's mean "
+                      f"iterations per k-point)"}
+
+
+def kernel_table(prof, wall_s=None):
+    """Per-kernel average durations and rates from the library's HIP-event
+    timing.  Gram: flops (8 n K (K+1) per launch) against the FP64 MFMA peak
+    (its arithmetic as built); the others: algorithmic bytes against HBM."""
+    rl = {}
+    for cat in ("stencil", "precond", "gram", "update", "rr", "other"):
+        p = prof[cat]
+        if p["count"] == 0 or p["ms"] == 0:
+            continue
+        avg_s = p["ms"] / p["count"] * 1e-3
+        per = p["bytes"] / p["count"]
+        e = {"avg_us": avg_s * 1e6, "total_ms": p["ms"], "launches": p["count"]}
+        if cat == "rr":
+            e.update(bound="latency", note="one workgroup (one CU); overlaps other segments' kernels")
+        elif cat == "other":
+            e.update(bound="latency", note="fixed-order sums of the Gram tiles and of the update's column norms")
+        elif cat == "gram":
+            e.update(bound="mfma", achieved=per / avg_s / 1e12, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
+                     frac=per / avg_s / FP64_PEAK, per_launch=per,
+                     per_launch_note="8 n K (K+1) flops for the launch's basis of K = mb + 2 na columns "
+                                     "(S^H S and S^H AS, Hermitian halves); mean over launches")
+        else:
+            e.update(bound="hbm", achieved=per / avg_s / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                     frac=per / avg_s / HBM_PEAK, per_launch=per, per_launch_note="algorithmic bytes")
+        rl[cat] = e
+    total = sum(v["total_ms"] for v in rl.values())
+    for v in rl.values():
+        v["share"] = v["total_ms"] / total if total else None
+    return rl, total
 
 
 def main():
@@ -381,9 +495,10 @@ def main():
     kpts = workloads.kpath(cfg["path"], cfg["nk"])[:nk]
     torch.cuda.set_device(0)
     ctx = B.mfd_build(N, L, 2, eps)
-    def make_opts(precision, warm):
+
+    def make_opts(precision, warm, streams=args.streams):
         return B.default_opts(precision=1 if precision == "mixed" else 0, warm_start=2 if warm == "learned" else 1,
-                              seed=0, guard=args.guard, max_iter=500, streams=args.streams)
+                              seed=0, guard=args.guard, max_iter=500, streams=streams)
 
     opts = make_opts(args.precision, args.warm)
 
@@ -407,13 +522,32 @@ def main():
         torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
 
+    nk_iso = max(1, min(args.roofline_nk, nk))
+
+    def single_stream_pass():
+        """The kernels without the overlap of concurrent segments: one stream
+        over the first k-points of the path, HIP events around every launch on
+        that stream.  Returns (per-kernel table, wall seconds, summed event time)."""
+        B.mfd_profile(ctx, True)
+        o1 = make_opts(args.precision, "prev", streams=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.mfd_bands(ctx, kpts[:nk_iso], m, args.tol, o1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = B.mfd_profile_read(ctx)
+        B.mfd_profile(ctx, False)
+        table, total_ms = kernel_table(prof)
+        return table, wall, total_ms
+
     if args.lattice_only:
         print(json.dumps(lattice_only(B, torch)))
         if args.copy_calib:
             copy_calibration()
         return
     if args.stencil_only:
-        print(json.dumps(stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch)))
+        print(json.dumps({"stencil": stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch),
+                          "precond": precond_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch)}))
         if args.copy_calib:
             copy_calibration()
         return
@@ -423,27 +557,31 @@ def main():
         if args.copy_calib:
             copy_calibration()
         return
-    for _ in range(args.warmup):
+    if args.roofline_only:
+        B.mfd_bands(ctx, kpts[:nk_iso], m, args.tol, make_opts(args.precision, "prev", streams=1))
+        table, wall, total_ms = single_stream_pass()
+        print(json.dumps({"kernels_isolated": table, "wall_ms": wall * 1e3, "event_ms": total_ms}))
+        if args.copy_calib:
+            copy_calibration()
+        return
+    for i in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    # Per-kernel durations: HIP events recorded by the library around each
-    # launch on the stream it is launched on, during the timed steps.
+        torch.cuda.synchronize()
+        progress(f"warm-up step {i + 1} of {args.warmup} done")
+    # Per-kernel durations during the timed steps: HIP events recorded by the
+    # library around each launch on the stream it is launched on.
     B.mfd_profile(ctx, True)
     t0 = time.perf_counter()
     results = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         results.append(step())
+        progress(f"timed step {i + 1} of {args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = B.mfd_profile_read(ctx)
-    # The same kernels without the overlap of concurrent segments: a
-    # single-stream pass over the first k-points of the path.
-    B.mfd_profile(ctx, True)
-    o1 = B.default_opts(precision=opts.precision, warm_start=1, seed=0, guard=args.guard, max_iter=500, streams=1)
-    B.mfd_bands(ctx, kpts[:max(1, min(args.roofline_nk, nk))], m, args.tol, o1)
-    torch.cuda.synchronize()
-    prof_iso = B.mfd_profile_read(ctx)
     B.mfd_profile(ctx, False)
+    iso, iso_wall, iso_event_ms = single_stream_pass()
+    progress("single-stream pass done")
 
     if args.verbose:
         for ev, st, status in results:
@@ -454,11 +592,11 @@ def main():
     ok, iters, maxres = count(results)
     value = ok / dt
 
-    # One-step comparison runs on the same GPU: the plain FP64 solve, and the
-    # learned warm start (each after an untimed call that sizes its workspaces).
+    # One-step comparison runs on the same GPU (each after an untimed call
+    # that sizes its workspaces).
     variants = {}
     if not args.no_variants:
-        for name, prec, warm in (("fp64_prev", "fp64", "prev"), ("mixed_learned", "mixed", "learned")):
+        for name, prec, warm in (("fp64_prev", "fp64", "prev"),):
             if (prec, warm) == (args.precision, args.warm):
                 continue
             o = make_opts(prec, warm)
@@ -472,45 +610,25 @@ def main():
             variants[name] = {"value": vok / d1, "unit": "k-points/s", "steps": 1, "ms_per_step": d1 * 1e3,
                               "iters_per_k": float(np.mean(vit)), "converged_kpoints": vok,
                               "max_rel_resid": vres, "precision": prec, "warm_start": warm}
-        variants["random_batch"] = batch_variant(B, args, torch, count)
-        variants["sc_sphere_cyl_gap"] = band_gap_variant(B, args, torch)
-        variants["bcc_gyroid"] = gyroid_variant(B, args, torch)
-        variants["fcc_diamond_gap"] = fcc_gap_variant(B, args, torch)
+            progress(f"variant {name} done")
+        for name, fn in (("random_batch", lambda: batch_variant(B, args, torch, count)),
+                         ("learned_n96", lambda: learned_variant(B, args, torch)),
+                         ("sc_sphere_cyl_gap", lambda: band_gap_variant(B, args, torch)),
+                         ("bcc_gyroid", lambda: gyroid_variant(B, args, torch))):
+            variants[name] = fn()
+            progress(f"variant {name} done")
     n = 3 * N ** 3
-
-    mb = m + args.guard
     traffic = measured_traffic(args.workload, args.precision)
-
-    def rooflines(prof):
-        rl = {}
-        for cat in ("stencil", "precond", "gram", "update", "rr"):
-            p = prof[cat]
-            if p["count"] == 0 or p["ms"] == 0:
-                continue
-            avg_s = p["ms"] / p["count"] * 1e-3
-            by = p["bytes"] / p["count"]
-            if cat == "rr":
-                rl[cat] = {"bound": "latency", "avg_us": avg_s * 1e6, "total_ms": p["ms"], "launches": p["count"]}
-            elif cat == "gram":
-                # the library records 8 n K (K+1) per launch for its basis of K
-                # columns (soft locking shrinks K): two Hermitian products, upper halves
-                flops = by
-                rl[cat] = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": FP64_PEAK / 1e12,
-                           "unit": "TFLOP/s", "frac": flops / avg_s / FP64_PEAK, "traffic": traffic.get(cat),
-                           "avg_us": avg_s * 1e6, "total_ms": p["ms"], "launches": p["count"],
-                           "per_launch": f"S^H S and S^H AS, Hermitian: 8 n K (K+1) = {flops:.3e} FLOP "
-                                         f"(mean over launches; K = mb + 2 na with na active bands)"}
-            else:
-                rl[cat] = {"bound": "hbm", "achieved": by / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                           "frac": by / avg_s / HBM_PEAK, "traffic": traffic.get(cat), "avg_us": avg_s * 1e6,
-                           "total_ms": p["ms"], "launches": p["count"],
-                           "per_launch": f"{by:.4e} algorithmic bytes"}
-        return rl
-
-    rl = rooflines(prof)
-    rl_iso = rooflines(prof_iso)
-    hbm = {c: v for c, v in rl.items() if v["bound"] == "hbm"}
-    dom = max(hbm, key=lambda c: hbm[c]["total_ms"]) if hbm else None
+    for cat, v in iso.items():
+        if v.get("bound") in ("hbm", "mfma"):
+            v["traffic"] = traffic.get(cat)
+    timed, timed_total = kernel_table(prof)
+    # the dominant kernel: the largest share of the single-stream time among
+    # the kernels that occupy the whole chip (the Rayleigh-Ritz step runs on
+    # one CU and the sums are latency-bound)
+    chip = {c: v for c, v in iso.items() if v.get("bound") in ("hbm", "mfma")}
+    dom = max(chip, key=lambda c: chip[c]["total_ms"]) if chip else None
+    fits = iso_event_ms <= iso_wall * 1e3 * 1.001
     line = {
         "metric": "k-point band solves/sec at N=64, 16 bands, 1e-8 resid; stencil HBM GB/s vs peak",
         "value": value,
@@ -530,22 +648,20 @@ def main():
                    "N": N, "nbands": m, "nk": nk, "tol": args.tol, "precision": args.precision,
                    "warm_start": args.warm, "guard": args.guard, "streams": args.streams,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
-        "roofline_source": "HIP events recorded around each launch on its own stream during the timed steps "
-                           "(concurrent k-path segments overlap); kernels_isolated: the same from a "
-                           f"single-stream pass over {min(args.roofline_nk, nk)} k-points after the timed steps",
-        # the timed region's durations include the wait for CUs that the other
-        # concurrent segments hold; the same kernel alone on the chip beside them
-        "roofline": dict(rl[dom], kernel=dom,
-                         single_stream={k: rl_iso[dom][k] for k in ("achieved", "frac", "avg_us")}
-                         if dom in rl_iso else None) if dom else None,
-        # the metric's second part: the fused stencil on a full block of the
-        # workload's 16 bands in FP32 (one call: 204.5 MB at N = 64), alone on
-        # the chip; beside it the FP64-arithmetic form the solver applies to
-        # its FP32 W, and the solver's own soft-locked launches
-        "stencil": stencil_object(stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch),
-                                  rl.get("stencil"), rl_iso.get("stencil")),
-        "kernels": rl,
-        "kernels_isolated": rl_iso,
+        # the kernels alone: a single-stream pass over the first k-points of
+        # the path after the timed steps, HIP events on the launching stream
+        "roofline": dict(chip[dom], kernel=dom, source=f"single-stream pass over {nk_iso} k-points after the "
+                         "timed steps; HIP events around each launch on its stream") if dom else None,
+        "roofline_check": {"event_ms": iso_event_ms, "wall_ms": iso_wall * 1e3, "events_fit_in_wall": fits},
+        # the metric's second part: the fused stencil (and the FFT
+        # preconditioner) alone on full blocks, working sets above the
+        # Infinity Cache
+        "kernels_isolated": iso,
+        # in the timed steps the concurrent segments overlap: a launch's event
+        # time includes the wait for CUs held by other segments, so these are
+        # shares of stream time, not kernel rates
+        "kernels_timed_region_share": {c: {"share": v["share"], "launches": v["launches"]}
+                                       for c, v in timed.items()},
         "iters_per_k": float(np.mean(iters)) if iters else None,
         "max_rel_resid": maxres,
         "converged_kpoints": ok,
@@ -553,9 +669,19 @@ def main():
         "variants": variants,
         "tuning": B.mfd_tuning(ctx)[1],
     }
+    line["stencil"] = stencil_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch)
+    line["precond"] = precond_direct(B, ctx, kpts[min(16, nk - 1)], m, N, torch)
+    progress("stencil and preconditioner on full blocks done")
+    if not args.no_variants:
+        s96 = workloads.CONFIGS["diamond_n96"]
+        ctx96 = B.mfd_build(s96["N"], 1.0, 2, workloads.crystal_eps(s96["eps"], s96["N"]))
+        k96 = workloads.kpath(s96["path"], s96["nk"])[16]
+        line["stencil_n96_20bands"] = stencil_direct(B, ctx96, k96, s96["nbands"], s96["N"], torch)
+        ctx96.close()
+        progress("stencil on the N = 96, 20-band block done")
     if not args.no_cpu_baseline:
-        kidx = min(16, len(kpts) - 1)
-        line["cpu_baseline"] = cpu_baseline(eps, L, kpts[kidx], m, args.cpu_iters,
+        kidx = [i for i in (0, 16, 32, 48) if i < len(kpts)]
+        line["cpu_baseline"] = cpu_baseline(eps, L, kpts, kidx, m, args.guard,
                                             float(np.mean(iters)) if iters else 1.0)
     print(json.dumps(line))
 

@@ -283,8 +283,7 @@ CONFIGS = {
     # BCC single gyroid (Section 6.3, Table time_comp_bc): first 10 bands at
     # k = (pi, pi, pi)/l, N = 100 and 120, relative residual 1e-5
     "bcc_gyroid": dict(Ns=(100, 120), lattice="bcc", mu="bcc_gyroid", k=(np.pi, np.pi, np.pi), nbands=10,
-                       tol=1e-5, precision="mixed", steps_paper={100: 70, 120: 65},
-                       gpu_s_paper={100: 40.55, 120: 54.92}, path="hGPNH", nk=40, gap_ratio_paper=0.31745,
+                       tol=1e-5, precision="mixed", path="hGPNH", nk=40, gap_ratio_paper=0.31745,
                        N_paper=150),
     # FCC sp3 diamond of spheres and spheroids (Section 6.3): band gap
     "fcc_diamond": dict(lattice="fcc", mu="fcc_diamond", path="XULGXWK", nk=40, nbands=10, tol=1e-5,
