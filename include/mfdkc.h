@@ -187,6 +187,9 @@ int mfd_build_lattice_mu(int N, const double* lattice, int order, const double* 
  * 1-2, no value of band 3). */
 int mfd_gap_ratio(int nk, int nbands, const double* kpts, const double* evals, double* ratio, int* below);
 
+/* Largest nbands + guard that mfd_bands and mfd_bands_batch accept. */
+int mfd_max_block(void);
+
 /* 1 if this build has an FFT plan and stencil for grid size N, else 0. */
 int mfd_supported_n(int N);
 
@@ -251,8 +254,9 @@ int mfd_bands_batch(int ncrys, mfd_ctx* const* ctxs, const int* nk, const double
  * stream around each launch group.  mfd_profile(ctx, 1) clears the counters
  * and starts recording, (ctx, 0) stops.  mfd_profile_read fills 6 entries per
  * array, by category: 0 stencil (mfd_op_apply kernel), 1 FFT preconditioner
- * (three kernels), 2 Gram product (+ partial-sum reduction), 3 Rayleigh-Ritz,
- * 4 block update (+ norm reduction), 5 unused.  ms: total event time, count:
+ * (three kernels), 2 Gram product (the tile kernel alone), 3 Rayleigh-Ritz,
+ * 4 block update (the update kernel alone), 5 the fixed-order sums of the
+ * Gram tiles and of the update's column norms.  ms: total event time, count:
  * launches, bytes: algorithmic HBM bytes (each block read or written once);
  * for the Gram product (category 2) its flops instead, 8 n K (K + 1) for the
  * launch's basis of K columns (two Hermitian K x K products, upper halves). */

@@ -61,6 +61,7 @@ def lib():
         L.mfd_build_lattice_mu.argtypes = [i, dp, i, dp, vp, ctypes.POINTER(vp)]
         L.mfd_gap_ratio.argtypes = [i, i, dp, dp, dp, ctypes.POINTER(i)]
         L.mfd_supported_n.argtypes = [i]
+        L.mfd_max_block.argtypes = []
         L.mfd_set_gamma.argtypes = [vp, d]
         L.mfd_gamma_shift.argtypes = [vp, dp, dp, dp]
         L.mfd_op_apply.argtypes = [vp, dp, i, i, vp, vp, vp]
@@ -284,6 +285,11 @@ def mfd_profile_read(ctx: Context) -> dict:
     by = (ctypes.c_double * 6)()
     _check(lib().mfd_profile_read(ctx.handle, ms, cnt, by))
     return {PROFILE_CATEGORIES[i]: dict(ms=ms[i], count=cnt[i], bytes=by[i]) for i in range(6)}
+
+
+def max_block() -> int:
+    """Largest nbands + guard a band solve accepts."""
+    return int(lib().mfd_max_block())
 
 
 def default_opts(**kw) -> mfd_opts:

@@ -25,6 +25,10 @@ using namespace mfd;
 
 static thread_local std::string g_last_error;
 
+// Largest block (nbands + guard) of a band solve: the basis of 3 blocks must
+// fit the Rayleigh-Ritz step, the Gram and the update kernels.
+constexpr int MAX_BLOCK = 21;
+
 static int fail(int status, const std::string& msg) {
     g_last_error = msg;
     return status;
@@ -489,8 +493,11 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             w.prof.end(e0, 0, N3 * (6.0 * rb * na + 24.0), s);
         }
         hipEvent_t e1 = w.prof.begin(s);
-        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s));
+        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s, 1));
         w.prof.end(e1, 2, 8.0 * (double)n * bm.K * (bm.K + 1), s);   // flops, not bytes
+        e1 = w.prof.begin(s);
+        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s, 2));
+        w.prof.end(e1, 5, 0.0, s);
         if (it == 0 && union_start) {
             const int Kb = bm.K;
             std::vector<double2> hG((size_t)Kb * 2 * Kb);
@@ -513,10 +520,13 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         w.prof.end(e1, 3, 0.0, s);
         e1 = w.prof.begin(s);
         HIPCHK(launch_update_mfma(V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, bm, w.C, w.theta,
-                                  w.nparts_upd, w.npart, w.norms, s, w.upd_rows));
+                                  w.nparts_upd, w.npart, w.norms, s, w.upd_rows, false));
         // reads X, AX (FP64) and the W, P, AW, AP of the basis; writes X', AX'
         // (FP64) and R', P', AP' of every band
         w.prof.end(e1, 4, (double)n * (2 * mb * 16.0 + 2 * (bm.na + np) * rb + 2 * mb * 16.0 + 3 * mb * rb), s);
+        e1 = w.prof.begin(s);
+        HIPCHK(launch_reduce(w.npart, w.nparts_upd, 2 * mb, w.norms, s));
+        w.prof.end(e1, 5, 0.0, s);
         std::swap(V, U);
         if (mixed) std::swap(V32, U32);
         have_p = true;   // the update wrote P', AP' of every band
@@ -1074,7 +1084,7 @@ int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
         !(o.learn_rate >= 0.0f))
         return fail(MFD_EINVAL, "bad options");
     const int mb = nbands + o.guard;
-    if (3 * mb > 64) return fail(MFD_EUNSUPPORTED, "nbands + guard must be <= 21");
+    if (mb > MAX_BLOCK) return fail(MFD_EUNSUPPORTED, "nbands + guard exceeds mfd_max_block()");
     if ((size_t)mb > ctx->n) return fail(MFD_EINVAL, "nbands exceeds the problem size");
     if (o.precision != 0 && o.precision != 1) return fail(MFD_EINVAL, "precision must be 0 or 1");
     return MFD_OK;
@@ -1131,6 +1141,8 @@ int mfd_set_tuning(mfd_ctx* ctx, const int* in) {
     ctx->tune_mixed = -1;
     return MFD_OK;
 }
+
+int mfd_max_block(void) { return MAX_BLOCK; }
 
 int mfd_supported_n(int N) {
     return (N >= 4 && N <= 128 && fft_supported(N, 4)) ? 1 : 0;

@@ -248,7 +248,7 @@ static hipError_t gram_t(const void* V, const void* V32, size_t ld, size_t n, co
 }
 
 hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nparts,
-                            void* part, void* G, hipStream_t s) {
+                            void* part, void* G, hipStream_t s, int stages) {
     const int K = bm.K;
     if (K < 1 || K > 64) return hipErrorInvalidValue;
     const int T = (K + 15) / 16;
@@ -257,14 +257,16 @@ hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n,
     GramTiles tl = make_tiles(K);
     const size_t rows_per = ((n + nparts - 1) / nparts + GM_KS - 1) / GM_KS * GM_KS;
     const int nw = (int)((n + rows_per - 1) / rows_per);
-    hipError_t e;
-    switch (T) {
-        case 1: e = gram_t<1>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
-        case 2: e = gram_t<2>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
-        case 3: e = gram_t<3>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
-        default: e = gram_t<4>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+    hipError_t e = hipSuccess;
+    if (stages & 1) {
+        switch (T) {
+            case 1: e = gram_t<1>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+            case 2: e = gram_t<2>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+            case 3: e = gram_t<3>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+            default: e = gram_t<4>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+        }
     }
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !(stages & 2)) return e;
     // sum the nw partial tile sets (into the slot after the last), then scatter
     double2* sum = (double2*)part + (size_t)nw * tl.n * 256;
     if ((e = launch_reduce((const double*)part, nw, tl.n * 256 * 2, (double*)sum, s)) != hipSuccess) return e;
@@ -720,7 +722,7 @@ static hipError_t update_wave(const void* V, const void* V32, void* U, void* U32
 
 hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
                               const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
-                              double* norms, hipStream_t s, int rows) {
+                              double* norms, hipStream_t s, int rows, bool sum) {
     const int mb = bm.mb;
     const int nk0 = (bm.K - mb + 3) / 4;   // k-steps over the W and P columns
     hipError_t e;
@@ -743,7 +745,7 @@ hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32
         e = rows == 16 ? UPB(2, 16) : UPB(2, 32);
 #undef UPW
 #undef UPB
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !sum) return e;
     return launch_reduce(npart, nparts, 2 * mb, norms, s);
 }
 

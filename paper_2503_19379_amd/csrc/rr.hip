@@ -2,159 +2,174 @@
 //
 // Section 5.1 takes the eigenpairs from LOBPCG, which minimises the Rayleigh
 // quotient over span[X, W, P] at every step.  Given the Gram matrices
-// Gs = S^H S and Ga = S^H A S of the basis S = [X, W, P] (3 mb columns) this
-// kernel returns coefficients C with S C = the mb lowest Ritz vectors:
-//   1. keep X and the columns of W and P that belong to unconverged bands
-//      (residual above tol: "soft locking"); the kept columns form a
-//      compact Kk x Kk problem, each column scaled to unit norm
+// Gs = S^H S and Ga = S^H A S of the basis S = [X, W, P] this kernel returns
+// coefficients C with S C = the mb lowest Ritz vectors, and their Ritz values:
+//   0. keep the nonzero columns (soft locking has already left converged
+//      bands' W and P out of the basis), scale each to unit norm
 //      (d = diag(Gs)^-1/2);
-//   2. Cholesky factor D Gs D = R^H R column by column; a column whose pivot
+//   1. Cholesky factor D Gs D = R^H R column by column; a column whose pivot
 //      (squared distance to the span of the previous columns) falls below a
-//      threshold is dropped, W and P columns alike; the other P columns keep
-//      their conjugate directions (restarting all of P whenever one column
-//      was nearly dependent could leave P out at every step, which reduces
-//      the iteration to preconditioned steepest descent);
-//   3. Z = R^-1 and H = Z^H (D Ga D) Z, the operator in an orthonormal basis;
-//   4. cyclic Jacobi on the Hermitian H with round-robin pairs: in a round
-//      every index is in one pair, and the two-sided update J^H H J is done
-//      one 2 x 2 block per thread (plus Z <- Z J), two barriers per round;
-//   5. C = D Z[:, lowest mb eigenvalues], scattered back to the 3 mb rows.
-// Dropped columns (and a padding column when Kk is odd) are isolated in H with
-// a huge diagonal entry, so they are never selected.
+//      threshold is dropped, W and P columns alike;
+//   2. Z = R^-1, restricted to the columns kept: Z^H D Gs D Z = I;
+//   3. H = Z^H (D Ga D) Z, the operator in that orthonormal basis;
+//   4. Householder reduction H = Q T Q^H with T real symmetric tridiagonal
+//      (every reflector chosen so that the subdiagonal comes out real);
+//      Z <- Z Q;
+//   5. the mb lowest eigenvalues of T by bisection on Sturm counts, their
+//      eigenvectors by inverse iteration (LU of T - lambda I with partial
+//      pivoting), orthogonalised by modified Gram-Schmidt within clusters of
+//      close eigenvalues; the Ritz values are the Rayleigh quotients of T;
+//   6. C = D Z Y, scattered back to the basis rows.
+// The sequential parts (Cholesky, inverse, reduction, bisection, inverse
+// iteration) run in one wave with no barrier: the wave's lanes own columns
+// (rows) of the small matrices in LDS, and a wave's LDS accesses complete in
+// program order.  The dense products use the whole workgroup.
 #include "common.h"
 #include "solver.h"
 
 namespace mfd {
 
 using C128 = double2;
-constexpr int RR_NT = 512;
+constexpr int RR_NT = 256;
 constexpr int RR_KMAX = 64;
-constexpr double RR_BIG = 1e300;
+constexpr int RR_MBMAX = 21;
 
-struct Rot {
-    double c, s;
-    C128 em;   // e^{-i phi}
-    int p, q;
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// LDS layout (bytes): A [KMAX][LD] c128 | B [KMAX][LD] c128 | vectors
+struct RRShared {
+    int idx[RR_KMAX];          // compact index -> basis column
+    int vl[RR_KMAX];           // valid (kept and not dropped) compact indices
+    double dsc[RR_KMAX];
+    int dropped[RR_KMAX];
+    double d[RR_KMAX], e[RR_KMAX], lam[RR_KMAX];
+    C128 tau[RR_KMAX];
+    C128 vv[RR_KMAX], ww[RR_KMAX];
+    int cl0[RR_KMAX];          // first member of an eigenvalue's cluster
+    int Kk, Kv, dropP;
 };
 
 __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
     extern __shared__ unsigned char smem_raw[];
+    __shared__ RRShared sh;
     const int mb = a.mb;
     const int K = a.K;
-    const int Q = 2 * K;
-    const int pbeg = mb + a.nw;           // first P column of the basis
-    __shared__ int idx[RR_KMAX];        // compact index -> basis column
-    __shared__ double dsc[RR_KMAX];
-    __shared__ int dropped[RR_KMAX];
-    __shared__ double piv_s;
-    __shared__ int dropP, Kk_s, active_s;
-    __shared__ Rot rot[RR_KMAX / 2];
-    __shared__ double redv[2][RR_NT / 64];
-    __shared__ int perm[RR_KMAX];
+    const int Q2 = 2 * K;
+    const int pbeg = mb + a.nw;   // first P column of the basis
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     long long tstamp[6];
     tstamp[0] = wall_clock64();
 
-    // 1. kept columns: the basis holds only the W and P columns of unconverged
-    //    bands (soft locking is done by the caller); zero columns are left out
+    // 0. kept columns and their scaling
     if (tid == 0) {
         int kk = 0;
         for (int j = 0; j < K; ++j)
-            if (a.G[j * Q + j].x > 0.0) idx[kk++] = j;
-        Kk_s = kk;
-        active_s = a.nw;
-        dropP = 0;
+            if (a.G[j * Q2 + j].x > 0.0) sh.idx[kk++] = j;
+        sh.Kk = kk;
+        sh.dropP = 0;
     }
     __syncthreads();
-    const int Kk = Kk_s;
-    const int KE = Kk + (Kk & 1);                  // even size for the pairing
-    C128* A = reinterpret_cast<C128*>(smem_raw);   // KE x KE: Gs -> R -> Z
-    C128* B = A + KE * KE;                         // KE x KE: Ga -> T -> H
-    if (tid < KE) {
-        dropped[tid] = (tid >= Kk);
-        dsc[tid] = (tid < Kk) ? 1.0 / sqrt(a.G[idx[tid] * Q + idx[tid]].x) : 0.0;
+    const int Kk = sh.Kk;
+    const int LD = Kk | 1;   // odd row stride: lanes reading a column hit distinct bank groups
+    C128* A = reinterpret_cast<C128*>(smem_raw);   // Kk x LD: Gs -> R -> Z -> Z Q
+    C128* B = A + (size_t)Kk * LD;                  // Kk x LD: Ga -> T1 -> H -> reflectors -> workspace
+    if (tid < Kk) {
+        sh.dropped[tid] = 0;
+        sh.dsc[tid] = 1.0 / sqrt(a.G[sh.idx[tid] * Q2 + sh.idx[tid]].x);
     }
     __syncthreads();
-    for (int e = tid; e < KE * KE; e += RR_NT) {
-        const int i = e / KE, j = e % KE;
-        if (i < Kk && j < Kk) {
-            const int gi = idx[i], gj = idx[j];
-            const double s = dsc[i] * dsc[j];
-            const C128 gs = a.G[gi * Q + gj];
-            const C128 g1 = a.G[gi * Q + K + gj], g2 = a.G[gj * Q + K + gi];
-            A[e] = mk<C128>(gs.x * s, gs.y * s);
-            B[e] = mk<C128>(0.5 * (g1.x + g2.x) * s, 0.5 * (g1.y - g2.y) * s);
-        } else {
-            A[e] = mk<C128>(i == j ? 1.0 : 0.0, 0.0);
-            B[e] = mk<C128>(0.0, 0.0);
-        }
+    for (int q = tid; q < Kk * Kk; q += RR_NT) {
+        const int i = q / Kk, j = q % Kk;
+        const int gi = sh.idx[i], gj = sh.idx[j];
+        const double s = sh.dsc[i] * sh.dsc[j];
+        const C128 gs = a.G[gi * Q2 + gj];
+        const C128 g1 = a.G[gi * Q2 + K + gj], g2 = a.G[gj * Q2 + K + gi];
+        A[i * LD + j] = mk<C128>(gs.x * s, gs.y * s);
+        B[i * LD + j] = mk<C128>(0.5 * (g1.x + g2.x) * s, 0.5 * (g1.y - g2.y) * s);
     }
     __syncthreads();
-
     tstamp[1] = wall_clock64();
-    // 2. Cholesky with column dropping (upper factor R in A)
-    for (int j = 0; j < Kk; ++j) {
-        if (tid == 0) {
-            double rjj = 0.0;
-            const bool isP = idx[j] >= pbeg;
-            const double piv = A[j * KE + j].x;
+
+    // 1. Cholesky with column dropping, one wave: lane l owns column l of the
+    //    upper factor (rows 0..l of A)
+    if (wave == 0) {
+        for (int j = 0; j < Kk; ++j) {
+            const double piv = A[j * LD + j].x;
+            const bool isP = sh.idx[j] >= pbeg;
             const double thr = isP ? a.drop_p : a.drop_w;
-            if (!(piv > thr)) {
-                dropped[j] = 1;
-                if (isP) dropP = 1;
-            } else {
-                rjj = sqrt(piv);
+            const bool drop = !(piv > thr);
+            __builtin_amdgcn_wave_barrier();
+            if (drop) {
+                if (lane == 0) {
+                    sh.dropped[j] = 1;
+                    if (isP) sh.dropP = 1;
+                }
+                for (int l = lane; l < Kk; l += 64)
+                    if (l >= j) A[j * LD + l] = mk<C128>(l == j ? 1.0 : 0.0, 0.0);
+                __builtin_amdgcn_wave_barrier();
+                continue;
             }
-            piv_s = rjj;
-        }
-        __syncthreads();
-        const double rjj = piv_s;
-        if (rjj > 0.0) {
-            const double inv = 1.0 / rjj;
-            for (int l = j + 1 + tid; l < Kk; l += RR_NT) A[j * KE + l] = cscale(A[j * KE + l], inv);
-            if (tid == 0) A[j * KE + j] = mk<C128>(rjj, 0.0);
-            __syncthreads();
-            const int m = Kk - j - 1;
-            for (int e = tid; e < m * m; e += RR_NT) {
-                const int i = j + 1 + e / m, l = j + 1 + e % m;
-                if (l >= i) {
-                    const C128 ri = A[j * KE + i], rl = A[j * KE + l];
-                    C128 v = A[i * KE + l];
+            const double rjj = sqrt(piv), inv = 1.0 / rjj;
+            for (int l = lane; l < Kk; l += 64) {
+                if (l > j) A[j * LD + l] = cscale(A[j * LD + l], inv);
+                else if (l == j) A[j * LD + l] = mk<C128>(rjj, 0.0);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // trailing update of the upper triangle: A[i][l] -= conj(R[j][i]) R[j][l], j < i <= l
+            for (int l = lane; l < Kk; l += 64) {
+                if (l <= j) continue;
+                const C128 rl = A[j * LD + l];
+                for (int i = j + 1; i <= l; ++i) {
+                    const C128 ri = A[j * LD + i];
+                    C128 v = A[i * LD + l];
                     v.x -= ri.x * rl.x + ri.y * rl.y;
                     v.y -= ri.x * rl.y - ri.y * rl.x;
-                    A[i * KE + l] = v;
+                    A[i * LD + l] = v;
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
-        __syncthreads();
-    }
-    // isolate dropped columns
-    for (int e = tid; e < KE * KE; e += RR_NT) {
-        const int i = e / KE, l = e % KE;
-        if (l < i) A[e] = mk<C128>(0.0, 0.0);
-        else if (dropped[i] || dropped[l]) A[e] = mk<C128>(i == l ? 1.0 : 0.0, 0.0);
+        // isolate dropped columns: R becomes the identity in their rows and columns
+        for (int l = lane; l < Kk; l += 64)
+            for (int i = 0; i < Kk; ++i)
+                if (i != l && (sh.dropped[i] || sh.dropped[l])) A[i * LD + l] = mk<C128>(0.0, 0.0);
+        __builtin_amdgcn_wave_barrier();
+        // 2. Z = R^-1 in place (upper), column j from the columns before it:
+        //    Z[i][j] = -sum_{i <= l < j} Z[i][l] R[l][j] / R[j][j]; lane i owns row i
+        for (int j = 0; j < Kk; ++j) {
+            const double inv = 1.0 / A[j * LD + j].x;
+            C128 s[2] = {mk<C128>(0.0, 0.0), mk<C128>(0.0, 0.0)};
+            for (int h = 0; h < 2; ++h) {
+                const int i = lane + 64 * h;
+                if (i < j)
+                    for (int l = i; l < j; ++l) s[h] = cfma(s[h], A[i * LD + l], A[l * LD + j]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int h = 0; h < 2; ++h) {
+                const int i = lane + 64 * h;
+                if (i < j) A[i * LD + j] = mk<C128>(-s[h].x * inv, -s[h].y * inv);
+            }
+            if (lane == 0) A[j * LD + j] = mk<C128>(inv, 0.0);
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lane == 0) {
+            int kv = 0;
+            for (int j = 0; j < Kk; ++j)
+                if (!sh.dropped[j]) sh.vl[kv++] = j;
+            sh.Kv = kv;
+        }
     }
     __syncthreads();
-
     tstamp[2] = wall_clock64();
-    // 3a. Z = R^-1 in place, column by column (Z[i][j] = -sum_{i<=l<j} Z[i][l] R[l][j] / R[j][j]);
-    //     8 threads share each dot product
-    for (int j = 0; j < KE; ++j) {
-        const double inv = 1.0 / A[j * KE + j].x;
-        const int i = tid >> 3, g = tid & 7;
-        C128 s = mk<C128>(0.0, 0.0);
-        if (i < j)
-            for (int l = i + g; l < j; l += 8) s = cfma(s, A[i * KE + l], A[l * KE + j]);
-        for (int o = 4; o > 0; o >>= 1) {
-            s.x += __shfl_xor(s.x, o, 8);
-            s.y += __shfl_xor(s.y, o, 8);
-        }
-        __syncthreads();
-        if (i < j && g == 0) A[i * KE + j] = mk<C128>(-s.x * inv, -s.y * inv);
-        if (tid == 0) A[j * KE + j] = mk<C128>(inv, 0.0);
-        __syncthreads();
-    }
-    // 3b. T = Ga Z, then H = Z^H T (register-staged in place in B)
+    const int Kv = sh.Kv;
+
+    // 3. T1 = Bh Zv (Kk x Kv), then Zv = the valid columns of Z packed to the
+    //    left of A, then H = Zv^H T1 (Kv x Kv) into B; Z is upper triangular
     constexpr int PER = (RR_KMAX * RR_KMAX + RR_NT - 1) / RR_NT;
     {
         C128 t[PER];
@@ -162,10 +177,42 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
         for (int q = 0; q < PER; ++q) {
             const int e = tid + q * RR_NT;
             t[q] = mk<C128>(0.0, 0.0);
-            if (e < KE * KE) {
-                const int i = e / KE, j = e % KE;
+            if (e < Kk * Kv) {
+                const int i = e / Kv, b = e % Kv, c = sh.vl[b];
                 C128 s = mk<C128>(0.0, 0.0);
-                for (int l = 0; l <= j; ++l) s = cfma(s, B[i * KE + l], A[l * KE + j]);
+                for (int l = 0; l <= c; ++l) s = cfma(s, B[i * LD + l], A[l * LD + c]);
+                t[q] = s;
+            }
+        }
+        C128 z[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * RR_NT;
+            z[q] = mk<C128>(0.0, 0.0);
+            if (e < Kk * Kv) {
+                const int i = e / Kv, b = e % Kv, c = sh.vl[b];
+                if (i <= c) z[q] = A[i * LD + c];   // Z is upper triangular (A keeps Gs below)
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * RR_NT;
+            if (e < Kk * Kv) {
+                const int i = e / Kv, b = e % Kv;
+                B[i * LD + b] = t[q];
+                A[i * LD + b] = z[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * RR_NT;
+            t[q] = mk<C128>(0.0, 0.0);
+            if (e < Kv * Kv) {
+                const int i = e / Kv, j = e % Kv;
+                C128 s = mk<C128>(0.0, 0.0);
+                for (int l = 0; l < Kk; ++l) s = cfmac(s, A[l * LD + i], B[l * LD + j]);
                 t[q] = s;
             }
         }
@@ -173,42 +220,16 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + q * RR_NT;
-            if (e < KE * KE) B[e] = t[q];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * RR_NT;
-            if (e < KE * KE) {
-                const int i = e / KE, j = e % KE;
-                C128 s = mk<C128>(0.0, 0.0);
-                for (int l = 0; l <= i; ++l) s = cfmac(s, A[l * KE + i], B[l * KE + j]);
-                t[q] = s;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * RR_NT;
-            if (e < KE * KE) {
-                const int i = e / KE, j = e % KE;
-                if (dropped[i] || dropped[j]) t[q] = mk<C128>(i == j ? RR_BIG : 0.0, 0.0);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * RR_NT;
-            if (e < KE * KE) B[e] = t[q];
+            if (e < Kv * Kv) B[(e / Kv) * LD + e % Kv] = t[q];
         }
         __syncthreads();
         // Hermitian part
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + q * RR_NT;
-            if (e < KE * KE) {
-                const int i = e / KE, j = e % KE;
-                const C128 u = B[e], v = B[j * KE + i];
+            if (e < Kv * Kv) {
+                const int i = e / Kv, j = e % Kv;
+                const C128 u = B[i * LD + j], v = B[j * LD + i];
                 t[q] = (i == j) ? mk<C128>(u.x, 0.0) : mk<C128>(0.5 * (u.x + v.x), 0.5 * (u.y - v.y));
             }
         }
@@ -216,136 +237,313 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + q * RR_NT;
-            if (e < KE * KE) B[e] = t[q];
+            if (e < Kv * Kv) B[(e / Kv) * LD + e % Kv] = t[q];
         }
         __syncthreads();
     }
-
     tstamp[3] = wall_clock64();
-    // 4. cyclic Jacobi, round-robin pairs, one-phase two-sided rounds
-    const int npairs = KE / 2;
-    int sweep = 0;
-    for (; sweep < 30; ++sweep) {
-        double off = 0.0, dn = 0.0;
-        for (int e = tid; e < KE * KE; e += RR_NT) {
-            const int i = e / KE, j = e % KE;
-            if (dropped[i] || dropped[j]) continue;
-            const C128 v = B[e];
-            if (i == j) dn += v.x * v.x;
-            else off += cabs2(v);
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            off += __shfl_down(off, o);
-            dn += __shfl_down(dn, o);
-        }
-        if ((tid & 63) == 0) { redv[0][tid >> 6] = off; redv[1][tid >> 6] = dn; }
-        __syncthreads();
-        off = 0.0; dn = 0.0;
-        for (int w = 0; w < RR_NT / 64; ++w) { off += redv[0][w]; dn += redv[1][w]; }
-        __syncthreads();
-        // off-diagonal at 1e-12 of the diagonal: the Ritz values are then
-        // exact to about 1e-24 relative and the vectors to 1e-12 over the
-        // relative gap, far inside the 1e-8 residuals the solve works to
-        if (off <= 1e-24 * dn || KE <= 1) break;
-        for (int r = 0; r < KE - 1; ++r) {
-            if (tid < npairs) {
-                const int i = tid;
-                int p, q;
-                if (i == 0) { p = KE - 1; q = r; }
-                else { p = (r + i) % (KE - 1); q = (r - i + (KE - 1)) % (KE - 1); }
-                if (p > q) { const int t = p; p = q; q = t; }
-                Rot ro;
-                ro.p = p; ro.q = q; ro.c = 1.0; ro.s = 0.0; ro.em = mk<C128>(1.0, 0.0);
-                if (!dropped[p] && !dropped[q]) {
-                    const C128 b = B[p * KE + q];
-                    const double beta = sqrt(cabs2(b));
-                    const double ap = B[p * KE + p].x, dq = B[q * KE + q].x;
-                    if (beta > 1e-300 && beta > 1e-18 * sqrt(fabs(ap * dq))) {
-                        const double tau = (dq - ap) / (2.0 * beta);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        ro.c = 1.0 / sqrt(1.0 + t * t);
-                        ro.s = t * ro.c;
-                        ro.em = mk<C128>(b.x / beta, -b.y / beta);
+
+    // 4. Householder reduction to real tridiagonal, one wave.  Step j takes
+    //    x = H[j+1:, j] and the reflector I - tau v v^H (v[0] = 1) with
+    //    (I - tau v v^H)^H x = beta e_1, beta real; then
+    //    H22 <- H22 - v w^H - w v^H with p = tau H22 v, w = p - (tau/2)(p^H v) v.
+    //    Lane i owns column i of the trailing block (B[l][i] over l); v is kept
+    //    in B[l][j], l > j.
+    if (wave == 0) {
+        for (int j = 0; j + 1 < Kv; ++j) {
+            double xn2 = 0.0;
+            for (int l = lane; l < Kv; l += 64)
+                if (l >= j + 2) xn2 += cabs2(B[l * LD + j]);
+            xn2 = wave_sum(xn2);
+            const C128 alpha = B[(j + 1) * LD + j];
+            double beta;
+            C128 t, den;
+            if (xn2 == 0.0 && alpha.y == 0.0) {
+                t = mk<C128>(0.0, 0.0);
+                beta = alpha.x;
+                den = mk<C128>(1.0, 0.0);
+            } else {
+                const double nrm = sqrt(cabs2(alpha) + xn2);
+                beta = alpha.x >= 0.0 ? -nrm : nrm;
+                t = mk<C128>((beta - alpha.x) / beta, -alpha.y / beta);
+                den = mk<C128>(alpha.x - beta, alpha.y);   // v = x / (alpha - beta)
+            }
+            const double dd = cabs2(den);
+            const C128 rden = mk<C128>(den.x / dd, -den.y / dd);
+            __builtin_amdgcn_wave_barrier();
+            for (int l = lane; l < Kv; l += 64) {
+                if (l < j + 1) continue;
+                const C128 v = (l == j + 1) ? mk<C128>(1.0, 0.0) : cmul(B[l * LD + j], rden);
+                B[l * LD + j] = v;
+                sh.vv[l] = v;
+            }
+            if (lane == 0) {
+                sh.tau[j] = t;
+                sh.e[j] = beta;
+                sh.d[j] = B[j * LD + j].x;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (t.x != 0.0 || t.y != 0.0) {
+                // p_i = tau sum_l H[i][l] v_l = tau sum_l conj(H[l][i]) v_l
+                C128 p[2] = {mk<C128>(0.0, 0.0), mk<C128>(0.0, 0.0)};
+                double hr = 0.0, hi = 0.0;   // p^H v
+                for (int h = 0; h < 2; ++h) {
+                    const int i = lane + 64 * h;
+                    if (i < j + 1 || i >= Kv) continue;
+                    C128 s = mk<C128>(0.0, 0.0);
+                    for (int l = j + 1; l < Kv; ++l) s = cfmac(s, B[l * LD + i], sh.vv[l]);
+                    p[h] = cmul(t, s);
+                    const C128 vi = sh.vv[i];
+                    hr += p[h].x * vi.x + p[h].y * vi.y;
+                    hi += p[h].x * vi.y - p[h].y * vi.x;
+                }
+                hr = wave_sum(hr);
+                hi = wave_sum(hi);
+                // alpha2 = -(tau / 2) (p^H v)
+                const C128 al = mk<C128>(-0.5 * (t.x * hr - t.y * hi), -0.5 * (t.x * hi + t.y * hr));
+                for (int h = 0; h < 2; ++h) {
+                    const int i = lane + 64 * h;
+                    if (i < j + 1 || i >= Kv) continue;
+                    sh.ww[i] = cfma(p[h], al, sh.vv[i]);
+                }
+                __builtin_amdgcn_wave_barrier();
+                for (int h = 0; h < 2; ++h) {
+                    const int i = lane + 64 * h;
+                    if (i < j + 1 || i >= Kv) continue;
+                    const C128 wi = sh.ww[i], vi = sh.vv[i];
+                    for (int l = j + 1; l < Kv; ++l) {
+                        const C128 vl = sh.vv[l], wl = sh.ww[l];
+                        C128 x = B[l * LD + i];
+                        // x -= v_l conj(w_i) + w_l conj(v_i)
+                        x.x -= vl.x * wi.x + vl.y * wi.y + wl.x * vi.x + wl.y * vi.y;
+                        x.y -= vl.y * wi.x - vl.x * wi.y + wl.y * vi.x - wl.x * vi.y;
+                        B[l * LD + i] = x;
                     }
                 }
-                rot[i] = ro;
+                __builtin_amdgcn_wave_barrier();
             }
-            __syncthreads();
-            // (a) 2 x 2 blocks of H: rows of pair u, columns of pair v: J_u^H H J_v
-            // (b) rows of Z: columns of pair v: Z J_v
-            const int nh = npairs * npairs;
-            for (int e = tid; e < nh + npairs * KE; e += RR_NT) {
-                if (e < nh) {
-                    const Rot ru = rot[e / npairs], rv = rot[e % npairs];
-                    if (ru.s == 0.0 && rv.s == 0.0) continue;
-                    const C128 hpp = B[ru.p * KE + rv.p], hpq = B[ru.p * KE + rv.q];
-                    const C128 hqp = B[ru.q * KE + rv.p], hqq = B[ru.q * KE + rv.q];
-                    // M = J_u^H H: row p = c h_p - s e^{i phi} h_q, row q = s h_p + c e^{i phi} h_q
-                    const C128 eu = mk<C128>(ru.em.x, -ru.em.y);
-                    const C128 tq0 = cmul(eu, hqp), tq1 = cmul(eu, hqq);
-                    const C128 m00 = mk<C128>(ru.c * hpp.x - ru.s * tq0.x, ru.c * hpp.y - ru.s * tq0.y);
-                    const C128 m01 = mk<C128>(ru.c * hpq.x - ru.s * tq1.x, ru.c * hpq.y - ru.s * tq1.y);
-                    const C128 m10 = mk<C128>(ru.s * hpp.x + ru.c * tq0.x, ru.s * hpp.y + ru.c * tq0.y);
-                    const C128 m11 = mk<C128>(ru.s * hpq.x + ru.c * tq1.x, ru.s * hpq.y + ru.c * tq1.y);
-                    // N = M J_v: col p = c m_p - s e^{-i phi} m_q, col q = s m_p + c e^{-i phi} m_q
-                    const C128 u0 = cmul(rv.em, m01), u1 = cmul(rv.em, m11);
-                    C128 n00 = mk<C128>(rv.c * m00.x - rv.s * u0.x, rv.c * m00.y - rv.s * u0.y);
-                    C128 n01 = mk<C128>(rv.s * m00.x + rv.c * u0.x, rv.s * m00.y + rv.c * u0.y);
-                    C128 n10 = mk<C128>(rv.c * m10.x - rv.s * u1.x, rv.c * m10.y - rv.s * u1.y);
-                    C128 n11 = mk<C128>(rv.s * m10.x + rv.c * u1.x, rv.s * m10.y + rv.c * u1.y);
-                    if (ru.p == rv.p) {   // the block of the pair itself: diagonal after the rotation
-                        n01 = mk<C128>(0.0, 0.0);
-                        n10 = mk<C128>(0.0, 0.0);
-                        n00.y = 0.0;
-                        n11.y = 0.0;
-                    }
-                    B[ru.p * KE + rv.p] = n00;
-                    B[ru.p * KE + rv.q] = n01;
-                    B[ru.q * KE + rv.p] = n10;
-                    B[ru.q * KE + rv.q] = n11;
-                } else {
-                    // consecutive threads take consecutive pairs of one row (unit-stride LDS)
-                    const int f = e - nh;
-                    const Rot rv = rot[f % npairs];
-                    if (rv.s == 0.0) continue;
-                    const int row = f / npairs;
-                    const C128 zp = A[row * KE + rv.p], zq = A[row * KE + rv.q];
-                    const C128 t = cmul(rv.em, zq);
-                    A[row * KE + rv.p] = mk<C128>(rv.c * zp.x - rv.s * t.x, rv.c * zp.y - rv.s * t.y);
-                    A[row * KE + rv.q] = mk<C128>(rv.s * zp.x + rv.c * t.x, rv.s * zp.y + rv.c * t.y);
-                }
-            }
-            __syncthreads();
+        }
+        if (lane == 0 && Kv > 0) {
+            sh.d[Kv - 1] = B[(Kv - 1) * LD + Kv - 1].x;
+            sh.e[Kv - 1] = 0.0;
         }
     }
+    __syncthreads();
+
+    // Z <- Z Q = Z H_0 H_1 ... H_{Kv-2}: (Z H)[r][l] = Z[r][l] - tau (Z v)_r conj(v_l).
+    // Every wave takes 16 rows of Z, 4 lanes per row splitting l; no barrier.
+    {
+        const int r = wave * 16 + (lane >> 2), sub = lane & 3;
+        const int nrow = Kk;
+        for (int j = 0; j + 1 < Kv; ++j) {
+            const C128 t = sh.tau[j];
+            if (t.x == 0.0 && t.y == 0.0) continue;
+            for (int rr = r; rr < nrow; rr += 64) {
+                C128 s = mk<C128>(0.0, 0.0);
+                for (int l = j + 1 + sub; l < Kv; l += 4) s = cfma(s, A[rr * LD + l], B[l * LD + j]);
+                s.x += __shfl_xor(s.x, 1);
+                s.y += __shfl_xor(s.y, 1);
+                s.x += __shfl_xor(s.x, 2);
+                s.y += __shfl_xor(s.y, 2);
+                const C128 ts = cmul(t, s);
+                for (int l = j + 1 + sub; l < Kv; l += 4) {
+                    const C128 v = B[l * LD + j];
+                    C128 z = A[rr * LD + l];
+                    // z -= ts conj(v)
+                    z.x -= ts.x * v.x + ts.y * v.y;
+                    z.y -= ts.y * v.x - ts.x * v.y;
+                    A[rr * LD + l] = z;
+                }
+            }
+        }
+    }
+    __syncthreads();
     tstamp[4] = wall_clock64();
-    // 5. order the eigenvalues, emit coefficients of the lowest mb
-    if (tid < KE) {
-        const double ti = B[tid * KE + tid].x;
-        int rank = 0;
-        for (int j = 0; j < KE; ++j) {
-            const double tj = B[j * KE + j].x;
-            rank += (tj < ti) || (tj == ti && j < tid);
+
+    // 5. lowest nsel eigenpairs of T (d, e; Kv x Kv), one wave; B is free now:
+    //    per-lane LU workspace and the eigenvectors Y (Kv x nsel, real)
+    const int nsel = min(mb, Kv);
+    double* Y = reinterpret_cast<double*>(B);                 // [Kv][nsel]
+    double* U0 = Y + (size_t)RR_KMAX * RR_MBMAX;               // [Kv][nsel] each
+    double* U1 = U0 + (size_t)RR_KMAX * RR_MBMAX;
+    double* U2 = U1 + (size_t)RR_KMAX * RR_MBMAX;
+    double* ML = U2 + (size_t)RR_KMAX * RR_MBMAX;
+    unsigned char* SW = reinterpret_cast<unsigned char*>(ML + (size_t)RR_KMAX * RR_MBMAX);
+    if (wave == 0) {
+        const int n = Kv;
+        // Gershgorin interval and the pivot floor of the Sturm counts
+        double lo = 1e300, hi = -1e300;
+        for (int i = 0; i < n; ++i) {
+            const double r = (i ? fabs(sh.e[i - 1]) : 0.0) + (i + 1 < n ? fabs(sh.e[i]) : 0.0);
+            lo = fmin(lo, sh.d[i] - r);
+            hi = fmax(hi, sh.d[i] + r);
         }
-        perm[rank] = tid;
+        const double tn = fmax(fabs(lo), fabs(hi));
+        const double eps = 2.220446049250313e-16;
+        const double pivmin = fmax(2.2250738585072014e-308, eps * eps * tn * 1e-8);
+        lo -= 4.0 * eps * tn * n + pivmin;
+        hi += 4.0 * eps * tn * n + pivmin;
+        // bisection: lane r finds the (r+1)-th smallest eigenvalue
+        if (lane < nsel) {
+            const int r = lane;
+            double x0 = lo, x1 = hi;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (x0 + x1);
+                if (!(x1 - x0 > 2.0 * eps * fmax(fabs(x0), fabs(x1)) + pivmin) || mid <= x0 || mid >= x1) break;
+                int cnt = 0;
+                double q = sh.d[0] - mid;
+                if (fabs(q) < pivmin) q = -pivmin;
+                cnt += q < 0.0;
+                for (int i = 1; i < n; ++i) {
+                    const double ei = sh.e[i - 1];
+                    q = (sh.d[i] - mid) - ei * ei / q;
+                    if (fabs(q) < pivmin) q = -pivmin;
+                    cnt += q < 0.0;
+                }
+                if (cnt > r) x1 = mid;
+                else x0 = mid;
+            }
+            sh.lam[r] = 0.5 * (x0 + x1);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // clusters: consecutive eigenvalues closer than 1e-3 |T|
+        const double ortol = 1e-3 * tn;
+        if (lane < nsel) {
+            int c0 = lane;
+            while (c0 > 0 && sh.lam[c0] - sh.lam[c0 - 1] <= ortol) --c0;
+            sh.cl0[lane] = c0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // inverse iteration: (T - lambda_r I) y = b, LU with partial pivoting
+        // (lane r), then modified Gram-Schmidt within the cluster (whole wave)
+        const double tiny = eps * tn + pivmin;
+        for (int it = 0; it < 3; ++it) {
+            if (lane < nsel) {
+                const int r = lane;
+                const double lr = sh.lam[r];
+                auto at = [&](double* M, int i) -> double& { return M[(size_t)i * nsel + r]; };
+                // right-hand side: a fixed pseudo-random start, then the previous iterate
+                double bmax = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    double b;
+                    if (it == 0) {
+                        unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)(r * 40503u + 12345u);
+                        h ^= h >> 15; h *= 2246822519u; h ^= h >> 13;
+                        b = ((double)(h & 0xffff) + 1.0) / 65536.0 - 0.5;
+                    } else {
+                        b = at(Y, i);
+                    }
+                    at(Y, i) = b;
+                    bmax = fmax(bmax, fabs(b));
+                }
+                const double bs = bmax > 0.0 ? 1.0 / bmax : 1.0;
+                double p0 = sh.d[0] - lr, p1 = n > 1 ? sh.e[0] : 0.0, p2 = 0.0;
+                double bk = at(Y, 0) * bs;
+                for (int k = 0; k + 1 < n; ++k) {
+                    const double q0 = sh.e[k], q1 = sh.d[k + 1] - lr, q2 = k + 2 < n ? sh.e[k + 1] : 0.0;
+                    double bn = at(Y, k + 1) * bs;
+                    double m;
+                    if (fabs(q0) > fabs(p0)) {
+                        at(U0, k) = q0;
+                        at(U1, k) = q1;
+                        at(U2, k) = q2;
+                        SW[(size_t)k * nsel + r] = 1;
+                        m = p0 / q0;
+                        const double np0 = p1 - m * q1, np1 = p2 - m * q2;
+                        p0 = np0; p1 = np1; p2 = 0.0;
+                        const double tb = bk; bk = bn; bn = tb;
+                    } else {
+                        if (p0 == 0.0) p0 = tiny;
+                        at(U0, k) = p0;
+                        at(U1, k) = p1;
+                        at(U2, k) = p2;
+                        SW[(size_t)k * nsel + r] = 0;
+                        m = q0 / p0;
+                        const double np0 = q1 - m * p1, np1 = q2 - m * p2;
+                        p0 = np0; p1 = np1; p2 = 0.0;
+                    }
+                    at(ML, k) = m;
+                    at(Y, k) = bk;          // the eliminated right-hand side
+                    bk = bn - m * bk;
+                }
+                if (p0 == 0.0) p0 = tiny;
+                at(U0, n - 1) = p0;
+                at(Y, n - 1) = bk;
+                // back substitution
+                double y1 = 0.0, y2 = 0.0, ymax = 0.0;
+                for (int k = n - 1; k >= 0; --k) {
+                    double s = at(Y, k);
+                    if (k + 1 < n) s -= at(U1, k) * y1;
+                    if (k + 2 < n) s -= at(U2, k) * y2;
+                    double u = at(U0, k);
+                    if (fabs(u) < tiny) u = u < 0.0 ? -tiny : tiny;
+                    const double y = s / u;
+                    at(Y, k) = y;
+                    y2 = y1;
+                    y1 = y;
+                    ymax = fmax(ymax, fabs(y));
+                }
+                const double ys = ymax > 0.0 && ymax < 1e300 ? 1.0 / ymax : 1.0;
+                for (int k = 0; k < n; ++k) at(Y, k) *= ys;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // modified Gram-Schmidt within clusters, then unit length
+            for (int r = 0; r < nsel; ++r) {
+                const int c0 = sh.cl0[r];
+                for (int s2 = c0; s2 < r; ++s2) {
+                    double dt = 0.0;
+                    for (int i = lane; i < n; i += 64) dt += Y[(size_t)i * nsel + s2] * Y[(size_t)i * nsel + r];
+                    dt = wave_sum(dt);
+                    for (int i = lane; i < n; i += 64) Y[(size_t)i * nsel + r] -= dt * Y[(size_t)i * nsel + s2];
+                    __builtin_amdgcn_wave_barrier();
+                }
+                double nn = 0.0;
+                for (int i = lane; i < n; i += 64) nn += Y[(size_t)i * nsel + r] * Y[(size_t)i * nsel + r];
+                nn = wave_sum(nn);
+                const double sc = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+                for (int i = lane; i < n; i += 64) Y[(size_t)i * nsel + r] *= sc;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        // Ritz values: Rayleigh quotients y^T T y
+        if (lane < nsel) {
+            const int r = lane;
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double yi = Y[(size_t)i * nsel + r];
+                s += sh.d[i] * yi * yi;
+                if (i + 1 < n) s += 2.0 * sh.e[i] * yi * Y[(size_t)(i + 1) * nsel + r];
+            }
+            sh.lam[r] = s;
+        }
     }
     __syncthreads();
-    for (int e = tid; e < K * mb; e += RR_NT) a.C[e] = mk<C128>(0.0, 0.0);
+
+    // 6. C = D Zv Y (rows idx[j]); columns beyond the kept rank keep their X
+    //    column (theta = its Rayleigh quotient) so that X never loses a column
+    for (int q = tid; q < K * mb; q += RR_NT) a.C[q] = mk<C128>(0.0, 0.0);
     __syncthreads();
-    for (int e = tid; e < Kk * mb; e += RR_NT) {
-        const int j = e / mb, r = e % mb;
-        const int c = perm[r];
-        const C128 z = A[j * KE + c];
-        a.C[idx[j] * mb + r] = mk<C128>(dsc[j] * z.x, dsc[j] * z.y);
+    for (int q = tid; q < Kk * nsel; q += RR_NT) {
+        const int j = q / nsel, r = q % nsel;
+        C128 s = mk<C128>(0.0, 0.0);
+        for (int b = 0; b < Kv; ++b) {
+            const double y = Y[(size_t)b * nsel + r];
+            const C128 z = A[j * LD + b];
+            s.x += z.x * y;
+            s.y += z.y * y;
+        }
+        a.C[sh.idx[j] * mb + r] = mk<C128>(sh.dsc[j] * s.x, sh.dsc[j] * s.y);
     }
-    if (tid < mb) a.theta[tid] = B[perm[tid] * KE + perm[tid]].x;
+    if (tid < nsel) a.theta[tid] = sh.lam[tid];
+    for (int r = nsel + tid; r < mb; r += RR_NT) {
+        a.C[r * mb + r] = mk<C128>(1.0, 0.0);
+        a.theta[r] = a.G[r * Q2 + K + r].x / a.G[r * Q2 + r].x;
+    }
     if (tid == 0) {
-        int nk = 0;
-        for (int j = 0; j < Kk; ++j) nk += !dropped[j];
-        a.info[0] = nk;
-        a.info[1] = dropP;
-        a.info[2] = active_s;
-        a.info[3] = sweep;
+        a.info[0] = Kv;
+        a.info[1] = sh.dropP;
+        a.info[2] = a.nw;
+        a.info[3] = 0;
         tstamp[5] = wall_clock64();
         for (int q = 0; q < 5; ++q) a.info[4 + q] = (int)(tstamp[q + 1] - tstamp[q]);   // phase ticks
         a.info[9] = Kk;
@@ -354,9 +552,12 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
 
 hipError_t launch_rr(const RRArgs& a, hipStream_t s) {
     const int K = a.K;
-    if (K > RR_KMAX || K < a.mb || a.nw < 0 || a.mb + a.nw > K) return hipErrorInvalidValue;
-    const int KE = K + (K & 1);
-    const size_t lds = (size_t)2 * KE * KE * sizeof(C128);
+    if (K > RR_KMAX || K < a.mb || a.mb > RR_MBMAX || a.nw < 0 || a.mb + a.nw > K) return hipErrorInvalidValue;
+    const int LD = K | 1;
+    const size_t mats = (size_t)2 * K * LD * sizeof(C128);
+    // the eigenvector workspace (Y, the LU factors, multipliers and swaps) reuses B
+    const size_t work = (size_t)5 * RR_KMAX * RR_MBMAX * sizeof(double) + (size_t)RR_KMAX * RR_MBMAX;
+    const size_t lds = std::max(mats, (size_t)K * LD * sizeof(C128) + work);
     hipError_t e = hipFuncSetAttribute((const void*)rr_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rr_kernel, dim3(1), dim3(RR_NT), lds, s, a);

@@ -27,8 +27,10 @@ struct BasisMap {
 // MFMA (FP64 matrix core) versions: Gram of the K basis columns against
 // [S | AS] (Hermitian halves only), and the block update (gemm.hip).
 // V32 (or null): FP32 storage of the W, P, AW, AP columns (mixed precision).
+// stages: 1 the tile kernel (per-workgroup partial tiles), 2 their fixed-order
+// sum and the Hermitian scatter into G, 3 both.
 hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nparts,
-                            void* part, void* G, hipStream_t s);
+                            void* part, void* G, hipStream_t s, int stages = 3);
 int gram_mfma_parts(size_t n);
 size_t gram_mfma_part_elems(int K, int nparts);
 // U = [X' | R' | P' | AX' | - | AP'] from the K x mb coefficients C, every
@@ -36,7 +38,7 @@ size_t gram_mfma_part_elems(int K, int nparts);
 // rows: 0 one wave per 16-row strip; 16 or 32 rows per workgroup block.
 hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32, size_t ld, size_t n,
                               const BasisMap& bm, const void* C, const double* theta, int nparts, double* npart,
-                              double* norms, hipStream_t s, int rows = 0);
+                              double* norms, hipStream_t s, int rows = 0, bool sum = true);
 // R = AX - X theta written to W (FP32 if R32), column norms |R|^2, |X|^2 (blas.hip).
 hipError_t launch_residual(const void* X, const void* AX, void* R, bool r32, size_t ld, size_t n, int mb,
                            const double* theta, int nparts, double* npart, double* norms, hipStream_t s);

@@ -38,6 +38,7 @@ def test_host_only_calls():
     assert not b.mfd_supported_n(7) and not b.mfd_supported_n(2)
     o = b.default_opts()
     assert o.max_iter > 0 and o.max_gamma_doublings == 4
+    assert b.max_block() >= 21
     # argument validation happens before any device work
     h = ctypes.c_void_p()
     assert L.mfd_build(8, 1.0, 2, None, None, ctypes.byref(h)) == -1
