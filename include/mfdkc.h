@@ -97,6 +97,13 @@ typedef struct {
     int autotune;             /* 1 (default): on the first call for a context and block shape, time
                                  candidate launch shapes of the Gram, update, stencil and FFT kernels
                                  and keep the fastest (see mfd_tuning); 0: built-in shapes */
+    int precond;              /* preconditioner solve: 0 (default) the FFT solve of Alg 5.1
+                                 (mfd_precond_solve); 1 the multigrid solve of Section 5.3
+                                 (mfd_precond_solve_mg: cubic contexts of order 2 whose grid
+                                 mfd_mg_supported accepts; MFD_EUNSUPPORTED otherwise) */
+    int mg_cycles;            /* precond 1: V-cycles per scalar solve (default 2) */
+    int mg_smooth;            /* precond 1: pre- and post-smoothing steps per level (default 2) */
+    int mg_sweeps;            /* precond 1: Jacobi sweeps per ILU factor in a smoothing step (default 2) */
 } mfd_opts;
 
 typedef struct {
@@ -215,6 +222,30 @@ int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void*
  * (MFD_EUNSUPPORTED above), MFD_C64 every N that mfd_supported_n accepts. */
 int mfd_precond_solve(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* R, void* T,
                       void* stream);
+
+/* The same system as mfd_precond_solve, (P + c(k) I) T = R, solved by
+ * multigrid (Section 5.3, Alg 5.2).  The distributive form of Section 5.3 is
+ * used: with L_k = B B' the cell Laplacian of Cor 4.4 (A A' + B'B =
+ * diag(L_k, L_k, L_k), B A = 0), the exact solution is y = (L_k + c)^-1 R per
+ * component, q = -(gamma L_k + c)^-1 (gamma - 1) B y, T = y + B' q; each scalar
+ * solve is replaced by `cycles` V-cycles from a zero guess on the grids N,
+ * N/2, ... (rediscretised, halving while N is even and above 4; exact solve on
+ * the coarsest grid), with `smooth` pre- and post-smoothing steps of the
+ * ILU(0) smoother whose triangular factors are inverted approximately by
+ * `sweeps` Jacobi sweeps (ILU-SAIT), cell-centred full-weighting restriction
+ * and trilinear prolongation.  cycles >= 1, smooth >= 0, sweeps >= 0.
+ * R, T: device [nb][3][N][N][N] of `dtype` (MFD_C64 or MFD_C128; arithmetic is
+ * FP64 either way); T may be R.  Work space (about 7 x 3 nb FP64 grids) is
+ * owned by the context and grows on demand.
+ * MFD_EUNSUPPORTED unless the context is cubic, of order 2, and
+ * mfd_mg_supported(N). */
+int mfd_precond_solve_mg(mfd_ctx* ctx, const double k[3], int nb, int dtype, int cycles, int smooth, int sweeps,
+                         const void* R, void* T, void* stream);
+
+/* 1 if the multigrid hierarchy of grid size N (halving while even and above
+ * 4) ends on a grid of at most 5 cells per axis, e.g. N = 8, 16, 24, 32, 48,
+ * 64, 80, 96; else 0 (e.g. N = 100, 120). */
+int mfd_mg_supported(int N);
 
 /* lambda_re of Alg 4.1: out[i] = |M_0^(1/2) A' x_i|^2 / |x_i|^2 for nb c128
  * fields X (device).  out: host, nb doubles. */

@@ -33,7 +33,9 @@ class mfd_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("precision", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("seed", ctypes.c_ulonglong), ("max_gamma_doublings", ctypes.c_int), ("guard", ctypes.c_int),
                 ("streams", ctypes.c_int), ("x0", ctypes.c_void_p), ("stall_window", ctypes.c_int),
-                ("learn_steps", ctypes.c_int), ("learn_rate", ctypes.c_float), ("autotune", ctypes.c_int)]
+                ("learn_steps", ctypes.c_int), ("learn_rate", ctypes.c_float), ("autotune", ctypes.c_int),
+                ("precond", ctypes.c_int), ("mg_cycles", ctypes.c_int), ("mg_smooth", ctypes.c_int),
+                ("mg_sweeps", ctypes.c_int)]
 
 
 class mfd_kstats(ctypes.Structure):
@@ -62,6 +64,8 @@ def lib():
         L.mfd_gap_ratio.argtypes = [i, i, dp, dp, dp, ctypes.POINTER(i)]
         L.mfd_supported_n.argtypes = [i]
         L.mfd_max_block.argtypes = []
+        L.mfd_precond_solve_mg.argtypes = [vp, dp, i, i, i, i, i, vp, vp, vp]
+        L.mfd_mg_supported.argtypes = [i]
         L.mfd_set_gamma.argtypes = [vp, d]
         L.mfd_gamma_shift.argtypes = [vp, dp, dp, dp]
         L.mfd_op_apply.argtypes = [vp, dp, i, i, vp, vp, vp]
@@ -261,6 +265,20 @@ def mfd_precond_solve(ctx: Context, k, R, T, stream=None):
         raise ValueError("R and T must match in dtype and shape")
     _check(lib().mfd_precond_solve(ctx.handle, kp, int(R.shape[0]), _dtype(R), _dev(R), _dev(T), _stream(stream)))
     return T
+
+
+def mfd_precond_solve_mg(ctx: Context, k, R, T, cycles=2, smooth=2, sweeps=2, stream=None):
+    """T <- multigrid approximation of (P + c I)^-1 R (device tensors; T may be R)."""
+    ka, kp = _k(k)
+    if R.dtype != T.dtype or R.shape != T.shape:
+        raise ValueError("R and T must match in dtype and shape")
+    _check(lib().mfd_precond_solve_mg(ctx.handle, kp, int(R.shape[0]), _dtype(R), int(cycles), int(smooth),
+                                      int(sweeps), _dev(R), _dev(T), _stream(stream)))
+    return T
+
+
+def mfd_mg_supported(N: int) -> bool:
+    return bool(lib().mfd_mg_supported(int(N)))
 
 
 def mfd_lambda_re(ctx: Context, k, X, stream=None):

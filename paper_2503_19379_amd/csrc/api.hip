@@ -128,6 +128,9 @@ struct Ws {
     int stencil_wgs = 2048, fft_xc = 0, upd_rows = 0;   // upd_rows 0: one wave per 16-row strip
     WarmStart* warm = nullptr; // learned warm start (warm_start = 2), allocated on first use
     void* wtmp = nullptr;      // two-pass operator: scratch of this workspace's stream
+    MGWork* mg = nullptr;      // multigrid preconditioner work space (precond 1), on first use
+    int precond = 0;           // 0 FFT solve, 1 multigrid solve
+    MGOpts mgo;
     Prof prof;
 };
 
@@ -151,6 +154,7 @@ struct mfd_ctx {
     void* tw32 = nullptr;
     size_t n = 0;
     std::vector<Ws*> ws;
+    MGWork* mg = nullptr;      // multigrid work space of mfd_precond_solve_mg
     bool prof_on = false;
     Prof prof_done;            // timing of finished solves (summed over workspaces)
 };
@@ -230,6 +234,7 @@ void ws_free(Ws* w) {
     hipFree(w->V32); hipFree(w->U32); hipFree(w->stage32);
     hipFree(w->npart); hipFree(w->norms); hipFree(w->theta); hipFree(w->info);
     hipFree(w->cpart); hipFree(w->cout); hipFree(w->wtmp);
+    mg_destroy(w->mg);
     if (w->host) hipHostFree(w->host);
     if (w->warm) {
         w->warm->release();
@@ -484,8 +489,14 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             fl.on = 1;
             for (int t = 0; t < na; ++t) fl.idx[t] = (unsigned char)act[t];
             hipEvent_t e0 = w.prof.begin(s);
-            if (mixed) HIPCHK(launch_precond<float>(p, na, V32 + n * mb, V32 + n * mb, c->tw32, s, fl));
-            else HIPCHK(precond_fp64(c, p, na, col(V, n, mb), w.mixed ? V32 + n * mb : w.stage32, n, fl, s));
+            if (w.precond == 1) {
+                if (mixed) HIPCHK(launch_precond_mg<float2>(w.mg, p, w.mgo, na, V32 + n * mb, V32 + n * mb, s, fl));
+                else HIPCHK(launch_precond_mg<double2>(w.mg, p, w.mgo, na, col(V, n, mb), col(V, n, mb), s, fl));
+            } else if (mixed) {
+                HIPCHK(launch_precond<float>(p, na, V32 + n * mb, V32 + n * mb, c->tw32, s, fl));
+            } else {
+                HIPCHK(precond_fp64(c, p, na, col(V, n, mb), w.mixed ? V32 + n * mb : w.stage32, n, fl, s));
+            }
             w.prof.end(e0, 1, N3 * 3 * rb * 2.0 * na, s);
             e0 = w.prof.begin(s);
             if (mixed) HIPCHK(launch_stencil_f64_s32(p, na, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s, fl));
@@ -887,6 +898,11 @@ void run_segment(Segment* sg) {
     const size_t n = w.n;
     const int mb = w.mb;
     const mfd_opts& o = sg->opts;
+    w.precond = o.precond;
+    w.mgo.cycles = o.mg_cycles;
+    w.mgo.n1 = w.mgo.n2 = o.mg_smooth;
+    w.mgo.sweeps = o.mg_sweeps;
+    if (o.precond == 1 && !w.mg) w.mg = mg_create();
     const bool learned = o.warm_start == 2;
     if (learned) {
         if (!w.warm) {
@@ -1087,6 +1103,12 @@ int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
     if (mb > MAX_BLOCK) return fail(MFD_EUNSUPPORTED, "nbands + guard exceeds mfd_max_block()");
     if ((size_t)mb > ctx->n) return fail(MFD_EINVAL, "nbands exceeds the problem size");
     if (o.precision != 0 && o.precision != 1) return fail(MFD_EINVAL, "precision must be 0 or 1");
+    if (o.precond != 0 && o.precond != 1) return fail(MFD_EINVAL, "precond must be 0 or 1");
+    if (o.precond == 1) {
+        if (o.mg_cycles < 1 || o.mg_smooth < 0 || o.mg_sweeps < 0) return fail(MFD_EINVAL, "bad multigrid options");
+        if (ctx->order != 2 || ctx->lattice || !mg_supported(ctx->N))
+            return fail(MFD_EUNSUPPORTED, "multigrid needs a cubic order-2 context and a grid mfd_mg_supported accepts");
+    }
     return MFD_OK;
 }
 
@@ -1109,6 +1131,10 @@ void mfd_default_opts(mfd_opts* o) {
     o->learn_steps = 30;
     o->learn_rate = 1e-3f;
     o->autotune = 1;
+    o->precond = 0;
+    o->mg_cycles = 2;
+    o->mg_smooth = 2;
+    o->mg_sweeps = 2;
 }
 
 int mfd_tuning(const mfd_ctx* ctx, int* out) {
@@ -1379,6 +1405,32 @@ int mfd_precond_solve(mfd_ctx* ctx, const double k[3], int nb, int dtype, const 
     return MFD_OK;
 }
 
+int mfd_mg_supported(int N) { return mg_supported(N) ? 1 : 0; }
+
+int mfd_precond_solve_mg(mfd_ctx* ctx, const double k[3], int nb, int dtype, int cycles, int smooth, int sweeps,
+                         const void* R, void* T, void* stream) {
+    int st = check_block(ctx, k, nb, dtype, R, T);
+    if (st) return st;
+    if (cycles < 1 || smooth < 0 || sweeps < 0) return fail(MFD_EINVAL, "bad multigrid options");
+    if (ctx->order != 2 || ctx->lattice || !mg_supported(ctx->N))
+        return fail(MFD_EUNSUPPORTED, "multigrid needs a cubic order-2 context and a grid mfd_mg_supported accepts");
+    if (nb == 0) return MFD_OK;
+    const size_t bytes = ctx->n * nb * (dtype == MFD_C64 ? 8 : 16);
+    const char* r = (const char*)R;
+    const char* t = (const char*)T;
+    if (r != t && r < t + bytes && t < r + bytes) return fail(MFD_EINVAL, "R and T overlap partially");
+    if (!ctx->mg) ctx->mg = mg_create();
+    MGOpts o;
+    o.cycles = cycles;
+    o.n1 = o.n2 = smooth;
+    o.sweeps = sweeps;
+    OpParams p = params(ctx, k);
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == MFD_C128) HIPCHK(launch_precond_mg<double2>(ctx->mg, p, o, nb, R, T, s));
+    else HIPCHK(launch_precond_mg<float2>(ctx->mg, p, o, nb, R, T, s));
+    return MFD_OK;
+}
+
 int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double* out, void* stream) {
     if (!ctx || !k || !X || !out) return fail(MFD_EINVAL, "NULL argument");
     if (nb <= 0) return fail(MFD_EINVAL, "nb must be > 0");
@@ -1545,6 +1597,7 @@ void mfd_destroy(mfd_ctx* ctx) {
     hipFree(ctx->tw64);
     hipFree(ctx->tw32);
     hipFree(ctx->wtmp);
+    mg_destroy(ctx->mg);
     delete ctx;
 }
 

@@ -70,6 +70,21 @@ hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout
                           const FieldList& fl = FieldList());
 bool fft_supported(int N, int real_bytes);
 
+// Multigrid solve of the same system (mg.hip; Section 5.3, Alg 5.2): cubic
+// order-2 contexts whose grid halves down to at most 5^3 cells.
+struct MGOpts {
+    int cycles = 2;   // V-cycles per scalar solve, from a zero guess
+    int n1 = 2, n2 = 2;   // pre- and post-smoothing steps
+    int sweeps = 2;   // Jacobi sweeps per triangular factor in a smoothing step
+};
+struct MGWork;
+MGWork* mg_create();
+void mg_destroy(MGWork* w);
+bool mg_supported(int N);
+template <class S>
+hipError_t launch_precond_mg(MGWork* w, const OpParams& p, const MGOpts& o, int nb, const void* Rin, void* Tout,
+                             hipStream_t s, const FieldList& fl = FieldList());
+
 // out[b] = sum mu |A' x_b|^2 and out[nb + b] = sum |x_b|^2, c128 fields (blas.hip).
 hipError_t launch_lambda_re(const OpParams& p, int nb, const void* X, const void* mu, double* partial,
                             int nparts, double* out, hipStream_t s);
