@@ -104,6 +104,11 @@ typedef struct {
     int mg_cycles;            /* precond 1: V-cycles per scalar solve (default 2) */
     int mg_smooth;            /* precond 1: pre- and post-smoothing steps per level (default 2) */
     int mg_sweeps;            /* precond 1: Jacobi sweeps per ILU factor in a smoothing step (default 2) */
+    int graph;                /* 1: from the third iteration of a k-point on, run the iterations in
+                                 chunks of 2 to 8 replayed from a HIP graph captured once per basis
+                                 shape (two LOBPCG iterations per graph), with the host reading the
+                                 residuals only between chunks; the active set is frozen within a
+                                 chunk.  0 (default): the host steps every iteration */
 } mfd_opts;
 
 typedef struct {
@@ -126,6 +131,7 @@ typedef struct {
                                  (a nearly dependent search direction amplified the rounding of its
                                  Gram entries) is undone, A X recomputed and P restarted; mixed
                                  precision then continues in FP64 (unless stall_window is 0) */
+    int host_syncs;           /* host synchronisations with the solve's stream for this k-point */
 } mfd_kstats;
 
 void mfd_default_opts(mfd_opts* opts);
@@ -260,9 +266,9 @@ int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double
  * concurrently; inside a segment each k-point starts from the previous one's
  * vectors (warm_start = 1).
  * kpts: host nk x 3.  tol: relative residual target (see mfd_kstats).
- * nbands + opts->guard <= 21 (the basis of 3 (nbands + guard) columns is
- * at most 63, the size the one-workgroup Rayleigh-Ritz step holds in LDS);
- * MFD_EUNSUPPORTED otherwise.  20 bands therefore take guard <= 1.
+ * nbands + opts->guard <= mfd_max_block() = 22 (the basis of 3 (nbands +
+ * guard) columns, at most 66, is what the one-workgroup Rayleigh-Ritz step
+ * holds in LDS); MFD_EUNSUPPORTED otherwise.  20 bands take guard <= 2.
  * FP64 iterations on grids above N = 96 apply the preconditioner to an FP32
  * copy of the search directions (the FP64 plane FFT does not fit in LDS). 
  * evals: host nk x nbands, ascending.  evecs: device c128
@@ -352,7 +358,7 @@ int mfd_mlp_adam_step(mfd_mlp* net, float lr, void* stream);
 void mfd_mlp_destroy(mfd_mlp* net);
 
 /* Training target of the warm start from three converged blocks Xa = X_{j-1},
- * Xb = X_j, Xc = X_{j+1} (device c128, each n x mb column-major, mb <= 21):
+ * Xb = X_j, Xc = X_{j+1} (device c128, each n x mb column-major, mb <= 22):
  * C (device c128, 2mb x mb row-major) = Y^H Xc Q with Y = [Xb Xa] R^-1
  * (R^H R the Gram matrix of [Xb Xa]) and Q the unitary polar factor of
  * Xc^H Xb; Rinv (device c128, 2mb x 2mb row-major, or NULL) = R'^-1 for the

@@ -27,7 +27,7 @@ static thread_local std::string g_last_error;
 
 // Largest block (nbands + guard) of a band solve: the basis of 3 blocks must
 // fit the Rayleigh-Ritz step, the Gram and the update kernels.
-constexpr int MAX_BLOCK = 21;
+constexpr int MAX_BLOCK = 22;
 
 static int fail(int status, const std::string& msg) {
     g_last_error = msg;
@@ -131,6 +131,14 @@ struct Ws {
     MGWork* mg = nullptr;      // multigrid preconditioner work space (precond 1), on first use
     int precond = 0;           // 0 FFT solve, 1 multigrid solve
     MGOpts mgo;
+    // graph chunks (opts.graph): two LOBPCG iterations captured once per basis
+    // shape and replayed; the key is the shape the graph was captured for
+    bool graph = false;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int> gkey_act;
+    double gkey[6] = {0, 0, 0, 0, 0, 0};   // k, gamma, shift
+    int gkey_flags = -1;                    // mixed + 2 accurate
+    int syncs = 0;             // host synchronisations of the current k-point
     Prof prof;
 };
 
@@ -235,6 +243,7 @@ void ws_free(Ws* w) {
     hipFree(w->npart); hipFree(w->norms); hipFree(w->theta); hipFree(w->info);
     hipFree(w->cpart); hipFree(w->cout); hipFree(w->wtmp);
     mg_destroy(w->mg);
+    if (w->gexec) hipGraphExecDestroy(w->gexec);
     if (w->host) hipHostFree(w->host);
     if (w->warm) {
         w->warm->release();
@@ -269,7 +278,7 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
                                             gram_mfma_part_elems((int)K, max_gram)) * sizeof(double2))) &&
           chk(hipMalloc(&w->G, K * 2 * K * sizeof(double2))) && chk(hipMalloc(&w->C, K * mb * sizeof(double2))) &&
           chk(hipMalloc(&w->npart, (size_t)w->cap_upd * 2 * mb * sizeof(double))) &&
-          chk(hipMalloc(&w->norms, 2 * mb * sizeof(double))) && chk(hipMalloc(&w->theta, mb * sizeof(double))) &&
+          chk(hipMalloc(&w->norms, 2 * mb * sizeof(double))) && chk(hipMalloc(&w->theta, (mb + 1) * sizeof(double))) &&
           chk(hipMalloc(&w->info, 16 * sizeof(int))) &&
           chk(hipMalloc(&w->cpart, (size_t)std::max(w->nparts_col, 1024) * 2 * mb * sizeof(double))) &&
           chk(hipMalloc(&w->cout, 2 * mb * sizeof(double))) &&
@@ -383,6 +392,12 @@ double ritz_trace(const double2* G, int K, int r, int m) {
     return tr;
 }
 
+// A host synchronisation with the workspace's stream, counted per k-point.
+hipError_t wsync(Ws& w) {
+    ++w.syncs;
+    return hipStreamSynchronize(w.stream);
+}
+
 // The Rayleigh-Ritz basis [X, W(act), P(pact)] as a column map of V.
 BasisMap make_basis(int mb, const std::vector<int>& act, const std::vector<int>& pact, bool mixed) {
     BasisMap bm;
@@ -449,7 +464,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     if (union_start)
         for (int j = 0; j < mb; ++j) act.push_back(j);
     RRArgs ra;
-    ra.G = w.G; ra.theta = w.theta; ra.C = w.C; ra.info = w.info;
+    ra.G = w.G; ra.theta = w.theta; ra.C = w.C; ra.info = w.info; ra.floor = w.theta + mb;
     ra.mb = mb;
     // the Gram of FP32-stored directions is exact for the stored values, but
     // their images AW, AP carry FP32 rounding: drop nearly dependent ones sooner
@@ -457,6 +472,9 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     ra.drop_p = mixed ? 1e-5 : 1e-8;
     double* hth = w.host;
     double* hnorm = w.host + mb;
+    double* hfloor = w.host + 7 * mb + 16;   // the Rayleigh-Ritz step's accuracy estimate
+    *hfloor = 0.0;
+    bool accurate_rr = false;
     static const bool trace = std::getenv("MFD_TRACE") != nullptr;
     const double N3 = (double)c->N * c->N * c->N;
     int it = 0, last_refresh = 0, refreshes = 0, best_it = 0, rejected = 0;
@@ -474,8 +492,106 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         *rmax_out = rmax;
         return conv;
     };
+    // One iteration's kernels on stream s from buffers (Vi, Vi32) into (Ui,
+    // Ui32), for the basis of the active bands `act` with their P columns,
+    // as the eager loop below issues them (no timing events: used under
+    // graph capture).
+    auto issue = [&](double2* Vi, double2* Ui, float2* Vi32, float2* Ui32, const std::vector<int>& act_,
+                     bool acc) -> hipError_t {
+        const BasisMap bm = make_basis(mb, act_, act_, mixed);
+        const int na = (int)act_.size();
+        FieldList fl;
+        fl.on = 1;
+        for (int t = 0; t < na; ++t) fl.idx[t] = (unsigned char)act_[t];
+        hipError_t e;
+        if (w.precond == 1)
+            e = mixed ? launch_precond_mg<float2>(w.mg, p, w.mgo, na, Vi32 + n * mb, Vi32 + n * mb, s, fl)
+                      : launch_precond_mg<double2>(w.mg, p, w.mgo, na, col(Vi, n, mb), col(Vi, n, mb), s, fl);
+        else if (mixed)
+            e = launch_precond<float>(p, na, Vi32 + n * mb, Vi32 + n * mb, c->tw32, s, fl);
+        else
+            e = precond_fp64(c, p, na, col(Vi, n, mb), w.mixed ? Vi32 + n * mb : w.stage32, n, fl, s);
+        if (e != hipSuccess) return e;
+        e = mixed ? launch_stencil_f64_s32(p, na, Vi32 + n * mb, Vi32 + n * 4 * mb, c->mu64, s, fl)
+                  : launch_stencil<double>(p, na, col(Vi, n, mb), col(Vi, n, 4 * mb), c->mu64, s, fl);
+        if (e != hipSuccess) return e;
+        if ((e = launch_gram_mfma(Vi, mixed ? Vi32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s)) != hipSuccess)
+            return e;
+        RRArgs r2 = ra;
+        r2.K = bm.K;
+        r2.nw = bm.na;
+        if ((e = acc ? launch_rr_jacobi(r2, s) : launch_rr(r2, s)) != hipSuccess) return e;
+        return launch_update_mfma(Vi, mixed ? Vi32 : nullptr, Ui, mixed ? Ui32 : nullptr, n, n, bm, w.C, w.theta,
+                                  w.nparts_upd, w.npart, w.norms, s, w.upd_rows);
+    };
+    // A chunk of `cn` (even) iterations: a graph of two iterations (V -> U,
+    // U -> V) captured for the current basis shape, Bloch vector and
+    // precision, replayed cn / 2 times.  Returns 1 when the graph cannot be
+    // captured (graph chunks are then off for this workspace).
+    auto run_chunk = [&](int cn) -> int {
+        const int flags = (mixed ? 1 : 0) + (accurate_rr ? 2 : 0);
+        const double key[6] = {p.k[0], p.k[1], p.k[2], p.gamma, p.shift, (double)(size_t)V};
+        bool same = w.gexec && flags == w.gkey_flags && act == w.gkey_act;
+        for (int q = 0; q < 6 && same; ++q) same = key[q] == w.gkey[q];
+        if (!same) {
+            if (w.gexec) {
+                hipGraphExecDestroy(w.gexec);
+                w.gexec = nullptr;
+            }
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return 1;
+            hipError_t e = issue(V, U, V32, U32, act, accurate_rr);
+            if (e == hipSuccess) e = issue(U, V, U32, V32, act, accurate_rr);
+            hipGraph_t g = nullptr;
+            const hipError_t ee = hipStreamEndCapture(s, &g);
+            if (e != hipSuccess || ee != hipSuccess || !g) {
+                if (g) hipGraphDestroy(g);
+                (void)hipGetLastError();
+                return 1;
+            }
+            e = hipGraphInstantiate(&w.gexec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                w.gexec = nullptr;
+                return 1;
+            }
+            w.gkey_act = act;
+            w.gkey_flags = flags;
+            for (int q = 0; q < 6; ++q) w.gkey[q] = key[q];
+        }
+        for (int r = 0; r < cn / 2; ++r)
+            if (hipGraphLaunch(w.gexec, s) != hipSuccess) return -1;
+        return 0;
+    };
+    double rate = 0.85, r_chunk0 = HUGE_VAL;   // residual reduction per iteration, for the chunk length
+    int chunk_prev = 0;
     for (;; ++it) {
         const int rb = mixed ? 8 : 16;   // bytes per complex of the W/AW blocks
+        // Graph chunks: from the third iteration on, several iterations run
+        // from one captured graph with no host step between them; the active
+        // set is the one of the chunk's start (bands that converge inside a
+        // chunk keep iterating until its end).  The chunk's length follows
+        // the residual's rate of decrease, so that it ends near convergence.
+        bool chunked = false;
+        if (w.graph && it >= 2 && have_p && !act.empty() && !union_start) {
+            if (chunk_prev > 0 && r_chunk0 < HUGE_VAL && rprev > 0.0)
+                rate = std::min(0.98, std::max(0.3, std::pow(rprev / r_chunk0, 1.0 / chunk_prev)));
+            const double left = (rprev > tol) ? std::log(tol / rprev) / std::log(rate) : 1.0;
+            int cn = 2 * std::min(4, std::max(1, (int)std::floor(left / 2.0)));
+            cn = std::min(cn, std::max(2, (max_iter - it) / 2 * 2));
+            if (cn >= 2 && it + cn - 1 <= max_iter) {
+                const int st = run_chunk(cn);
+                if (st < 0) return fail(MFD_EDEVICE, "graph launch failed");
+                if (st == 0) {
+                    chunked = true;
+                    it += cn - 1;
+                    r_chunk0 = rprev;
+                    chunk_prev = cn;
+                } else {
+                    w.graph = false;
+                }
+            }
+        }
+        if (!chunked) {
         // P columns: every update writes P' of every band, so each active band
         // has one from the second iteration on (zero after the first, which the
         // Rayleigh-Ritz step leaves out)
@@ -513,7 +629,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             const int Kb = bm.K;
             std::vector<double2> hG((size_t)Kb * 2 * Kb);
             HIPCHK(hipMemcpyAsync(hG.data(), w.G, hG.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(wsync(w));
             const double tx = ritz_trace(hG.data(), Kb, 0, mb), tw = ritz_trace(hG.data(), Kb, mb, mb);
             out.proposal_used = tw < tx;
             if (trace) std::fprintf(stderr, "[%p] proposal: Ritz sum %.6e vs previous-k %.6e -> %s\n", (void*)&w,
@@ -527,7 +643,10 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         ra.K = bm.K;
         ra.nw = bm.na;
         e1 = w.prof.begin(s);
-        HIPCHK(launch_rr(ra, s));
+        // The Householder route (launch_rr) has Ritz values accurate to about
+        // Kv eps |H| in absolute terms; within a factor 100 of that floor the
+        // iteration takes the Jacobi route, whose errors are relative.
+        HIPCHK(accurate_rr ? launch_rr_jacobi(ra, s) : launch_rr(ra, s));
         w.prof.end(e1, 3, 0.0, s);
         e1 = w.prof.begin(s);
         HIPCHK(launch_update_mfma(V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, bm, w.C, w.theta,
@@ -541,11 +660,13 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         std::swap(V, U);
         if (mixed) std::swap(V32, U32);
         have_p = true;   // the update wrote P', AP' of every band
+        }   // eager iteration
         HIPCHK(hipMemcpyAsync(hth, w.theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hfloor, w.theta + mb, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
         int* hinfo = (int*)(w.host + 3 * mb);
         if (trace) HIPCHK(hipMemcpyAsync(hinfo, w.info, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(wsync(w));
         w.prof.drain();
         double rmax = 0.0;
         bool conv = residuals(&rmax);
@@ -587,7 +708,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, nullptr, w.nparts_col, w.cpart, w.cout,
                                    s));
             HIPCHK(hipMemcpyAsync(rq, w.cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(wsync(w));
             double dev = 0.0, scale = 0.0;
             for (int j = 0; j < mb; ++j) {
                 const double t = rq[2 * j + 1] / rq[2 * j];
@@ -602,7 +723,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
                                        mixed ? (void*)(V32 + n * mb) : col(V, n, mb), mixed, n, n, mb, w.theta,
                                        w.nparts_col, w.npart, w.norms, s));
                 HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
+                HIPCHK(wsync(w));
                 conv = residuals(&rmax);
                 active_set();
                 last_refresh = it;
@@ -625,7 +746,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), mixed ? (void*)(V32 + n * mb) : col(V, n, mb),
                                    mixed, n, n, mb, w.theta, w.nparts_col, w.npart, w.norms, s));
             HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(wsync(w));
             have_p = false;
             conv = residuals(&rmax);
             active_set();
@@ -644,7 +765,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), mixed ? (void*)(V32 + n * mb) : col(V, n, mb),
                                    mixed, n, n, mb, w.theta, w.nparts_col, w.npart, w.norms, s));
             HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(wsync(w));
             conv = residuals(&rmax);
             active_set();
             last_refresh = it;
@@ -671,7 +792,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), col(V, n, mb), false, n, n, mb, w.theta,
                                    w.nparts_col, w.npart, w.norms, s));
             HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(wsync(w));
             active_set();
             ra.drop_w = 1e-10;
             ra.drop_p = 1e-8;
@@ -689,11 +810,16 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), col(V, n, mb), false, n, n, mb, w.theta,
                                    w.nparts_col, w.npart, w.norms, s));
             HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(wsync(w));
             active_set();
             best = rmax;
             best_it = it;
             if (trace) std::fprintf(stderr, "[%p] it %d: stalled at %.3e, P restarted\n", (void*)&w, it, rmax);
+        }
+        {
+            double tmin = HUGE_VAL;
+            for (int j = 0; j < nreq; ++j) tmin = std::min(tmin, std::fabs(hth[j]));
+            accurate_rr = rmax < 100.0 * *hfloor / tmin;
         }
         rprev = rmax;
         std::memcpy(th_prev.data(), hth, mb * sizeof(double));
@@ -708,7 +834,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
     HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, nullptr, w.nparts_col, w.cpart, w.cout, s));
     HIPCHK(hipMemcpyAsync(w.host, w.cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(wsync(w));
     out.theta.assign(mb, 0.0);
     std::vector<double> xx(mb);
     for (int j = 0; j < mb; ++j) {
@@ -719,7 +845,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     HIPCHK(hipMemcpyAsync(w.theta, w.host + 4 * mb, mb * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(launch_colstats(col(V, n, 0), col(V, n, 3 * mb), n, n, mb, w.theta, w.nparts_col, w.cpart, w.cout, s));
     HIPCHK(hipMemcpyAsync(w.host, w.cout, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(wsync(w));
     out.res.assign(mb, 0.0);
     for (int j = 0; j < mb; ++j) out.res[j] = std::sqrt(w.host[2 * j]) / (std::fabs(out.theta[j]) * std::sqrt(xx[j]));
     return MFD_OK;
@@ -730,7 +856,7 @@ int lambda_re_ws(mfd_ctx* c, Ws& w, const OpParams& p, int nb, const void* X, do
     const int nparts = 128;
     HIPCHK(launch_lambda_re(p, nb, X, c->mu64, w.cpart, nparts, w.cout, w.stream));
     HIPCHK(hipMemcpyAsync(w.host, w.cout, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, w.stream));
-    HIPCHK(hipStreamSynchronize(w.stream));
+    HIPCHK(wsync(w));
     for (int b = 0; b < nb; ++b) out[b] = w.host[2 * b] / w.host[2 * b + 1];
     return MFD_OK;
 }
@@ -749,6 +875,7 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
     const int mb = w.mb;
     hipStream_t s = w.stream;
     auto t0 = std::chrono::steady_clock::now();
+    w.syncs = 0;
     OpParams p = params(c, k);
     p.wtmp = w.wtmp;
     p.stencil_wgs = w.stencil_wgs;
@@ -813,7 +940,7 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
         for (int j = 0; j < nbands; ++j)
             HIPCHK(hipMemcpyAsync(ko.evecs + (size_t)j * n, col(w.V, n, idx[j]), n * sizeof(double2),
                                   hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(wsync(w));
     }
     auto t1 = std::chrono::steady_clock::now();
     if (ko.stats) {
@@ -827,6 +954,7 @@ int solve_k(mfd_ctx* c, Ws& w, const double* k, int nbands, double tol, const mf
         ks.used_fallback = 0;
         ks.fp64_fallback = fp64_fallback;
         ks.rejected_steps = rejected;
+        ks.host_syncs = w.syncs;
         ks.ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     *converged = (maxres <= tol) ? (nspur ? 2 : 1) : 0;
@@ -899,6 +1027,7 @@ void run_segment(Segment* sg) {
     const int mb = w.mb;
     const mfd_opts& o = sg->opts;
     w.precond = o.precond;
+    w.graph = o.graph != 0;
     w.mgo.cycles = o.mg_cycles;
     w.mgo.n1 = w.mgo.n2 = o.mg_smooth;
     w.mgo.sweeps = o.mg_sweeps;
@@ -1096,7 +1225,7 @@ int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
     if (nbands <= 0) return fail(MFD_EINVAL, "nbands must be > 0");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
     if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0 || o.streams < 1 || o.streams > 16 ||
-        o.stall_window < 0 || o.warm_start < 0 || o.warm_start > 2 || o.learn_steps < 0 ||
+        o.stall_window < 0 || o.warm_start < 0 || o.warm_start > 2 || o.learn_steps < 0 || o.graph < 0 || o.graph > 1 ||
         !(o.learn_rate >= 0.0f))
         return fail(MFD_EINVAL, "bad options");
     const int mb = nbands + o.guard;
@@ -1135,6 +1264,7 @@ void mfd_default_opts(mfd_opts* o) {
     o->mg_cycles = 2;
     o->mg_smooth = 2;
     o->mg_sweeps = 2;
+    o->graph = 0;
 }
 
 int mfd_tuning(const mfd_ctx* ctx, int* out) {
@@ -1691,7 +1821,7 @@ void mfd_mlp_destroy(mfd_mlp* m) {
 int mfd_warm_target(long long n, int mb, const void* Xa, const void* Xb, const void* Xc, void* C, void* Rinv,
                     void* stream) {
     if (!Xa || !Xb || !Xc || !C) return fail(MFD_EINVAL, "NULL argument");
-    if (n < 1 || mb < 1 || mb > 21 || 2 * mb > n) return fail(MFD_EINVAL, "bad sizes");
+    if (n < 1 || mb < 1 || mb > 22 || 2 * mb > n) return fail(MFD_EINVAL, "bad sizes");
     const int st = mfd::warm_target_blocks((size_t)n, mb, (const double2*)Xa, (const double2*)Xb,
                                            (const double2*)Xc, (double2*)C, (double2*)Rinv, (hipStream_t)stream);
     if (st == MFD_ENOTCONV) return fail(st, "history blocks are numerically dependent");

@@ -30,7 +30,6 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 // Workgroup w sums rows [w rows_per, (w+1) rows_per) into its own partial
 // tile set; reduce_parts_kernel adds the partials in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int GM_KS = 32;       // rows per LDS slab
 constexpr int GM_PF = 8;        // prefetch registers (complex) per thread
 
 struct GramTiles {
@@ -60,12 +59,15 @@ __device__ __forceinline__ double2 widen(double2 raw, bool f32) {
 // consumed by the matrix cores, with one barrier per slab.  The two waves of a
 // block (alternate 4-row steps) add their tiles through LDS at the end, so a
 // workgroup writes one partial tile set.
-template <int T>
-__global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __restrict__ V,
-                                                             const float2* __restrict__ V32, size_t ld, size_t n,
-                                                             BasisMap bm, size_t rows_per,
-                                                             double2* __restrict__ part) {
-    constexpr int NT = 128 * T;   // two waves per block of S, each taking every other 4 rows
+// SUBS waves per block of S take alternate 4-row steps of a slab of KS rows
+// (two for T <= 4; one for T = 5, whose accumulators would not fit beside a
+// second wave's registers); KS rows per slab.
+template <int T, int SUBS = 2, int GM_KS = 32>
+__global__ __launch_bounds__(64 * SUBS * T) void gram_mfma_kernel(const double2* __restrict__ V,
+                                                                   const float2* __restrict__ V32, size_t ld,
+                                                                   size_t n, BasisMap bm, size_t rows_per,
+                                                                   double2* __restrict__ part) {
+    constexpr int NT = 64 * SUBS * T;   // SUBS waves per block of S, each taking every SUBS-th 4 rows
     constexpr int TG = T + 1;     // tiles per wave
     extern __shared__ unsigned char smem_raw[];
     double2* slabs = reinterpret_cast<double2*>(smem_raw);   // [2][GM_KS][2K]
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __res
     const int C2 = 2 * K;
     const int SL = GM_KS * C2;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, g = (tid >> 6) >> 1, sub = (tid >> 6) & 1;
+    const int lane = tid & 63, g = (tid >> 6) / SUBS, sub = (tid >> 6) % SUBS;
     const size_t r0 = (size_t)blockIdx.x * rows_per;
     const size_t r1 = min(n, r0 + rows_per);
     d4 acc[TG][3];
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __res
         if (more) prefetch(s0 + GM_KS);
         const double2* slab = slabs + buf * SL;
 #pragma unroll
-        for (int k0 = 4 * sub; k0 < GM_KS; k0 += 8) {
+        for (int k0 = 4 * sub; k0 < GM_KS; k0 += 4 * SUBS) {
             const double2* srow_p = slab + (k0 + lk) * C2;
             const double2 a = va ? srow_p[ia] : mk<double2>(0.0, 0.0);
             const double amd = a.x - a.y;
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __res
     // sub 1 hands its tiles to sub 0 through LDS (the slabs are free after the
     // last barrier); partial tiles part[w][tile][16][16], tiles of block g at g TG .. g TG + T
     double2* xch = slabs;   // [T TG][4][64]
-    if (sub == 1) {
+    if (SUBS == 2 && sub == 1) {
 #pragma unroll
         for (int t = 0; t < TG; ++t)
 #pragma unroll
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(128 * T) void gram_mfma_kernel(const double2* __res
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const double t1 = acc[t][0][r], t2 = acc[t][1][r], t3 = acc[t][2][r];
-                const double2 o = xch[((g * TG + t) * 4 + r) * 64 + lane];
+                const double2 o = SUBS == 2 ? xch[((g * TG + t) * 4 + r) * 64 + lane] : mk<double2>(0.0, 0.0);
                 out[(size_t)ti * 256 + (lk + 4 * r) * 16 + li] = mk<double2>(t1 + t2 + o.x, t3 - t1 + t2 + o.y);
             }
         }
@@ -234,28 +236,35 @@ size_t gram_mfma_part_elems(int K, int nparts) {
     return (size_t)(nparts + 1) * T * (T + 1) * 256;   // one partial set per workgroup + their sum
 }
 
+// rows per slab of the instance for T column blocks
+template <int T> constexpr int gram_ks() { return T == 5 ? 16 : 32; }
+template <int T> constexpr int gram_subs() { return T == 5 ? 1 : 2; }
+
 template <int T>
 static hipError_t gram_t(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nw,
                          size_t rows_per, void* part, hipStream_t s) {
-    // two slabs, or the tile exchange at the end if larger
-    const size_t lds = std::max((size_t)2 * GM_KS * 2 * bm.K, (size_t)T * (T + 1) * 4 * 64) * sizeof(double2);
-    auto kern = gram_mfma_kernel<T>;
+    constexpr int KS = gram_ks<T>(), SUBS = gram_subs<T>();
+    // the slab of KS x 2K elements must fit the prefetch registers of the workgroup
+    if (KS * 2 * bm.K > GM_PF * 64 * SUBS * T) return hipErrorInvalidValue;
+    // two slabs, or the tile exchange between the two waves of a block at the end if larger
+    const size_t lds =
+        std::max((size_t)2 * KS * 2 * bm.K, SUBS == 2 ? (size_t)T * (T + 1) * 4 * 64 : (size_t)0) * sizeof(double2);
+    auto kern = gram_mfma_kernel<T, SUBS, KS>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nw), dim3(128 * T), lds, s, (const double2*)V, (const float2*)V32, ld, n, bm,
-                       rows_per, (double2*)part);
+    hipLaunchKernelGGL(kern, dim3(nw), dim3(64 * SUBS * T), lds, s, (const double2*)V, (const float2*)V32, ld, n,
+                       bm, rows_per, (double2*)part);
     return hipGetLastError();
 }
 
 hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n, const BasisMap& bm, int nparts,
                             void* part, void* G, hipStream_t s, int stages) {
     const int K = bm.K;
-    if (K < 1 || K > 64) return hipErrorInvalidValue;
+    if (K < 1 || K > BASIS_KMAX) return hipErrorInvalidValue;
     const int T = (K + 15) / 16;
-    // the slab of GM_KS x 2K elements must fit the prefetch registers of 128 T threads
-    if (GM_KS * 2 * K > GM_PF * 128 * T) return hipErrorInvalidValue;
     GramTiles tl = make_tiles(K);
-    const size_t rows_per = ((n + nparts - 1) / nparts + GM_KS - 1) / GM_KS * GM_KS;
+    // rows per workgroup: a multiple of 32, hence of every instance's slab
+    const size_t rows_per = ((n + nparts - 1) / nparts + 31) / 32 * 32;
     const int nw = (int)((n + rows_per - 1) / rows_per);
     hipError_t e = hipSuccess;
     if (stages & 1) {
@@ -263,7 +272,8 @@ hipError_t launch_gram_mfma(const void* V, const void* V32, size_t ld, size_t n,
             case 1: e = gram_t<1>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
             case 2: e = gram_t<2>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
             case 3: e = gram_t<3>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
-            default: e = gram_t<4>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+            case 4: e = gram_t<4>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
+            default: e = gram_t<5>(V, V32, ld, n, bm, nw, rows_per, part, s); break;
         }
     }
     if (e != hipSuccess || !(stages & 2)) return e;
@@ -705,7 +715,7 @@ static hipError_t update_wave(const void* V, const void* V32, void* U, void* U32
                               hipStream_t s) {
     constexpr int CW = 16 + ((NT + 1) & ~1), NX = 4 + NT;   // as in the kernel
     const int K = bm.K, mb = bm.mb;
-    if (mb > CW || (K - mb + 3) / 4 > KS0 || (mb + 3) / 4 > KS1 || 2 * K > 128 || !n) return hipErrorInvalidValue;
+    if (mb > CW || (K - mb + 3) / 4 > KS0 || (mb + 3) / 4 > KS1 || K > BASIS_KMAX || !n) return hipErrorInvalidValue;
     if ((V32 == nullptr) != (U32 == nullptr)) return hipErrorInvalidValue;
     const size_t lds = (size_t)std::max(mb + 4 * KS0, 4 * KS1) * CW * sizeof(double2) +
                        (size_t)9 * CW * sizeof(double) + (size_t)4 * NX * 64 * sizeof(double2) +
@@ -728,7 +738,7 @@ hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32
     hipError_t e;
 #define UPW(KS0, KS1, NT) update_wave<KS0, KS1, NT>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
 #define UPB(MJ, RB) update_mj<MJ, RB>(V, V32, U, U32, ld, n, bm, C, theta, nparts, npart, s)
-    if (mb < 1 || mb > 21) return hipErrorInvalidValue;
+    if (mb < 1 || mb > 22) return hipErrorInvalidValue;
     if (rows == 0 && mb <= 16)
         e = nk0 <= 2 ? UPW(2, 4, 0) : nk0 <= 4 ? UPW(4, 4, 0) : nk0 <= 6 ? UPW(6, 4, 0) : UPW(8, 4, 0);
     else if (rows == 0 && mb <= 20)
@@ -737,8 +747,10 @@ hipError_t launch_update_mfma(const void* V, const void* V32, void* U, void* U32
             : nk0 <= 6 ? UPW(6, 5, 4)
             : nk0 <= 8 ? UPW(8, 5, 4)
                        : UPW(10, 5, 4);
-    else if (rows == 0)
+    else if (rows == 0 && mb <= 21)
         e = nk0 <= 4 ? UPW(4, 6, 5) : nk0 <= 8 ? UPW(8, 6, 5) : UPW(11, 6, 5);
+    else if (rows == 0)
+        e = nk0 <= 4 ? UPW(4, 6, 6) : nk0 <= 8 ? UPW(8, 6, 6) : UPW(11, 6, 6);
     else if (mb <= 16)
         e = rows == 16 ? UPB(1, 16) : UPB(1, 32);
     else

@@ -31,8 +31,8 @@ namespace mfd {
 
 using C128 = double2;
 constexpr int RR_NT = 256;
-constexpr int RR_KMAX = 64;
-constexpr int RR_MBMAX = 21;
+constexpr int RR_KMAX = 66;
+constexpr int RR_MBMAX = 22;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -405,6 +405,7 @@ __global__ __launch_bounds__(RR_NT) void rr_kernel(RRArgs a) {
             }
             sh.lam[r] = 0.5 * (x0 + x1);
         }
+        if (lane == 0) *a.floor = (double)n * eps * tn;
         __builtin_amdgcn_wave_barrier();
         // clusters: consecutive eigenvalues closer than 1e-3 |T|
         const double ortol = 1e-3 * tn;

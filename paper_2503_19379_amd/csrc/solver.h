@@ -16,10 +16,11 @@ hipError_t launch_update(const void* V, void* U, size_t ld, size_t n, int mb, co
 // The basis of one Rayleigh-Ritz step: X (mb columns), the W columns of the
 // na unconverged bands and the np P columns of those bands, K = mb + na + np, with the images AX, AW, AP at basis columns K..2K.  V holds
 // [X | W | P | AX | AW | AP], mb columns each, in band order.
+constexpr int BASIS_KMAX = 66;   // 3 x the largest block (22 columns)
 struct BasisMap {
     int mb, K, na;
-    short lc[128];             // load ordinal -> basis column (FP64 columns first in mixed precision)
-    short pc[128];             // load ordinal -> column of V
+    short lc[2 * BASIS_KMAX];  // load ordinal -> basis column (FP64 columns first in mixed precision)
+    short pc[2 * BASIS_KMAX];  // load ordinal -> column of V
     signed char tpos[32];      // band -> its W column among the na (-1: converged)
     unsigned char act[32];     // W column t -> band
 };
@@ -60,9 +61,14 @@ struct RRArgs {
     double* theta;
     double2* C;
     int* info;
+    double* floor;   // (out) Kv eps max|eig(H)|: the absolute accuracy of a Householder-route Ritz value
     int mb, K, nw;
     double drop_w, drop_p;
 };
 hipError_t launch_rr(const RRArgs& a, hipStream_t s);
+// The same step with cyclic Jacobi on H (rr_jacobi.hip): slower, and accurate
+// relative to the Ritz values themselves; the solver takes it in its last
+// iterations, where rr.hip's absolute accuracy would bound the residual.
+hipError_t launch_rr_jacobi(const RRArgs& a, hipStream_t s);
 
 }  // namespace mfd

@@ -28,7 +28,7 @@ namespace mfd {
 
 using C128 = double2;
 constexpr int WS_NT = 256;
-constexpr int WS_MB = 21;        // mb <= 21
+constexpr int WS_MB = 22;        // mb <= 22
 constexpr int WS_K2 = 2 * WS_MB;
 
 // Upper Cholesky factor in place (A = R^H R, lower part zeroed).  Returns false

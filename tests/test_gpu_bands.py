@@ -242,3 +242,59 @@ def test_update_forms_agree(B, form, precision):
                                    fft_x_run=0, update_rows=8))
     B.mfd_set_tuning(ctx, None)
     assert B.mfd_tuning(ctx)[0] is False
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_largest_block_vs_oracle(B, precision):
+    """20 bands with 2 guard columns (the largest block, 22 columns: a
+    66-column basis, five 16-column Gram blocks, six tail bands in the
+    update) on a random two-material crystal against the oracle."""
+    assert B.max_block() == 22
+    N, m = 12, 20
+    rng = np.random.default_rng(12)
+    eps = rand_eps(rng, N)
+    k = np.array([0.6, -0.2, 0.3]) * np.pi
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    tol = 1e-8 if precision else 1e-10
+    ev, st, status = B.mfd_bands(ctx, [k], m, tol, B.default_opts(precision=precision, guard=2, streams=1))
+    assert status == 0, st
+    lam, _, info = olob.solve_bands(eps, 1.0, k, m, tol=1e-10)
+    assert np.allclose(ev[0], lam, rtol=1e-7 if precision else 1e-10), (ev[0], lam)
+    with pytest.raises(B.MfdError):
+        B.mfd_bands(ctx, [k], m, tol, B.default_opts(guard=3, streams=1))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_chunks_match_host_stepped(B, precision):
+    """Iterations replayed from captured graphs (opts.graph = 1) give the same
+    bands as the host-stepped loop, with fewer host synchronisations per
+    iteration."""
+    N, m = 16, 8
+    eps = workloads.eps_diamond(N)
+    kp = workloads.kpath("GXMGR", 6)
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    tol = 1e-8 if precision else 1e-10
+    e0, s0, st0 = B.mfd_bands(ctx, kp, m, tol, B.default_opts(precision=precision, streams=2, graph=0))
+    e1, s1, st1 = B.mfd_bands(ctx, kp, m, tol, B.default_opts(precision=precision, streams=2, graph=1))
+    assert st0 == 0 and st1 == 0, (s0, s1)
+    assert all(s["max_rel_resid"] <= tol for s in s1)
+    assert np.allclose(e0, e1, rtol=1e-7 if precision else 1e-9, atol=1e-9), (e0, e1)
+    per0 = sum(s["host_syncs"] for s in s0) / sum(s["iters"] for s in s0)
+    per1 = sum(s["host_syncs"] for s in s1) / sum(s["iters"] for s in s1)
+    assert per1 < 0.6 * per0, (per0, per1)
+
+
+def test_graph_batch_matches_single(B):
+    """The multi-crystal batch with graph chunks equals each crystal alone."""
+    Ns = (8, 12, 16)
+    crystals = [(N, workloads.eps_random_field(N, c)) for c, N in enumerate(Ns)]
+    kp = workloads.kpath("GXMGR", 4)
+    ctxs = [B.mfd_build(N, 1.0, 2, eps) for N, eps in crystals]
+    evs, sts, status = B.mfd_bands_batch(ctxs, [kp] * len(ctxs), 5, 1e-9,
+                                         B.default_opts(precision=1, streams=3, graph=1))
+    assert status == 0
+    for c, (N, eps) in enumerate(crystals):
+        one = B.mfd_build(N, 1.0, 2, eps)
+        e1, s1, st1 = B.mfd_bands(one, kp, 5, 1e-9, B.default_opts(precision=1, streams=1, graph=0))
+        assert st1 == 0
+        assert np.allclose(evs[c], e1, rtol=1e-7, atol=1e-9), (N, evs[c], e1)
