@@ -257,6 +257,19 @@ int mfd_mg_supported(int N);
  * fields X (device).  out: host, nb doubles. */
 int mfd_lambda_re(mfd_ctx* ctx, const double k[3], int nb, const void* X, double* out, void* stream);
 
+/* mfd_lambda_re for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same values, computed by the same kernels, with the partial sums kept in
+ * a static device array of the library (about 130 KB per GPU, held until the
+ * process ends) instead of buffers allocated per call.
+ * X: device c128 [nb][3][N][N][N]; out: device, nb doubles (written by a
+ * kernel: the call is asynchronous, stream-ordered on `stream`, and calls no
+ * hipMalloc, hipFree or host synchronisation).  nb <= 64 (MFD_EINVAL above).
+ * The context must belong to the current device.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be ordered by the caller. */
+int mfd_lambda_re_static(mfd_ctx* ctx, const double k[3], int nb, const void* X, double* out, void* stream);
+
 /* Lowest nbands physical eigenpairs at each of nk Bloch vectors: LOBPCG
  * (Section 5.1) on nbands + guard columns preconditioned by
  * mfd_precond_solve, then the recompute check of Alg 4.1: bands it flags as

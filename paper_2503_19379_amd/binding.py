@@ -64,6 +64,7 @@ def lib():
         L.mfd_gap_ratio.argtypes = [i, i, dp, dp, dp, ctypes.POINTER(i)]
         L.mfd_supported_n.argtypes = [i]
         L.mfd_max_block.argtypes = []
+        L.mfd_lambda_re_static.argtypes = [vp, dp, i, vp, vp, vp]
         L.mfd_precond_solve_mg.argtypes = [vp, dp, i, i, i, i, i, vp, vp, vp]
         L.mfd_mg_supported.argtypes = [i]
         L.mfd_set_gamma.argtypes = [vp, d]
@@ -287,6 +288,18 @@ def mfd_lambda_re(ctx: Context, k, X, stream=None):
     out = np.zeros(nb)
     _check(lib().mfd_lambda_re(ctx.handle, kp, nb, _dev(X), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                _stream(stream)))
+    return out
+
+
+def mfd_lambda_re_static(ctx: Context, k, X, out, stream=None):
+    """out (device float64 tensor, nb entries) <- lambda_re of the nb fields of
+    X, with no device allocation (mfd_lambda_re_static)."""
+    import torch
+    ka, kp = _k(k)
+    nb = int(X.shape[0])
+    if out.dtype != torch.float64 or out.numel() < nb:
+        raise ValueError("out must be a float64 device tensor with nb entries")
+    _check(lib().mfd_lambda_re_static(ctx.handle, kp, nb, _dev(X), _dev(out), _stream(stream)))
     return out
 
 

@@ -1243,6 +1243,14 @@ int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
 
 }  // namespace
 
+// Accessors for the other translation units of the library (noalloc.hip).
+namespace mfd {
+OpParams ctx_params(const mfd_ctx* ctx, const double k[3]) { return params(ctx, k); }
+int ctx_device(const mfd_ctx* ctx) { return ctx->device; }
+const void* ctx_mu64(const mfd_ctx* ctx) { return ctx->mu64; }
+int set_error(int status, const char* msg) { return fail(status, msg); }
+}  // namespace mfd
+
 extern "C" {
 
 void mfd_default_opts(mfd_opts* o) {
