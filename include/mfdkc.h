@@ -320,7 +320,9 @@ const char* mfd_last_error(void);
 
 /* Launch shapes the autotuner chose for ctx (out: 5 ints): out[0] Gram
  * workgroups, out[1] update workgroups, out[2] stencil workgroup target,
- * out[3] FFT z-pass x run, out[4] update form: 0 one wave per 16-row strip,
+ * out[3] FFT plan: the z-pass x run (0 built-in), or -1 for the
+ * register-resident passes (FP32 storage, cubic order 2, N = 16, 32 or 64),
+ * out[4] update form: 0 one wave per 16-row strip,
  * 16 or 32 rows per workgroup block.
  * Returns 1 when tuned or pinned, 0 when not yet (out holds zeros), MFD_EINVAL
  * on NULL. */
@@ -330,8 +332,9 @@ int mfd_tuning(const mfd_ctx* ctx, int* out);
  * every later solve on ctx, whatever its block shape; the autotuner then does
  * not run on ctx.  Each value must be one of the autotuner's candidates:
  * Gram workgroups {128, 256, 512, 1024}, update workgroups {256, 512, 1024,
- * 2048}, stencil workgroups {512, 1024, 2048, 4096}, FFT x run {0 (built-in),
- * 4, 8, 16} dividing N, update form {0, 16, 32}; else MFD_EINVAL and nothing
+ * 2048}, stencil workgroups {512, 1024, 2048, 4096}, FFT plan {0 (built-in),
+ * 4, 8, 16 dividing N, -1 where the register-resident passes apply}, update
+ * form {0, 16, 32}; else MFD_EINVAL and nothing
  * changes.  A workgroup count beyond what a workspace's partial buffers hold
  * keeps the built-in one for that workspace.  in = NULL clears the pin and any
  * tuning: the built-in shapes apply until the autotuner runs again.

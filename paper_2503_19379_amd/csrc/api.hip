@@ -1164,8 +1164,10 @@ int autotune(mfd_ctx* c, Ws& w, const double* k) {
         if (t < tb) { tb = t; best_wgs = wg; }
     }
     tb = HUGE_VAL;
-    for (int xc : {4, 8, 16}) {
-        if (c->N % xc) continue;
+    best_xc = 0;   // the built-in choice when no candidate applies
+    for (int xc : {4, 8, 16, -1}) {   // -1: the register-resident passes (FP32, cubic order 2, N = 16, 32, 64)
+        if (xc > 0 && c->N % xc) continue;
+        if (xc < 0 && !(w.mixed && reg_precond_ok(p))) continue;
         OpParams q = p;
         q.fft_xc = xc;
         const double t = timeit([&] {
@@ -1297,8 +1299,13 @@ int mfd_set_tuning(mfd_ctx* ctx, const int* in) {
     if (!one_of(in[0], {128, 256, 512, 1024})) return fail(MFD_EINVAL, "Gram workgroups not a candidate");
     if (!one_of(in[1], {256, 512, 1024, 2048})) return fail(MFD_EINVAL, "update workgroups not a candidate");
     if (!one_of(in[2], {512, 1024, 2048, 4096})) return fail(MFD_EINVAL, "stencil workgroups not a candidate");
-    if (!one_of(in[3], {0, 4, 8, 16}) || (in[3] && ctx->N % in[3]))
-        return fail(MFD_EINVAL, "FFT x run must be 0, or 4, 8 or 16 dividing N");
+    if (!one_of(in[3], {0, 4, 8, 16, -1}) || (in[3] > 0 && ctx->N % in[3]))
+        return fail(MFD_EINVAL, "FFT x run must be 0, -1, or 4, 8 or 16 dividing N");
+    if (in[3] < 0) {
+        const double k0[3] = {0.0, 0.0, 0.0};
+        const OpParams q = ctx_params(ctx, k0);
+        if (!reg_precond_ok(q)) return fail(MFD_EINVAL, "register-resident FFT passes need a cubic order-2 grid of 16, 32 or 64");
+    }
     if (!one_of(in[4], {0, 16, 32})) return fail(MFD_EINVAL, "update form must be 0, 16 or 32");
     for (int i = 0; i < 5; ++i) ctx->tune[i] = in[i];
     ctx->tune_mb = -1;

@@ -398,6 +398,10 @@ bool fft_supported(int N, int real_bytes) {
 template <class R>
 hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s,
                           const FieldList& fl) {
+    // x run -1: the register-resident passes (FP32 on cubic order-2 grids of
+    // 16, 32 or 64; elsewhere the built-in x run)
+    if constexpr (sizeof(R) == 4)
+        if (p.fft_xc == -1 && reg_precond_ok(p)) return launch_precond_reg(p, nb, Rin, Tout, tw, s, fl);
     switch (p.N) {
 #define CASE(n) case n: return precond_n<R, n>(p, nb, Rin, Tout, tw, s, fl);
         MFD_FFT_SIZES(CASE)

@@ -69,6 +69,10 @@ template <class R>
 hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s,
                           const FieldList& fl = FieldList());
 bool fft_supported(int N, int real_bytes);
+// FP32 register-resident passes (fft_reg.hip): cubic order-2 contexts of N = 16, 32, 64
+bool reg_precond_ok(const OpParams& p);
+hipError_t launch_precond_reg(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s,
+                              const FieldList& fl = FieldList());
 
 // Multigrid solve of the same system (mg.hip; Section 5.3, Alg 5.2): cubic
 // order-2 contexts whose grid halves down to at most 5^3 cells.

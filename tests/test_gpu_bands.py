@@ -205,7 +205,7 @@ def test_autotune_changes_launch_shapes_not_results(B):
     assert t["gram_workgroups"] in (128, 256, 512, 1024)
     assert t["update_workgroups"] in (256, 512, 1024, 2048)
     assert t["stencil_workgroups"] in (512, 1024, 2048, 4096)
-    assert t["fft_x_run"] in (4, 8)
+    assert t["fft_x_run"] in (4, 8)   # N = 24: no register-resident plan
     assert t["update_rows"] in (0, 16, 32)
     assert np.allclose(e0, e1, rtol=1e-8, atol=1e-9)
 

@@ -150,12 +150,13 @@ def test_precond_fp32(B, N):
     assert rel_err(Td.cpu().numpy(), ref) < 5e-6
 
 
-@pytest.mark.parametrize("N,xrun", [(64, 4), (64, 8), (64, 16), (100, 0), (120, 0)])
+@pytest.mark.parametrize("N,xrun", [(64, 4), (64, 8), (64, 16), (64, -1), (32, -1), (16, -1), (100, 0), (120, 0)])
 def test_precond_fp32_solver_instances(B, N, xrun):
     """Element-wise FP32 parity of the instances the solves run: N = 64 with
-    each z-pass x run the autotuner may pick (16 is the benchmark's), and the
-    radix-5 and radix-3 plans of N = 100 and 120 (band-gap workloads), on a
-    two-field block at a generic k and at k = 0 (shifted)."""
+    each z-pass x run the autotuner may pick, the register-resident passes
+    (plan -1) at N = 16, 32, 64, and the radix-5 and radix-3 plans of N = 100
+    and 120 (band-gap workloads), on a two-field block at a generic k and at
+    k = 0 (shifted)."""
     rng = np.random.default_rng(400 + N + xrun)
     L = 1.0
     ctx = B.mfd_build(N, L, 2, np.ones((N, N, N)))
