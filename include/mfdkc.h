@@ -384,6 +384,17 @@ void mfd_mlp_destroy(mfd_mlp* net);
 int mfd_warm_target(long long n, int mb, const void* Xa, const void* Xb, const void* Xc, void* C, void* Rinv,
                     void* stream);
 
+/* Input row of the warm start's network for the step k_j -> k_next (the
+ * learned warm start is not in the paper): row (device FP32, 6 + 2mb + 4mb^2
+ * floats) = [k_next L/pi (3), (k_next - k_prev) L/pi (3), lam_j / (2pi/L)^2
+ * (mb), lam_jm1 / (2pi/L)^2 (mb), C as (re, im) pairs in row-major order],
+ * with k_prev = k_j and C (device c128, 2mb x mb row-major) the training
+ * target C*_j of the previous step (mfd_warm_target).  k_prev, k_next (3
+ * doubles) and lam_j, lam_jm1 (mb doubles) are host arrays.  mb <= 22.
+ * Blocking; MFD_EINVAL on NULL pointers or bad sizes. */
+int mfd_warm_features(double L, int mb, const double* k_prev, const double* k_next, const double* lam_j,
+                      const double* lam_jm1, const void* C, float* row, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

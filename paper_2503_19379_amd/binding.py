@@ -98,6 +98,7 @@ def lib():
         L.mfd_mlp_destroy.argtypes = [vp]
         L.mfd_mlp_destroy.restype = None
         L.mfd_warm_target.argtypes = [ctypes.c_longlong, i, vp, vp, vp, vp, vp, vp]
+        L.mfd_warm_features.argtypes = [ctypes.c_double, i, dp, dp, dp, dp, vp, vp, vp]
         L.mfd_tuning.argtypes = [vp, ctypes.POINTER(i)]
         L.mfd_set_tuning.argtypes = [vp, ctypes.POINTER(i)]
         _lib = L
@@ -429,6 +430,15 @@ def mfd_warm_target(Xa, Xb, Xc, C, Rinv=None, stream=None):
     mb, n = Xa.shape
     _check(lib().mfd_warm_target(n, mb, _dev(Xa), _dev(Xb), _dev(Xc), _dev(C),
                                  _dev(Rinv) if Rinv is not None else None, _stream(stream)))
+
+
+def mfd_warm_features(L, k_prev, k_next, lam_j, lam_jm1, C, row, stream=None):
+    """The network's input row (device f32 tensor of 6 + 2mb + 4mb^2) from
+    host k-points and Ritz values and the device target C (2mb x mb c128)."""
+    mb = C.shape[1]
+    arr = lambda v, n: (ctypes.c_double * n)(*[float(x) for x in v])
+    _check(lib().mfd_warm_features(float(L), mb, arr(k_prev, 3), arr(k_next, 3), arr(lam_j, mb),
+                                   arr(lam_jm1, mb), _dev(C), _dev(row), _stream(stream)))
 
 
 def mfd_tuning(ctx: Context):

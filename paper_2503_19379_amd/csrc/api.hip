@@ -1843,4 +1843,17 @@ int mfd_warm_target(long long n, int mb, const void* Xa, const void* Xb, const v
     return st ? fail(st, "warm target failed") : MFD_OK;
 }
 
+int mfd_warm_features(double L, int mb, const double* k_prev, const double* k_next, const double* lam_j,
+                      const double* lam_jm1, const void* C, float* row, void* stream) {
+    if (!k_prev || !k_next || !lam_j || !lam_jm1 || !C || !row) return fail(MFD_EINVAL, "NULL argument");
+    if (!(L > 0.0) || mb < 1 || mb > 22) return fail(MFD_EINVAL, "bad sizes");
+    std::vector<float> stage(6 + 2 * mb);
+    hipStream_t s = (hipStream_t)stream;
+    if (mfd::warm_feature_row(L, mb, k_prev, k_next, lam_j, lam_jm1, (const double2*)C, row, stage.data(), s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(MFD_EDEVICE, "feature row failed");
+    return MFD_OK;
+}
+
 }  // extern "C"

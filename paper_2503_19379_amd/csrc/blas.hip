@@ -18,7 +18,7 @@ using C128 = double2;
 // Gram:  Gpart[w] = V[rows of w, :P]^H V[rows of w, :Q]   (split over rows)
 // ---------------------------------------------------------------------------
 constexpr int GRAM_KS = 32;       // rows per LDS slab
-constexpr int GRAM_TI = 4;        // P <= 16 * GRAM_TI
+constexpr int GRAM_TI = 5;        // P <= 16 * GRAM_TI
 constexpr int GRAM_TJ = 8;        // Q <= 16 * GRAM_TJ
 
 __global__ __launch_bounds__(256) void gram_kernel(const C128* __restrict__ V, size_t ld, size_t n, int P, int Q,

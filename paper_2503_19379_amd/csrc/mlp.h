@@ -93,6 +93,8 @@ struct WarmStart {
 
 hipError_t launch_warm_target(const double2* G, int mb, int a, int b, int c, double2* Cout, double2* Qout,
                               double2* Rinv, int* status, hipStream_t s);
+hipError_t warm_feature_row(double L, int mb, const double* k_prev, const double* k_next, const double* lam_j,
+                            const double* lam_jm1, const double2* Cj, float* row, float* stage, hipStream_t s);
 int warm_target_blocks(size_t n, int mb, const double2* Xa, const double2* Xb, const double2* Xc, double2* C,
                        double2* Rinv, hipStream_t s);
 

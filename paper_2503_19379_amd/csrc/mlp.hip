@@ -5,11 +5,14 @@
 // gelu(z) = z Phi(z), Phi the normal CDF (exact erf form); loss = mean squared
 // error over batch and outputs; Adam (Kingma and Ba) with bias correction.
 // Parameters are one flat FP32 master vector (per layer W (out x in,
-// row-major), then b).  The matrix products read a bfloat16 copy of the
-// weights (rounded to nearest even from the master after every step) and
-// accumulate in FP32; a debug mode reads the FP32 master instead.  Batches are
-// small (the replay buffer of one k-path), so the kernels are LDS-tiled FP32
-// FMA loops rather than matrix-core tiles.
+// row-major), then b).  The three products of a layer (forward Z = A W^T,
+// data gradient dZ W, weight gradient dZ^T A) run on bfloat16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulate): the weights are a bfloat16
+// copy of the master (rounded to nearest even after every step), and each
+// FP32 activation or gradient operand is split into hi + lo bfloat16 parts,
+// so that the products carry about 16 bits of the FP32 operand (the
+// hi x lo and lo x hi terms are formed, lo x lo is dropped).  A debug mode
+// reads the FP32 master and runs the products as FP32 FMA loops.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -38,10 +41,6 @@ __host__ __device__ __forceinline__ bf16_t f_to_bf16(float f) {
     return (bf16_t)(u >> 16);
 }
 
-template <class WT> __device__ __forceinline__ float ldw(const WT* w, size_t i);
-template <> __device__ __forceinline__ float ldw<float>(const float* w, size_t i) { return w[i]; }
-template <> __device__ __forceinline__ float ldw<bf16_t>(const bf16_t* w, size_t i) { return bf16_to_f(w[i]); }
-
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
@@ -51,10 +50,10 @@ constexpr int ML_TB = 16;   // batch rows per tile
 constexpr int ML_TO = 64;   // outputs (or inputs) per tile
 constexpr int ML_KC = 32;   // reduction chunk
 
-// Z = A W^T + b (A: B x I, W: O x I), Aout = gelu(Z) (act) or Z.
-template <class WT>
+// FP32 debug products.  Z = A W^T + b (A: B x I, W: O x I), Aout = gelu(Z)
+// (act) or Z.
 __global__ __launch_bounds__(256) void linear_fwd_kernel(const float* __restrict__ A, int B, int I,
-                                                         const WT* __restrict__ W, const float* __restrict__ bias,
+                                                         const float* __restrict__ W, const float* __restrict__ bias,
                                                          int O, int act, float* __restrict__ Z,
                                                          float* __restrict__ Aout) {
     __shared__ float As[ML_TB][ML_KC + 1];
@@ -70,7 +69,7 @@ __global__ __launch_bounds__(256) void linear_fwd_kernel(const float* __restrict
         }
         for (int e = tid; e < ML_TO * ML_KC; e += 256) {
             const int r = e / ML_KC, c = e % ML_KC;
-            Ws[r][c] = (o0 + r < O && k0 + c < I) ? ldw(W, (size_t)(o0 + r) * I + k0 + c) : 0.f;
+            Ws[r][c] = (o0 + r < O && k0 + c < I) ? W[(size_t)(o0 + r) * I + k0 + c] : 0.f;
         }
         __syncthreads();
 #pragma unroll 8
@@ -94,9 +93,8 @@ __global__ __launch_bounds__(256) void linear_fwd_kernel(const float* __restrict
 }
 
 // dA = dZ W (dZ: B x O, W: O x I); times gelu'(Zprev) when Zprev is given.
-template <class WT>
 __global__ __launch_bounds__(256) void linear_bwd_data_kernel(const float* __restrict__ dZ, int B, int O,
-                                                              const WT* __restrict__ W, int I,
+                                                              const float* __restrict__ W, int I,
                                                               const float* __restrict__ Zprev,
                                                               float* __restrict__ dA) {
     __shared__ float Ds[ML_TB][ML_KC + 1];
@@ -112,7 +110,7 @@ __global__ __launch_bounds__(256) void linear_bwd_data_kernel(const float* __res
         }
         for (int e = tid; e < ML_KC * ML_TO; e += 256) {
             const int r = e / ML_TO, c = e % ML_TO;
-            Ws[r][c] = (k0 + r < O && i0 + c < I) ? ldw(W, (size_t)(k0 + r) * I + i0 + c) : 0.f;
+            Ws[r][c] = (k0 + r < O && i0 + c < I) ? W[(size_t)(k0 + r) * I + i0 + c] : 0.f;
         }
         __syncthreads();
 #pragma unroll 8
@@ -151,6 +149,136 @@ __global__ void linear_bwd_weight_kernel(const float* __restrict__ dZ, const flo
         for (int b = 0; b < B; ++b) acc += dZ[(size_t)b * O + o];
         gb[o] = acc;
     }
+}
+
+// ---------------------------------------------------------------------------
+// bfloat16 matrix-core products.  C (M x N) = sum_k a(m, k) b(k, n) with
+//   MM_FWD:         a = A (B x I), b(k, n) = W[n][k]; M = B, N = O, K = I;
+//                   epilogue z = C + bias, Z = z, Aout = gelu(z) or z
+//   MM_BWD_DATA:    a = dZ (B x O), b(k, n) = W[k][n]; M = B, N = I, K = O;
+//                   epilogue dA = C (times gelu'(Zprev) when given)
+//   MM_BWD_WEIGHT:  a(m, k) = dZ[k][m], b(k, n) = A[k][n]; M = O, N = I, K = B;
+//                   epilogue gW = C
+// A workgroup (4 waves) owns a 32 x 64 tile of C; wave w a 16 x 32 strip
+// (two 16 x 16 MFMA blocks).  Per 32-wide k chunk the operands are staged in
+// LDS as bfloat16, k contiguous per row of a and per column of b, so that a
+// lane's 8 k values are one 16-byte read: lane l supplies row (column) l % 16
+// and k values 8 (l / 16) .. 8 (l / 16) + 7 of the chunk, for a and b alike.
+enum { MM_FWD = 0, MM_BWD_DATA = 1, MM_BWD_WEIGHT = 2 };
+constexpr int MM_TM = 32, MM_TN = 64, MM_KC = 32, MM_LD = MM_KC + 8;
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short s16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+struct MmArgs {
+    const float* a;
+    const void* b;          // bfloat16 weights (MM_FWD, MM_BWD_DATA) or FP32 A (MM_BWD_WEIGHT)
+    const float* bias;      // MM_FWD
+    const float* zprev;     // MM_BWD_DATA, may be null
+    float* out;             // Z, dA or gW
+    float* out2;            // MM_FWD: the activation
+    int M, N, K, act;
+};
+
+__device__ __forceinline__ bf16x8_t lds_bf16x8(const bf16_t* p) {
+    return __builtin_bit_cast(bf16x8_t, *(const s16x8_t*)p);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void mlp_mfma_kernel(MmArgs g) {
+    constexpr bool BSPLIT = MODE == MM_BWD_WEIGHT;   // b is FP32 too: split it
+    __shared__ __align__(16) bf16_t Ah[MM_TM * MM_LD], Al[MM_TM * MM_LD];
+    __shared__ __align__(16) bf16_t Bh[MM_TN * MM_LD], Bl[BSPLIT ? MM_TN * MM_LD : 8];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * MM_TM, n0 = blockIdx.x * MM_TN;
+    const int wm = (w & 1) * 16, wn = (w >> 1) * 32;
+    const int r = lane & 15, kg = (lane >> 4) * 8;
+    const float* A = g.a;
+    f32x4_t acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    for (int k0 = 0; k0 < g.K; k0 += MM_KC) {
+        // a: k contiguous in memory except for the weight gradient (m contiguous)
+        for (int e = tid; e < MM_TM * MM_KC; e += 256) {
+            const int mm = MODE == MM_BWD_WEIGHT ? e % MM_TM : e / MM_KC;
+            const int kk = MODE == MM_BWD_WEIGHT ? e / MM_TM : e % MM_KC;
+            const int m = m0 + mm, k = k0 + kk;
+            float v = 0.f;
+            if (m < g.M && k < g.K) v = MODE == MM_BWD_WEIGHT ? A[(size_t)k * g.M + m] : A[(size_t)m * g.K + k];
+            const bf16_t h = f_to_bf16(v);
+            Ah[mm * MM_LD + kk] = h;
+            Al[mm * MM_LD + kk] = f_to_bf16(v - bf16_to_f(h));
+        }
+        // b: k contiguous for the forward product, n contiguous otherwise
+        for (int e = tid; e < MM_TN * MM_KC; e += 256) {
+            const int nn = MODE == MM_FWD ? e / MM_KC : e % MM_TN;
+            const int kk = MODE == MM_FWD ? e % MM_KC : e / MM_TN;
+            const int n = n0 + nn, k = k0 + kk;
+            const bool in = n < g.N && k < g.K;
+            if (MODE == MM_BWD_WEIGHT) {
+                const float v = in ? ((const float*)g.b)[(size_t)k * g.N + n] : 0.f;
+                const bf16_t h = f_to_bf16(v);
+                Bh[nn * MM_LD + kk] = h;
+                Bl[nn * MM_LD + kk] = f_to_bf16(v - bf16_to_f(h));
+            } else {
+                const bf16_t* W = (const bf16_t*)g.b;
+                Bh[nn * MM_LD + kk] =
+                    in ? (MODE == MM_FWD ? W[(size_t)n * g.K + k] : W[(size_t)k * g.N + n]) : (bf16_t)0;
+            }
+        }
+        __syncthreads();
+        const bf16x8_t ah = lds_bf16x8(&Ah[(wm + r) * MM_LD + kg]);
+        const bf16x8_t al = lds_bf16x8(&Al[(wm + r) * MM_LD + kg]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const bf16x8_t bh = lds_bf16x8(&Bh[(wn + j * 16 + r) * MM_LD + kg]);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[j], 0, 0, 0);
+            if (BSPLIT) {
+                const bf16x8_t bl = lds_bf16x8(&Bl[(wn + j * 16 + r) * MM_LD + kg]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // lane l holds rows 4 (l / 16) + i, column l % 16 of each 16 x 16 block
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int n = n0 + wn + j * 16 + r;
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + wm + (lane >> 4) * 4 + i;
+            if (m >= g.M) continue;
+            const size_t o = (size_t)m * g.N + n;
+            float v = acc[j][i];
+            if (MODE == MM_FWD) {
+                v += g.bias[n];
+                g.out[o] = v;
+                g.out2[o] = g.act ? gelu_f(v) : v;
+            } else if (MODE == MM_BWD_DATA) {
+                if (g.zprev) v *= gelu_grad_f(g.zprev[o]);
+                g.out[o] = v;
+            } else {
+                g.out[o] = v;
+            }
+        }
+    }
+}
+
+// gb = column sums of dZ (B x O), the batch summed in order
+__global__ void bias_grad_kernel(const float* __restrict__ dZ, int B, int O, float* __restrict__ gb) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= O) return;
+    float acc = 0.f;
+    for (int b = 0; b < B; ++b) acc += dZ[(size_t)b * O + o];
+    gb[o] = acc;
+}
+
+template <int MODE>
+static hipError_t launch_mm(const MmArgs& g, hipStream_t s) {
+    dim3 grid((g.N + MM_TN - 1) / MM_TN, (g.M + MM_TM - 1) / MM_TM);
+    hipLaunchKernelGGL(mlp_mfma_kernel<MODE>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
 }
 
 // dY = 2 (Y - T) / (B O); loss = mean (Y - T)^2 (one workgroup, fixed order).
@@ -293,50 +421,65 @@ float* Mlp::grad_buf(int which) const {
     return work + off + (size_t)which * bmax * wmax;
 }
 
-template <class WT>
 static hipError_t run_fwd(const Mlp& net, int B, const float* X, float* Y, hipStream_t s) {
     const int L = (int)net.dims.size() - 1;
-    const WT* w = net.bf16 ? (const WT*)net.pb : (const WT*)net.p;
     const float* a = X;
     for (int l = 0; l < L; ++l) {
         const int I = net.dims[l], O = net.dims[l + 1];
         const size_t wo = net.woff[l];
         float* out = (l == L - 1) ? Y : net.act_in(l + 1);
-        dim3 grid((O + ML_TO - 1) / ML_TO, (B + ML_TB - 1) / ML_TB);
-        hipLaunchKernelGGL(linear_fwd_kernel<WT>, grid, dim3(256), 0, s, a, B, I, w + wo, net.p + wo + (size_t)O * I,
-                           O, l < L - 1 ? 1 : 0, net.pre(l), out);
-        hipError_t e = hipGetLastError();
+        const int act = l < L - 1 ? 1 : 0;
+        hipError_t e;
+        if (net.bf16) {
+            MmArgs g{a, (const bf16_t*)net.pb + wo, net.p + wo + (size_t)O * I, nullptr, net.pre(l), out, B, O, I, act};
+            e = launch_mm<MM_FWD>(g, s);
+        } else {
+            dim3 grid((O + ML_TO - 1) / ML_TO, (B + ML_TB - 1) / ML_TB);
+            hipLaunchKernelGGL(linear_fwd_kernel, grid, dim3(256), 0, s, a, B, I, net.p + wo,
+                               net.p + wo + (size_t)O * I, O, act, net.pre(l), out);
+            e = hipGetLastError();
+        }
         if (e != hipSuccess) return e;
         a = out;
     }
     return hipSuccess;
 }
 
-hipError_t Mlp::forward(int B, const float* X, float* Y, hipStream_t s) {
-    return bf16 ? run_fwd<bf16_t>(*this, B, X, Y, s) : run_fwd<float>(*this, B, X, Y, s);
-}
+hipError_t Mlp::forward(int B, const float* X, float* Y, hipStream_t s) { return run_fwd(*this, B, X, Y, s); }
 
-template <class WT>
 static hipError_t run_bwd(const Mlp& net, int B, const float* X, const float* dY, hipStream_t s) {
     const int L = (int)net.dims.size() - 1;
-    const WT* w = net.bf16 ? (const WT*)net.pb : (const WT*)net.p;
     const float* dZ = dY;
     int which = 0;
     for (int l = L - 1; l >= 0; --l) {
         const int I = net.dims[l], O = net.dims[l + 1];
         const size_t wo = net.woff[l];
         const float* a_in = (l == 0) ? X : net.act_in(l);
-        const size_t nw = (size_t)O * I + O;
-        hipLaunchKernelGGL(linear_bwd_weight_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, dZ, a_in, B,
-                           O, I, net.g + wo, net.g + wo + (size_t)O * I);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        hipError_t e;
+        if (net.bf16) {
+            MmArgs g{dZ, a_in, nullptr, nullptr, net.g + wo, nullptr, O, I, B, 0};
+            if ((e = launch_mm<MM_BWD_WEIGHT>(g, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(bias_grad_kernel, dim3((O + 255) / 256), dim3(256), 0, s, dZ, B, O,
+                               net.g + wo + (size_t)O * I);
+        } else {
+            const size_t nw = (size_t)O * I + O;
+            hipLaunchKernelGGL(linear_bwd_weight_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, dZ,
+                               a_in, B, O, I, net.g + wo, net.g + wo + (size_t)O * I);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         if (l == 0) break;
         float* dA = net.grad_buf(which);
         which ^= 1;
-        dim3 grid((I + ML_TO - 1) / ML_TO, (B + ML_TB - 1) / ML_TB);
-        hipLaunchKernelGGL(linear_bwd_data_kernel<WT>, grid, dim3(256), 0, s, dZ, B, O, w + wo, I, net.pre(l - 1), dA);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (net.bf16) {
+            MmArgs g{dZ, (const bf16_t*)net.pb + wo, nullptr, net.pre(l - 1), dA, nullptr, B, I, O, 0};
+            e = launch_mm<MM_BWD_DATA>(g, s);
+        } else {
+            dim3 grid((I + ML_TO - 1) / ML_TO, (B + ML_TB - 1) / ML_TB);
+            hipLaunchKernelGGL(linear_bwd_data_kernel, grid, dim3(256), 0, s, dZ, B, O, net.p + wo, I,
+                               net.pre(l - 1), dA);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return e;
         dZ = dA;
     }
     return hipSuccess;
@@ -351,7 +494,7 @@ hipError_t Mlp::loss_grad(int B, const float* X, const float* T, hipStream_t s) 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, s, Y, T, B * nout, dY, dloss);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return bf16 ? run_bwd<bf16_t>(*this, B, X, dY, s) : run_bwd<float>(*this, B, X, dY, s);
+    return run_bwd(*this, B, X, dY, s);
 }
 
 hipError_t Mlp::adam(float lr, hipStream_t s) {

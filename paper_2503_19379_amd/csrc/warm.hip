@@ -465,23 +465,34 @@ int WarmStart::reset(hipStream_t s) {
     return net.randomize(seed, s);
 }
 
+// The network's input row (device FP32, 6 + 2 mb + 4 mb^2): k_next L / pi,
+// (k_next - k_prev) L / pi, the Ritz values at k_j and k_{j-1} over
+// (2 pi / L)^2, then C_j (2mb x mb c128, row-major) as (re, im) pairs.  The
+// head is staged in `stage` (pinned host, 6 + 2 mb floats), which the copy
+// reads until the stream reaches it.
+hipError_t warm_feature_row(double L, int mb, const double* k_prev, const double* k_next, const double* lam_j,
+                            const double* lam_jm1, const double2* Cj, float* row, float* stage, hipStream_t s) {
+    const double sc = L / M_PI, ls = std::pow(2.0 * M_PI / L, 2);
+    for (int i = 0; i < 3; ++i) {
+        stage[i] = (float)(k_next[i] * sc);
+        stage[3 + i] = (float)((k_next[i] - k_prev[i]) * sc);
+    }
+    for (int q = 0; q < mb; ++q) {
+        stage[6 + q] = (float)(lam_j[q] / ls);
+        stage[6 + mb + q] = (float)(lam_jm1[q] / ls);
+    }
+    hipError_t e = hipMemcpyAsync(row, stage, (6 + 2 * mb) * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    const int cnt = 2 * mb * mb;
+    hipLaunchKernelGGL(warm_reals_kernel, dim3((cnt + 255) / 256), dim3(256), 0, s, (const C128*)Cj,
+                       (const C128*)nullptr, cnt, row + 6 + 2 * mb);
+    return hipGetLastError();
+}
+
 static hipError_t feature_row(WarmStart& w, const double* k_prev, const double* k_next, const double* lam_j,
                               const double* lam_jm1, const C128* Cj, float* row, hipStream_t s) {
-    const double sc = w.L / M_PI, ls = std::pow(2.0 * M_PI / w.L, 2);
-    for (int i = 0; i < 3; ++i) {
-        w.hstage[i] = (float)(k_next[i] * sc);
-        w.hstage[3 + i] = (float)((k_next[i] - k_prev[i]) * sc);
-    }
-    for (int q = 0; q < w.mb; ++q) {
-        w.hstage[6 + q] = (float)(lam_j[q] / ls);
-        w.hstage[6 + w.mb + q] = (float)(lam_jm1[q] / ls);
-    }
-    hipError_t e = hipMemcpyAsync(row, w.hstage, (6 + 2 * w.mb) * sizeof(float), hipMemcpyHostToDevice, s);
+    hipError_t e = warm_feature_row(w.L, w.mb, k_prev, k_next, lam_j, lam_jm1, (const double2*)Cj, row, w.hstage, s);
     if (e != hipSuccess) return e;
-    const int cnt = 2 * w.mb * w.mb;
-    hipLaunchKernelGGL(warm_reals_kernel, dim3((cnt + 255) / 256), dim3(256), 0, s, Cj, (const C128*)nullptr, cnt,
-                       row + 6 + 2 * w.mb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     // the staging buffer is reused by the next row: wait for the copy
     return hipStreamSynchronize(s);
 }

@@ -22,8 +22,9 @@ def B():
     return binding
 
 
-# the production shape for mb = 8 columns (6 bands + 2 guard), and a ragged small one
-SHAPES = [(6 + 16 + 256, 256, 3, 256, 5), (37, 20, 2, 19, 3)]
+# the production shapes for mb = 8 columns (6 bands + 2 guard) and mb = 22
+# (20 bands + 2 guard, a full replay buffer), and a ragged small one
+SHAPES = [(6 + 16 + 256, 256, 3, 256, 5), (6 + 44 + 1936, 256, 3, 1936, 64), (37, 20, 2, 19, 3)]
 
 
 def _net(B, nin, nh, nl, nout, bmax, bf16, seed=0):
@@ -69,7 +70,7 @@ def test_mlp_forward_and_gradient(B, shape, bf16):
 
 
 def test_mlp_adam_step(B):
-    nin, nh, nl, nout, bmax = SHAPES[1]
+    nin, nh, nl, nout, bmax = SHAPES[-1]   # the ragged small shape
     net, shapes, theta, X, T = _net(B, nin, nh, nl, nout, bmax, False, seed=2)
     Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
     th = theta.astype(np.float64)
@@ -130,6 +131,21 @@ def test_warm_target_dependent_blocks(B):
     with pytest.raises(B.MfdError) as e:
         B.mfd_warm_target(dev(Xb), dev(Xb), dev(Xc), C)
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("mb,L", [(8, 1.0), (22, 1.7)])
+def test_warm_features_vs_oracle(B, mb, L):
+    """The network's input row built on the device equals the oracle's
+    features() (FP32 rounding of the FP64 values)."""
+    rng = np.random.default_rng(mb)
+    k_prev, k_next = rng.standard_normal(3), rng.standard_normal(3)
+    lam_j, lam_jm1 = rng.random(mb) * 40, rng.random(mb) * 40
+    C = rng.standard_normal((2 * mb, mb)) + 1j * rng.standard_normal((2 * mb, mb))
+    row = torch.empty(6 + 2 * mb + 4 * mb * mb, dtype=torch.float32, device="cuda")
+    B.mfd_warm_features(L, k_prev, k_next, lam_j, lam_jm1, torch.from_numpy(C).cuda(), row)
+    ref = omlp.features(k_prev, k_next, lam_j, lam_jm1, C, L=L)
+    assert ref.shape == row.shape
+    assert np.array_equal(row.cpu().numpy(), ref.astype(np.float32))
 
 
 def _path_run(B, ctx, kp, m, tol, **kw):
