@@ -113,26 +113,43 @@ __global__ __launch_bounds__(64 * SUBS * T) void gram_mfma_kernel(const double2*
             if (V32 && col_is_f32(vcol[q], bm.mb)) f32m |= 1u << q;
         }
     }
+    // FP32 and FP64 columns prefetch into separate registers, and rows past
+    // the end are clamped to the last row and zeroed when the slab is
+    // written, so that the loads are the only writes to these registers: a
+    // wave may hold both kinds, and a register written on one side of the
+    // exec-masked branch while the other side's load is in flight makes the
+    // compiler drain every load before it
     double2 pf[GM_PF];
+    float2 pf32[GM_PF];
     auto prefetch = [&](size_t s0) {
-        const bool inb = s0 + srow < r1;
+        const size_t row = min(s0 + srow, r1 - 1);
+        // nothing is in flight here (the previous slab's registers were
+        // written to LDS), but the compiler's wait tracking does not see it
+        // through the exec-masked branches below and would otherwise drain
+        // the loads one q at a time: vmcnt(0), the other counters left open
+        __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
         for (int q = 0; q < GM_PF; ++q) {
-            pf[q] = mk<double2>(0.0, 0.0);
-            if (((okm >> q) & 1u) && inb) {
-                const size_t o = (size_t)vcol[q] * ld + s0 + srow;
-                if ((f32m >> q) & 1u) pf[q].x = __builtin_bit_cast(double, V32[o]);
+            if ((okm >> q) & 1u) {
+                const size_t o = (size_t)vcol[q] * ld + row;
+                if ((f32m >> q) & 1u) pf32[q] = V32[o];
                 else pf[q] = V[o];
             }
         }
     };
-    auto fill = [&](double2* slab) {
+    // the registers are read on every lane, outside the branch on the
+    // ordinal, so that the wait for the loads is not conditional either
+    auto fill = [&](double2* slab, size_t s0) {
+        const bool inb = s0 + srow < r1;
 #pragma unroll
-        for (int q = 0; q < GM_PF; ++q)
-            if ((okm >> q) & 1u) slab[srow * C2 + scol[q]] = widen(pf[q], (f32m >> q) & 1u);
+        for (int q = 0; q < GM_PF; ++q) {
+            double2 v = ((f32m >> q) & 1u) ? mk<double2>((double)pf32[q].x, (double)pf32[q].y) : pf[q];
+            if (!inb) v = mk<double2>(0.0, 0.0);
+            if ((okm >> q) & 1u) slab[srow * C2 + scol[q]] = v;
+        }
     };
     prefetch(r0);
-    fill(slabs);
+    fill(slabs, r0);
     __syncthreads();
     int buf = 0;
     for (size_t s0 = r0; s0 < r1; s0 += GM_KS) {
@@ -152,8 +169,11 @@ __global__ __launch_bounds__(64 * SUBS * T) void gram_mfma_kernel(const double2*
                 acc[t][2] = mfma64(amd, b.x + b.y, acc[t][2]);
             }
         }
-        // the free slab was last read before the previous barrier
-        if (more) fill(slabs + (buf ^ 1) * SL);
+        // the free slab was last read before the previous barrier.  After
+        // the last slab this writes stale registers into it, which nothing
+        // reads; filling unconditionally keeps the wait for the prefetch on
+        // every path, so no load appears in flight at the top of the loop
+        fill(slabs + (buf ^ 1) * SL, s0 + GM_KS);
         __syncthreads();
         buf ^= 1;
     }
