@@ -159,11 +159,20 @@ __global__ __launch_bounds__(64 * SUBS * T) void gram_mfma_kernel(const double2*
 #pragma unroll
         for (int k0 = 4 * sub; k0 < GM_KS; k0 += 4 * SUBS) {
             const double2* srow_p = slab + (k0 + lk) * C2;
+            // every fragment of the step is read before the first product, so
+            // that one LDS round trip, not one per tile, precedes the matrix
+            // work (T = 5 has no registers to spare for it)
+            constexpr bool ALLB = T <= 4;
             const double2 a = va ? srow_p[ia] : mk<double2>(0.0, 0.0);
+            double2 bt[TG];
+            if constexpr (ALLB) {
+#pragma unroll
+                for (int t = 0; t < TG; ++t) bt[t] = vb[t] ? srow_p[ob[t]] : mk<double2>(0.0, 0.0);
+            }
             const double amd = a.x - a.y;
 #pragma unroll
             for (int t = 0; t < TG; ++t) {
-                const double2 b = vb[t] ? srow_p[ob[t]] : mk<double2>(0.0, 0.0);
+                const double2 b = ALLB ? bt[t] : (vb[t] ? srow_p[ob[t]] : mk<double2>(0.0, 0.0));
                 acc[t][0] = mfma64(a.x, b.x, acc[t][0]);
                 acc[t][1] = mfma64(a.y, b.y, acc[t][1]);
                 acc[t][2] = mfma64(amd, b.x + b.y, acc[t][2]);
