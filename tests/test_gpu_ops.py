@@ -23,10 +23,12 @@ def B():
 KS = [np.array([0.7, -0.4, 1.3]), np.zeros(3), np.array([np.pi, np.pi, np.pi])]
 
 
-@pytest.mark.parametrize("N", [8, 12, 24, 32, 64, 100])
+@pytest.mark.parametrize("N", [8, 12, 20, 24, 32, 64, 96, 100, 128])
 @pytest.mark.parametrize("ki", [0, 1, 2])
 def test_op_apply_fp64(B, N, ki):
-    """N = 100: odd z chunks (the stencil's two-plane loop ends on a half step)."""
+    """Every lane layout of the stencil: whole rows packed 8, 5, 3, 2 and 2 to
+    a wave (N = 8, 12, 20, 24, 32), one row (64), and rows cut into segments
+    with halo lanes: 2 x 48 (96), 2 x 50 (100) and 43 + 43 + 42 (128)."""
     rng = np.random.default_rng(100 + N + ki)
     L = 1.0
     k = KS[ki]
@@ -44,9 +46,10 @@ def test_op_apply_fp64(B, N, ki):
     assert rel_err(Yd.cpu().numpy(), ref) < 1e-13
 
 
-@pytest.mark.parametrize("N", [16, 48, 100, 128])
+@pytest.mark.parametrize("N", [16, 48, 96, 100, 120, 128])
 def test_op_apply_fp32(B, N):
-    """N = 100: odd z chunks; N = 128: the 1024-thread stencil workgroups."""
+    """Rows packed 4 to a wave (16), a 48-lane row (48), and segmented rows
+    (96, 100, 120: two segments, 128: three)."""
     rng = np.random.default_rng(7 + N)
     L, k = 1.0, np.array([0.3, 0.2, -0.9]) * np.pi
     eps = rand_eps(rng, N)
@@ -61,7 +64,7 @@ def test_op_apply_fp32(B, N):
     assert rel_err(Yd.cpu().numpy(), ref) < 2e-6
 
 
-@pytest.mark.parametrize("N", [16, 64, 100])
+@pytest.mark.parametrize("N", [16, 24, 32, 48, 64, 96, 100])
 @pytest.mark.parametrize("ki", [0, 1])
 def test_op_apply_fp32_storage_fp64_arith(B, N, ki):
     """MFD_C64_F64, the operator the mixed-precision solver applies to its
