@@ -54,7 +54,9 @@ def parse():
                     help="mixed: FP32 corrections with FP64 refinement, the workload's own precision")
     ap.add_argument("--nk", type=int, default=0, help="k-points per step (0: the workload's path)")
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--guard", type=int, default=2)
+    ap.add_argument("--guard", type=int, default=4,
+                    help="extra block columns beyond the bands (16 + 4 = 20 columns: fewest seconds per "
+                         "k-point of guard 2..6 on the diamond N = 64 path)")
     ap.add_argument("--streams", type=int, default=12, help="k-path segments solved concurrently")
     ap.add_argument("--warm", default="prev", choices=["prev", "learned"],
                     help="start block after a segment's first k-point: previous k, or the learned proposal")

@@ -174,7 +174,7 @@ def test_mg_preconditioned_lobpcg_reaches_dense_bands():
     """LOBPCG preconditioned by two V-cycles of the distributive solve reaches
     the lowest eigenvalues of the dense compensated matrix (random eps)."""
     rng = np.random.default_rng(6)
-    N, L, m = 8, 1.0, 6
+    N, L, m = 6, 1.0, 6
     k = np.array([0.5, 0.1, 0.2]) * np.pi
     eps = 1.0 + 12.0 * (rng.random((N, N, N)) < 0.3)
     mu = mfd.mu_from_eps(eps)

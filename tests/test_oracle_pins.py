@@ -431,7 +431,7 @@ def test_divergence_free_eigenvectors():
 def test_k_symmetry():
     """Real eps: lambda(k) = lambda(-k); a cubic-symmetric crystal is invariant
     under permutations of k's components."""
-    N, L = 8, 1.0
+    N, L = 6, 1.0
     eps = workloads.eps_sphere(N)
     k = np.array([0.6, 0.3, 0.1]) * np.pi
     g = mfd.gamma_rule(N, L, k)
