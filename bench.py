@@ -158,9 +158,18 @@ def batch_variant(B, args, torch, count):
     return out
 
 
+def gap_streams(args, N, mb):
+    """Segments for a band-structure run: at most args.streams, and no more
+    mixed-precision workspaces (V and U with 6 mb columns of n = 3 N^3 rows,
+    in FP64 and again in FP32: 48 bytes per entry pair) than fit in 200 GB of
+    HBM (6 at N = 150 with 12 columns)."""
+    per = 3 * N ** 3 * 6 * mb * (2 * 16 + 2 * 8)
+    return max(1, min(args.streams, int(200e9 // per)))
+
+
 def band_gap_variant(B, args, torch):
     """Section 6.2's curved-interface cubic cell (sphere 0.345 + three
-    cylinders 0.11, eps 13 in 1, M_0 set per edge) at N = 120: 10 bands along
+    cylinders 0.11, eps 13 in 1, M_0 set per edge) at the paper's N = 150: 10 bands along
     Gamma-X-M-Gamma-R-X-M-R with every symmetry point, the paper's tolerance
     1e-5, mixed precision, then the band-gap ratio.  One timed call after an
     untimed one at the first k-point."""
@@ -169,7 +178,8 @@ def band_gap_variant(B, args, torch):
     N = cfg["N"]
     kp = workloads.kpath_vertices(cfg["path"], cfg["nk"])
     ctx = B.mfd_build_mu(N, 1.0, 2, workloads.mu_sc_sphere_cylinders(N))
-    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, streams=args.streams)
+    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500,
+                       streams=gap_streams(args, N, cfg["nbands"] + 2))
     B.mfd_bands(ctx, kp[:1], cfg["nbands"], cfg["tol"], o)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -182,7 +192,7 @@ def band_gap_variant(B, args, torch):
     return {"value": ok / dt, "unit": "k-points/s", "steps": 1, "ms_per_step": dt * 1e3,
             "iters_per_k": float(np.mean([x["iters"] for x in st])), "converged_kpoints": ok,
             "total_kpoints": len(st), "gap_ratio": ratio, "gap_above_band": below,
-            "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"],
+            "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"], "segments": o.streams,
             "workload": f"simple cubic sphere r 0.345 + 3 cylinders r 0.11, eps 13 in 1, M_0 per edge, N = {N}, "
                         f"{len(kp)} k-points on {cfg['path']}, {cfg['nbands']} bands, tol {cfg['tol']:g}, mixed"}
 
@@ -234,8 +244,8 @@ def gyroid_variant(B, args, torch):
     bands at k = (pi, pi, pi)/l to the paper's tolerance 1e-5 from a random
     start, N = 100 and 120, one timed solve after an untimed one; the paper's
     steps and its A100 seconds are carried beside for context.  (2) The band
-    structure on H'-Gamma-P-N-H at N = 120 and its gap ratio.  (3) The
-    lattice operator alone on a 12-band block at N = 120
+    structure on H'-Gamma-P-N-H at the paper's N = 150 and its gap ratio.
+    (3) The lattice operator alone on a 12-band block at N = 120
     (lattice_op_direct)."""
     from paper_2503_19379_amd import workloads
     cfg = workloads.CONFIGS["bcc_gyroid"]
@@ -255,19 +265,26 @@ def gyroid_variant(B, args, torch):
         out[f"P_N{N}"] = {"value": 1.0 / dt, "unit": "k-points/s", "ms": dt * 1e3, "iters": st[0]["iters"],
                           "max_rel_resid": st[0]["max_rel_resid"], "status": status}
         if N == cfg["Ns"][-1]:
-            kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.bcc_points())
-            o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, streams=args.streams)
-            t0 = time.perf_counter()
-            ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], o)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            ratio, below = B.mfd_gap_ratio(ev, kp)
-            ok = sum(1 for x in st if x["max_rel_resid"] <= cfg["tol"])
-            out[f"path_N{N}"] = {"value": ok / dt, "unit": "k-points/s", "ms": dt * 1e3, "kpoints": len(kp),
-                                 "converged_kpoints": ok, "gap_ratio": ratio, "gap_above_band": below,
-                                 "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"]}
             out["lattice_operator"] = lattice_op_direct(B, ctx, kP[0], cfg["nbands"] + 2, N, torch)
         ctx.close()
+    N = cfg["N_path"]
+    ctx = B.mfd_build_lattice_mu(N, A, 2, workloads.mu_bcc_gyroid(N))
+    kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.bcc_points())
+    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500,
+                       streams=gap_streams(args, N, cfg["nbands"] + 2))
+    B.mfd_bands(ctx, kp[:1], cfg["nbands"], cfg["tol"], o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ratio, below = B.mfd_gap_ratio(ev, kp)
+    ok = sum(1 for x in st if x["max_rel_resid"] <= cfg["tol"])
+    out[f"path_N{N}"] = {"value": ok / dt, "unit": "k-points/s", "ms": dt * 1e3, "kpoints": len(kp),
+                         "converged_kpoints": ok, "gap_ratio": ratio, "gap_above_band": below,
+                         "gap_ratio_paper": cfg["gap_ratio_paper"], "N_paper": cfg["N_paper"],
+                         "segments": o.streams}
+    ctx.close()
     return out
 
 

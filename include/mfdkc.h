@@ -137,8 +137,9 @@ typedef struct {
 void mfd_default_opts(mfd_opts* opts);
 
 /* Build a context for one crystal (Section 4.4: M_0 from eps).
- * N: cells per axis, 4 <= N <= 128, with an FFT plan for N (N = 2^a 3^b 5^c
- *    supported by this build: see mfd_supported_n).
+ * N: cells per axis, 4 <= N <= 150, with an FFT plan for N (N = 2^a 3^b 5^c
+ *    supported by this build: 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96,
+ *    100, 120, 128, 150; see mfd_supported_n).
  * L: cell side (> 0).  order: stencil order 2, 4, 6 or 8 (Section 4.1.3,
  *    eq. (2kfdm), Table FD_1D with k = order / 2; the sixth-order c_1 is read as
  *    75/64, the value the stencil's consistency requires).  Order 2 uses the
@@ -224,8 +225,10 @@ int mfd_op_apply(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void*
  * forward FFT along each axis, the 3 x 3 symbol solve at every frequency
  * (closed-form rank-one inverse: P_hat = s I + (gamma - 1) conj(d) d^T),
  * inverse FFT along each axis.  R and T may be the same buffer.
- * The x-y plane pass holds a whole plane in LDS: MFD_C128 needs N <= 96
- * (MFD_EUNSUPPORTED above), MFD_C64 every N that mfd_supported_n accepts. */
+ * Both dtypes take every N that mfd_supported_n accepts.  The x-y plane pass
+ * holds a whole plane in LDS where it fits (MFD_C128 up to N = 96, MFD_C64 up
+ * to 128); above that it runs as an x pass and a y pass, two more reads and
+ * writes of the block. */
 int mfd_precond_solve(mfd_ctx* ctx, const double k[3], int nb, int dtype, const void* R, void* T,
                       void* stream);
 

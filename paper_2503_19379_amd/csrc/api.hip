@@ -285,7 +285,7 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
           chk(hipHostMalloc(&w->host, (8 * mb + 32) * sizeof(double), hipHostMallocDefault)) &&
           (!mixed || (chk(hipMalloc(&w->V32, n * 6 * mb * sizeof(float2))) &&
                       chk(hipMalloc(&w->U32, n * 6 * mb * sizeof(float2))))) &&
-          (mixed || fft_supported(c->N, 8) || chk(hipMalloc(&w->stage32, n * mb * sizeof(float2)))) &&
+          (mixed || fft_plane_fits(c->N, 8) || chk(hipMalloc(&w->stage32, n * mb * sizeof(float2)))) &&
           (c->order == 2 || chk(hipMalloc(&w->wtmp, (size_t)c->wtmp_bands * 4 * (n / 3) * sizeof(double2)))))) {
         ws_free(w);
         return fail(e == hipErrorOutOfMemory ? MFD_ENOMEM : MFD_EDEVICE, hipGetErrorString(e));
@@ -325,13 +325,13 @@ struct KResult {
 };
 
 // W <- T W in place for the listed FP64 fields (field fl(t) at W + n fl(t)).
-// Grids whose FP64 plane FFT does not fit in LDS (N = 100, 120, 128) stage the
+// Grids whose FP64 plane FFT does not fit in LDS (N = 100, 120, 128, 150) stage the
 // fields through FP32 in `stage` (same field positions): T only approximates
 // the operator's inverse, so its rounding slows LOBPCG at most slightly and
 // does not limit the accuracy the residual test certifies.
 hipError_t precond_fp64(const mfd_ctx* c, const OpParams& p, int na, double2* W, float2* stage, size_t n,
                         const FieldList& fl, hipStream_t s) {
-    if (fft_supported(c->N, 8)) return launch_precond<double>(p, na, W, W, c->tw64, s, fl);
+    if (fft_plane_fits(c->N, 8)) return launch_precond<double>(p, na, W, W, c->tw64, s, fl);
     if (!stage) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     for (int t = 0; t < na && e == hipSuccess; ++t) e = launch_convert(W + n * fl(t), stage + n * fl(t), n, true, s);
@@ -1316,7 +1316,7 @@ int mfd_set_tuning(mfd_ctx* ctx, const int* in) {
 int mfd_max_block(void) { return MAX_BLOCK; }
 
 int mfd_supported_n(int N) {
-    return (N >= 4 && N <= 128 && fft_supported(N, 4)) ? 1 : 0;
+    return (N >= 4 && N <= 150 && fft_supported(N, 4)) ? 1 : 0;
 }
 
 }  // extern "C"
@@ -1331,7 +1331,7 @@ int build_ctx(int N, double L, int order, const double* src, bool edges, void* s
     if (!out) return fail(MFD_EINVAL, "out is NULL");
     *out = nullptr;
     if (!src) return fail(MFD_EINVAL, edges ? "mu_edges is NULL" : "eps_cells is NULL");
-    if (N < 4 || N > 128) return fail(MFD_EINVAL, "N must be in [4, 128]");
+    if (N < 4 || N > 150) return fail(MFD_EINVAL, "N must be in [4, 150]");
     if (!(L > 0.0) || !std::isfinite(L)) return fail(MFD_EINVAL, "L must be finite and > 0");
     if (order != 2 && order != 4 && order != 6 && order != 8)
         return fail(MFD_EUNSUPPORTED, "stencil order must be 2, 4, 6 or 8");

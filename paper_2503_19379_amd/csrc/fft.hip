@@ -179,6 +179,87 @@ __global__ __launch_bounds__(plane_nt(N)) void fft_plane_kernel(const cplx<R>* i
     for (int i = tid; i < N * N; i += NT) dst[i] = buf[i];
 }
 
+// Grids whose N x N plane does not fit in LDS (N = 150): kernels 1 and 3 are
+// each split into a pass along x and a pass along y.
+//   x pass: XL consecutive x lines of one (band, component, z) plane (they are
+//     contiguous in memory) per workgroup;
+//   y pass: N y values of XB consecutive x columns of one plane per workgroup,
+//     rows of XB cells read and written coalesced.
+template <int N> constexpr int line_block(int cap) {
+    int b = 1;
+    for (int d = 1; d <= cap; ++d)
+        if (N % d == 0) b = d;
+    return b;
+}
+template <int N> constexpr int xl_lines() { return line_block<N>(16); }
+template <int N> constexpr int yl_cols() { return line_block<N>(32); }
+
+template <class R, int N, bool INV>
+__global__ __launch_bounds__(FFT_NT) void fft_xlines_kernel(const cplx<R>* in, cplx<R>* out, const cplx<R>* tw_g,
+                                                           FieldList fl) {
+    using T = cplx<R>;
+    constexpr int XL = xl_lines<N>();
+    extern __shared__ unsigned char smem_raw[];
+    T* buf = reinterpret_cast<T*>(smem_raw);   // [XL][N]
+    T* tw = buf + XL * N;
+    const int tid = threadIdx.x;
+    constexpr int NCH = N / XL;                // line blocks per plane
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const size_t plane = (size_t)fl(bid / (3 * N * NCH)) * 3 * N + (bid / NCH) % (3 * N);
+    const size_t off = plane * N * N + (size_t)(bid % NCH) * XL * N;
+    for (int i = tid; i < N; i += FFT_NT) tw[i] = tw_g[i];
+    for (int i = tid; i < XL * N; i += FFT_NT) buf[i] = in[off + i];
+    __syncthreads();
+    fft_lines<T, N, XL, FFT_NT, INV, false, 1>(buf, tw, [](int l, int j) { return l * N + j; }, tid);
+    for (int i = tid; i < XL * N; i += FFT_NT) out[off + i] = buf[i];
+}
+
+template <class R, int N, bool INV>
+__global__ __launch_bounds__(FFT_NT) void fft_ylines_kernel(const cplx<R>* in, cplx<R>* out, const cplx<R>* tw_g,
+                                                           FieldList fl) {
+    using T = cplx<R>;
+    constexpr int XB = yl_cols<N>();
+    extern __shared__ unsigned char smem_raw[];
+    T* buf = reinterpret_cast<T*>(smem_raw);   // [N (y)][XB]
+    T* tw = buf + N * XB;
+    const int tid = threadIdx.x;
+    constexpr int NXB = N / XB;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const size_t plane = (size_t)fl(bid / (3 * N * NXB)) * 3 * N + (bid / NXB) % (3 * N);
+    const size_t off = plane * N * N + (size_t)(bid % NXB) * XB;
+    for (int i = tid; i < N; i += FFT_NT) tw[i] = tw_g[i];
+    for (int i = tid; i < N * XB; i += FFT_NT) buf[i] = in[off + (size_t)(i / XB) * N + i % XB];
+    __syncthreads();
+    fft_lines<T, N, XB, FFT_NT, INV, true, 1>(buf, tw, [](int l, int j) { return j * XB + l; }, tid);
+    for (int i = tid; i < N * XB; i += FFT_NT) out[off + (size_t)(i / XB) * N + i % XB] = buf[i];
+}
+
+template <class R, int N>
+static hipError_t split_plane(const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, int nb, bool inv, hipStream_t s,
+                              const FieldList& fl) {
+    using T = cplx<R>;
+    constexpr int XL = xl_lines<N>(), XB = yl_cols<N>();
+    const size_t lx = (size_t)(XL * N + N) * sizeof(T), ly = (size_t)(N * XB + N) * sizeof(T);
+    auto kx = inv ? fft_xlines_kernel<R, N, true> : fft_xlines_kernel<R, N, false>;
+    auto ky = inv ? fft_ylines_kernel<R, N, true> : fft_ylines_kernel<R, N, false>;
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void*)kx, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lx)) != hipSuccess ||
+        (e = hipFuncSetAttribute((const void*)ky, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ly)) != hipSuccess)
+        return e;
+    const unsigned gx = (unsigned)(nb * 3 * N * (N / XL)), gy = (unsigned)(nb * 3 * N * (N / XB));
+    // forward: x then y; inverse: y then x (as the plane kernel)
+    if (!inv) {
+        hipLaunchKernelGGL(kx, dim3(gx), dim3(FFT_NT), lx, s, in, out, tw, fl);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(ky, dim3(gy), dim3(FFT_NT), ly, s, (const T*)out, out, tw, fl);
+    } else {
+        hipLaunchKernelGGL(ky, dim3(gy), dim3(FFT_NT), ly, s, in, out, tw, fl);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(kx, dim3(gx), dim3(FFT_NT), lx, s, (const T*)out, out, tw, fl);
+    }
+    return hipGetLastError();
+}
+
 template <class R>
 struct SolveArgs {
     const cplx<R>* in;
@@ -312,7 +393,7 @@ __global__ __launch_bounds__(FFT_NT) void fft_zsolve_kernel(SolveArgs<R> a) {
 }
 
 static int pick_xc(int N) {
-    for (int xc : {16, 8, 4, 2, 1})
+    for (int xc : {16, 8, 4, 10, 2, 1})
         if (N % xc == 0) return xc;
     return 1;
 }
@@ -332,18 +413,23 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
                             const FieldList& fl) {
     if (fl.on && nb > 32) return hipErrorInvalidValue;
     using T = cplx<R>;
-    const size_t lds_plane = (size_t)(N * N + N) * sizeof(T);
-    if (lds_plane > 160 * 1024) return hipErrorInvalidValue;
+    constexpr size_t lds_plane = (size_t)(N * N + N) * sizeof(T);
+    constexpr bool SPLIT = lds_plane > 160 * 1024;
     auto kf = fft_plane_kernel<R, N, false>;
     auto ki = fft_plane_kernel<R, N, true>;
-    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_plane);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_plane);
-    if (e != hipSuccess) return e;
     const int nplanes = nb * 3 * N;
-    hipLaunchKernelGGL(kf, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Rin, (T*)Tout, (const T*)tw,
-                       fl);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipError_t e;
+    if constexpr (SPLIT) {
+        if ((e = split_plane<R, N>((const T*)Rin, (T*)Tout, (const T*)tw, nb, false, s, fl)) != hipSuccess) return e;
+    } else {
+        e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_plane);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_plane);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kf, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Rin, (T*)Tout,
+                           (const T*)tw, fl);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     SolveArgs<R> a;
     a.in = (const T*)Tout;
     a.out = (T*)Tout;
@@ -373,22 +459,26 @@ static hipError_t precond_n(const OpParams& p, int nb, const void* Rin, void* To
     const int xc = (p.fft_xc > 0 && N % p.fft_xc == 0 && p.fft_xc <= 16) ? p.fft_xc : pick_xc(N);
     switch (xc) {
         case 16: if constexpr (N % 16 == 0) e = zsolve_launch<R, N, 16>(a, nb, s); break;
+        case 10: if constexpr (N % 10 == 0 && N % 4) e = zsolve_launch<R, N, 10>(a, nb, s); break;
         case 8: if constexpr (N % 8 == 0) e = zsolve_launch<R, N, 8>(a, nb, s); break;
         case 4: if constexpr (N % 4 == 0) e = zsolve_launch<R, N, 4>(a, nb, s); break;
         case 2: if constexpr (N % 2 == 0) e = zsolve_launch<R, N, 2>(a, nb, s); break;
         default: e = zsolve_launch<R, N, 1>(a, nb, s); break;
     }
     if (e != hipSuccess) return e;
+    if constexpr (SPLIT) return split_plane<R, N>((const T*)Tout, (T*)Tout, (const T*)tw, nb, true, s, fl);
     hipLaunchKernelGGL(ki, dim3(nplanes), dim3(plane_nt(N)), lds_plane, s, (const T*)Tout, (T*)Tout, (const T*)tw,
                        fl);
     return hipGetLastError();
 }
 
-#define MFD_FFT_SIZES(X) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(100) X(120) X(128)
+#define MFD_FFT_SIZES(X) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(100) X(120) X(128) X(150)
+
+bool fft_plane_fits(int N, int real_bytes) { return (size_t)(N * N + N) * 2 * real_bytes <= 160 * 1024; }
 
 bool fft_supported(int N, int real_bytes) {
     switch (N) {
-#define CASE(n) case n: return fft_ok(n) && (size_t)(n * n + n) * 2 * real_bytes <= 160 * 1024;
+#define CASE(n) case n: return fft_ok(n);
         MFD_FFT_SIZES(CASE)
 #undef CASE
         default: return false;

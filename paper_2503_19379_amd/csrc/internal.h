@@ -69,6 +69,9 @@ template <class R>
 hipError_t launch_precond(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s,
                           const FieldList& fl = FieldList());
 bool fft_supported(int N, int real_bytes);
+// the x-y plane pass holds a whole plane in LDS (else it runs as separate x
+// and y passes, two more reads and writes of the block)
+bool fft_plane_fits(int N, int real_bytes);
 // FP32 register-resident passes (fft_reg.hip): cubic order-2 contexts of N = 16, 32, 64
 bool reg_precond_ok(const OpParams& p);
 hipError_t launch_precond_reg(const OpParams& p, int nb, const void* Rin, void* Tout, const void* tw, hipStream_t s,

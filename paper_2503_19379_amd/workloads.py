@@ -276,14 +276,15 @@ CONFIGS = {
     # 32 random-field crystals of uneven grids
     "random_batch": dict(Ns=(24, 32, 48, 64), ncrys=32, eps="random", path="GXMGR", nk=8,
                          nbands=12, tol=1e-8, precision="mixed"),
-    # simple cubic sphere + three cylinders (Section 6.2), M_0 on edges, band gap;
-    # the paper's grid is N = 150, beyond this build's FFT plans
-    "sc_sphere_cyl": dict(N=120, mu="sc_sphere_cyl", path="GXMGRXMR", nk=40, nbands=10, tol=1e-5,
+    # simple cubic sphere + three cylinders (Section 6.2), M_0 on edges, band gap
+    # at the paper's grid N = 150
+    "sc_sphere_cyl": dict(N=150, mu="sc_sphere_cyl", path="GXMGRXMR", nk=40, nbands=10, tol=1e-5,
                           precision="mixed", gap_ratio_paper=0.14019, N_paper=150),
     # BCC single gyroid (Section 6.3, Table time_comp_bc): first 10 bands at
-    # k = (pi, pi, pi)/l, N = 100 and 120, relative residual 1e-5
-    "bcc_gyroid": dict(Ns=(100, 120), lattice="bcc", mu="bcc_gyroid", k=(np.pi, np.pi, np.pi), nbands=10,
-                       tol=1e-5, precision="mixed", path="hGPNH", nk=40, gap_ratio_paper=0.31745,
+    # k = (pi, pi, pi)/l, N = 100 and 120, relative residual 1e-5; the band
+    # structure and gap at the paper's grid N = 150
+    "bcc_gyroid": dict(Ns=(100, 120), N_path=150, lattice="bcc", mu="bcc_gyroid", k=(np.pi, np.pi, np.pi),
+                       nbands=10, tol=1e-5, precision="mixed", path="hGPNH", nk=40, gap_ratio_paper=0.31745,
                        N_paper=150),
     # FCC sp3 diamond of spheres and spheroids (Section 6.3): band gap
     "fcc_diamond": dict(lattice="fcc", mu="fcc_diamond", path="XULGXWK", nk=40, nbands=10, tol=1e-5,

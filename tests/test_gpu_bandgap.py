@@ -164,3 +164,32 @@ def test_fcc_diamond_band_gap(B):
     print(f"N = {N}: FCC diamond gap ratio {r:.5f} above band {below} (the paper prints "
           f"{cfg['gap_ratio_paper']} at N = {cfg['N_paper']})")
     assert below == 2 and abs(r - cfg["gap_ratio_paper"]) < 0.005
+
+
+def test_paper_gap_ratios_at_n150(B):
+    """The paper's own grid, N = 150, for both of its printed band-gap ratios
+    (Section 6.2's cubic cell, Section 6.3's BCC gyroid), 10 bands, tol 1e-5,
+    mixed precision, 5 segments: every k-point converges and the ratios match
+    the printed 0.14019 (bands 5-6) and 0.31745 (bands 2-3) to their last
+    printed digit.  The FFT preconditioner runs its x-y plane pass as
+    separate x and y passes at this N."""
+    opts = B.default_opts(precision=1, warm_start=1, guard=2, streams=5, max_iter=500)
+    cfg = workloads.CONFIGS["sc_sphere_cyl"]
+    N = 150
+    kp = workloads.kpath_vertices(cfg["path"], cfg["nk"])
+    ctx = B.mfd_build_mu(N, 1.0, 2, workloads.mu_sc_sphere_cylinders(N))
+    ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], opts)
+    ctx.close()
+    assert status == 0 and all(s["max_rel_resid"] <= cfg["tol"] for s in st), st
+    r, below = B.mfd_gap_ratio(ev, kp)
+    print(f"cubic cell, N = 150: gap ratio {r:.6f} above band {below} (paper {cfg['gap_ratio_paper']})")
+    assert below == 5 and abs(r - cfg["gap_ratio_paper"]) < 5e-6
+    cfg = workloads.CONFIGS["bcc_gyroid"]
+    kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.bcc_points())
+    ctx = B.mfd_build_lattice_mu(N, workloads.lattice_vectors("bcc"), 2, workloads.mu_bcc_gyroid(N))
+    ev, st, status = B.mfd_bands(ctx, kp, cfg["nbands"], cfg["tol"], opts)
+    ctx.close()
+    assert status == 0 and all(s["max_rel_resid"] <= cfg["tol"] for s in st), st
+    r, below = B.mfd_gap_ratio(ev, kp)
+    print(f"BCC gyroid, N = 150: gap ratio {r:.6f} above band {below} (paper {cfg['gap_ratio_paper']})")
+    assert below == 2 and abs(r - cfg["gap_ratio_paper"]) < 5e-6

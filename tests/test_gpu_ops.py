@@ -46,10 +46,10 @@ def test_op_apply_fp64(B, N, ki):
     assert rel_err(Yd.cpu().numpy(), ref) < 1e-13
 
 
-@pytest.mark.parametrize("N", [16, 48, 96, 100, 120, 128])
+@pytest.mark.parametrize("N", [16, 48, 96, 100, 120, 128, 150])
 def test_op_apply_fp32(B, N):
     """Rows packed 4 to a wave (16), a 48-lane row (48), and segmented rows
-    (96, 100, 120: two segments, 128: three)."""
+    (96, 100, 120: two segments, 128 and 150: three)."""
     rng = np.random.default_rng(7 + N)
     L, k = 1.0, np.array([0.3, 0.2, -0.9]) * np.pi
     eps = rand_eps(rng, N)
@@ -117,9 +117,11 @@ def test_op_apply_n64_uneven_z_chunks(B, nb, dtype):
         assert rel_err(got, ref) < 2e-6
 
 
-@pytest.mark.parametrize("N", [8, 12, 20, 24, 32, 48, 64])
+@pytest.mark.parametrize("N", [8, 12, 20, 24, 32, 48, 64, 100, 150])
 @pytest.mark.parametrize("ki", [0, 1])
 def test_precond_fp64(B, N, ki):
+    """N = 100 and 150: FP64 planes larger than LDS, transformed as separate
+    x and y passes."""
     rng = np.random.default_rng(200 + N + ki)
     L = 1.0
     k = KS[ki]
@@ -153,12 +155,14 @@ def test_precond_fp32(B, N):
     assert rel_err(Td.cpu().numpy(), ref) < 5e-6
 
 
-@pytest.mark.parametrize("N,xrun", [(64, 4), (64, 8), (64, 16), (64, -1), (32, -1), (16, -1), (100, 0), (120, 0)])
+@pytest.mark.parametrize("N,xrun", [(64, 4), (64, 8), (64, 16), (64, -1), (32, -1), (16, -1), (100, 0), (120, 0),
+                                    (150, 0)])
 def test_precond_fp32_solver_instances(B, N, xrun):
     """Element-wise FP32 parity of the instances the solves run: N = 64 with
     each z-pass x run the autotuner may pick, the register-resident passes
-    (plan -1) at N = 16, 32, 64, and the radix-5 and radix-3 plans of N = 100
-    and 120 (band-gap workloads), on a two-field block at a generic k and at
+    (plan -1) at N = 16, 32, 64, the radix-5 and radix-3 plans of N = 100
+    and 120 (band-gap workloads), and N = 150 (split x and y passes, z runs of
+    10 x), on a two-field block at a generic k and at
     k = 0 (shifted)."""
     rng = np.random.default_rng(400 + N + xrun)
     L = 1.0

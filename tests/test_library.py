@@ -34,7 +34,7 @@ def test_host_only_calls():
     from paper_2503_19379_amd import binding as b
     L = b.lib()
     assert L.mfd_strerror(-1) == b"invalid argument"
-    assert b.mfd_supported_n(64) and b.mfd_supported_n(24) and b.mfd_supported_n(96)
+    assert b.mfd_supported_n(64) and b.mfd_supported_n(24) and b.mfd_supported_n(96) and b.mfd_supported_n(150)
     assert not b.mfd_supported_n(7) and not b.mfd_supported_n(2)
     o = b.default_opts()
     assert o.max_iter > 0 and o.max_gamma_doublings == 4
