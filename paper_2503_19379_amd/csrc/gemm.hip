@@ -719,14 +719,28 @@ __global__ __launch_bounds__(256, 2) void update_wave_kernel(const double2* __re
     // its S chain runs, the next strip's S fragments while its AS chain runs,
     // so each wave keeps one chain's loads in flight behind its matrix work.
     // The last prefetch repeats the wave's last strip (in bounds, unused).
-    Frag FA, FB;
+    // The widest instances (21 and 22 columns, and the FP64 one of up to 20
+    // columns at full basis) cannot hold two chains' fragments beside their
+    // accumulators without spilling: they load each chain just before it runs.
+    constexpr bool PIPE = NT < 5 && (MIX || KS0 < 10);
     size_t st = (size_t)blockIdx.x * 4 + wave;
-    if (st < nstrip) load(FA, st, 0);
-    for (; st < nstrip; st += nwaves) {
-        load(FB, st, 1);
-        chain(FA, st, 0);
-        load(FA, st + nwaves < nstrip ? st + nwaves : st, 0);
-        chain(FB, st, 1);
+    if constexpr (PIPE) {
+        Frag FA, FB;
+        if (st < nstrip) load(FA, st, 0);
+        for (; st < nstrip; st += nwaves) {
+            load(FB, st, 1);
+            chain(FA, st, 0);
+            load(FA, st + nwaves < nstrip ? st + nwaves : st, 0);
+            chain(FB, st, 1);
+        }
+    } else {
+        Frag F;
+        for (; st < nstrip; st += nwaves) {
+            load(F, st, 0);
+            chain(F, st, 0);
+            load(F, st, 1);
+            chain(F, st, 1);
+        }
     }
     // sums over the 4 waves in order
     __syncthreads();
