@@ -58,6 +58,9 @@ def parse():
                     help="extra block columns beyond the bands (16 + 4 = 20 columns: fewest seconds per "
                          "k-point of guard 2..6 on the diamond N = 64 path)")
     ap.add_argument("--streams", type=int, default=12, help="k-path segments solved concurrently")
+    ap.add_argument("--cold-start", default="planewave", choices=["planewave", "random"],
+                    help="start block of each segment's first k-point: the lowest transverse plane waves at k "
+                         "(opts.cold_start = 1) or seeded random values")
     ap.add_argument("--warm", default="prev", choices=["prev", "learned"],
                     help="start block after a segment's first k-point: previous k, or the learned proposal")
     ap.add_argument("--no-variants", action="store_true",
@@ -139,7 +142,7 @@ def batch_variant(B, args, torch, count):
                        f"N in {cfg['Ns']}, {cfg['nk']} k-points on {cfg['path']}, {cfg['nbands']} bands, "
                        f"tol {cfg['tol']:g}, mixed precision"}
     for name, graph in (("graph", 1), ("host_stepped", 0)):
-        o = B.default_opts(precision=1, warm_start=1, seed=0, guard=args.guard, max_iter=500,
+        o = B.default_opts(precision=1, warm_start=1, seed=0, guard=args.guard, max_iter=500, cold_start=cold(args),
                            streams=batch_workers(args), graph=graph)
         B.mfd_bands_batch(ctxs, [kp[:1]] * len(ctxs), cfg["nbands"], cfg["tol"], o)
         torch.cuda.synchronize()
@@ -156,6 +159,10 @@ def batch_variant(B, args, torch, count):
         c.close()
     out.update(value=out["graph"]["value"], unit="k-points/s")
     return out
+
+
+def cold(args):
+    return 1 if args.cold_start == "planewave" else 0
 
 
 def gap_streams(args, N, mb):
@@ -178,7 +185,7 @@ def band_gap_variant(B, args, torch):
     N = cfg["N"]
     kp = workloads.kpath_vertices(cfg["path"], cfg["nk"])
     ctx = B.mfd_build_mu(N, 1.0, 2, workloads.mu_sc_sphere_cylinders(N))
-    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500,
+    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, cold_start=cold(args),
                        streams=gap_streams(args, N, cfg["nbands"] + 2))
     B.mfd_bands(ctx, kp[:1], cfg["nbands"], cfg["tol"], o)
     torch.cuda.synchronize()
@@ -270,7 +277,7 @@ def gyroid_variant(B, args, torch):
     N = cfg["N_path"]
     ctx = B.mfd_build_lattice_mu(N, A, 2, workloads.mu_bcc_gyroid(N))
     kp = workloads.kpath_vertices(cfg["path"], cfg["nk"], points=workloads.bcc_points())
-    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500,
+    o = B.default_opts(precision=1, warm_start=1, seed=0, guard=2, max_iter=500, cold_start=cold(args),
                        streams=gap_streams(args, N, cfg["nbands"] + 2))
     B.mfd_bands(ctx, kp[:1], cfg["nbands"], cfg["tol"], o)
     torch.cuda.synchronize()
@@ -383,6 +390,7 @@ def learned_variant(B, args, torch):
                        f"{args.learned_streams} k-path segments"}
     for name, warm, steps in (("previous_k", 1, 30), ("learned", 2, 30), ("untrained", 2, 0)):
         o = B.default_opts(precision=1, warm_start=warm, learn_steps=steps, seed=0, guard=guard, max_iter=500,
+                           cold_start=cold(args),
                            streams=args.learned_streams)
         B.mfd_bands(ctx, kp[:args.learned_streams], m, cfg["tol"], o)
         torch.cuda.synchronize()
@@ -524,7 +532,7 @@ def main():
 
     def make_opts(precision, warm, streams=args.streams):
         return B.default_opts(precision=1 if precision == "mixed" else 0, warm_start=2 if warm == "learned" else 1,
-                              seed=0, guard=args.guard, max_iter=500, streams=streams)
+                              seed=0, guard=args.guard, max_iter=500, streams=streams, cold_start=cold(args))
 
     opts = make_opts(args.precision, args.warm)
 
@@ -672,7 +680,7 @@ def main():
                                f"({n} unknowns), {nk} k-points on {cfg['path']}, {m} bands, tol {args.tol:g}, "
                                f"{args.precision}, {args.streams} concurrent k-path segments",
                    "N": N, "nbands": m, "nk": nk, "tol": args.tol, "precision": args.precision,
-                   "warm_start": args.warm, "guard": args.guard, "streams": args.streams,
+                   "warm_start": args.warm, "cold_start": args.cold_start, "guard": args.guard, "streams": args.streams,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         # the kernels alone: a single-stream pass over the first k-points of
         # the path after the timed steps, HIP events on the launching stream

@@ -109,6 +109,10 @@ typedef struct {
                                  shape (two LOBPCG iterations per graph), with the host reading the
                                  residuals only between chunks; the active set is frozen within a
                                  chunk.  0 (default): the host steps every iteration */
+    int cold_start;           /* start block of a segment's first k-point (without x0): 0 (default)
+                                 seeded random; 1 the lowest transverse plane waves at k, ordered
+                                 by |k + G| (the eigenvectors of the operator with a uniform
+                                 medium), plus 0.1 of the seeded random block */
 } mfd_opts;
 
 typedef struct {

@@ -1020,6 +1020,8 @@ struct Segment {
     std::string err;
 };
 
+int planewave_start(const mfd_ctx* c, Ws& w, const double* k, int mb, uint64_t seed);
+
 void run_segment(Segment* sg) {
     mfd_ctx* c = sg->ctx;
     Ws& w = *sg->ws;
@@ -1069,6 +1071,8 @@ void run_segment(Segment* sg) {
                 e = launch_fill_random(col(w.V, n, sg->nbands), n * (mb - sg->nbands), seed_k + 17, w.stream);
             if (e != hipSuccess) st = fail(MFD_EDEVICE, hipGetErrorString(e));
             else st = fix_dependent_start(w, seed_k + 101);
+        } else if (!st && ik == sg->k0 && o.cold_start == 1) {
+            st = planewave_start(c, w, sg->kpts + 3 * ik, mb, seed_k);
         } else if (!st && (ik == sg->k0 || !o.warm_start)) {
             hipError_t e = launch_fill_random(w.V, n * mb, seed_k, w.stream);
             if (e != hipSuccess) st = fail(MFD_EDEVICE, hipGetErrorString(e));
@@ -1223,12 +1227,83 @@ int run_segments(std::vector<Segment>& segs) {
     return ret;
 }
 
+// Cold start from the lowest transverse plane waves at k.  With a uniform
+// medium the operator's eigenvectors are plane waves exp(i (k + G) . x)
+// (Section 4.4, Prop 3.2): the curl-curl part acts on the two polarisations
+// perpendicular to k + G, the compensation term on the third.  Columns take,
+// in order of |k + G|, those two polarisations of each reciprocal vector G
+// (all three where k + G = 0), plus 0.1 of a seeded random block; G = 2 pi m / L
+// on a cubic grid and 2 pi A^-T m on a lattice, m the grid frequency.
+int planewave_start(const mfd_ctx* c, Ws& w, const double* k, int mb, uint64_t seed) {
+    struct Cand {
+        double len;
+        int m[3];
+        double q[3];
+    };
+    std::vector<Cand> cand;
+    const int P = 3;
+    for (int a = -P; a <= P; ++a)
+        for (int b = -P; b <= P; ++b)
+            for (int d = -P; d <= P; ++d) {
+                Cand x;
+                x.m[0] = a; x.m[1] = b; x.m[2] = d;
+                double l2 = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    const double G = c->lattice ? 2.0 * M_PI / c->N * (c->B[i][0] * a + c->B[i][1] * b + c->B[i][2] * d)
+                                                : 2.0 * M_PI * x.m[i] / c->L;
+                    x.q[i] = k[i] + G;
+                    l2 += x.q[i] * x.q[i];
+                }
+                x.len = std::sqrt(l2);
+                cand.push_back(x);
+            }
+    std::stable_sort(cand.begin(), cand.end(), [](const Cand& u, const Cand& v) { return u.len < v.len; });
+    PlaneWaves pw;
+    pw.mb = mb;
+    const double tiny = 1e-9 * 2.0 * M_PI / c->L;
+    int j = 0;
+    for (const Cand& x : cand) {
+        if (j >= mb) break;
+        double e[3][3];
+        int npol = 2;
+        if (x.len < tiny) {
+            npol = 3;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) e[a][b] = a == b ? 1.0 : 0.0;
+        } else {
+            const double u[3] = {x.q[0] / x.len, x.q[1] / x.len, x.q[2] / x.len};
+            // e1 = u x (the axis least aligned with u), normalised; e2 = u x e1
+            int ax = 0;
+            for (int i = 1; i < 3; ++i)
+                if (std::fabs(u[i]) < std::fabs(u[ax])) ax = i;
+            double t[3] = {0.0, 0.0, 0.0};
+            t[ax] = 1.0;
+            double e1[3] = {u[1] * t[2] - u[2] * t[1], u[2] * t[0] - u[0] * t[2], u[0] * t[1] - u[1] * t[0]};
+            const double n1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+            for (int i = 0; i < 3; ++i) e[0][i] = e1[i] / n1;
+            e[1][0] = u[1] * e[0][2] - u[2] * e[0][1];
+            e[1][1] = u[2] * e[0][0] - u[0] * e[0][2];
+            e[1][2] = u[0] * e[0][1] - u[1] * e[0][0];
+        }
+        for (int p = 0; p < npol && j < mb; ++p, ++j) {
+            for (int i = 0; i < 3; ++i) {
+                pw.m[j][i] = x.m[i];
+                pw.pol[j][i] = mk<double2>(e[p][i], 0.0);
+            }
+        }
+    }
+    const size_t n = c->n;
+    hipError_t e = launch_fill_random(w.V, n * mb, seed, w.stream);
+    if (e == hipSuccess) e = launch_planewave_start(w.V, c->N, pw, 0.1, w.stream);
+    return e == hipSuccess ? MFD_OK : fail(MFD_EDEVICE, hipGetErrorString(e));
+}
+
 int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
     if (nbands <= 0) return fail(MFD_EINVAL, "nbands must be > 0");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
     if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0 || o.streams < 1 || o.streams > 16 ||
         o.stall_window < 0 || o.warm_start < 0 || o.warm_start > 2 || o.learn_steps < 0 || o.graph < 0 || o.graph > 1 ||
-        !(o.learn_rate >= 0.0f))
+        o.cold_start < 0 || o.cold_start > 1 || !(o.learn_rate >= 0.0f))
         return fail(MFD_EINVAL, "bad options");
     const int mb = nbands + o.guard;
     if (mb > MAX_BLOCK) return fail(MFD_EUNSUPPORTED, "nbands + guard exceeds mfd_max_block()");
@@ -1275,6 +1350,7 @@ void mfd_default_opts(mfd_opts* o) {
     o->mg_smooth = 2;
     o->mg_sweeps = 2;
     o->graph = 0;
+    o->cold_start = 0;
 }
 
 int mfd_tuning(const mfd_ctx* ctx, int* out) {

@@ -432,6 +432,31 @@ hipError_t launch_fill_random(void* X, size_t count, uint64_t seed, hipStream_t 
     return hipGetLastError();
 }
 
+__global__ void planewave_start_kernel(C128* __restrict__ X, int N, PlaneWaves pw, double noise) {
+    const size_t N3 = (size_t)N * N * N, n = 3 * N3, count = n * (size_t)pw.mb;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(i / n);
+        const size_t rem = i % n;
+        const int c = (int)(rem / N3);
+        const size_t cell = rem % N3;
+        const int x = (int)(cell % N), y = (int)((cell / N) % N), z = (int)(cell / ((size_t)N * N));
+        // the phase m . r mod N in integers, then sincospi(2 t / N)
+        long long t = ((long long)pw.m[j][0] * x + (long long)pw.m[j][1] * y + (long long)pw.m[j][2] * z) % N;
+        if (t < 0) t += N;
+        double sn, cs;
+        sincospi(2.0 * (double)t / (double)N, &sn, &cs);
+        const C128 a = pw.pol[j][c];
+        const C128 r = X[i];
+        X[i] = mk<C128>(a.x * cs - a.y * sn + noise * r.x, a.x * sn + a.y * cs + noise * r.y);
+    }
+}
+
+hipError_t launch_planewave_start(void* X, int N, const PlaneWaves& pw, double noise, hipStream_t s) {
+    if (pw.mb < 1 || pw.mb > 22) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(planewave_start_kernel, dim3(2048), dim3(256), 0, s, (C128*)X, N, pw, noise);
+    return hipGetLastError();
+}
+
 // Y[:, j] = X[:, j] scaled to FP32 / from FP32 (mixed precision helpers)
 __global__ void c128_to_c64_kernel(const C128* __restrict__ X, float2* __restrict__ Y, size_t count) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {

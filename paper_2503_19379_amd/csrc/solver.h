@@ -46,6 +46,15 @@ hipError_t launch_residual(const void* X, const void* AX, void* R, bool r32, siz
 hipError_t launch_colstats(const void* X, const void* Y, size_t ld, size_t n, int nb, const double* theta,
                            int nparts, double* part, double* out, hipStream_t s);
 hipError_t launch_fill_random(void* X, size_t count, uint64_t seed, hipStream_t s);
+// Cold start from plane waves: column j of X (n = 3 N^3 rows, c128) becomes
+// pol[j] exp(2 pi i m_j . r / N) plus `noise` times the column's present
+// (random) values.
+struct PlaneWaves {
+    int mb;
+    int m[22][3];
+    double2 pol[22][3];
+};
+hipError_t launch_planewave_start(void* X, int N, const PlaneWaves& pw, double noise, hipStream_t s);
 hipError_t launch_convert(const void* X, void* Y, size_t count, bool to_c64, hipStream_t s);
 
 // Rayleigh-Ritz on span[X, W, P] (rr.hip) for a basis of K = mb + nw + np

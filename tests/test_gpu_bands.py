@@ -298,3 +298,38 @@ def test_graph_batch_matches_single(B):
         e1, s1, st1 = B.mfd_bands(one, kp, 5, 1e-9, B.default_opts(precision=1, streams=1, graph=0))
         assert st1 == 0
         assert np.allclose(evs[c], e1, rtol=1e-7, atol=1e-9), (N, evs[c], e1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plane_wave_cold_start(B, precision):
+    """cold_start = 1 (segments start from the lowest transverse plane waves
+    at their first k-point, Gamma's three constant fields among them) changes
+    only the start blocks: the diamond N = 16 path in 4 segments returns the
+    random-start bands, and a k-point matches the oracle."""
+    N, m = 16, 6
+    eps = workloads.eps_diamond(N)
+    kp = workloads.kpath("GXMGR", 12)
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    tol = 1e-8 if precision else 1e-10
+    opts = dict(precision=precision, streams=4, guard=2)
+    e0, s0, st0 = B.mfd_bands(ctx, kp, m, tol, B.default_opts(cold_start=0, **opts))
+    e1, s1, st1 = B.mfd_bands(ctx, kp, m, tol, B.default_opts(cold_start=1, **opts))
+    assert st0 == 0 and st1 == 0, (s0, s1)
+    assert all(s["max_rel_resid"] <= tol for s in s1)
+    assert np.allclose(e0, e1, rtol=1e-7 if precision else 1e-9, atol=1e-9)
+    lam, _, _ = olob.solve_bands(eps, 1.0, kp[3], m, tol=1e-10)
+    assert np.allclose(e1[3], lam, rtol=1e-7 if precision else 1e-9), (e1[3], lam)
+
+
+def test_plane_wave_cold_start_on_a_lattice(B):
+    """The same on a BCC cell (reciprocal vectors 2 pi A^-T m): random and
+    plane-wave starts give the same bands."""
+    N, m = 12, 6
+    A = workloads.lattice_vectors("bcc")
+    rng = np.random.default_rng(5)
+    ctx = B.mfd_build_lattice(N, A, 2, rand_eps(rng, N))
+    kp = workloads.kpath_vertices("hGPNH", 8, points=workloads.bcc_points())
+    e0, s0, st0 = B.mfd_bands(ctx, kp, m, 1e-9, B.default_opts(cold_start=0, streams=2))
+    e1, s1, st1 = B.mfd_bands(ctx, kp, m, 1e-9, B.default_opts(cold_start=1, streams=2))
+    assert st0 == 0 and st1 == 0, (s0, s1)
+    assert np.allclose(e0, e1, rtol=1e-8, atol=1e-9)
