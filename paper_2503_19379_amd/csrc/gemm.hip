@@ -70,10 +70,15 @@ __global__ __launch_bounds__(64 * SUBS * T) void gram_mfma_kernel(const double2*
     constexpr int NT = 64 * SUBS * T;   // SUBS waves per block of S, each taking every SUBS-th 4 rows
     constexpr int TG = T + 1;     // tiles per wave
     extern __shared__ unsigned char smem_raw[];
-    double2* slabs = reinterpret_cast<double2*>(smem_raw);   // [2][GM_KS][2K]
+    double2* slabs = reinterpret_cast<double2*>(smem_raw);   // [2][GM_KS][2K + 1]
     const int K = bm.K;
     const int C2 = 2 * K;
-    const int SL = GM_KS * C2;
+    // slab rows are 2K + 1 elements apart: the fill writes one column of 32
+    // consecutive rows per instruction, and with a stride of 2K elements
+    // (8K dwords, a multiple of 16) those rows would share four or eight of
+    // the 32 LDS banks
+    const int RS = C2 + 1;
+    const int SL = GM_KS * RS;
     const int tid = threadIdx.x;
     const int lane = tid & 63, g = (tid >> 6) / SUBS, sub = (tid >> 6) % SUBS;
     const size_t r0 = (size_t)blockIdx.x * rows_per;
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(64 * SUBS * T) void gram_mfma_kernel(const double2*
         for (int q = 0; q < GM_PF; ++q) {
             double2 v = ((f32m >> q) & 1u) ? mk<double2>((double)pf32[q].x, (double)pf32[q].y) : pf[q];
             if (!inb) v = mk<double2>(0.0, 0.0);
-            if ((okm >> q) & 1u) slab[srow * C2 + scol[q]] = v;
+            if ((okm >> q) & 1u) slab[srow * RS + scol[q]] = v;
         }
     };
     prefetch(r0);
@@ -158,7 +163,7 @@ __global__ __launch_bounds__(64 * SUBS * T) void gram_mfma_kernel(const double2*
         const double2* slab = slabs + buf * SL;
 #pragma unroll
         for (int k0 = 4 * sub; k0 < GM_KS; k0 += 4 * SUBS) {
-            const double2* srow_p = slab + (k0 + lk) * C2;
+            const double2* srow_p = slab + (k0 + lk) * RS;
             // every fragment of the step is read before the first product, so
             // that one LDS round trip, not one per tile, precedes the matrix
             // work (T = 5 has no registers to spare for it)
@@ -275,9 +280,9 @@ static hipError_t gram_t(const void* V, const void* V32, size_t ld, size_t n, co
     constexpr int KS = gram_ks<T>(), SUBS = gram_subs<T>();
     // the slab of KS x 2K elements must fit the prefetch registers of the workgroup
     if (KS * 2 * bm.K > GM_PF * 64 * SUBS * T) return hipErrorInvalidValue;
-    // two slabs, or the tile exchange between the two waves of a block at the end if larger
-    const size_t lds =
-        std::max((size_t)2 * KS * 2 * bm.K, SUBS == 2 ? (size_t)T * (T + 1) * 4 * 64 : (size_t)0) * sizeof(double2);
+    // two slabs (rows of 2K + 1), or the tile exchange between the two waves of a block at the end if larger
+    const size_t lds = std::max((size_t)2 * KS * (2 * bm.K + 1), SUBS == 2 ? (size_t)T * (T + 1) * 4 * 64 : (size_t)0) *
+                       sizeof(double2);
     auto kern = gram_mfma_kernel<T, SUBS, KS>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
