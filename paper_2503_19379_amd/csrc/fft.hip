@@ -147,6 +147,51 @@ __device__ __forceinline__ void fft_lines(T* buf, const T* tw, Addr addr, int ti
 
 constexpr int FFT_NT = 256;
 
+// Global <-> LDS staging of CNT elements by NT threads: element i sits at LDS
+// index i and at global index at(i).  Each thread issues the loads of a chunk
+// (up to 16 elements) before its first LDS write; a rolled copy loop would
+// wait for every load in turn, one memory round trip per element.
+template <int CNT, int NT, class T, class At>
+__device__ __forceinline__ void stage_in(T* buf, const T* src, At at, int tid) {
+    constexpr int PE = (CNT + NT - 1) / NT;
+    constexpr int CH = PE < 16 ? PE : 16;
+#pragma unroll
+    for (int q0 = 0; q0 < PE; q0 += CH) {
+        T v[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int i = tid + (q0 + q) * NT;
+            if (q0 + q < PE && (CNT % NT == 0 || i < CNT)) v[q] = src[at(i)];
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int i = tid + (q0 + q) * NT;
+            if (q0 + q < PE && (CNT % NT == 0 || i < CNT)) buf[i] = v[q];
+        }
+    }
+}
+
+// The reverse: LDS reads of a chunk first, then its global stores.
+template <int CNT, int NT, class T, class At>
+__device__ __forceinline__ void stage_out(const T* buf, T* dst, At at, int tid) {
+    constexpr int PE = (CNT + NT - 1) / NT;
+    constexpr int CH = PE < 16 ? PE : 16;
+#pragma unroll
+    for (int q0 = 0; q0 < PE; q0 += CH) {
+        T v[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int i = tid + (q0 + q) * NT;
+            if (q0 + q < PE && (CNT % NT == 0 || i < CNT)) v[q] = buf[i];
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int i = tid + (q0 + q) * NT;
+            if (q0 + q < PE && (CNT % NT == 0 || i < CNT)) dst[at(i)] = v[q];
+        }
+    }
+}
+
 // Threads of the plane kernel: about 16 elements per thread per pass.
 constexpr int plane_nt(int N) {
     int t = (N * N / 16 + 63) / 64 * 64;
@@ -167,7 +212,7 @@ __global__ __launch_bounds__(plane_nt(N)) void fft_plane_kernel(const cplx<R>* i
     const T* src = in + plane * N * N;
     T* dst = out + plane * N * N;
     for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
-    for (int i = tid; i < N * N; i += NT) buf[i] = src[i];
+    stage_in<N * N, NT>(buf, src, [](int i) { return i; }, tid);
     __syncthreads();
     if (!INV) {
         fft_lines<T, N, N, NT, INV, false, 1>(buf, tw, [](int l, int j) { return l * N + j; }, tid);
@@ -176,7 +221,7 @@ __global__ __launch_bounds__(plane_nt(N)) void fft_plane_kernel(const cplx<R>* i
         fft_lines<T, N, N, NT, INV, true, 1>(buf, tw, [](int l, int j) { return j * N + l; }, tid);
         fft_lines<T, N, N, NT, INV, false, 1>(buf, tw, [](int l, int j) { return l * N + j; }, tid);
     }
-    for (int i = tid; i < N * N; i += NT) dst[i] = buf[i];
+    stage_out<N * N, NT>(buf, dst, [](int i) { return i; }, tid);
 }
 
 // Grids whose N x N plane does not fit in LDS (N = 150): kernels 1 and 3 are
@@ -208,10 +253,10 @@ __global__ __launch_bounds__(FFT_NT) void fft_xlines_kernel(const cplx<R>* in, c
     const size_t plane = (size_t)fl(bid / (3 * N * NCH)) * 3 * N + (bid / NCH) % (3 * N);
     const size_t off = plane * N * N + (size_t)(bid % NCH) * XL * N;
     for (int i = tid; i < N; i += FFT_NT) tw[i] = tw_g[i];
-    for (int i = tid; i < XL * N; i += FFT_NT) buf[i] = in[off + i];
+    stage_in<XL * N, FFT_NT>(buf, in + off, [](int i) { return i; }, tid);
     __syncthreads();
     fft_lines<T, N, XL, FFT_NT, INV, false, 1>(buf, tw, [](int l, int j) { return l * N + j; }, tid);
-    for (int i = tid; i < XL * N; i += FFT_NT) out[off + i] = buf[i];
+    stage_out<XL * N, FFT_NT>(buf, out + off, [](int i) { return i; }, tid);
 }
 
 template <class R, int N, bool INV>
@@ -228,10 +273,11 @@ __global__ __launch_bounds__(FFT_NT) void fft_ylines_kernel(const cplx<R>* in, c
     const size_t plane = (size_t)fl(bid / (3 * N * NXB)) * 3 * N + (bid / NXB) % (3 * N);
     const size_t off = plane * N * N + (size_t)(bid % NXB) * XB;
     for (int i = tid; i < N; i += FFT_NT) tw[i] = tw_g[i];
-    for (int i = tid; i < N * XB; i += FFT_NT) buf[i] = in[off + (size_t)(i / XB) * N + i % XB];
+    auto at = [](int i) { return (i / XB) * N + i % XB; };
+    stage_in<N * XB, FFT_NT>(buf, in + off, at, tid);
     __syncthreads();
     fft_lines<T, N, XB, FFT_NT, INV, true, 1>(buf, tw, [](int l, int j) { return j * XB + l; }, tid);
-    for (int i = tid; i < N * XB; i += FFT_NT) out[off + (size_t)(i / XB) * N + i % XB] = buf[i];
+    stage_out<N * XB, FFT_NT>(buf, out + off, at, tid);
 }
 
 template <class R, int N>
@@ -330,10 +376,11 @@ __global__ __launch_bounds__(FFT_NT) void fft_zsolve_kernel(SolveArgs<R> a) {
     const T* src = a.in + (size_t)band * 3 * N3 + (size_t)y * N + xc0;
     T* dst = a.out + (size_t)band * 3 * N3 + (size_t)y * N + xc0;
     for (int i = tid; i < N; i += FFT_NT) tw[i] = a.tw[i];
-    for (int i = tid; i < 3 * N * XC; i += FFT_NT) {
-        const int xc = i % XC, z = (i / XC) % N, c = i / (XC * N);
-        buf[i] = src[c * N3 + z * NN + xc];
-    }
+    // element i of buf: x run position i % XC, z = (i / XC) % N, component i / (XC N)
+    auto at = [](int i) {
+        return (size_t)(i / (XC * N)) * ((size_t)N * N * N) + (size_t)((i / XC) % N) * (N * N) + i % XC;
+    };
+    stage_in<3 * N * XC, FFT_NT>(buf, src, at, tid);
     __syncthreads();
     auto addr = [](int l, int j) { return (l / XC) * N * XC + j * XC + (l % XC); };
     fft_lines<T, N, 3 * XC, FFT_NT, false, true, 1>(buf, tw, addr, tid);
@@ -386,10 +433,7 @@ __global__ __launch_bounds__(FFT_NT) void fft_zsolve_kernel(SolveArgs<R> a) {
     }
     __syncthreads();
     fft_lines<T, N, 3 * XC, FFT_NT, true, true, 1>(buf, tw, addr, tid);
-    for (int i = tid; i < 3 * N * XC; i += FFT_NT) {
-        const int xc = i % XC, z = (i / XC) % N, c = i / (XC * N);
-        dst[c * N3 + z * NN + xc] = buf[i];
-    }
+    stage_out<3 * N * XC, FFT_NT>(buf, dst, at, tid);
 }
 
 static int pick_xc(int N) {
