@@ -625,6 +625,19 @@ def main():
                       f"ms={s['ms']:.1f} ev0={ev[i][0]:.6f} ev15={ev[i][-1]:.6f}", file=sys.stderr)
     ok, iters, maxres = count(results)
     value = ok / dt
+    # iterations at the segments' first k-points (cold starts; the library
+    # cuts the path at k0 = nk i / segments) and at the warm-started rest, and
+    # the k-points that left the mixed iteration or rejected a step
+    starts = {nk * i // args.streams for i in range(args.streams)}
+    cold_it = [s["iters"] for _, st, _ in results for i, s in enumerate(st) if i in starts]
+    warm_it = [s["iters"] for _, st, _ in results for i, s in enumerate(st) if i not in starts]
+    allst = [s for _, st, _ in results for s in st]
+    kstats = {"iters_cold_start_mean": float(np.mean(cold_it)) if cold_it else None,
+              "iters_warm_start_mean": float(np.mean(warm_it)) if warm_it else None,
+              "fp64_fallback_kpoints": int(sum(s["fp64_fallback"] for s in allst)),
+              "rejected_steps": int(sum(s["rejected_steps"] for s in allst)),
+              "gamma_doublings": int(sum(s["gamma_doublings"] for s in allst)),
+              "discarded_bands": int(sum(s["discarded"] for s in allst))}
 
     # One-step comparison runs on the same GPU (each after an untimed call
     # that sizes its workspaces).
@@ -697,6 +710,7 @@ def main():
         "kernels_timed_region_share": {c: {"share": v["share"], "launches": v["launches"]}
                                        for c, v in timed.items()},
         "iters_per_k": float(np.mean(iters)) if iters else None,
+        "kpoint_stats": kstats,
         "max_rel_resid": maxres,
         "converged_kpoints": ok,
         "total_kpoints": len(iters),
