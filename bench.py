@@ -58,6 +58,9 @@ def parse():
                     help="extra block columns beyond the bands (16 + 4 = 20 columns: fewest seconds per "
                          "k-point of guard 2..6 on the diamond N = 64 path)")
     ap.add_argument("--streams", type=int, default=12, help="k-path segments solved concurrently")
+    ap.add_argument("--balance", type=int, default=0, choices=[0, 1],
+                    help="1: a stream whose segment is done takes half of the busiest segment's remaining "
+                         "k-points (opts.balance); 0: fixed segments")
     ap.add_argument("--cold-start", default="planewave", choices=["planewave", "random"],
                     help="start block of each segment's first k-point: the lowest transverse plane waves at k "
                          "(opts.cold_start = 1) or seeded random values")
@@ -532,7 +535,8 @@ def main():
 
     def make_opts(precision, warm, streams=args.streams):
         return B.default_opts(precision=1 if precision == "mixed" else 0, warm_start=2 if warm == "learned" else 1,
-                              seed=0, guard=args.guard, max_iter=500, streams=streams, cold_start=cold(args))
+                              seed=0, guard=args.guard, max_iter=500, streams=streams, cold_start=cold(args),
+                              balance=args.balance if warm != "learned" else 0)
 
     opts = make_opts(args.precision, args.warm)
 
@@ -625,14 +629,14 @@ def main():
                       f"ms={s['ms']:.1f} ev0={ev[i][0]:.6f} ev15={ev[i][-1]:.6f}", file=sys.stderr)
     ok, iters, maxres = count(results)
     value = ok / dt
-    # iterations at the segments' first k-points (cold starts; the library
-    # cuts the path at k0 = nk i / segments) and at the warm-started rest, and
-    # the k-points that left the mixed iteration or rejected a step
-    starts = {nk * i // args.streams for i in range(args.streams)}
-    cold_it = [s["iters"] for _, st, _ in results for i, s in enumerate(st) if i in starts]
-    warm_it = [s["iters"] for _, st, _ in results for i, s in enumerate(st) if i not in starts]
+    # iterations at the segments' first k-points (cold starts) and at the
+    # warm-started rest, and the k-points that left the mixed iteration or
+    # rejected a step
+    cold_it = [s["iters"] for _, st, _ in results for s in st if s["segment_start"]]
+    warm_it = [s["iters"] for _, st, _ in results for s in st if not s["segment_start"]]
     allst = [s for _, st, _ in results for s in st]
-    kstats = {"iters_cold_start_mean": float(np.mean(cold_it)) if cold_it else None,
+    kstats = {"segment_starts": len(cold_it),
+              "iters_cold_start_mean": float(np.mean(cold_it)) if cold_it else None,
               "iters_warm_start_mean": float(np.mean(warm_it)) if warm_it else None,
               "fp64_fallback_kpoints": int(sum(s["fp64_fallback"] for s in allst)),
               "rejected_steps": int(sum(s["rejected_steps"] for s in allst)),
@@ -694,6 +698,7 @@ def main():
                                f"{args.precision}, {args.streams} concurrent k-path segments",
                    "N": N, "nbands": m, "nk": nk, "tol": args.tol, "precision": args.precision,
                    "warm_start": args.warm, "cold_start": args.cold_start, "guard": args.guard, "streams": args.streams,
+                   "balance": args.balance,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         # the kernels alone: a single-stream pass over the first k-points of
         # the path after the timed steps, HIP events on the launching stream

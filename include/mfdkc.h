@@ -113,6 +113,13 @@ typedef struct {
                                  seeded random; 1 the lowest transverse plane waves at k, ordered
                                  by |k + G| (the eigenvectors of the operator with a uniform
                                  medium), plus 0.1 of the seeded random block */
+    int balance;              /* mfd_bands: 1 = a stream whose k-path segment is done takes the
+                                 second half of the k-points still ahead of the busiest other
+                                 segment (at least 2 beyond the one it is solving), starting
+                                 it as a segment of its own (cold start); the cut points then
+                                 depend on timing, so bands agree between runs to the
+                                 tolerance, not bit for bit.  Not with warm_start 2.
+                                 0 (default): fixed segments of equal length */
 } mfd_opts;
 
 typedef struct {
@@ -136,6 +143,8 @@ typedef struct {
                                  Gram entries) is undone, A X recomputed and P restarted; mixed
                                  precision then continues in FP64 (unless stall_window is 0) */
     int host_syncs;           /* host synchronisations with the solve's stream for this k-point */
+    int segment_start;        /* 1: the k-point began a segment (x0, plane-wave or random start);
+                                 0: it started from the previous k-point's vectors */
 } mfd_kstats;
 
 void mfd_default_opts(mfd_opts* opts);

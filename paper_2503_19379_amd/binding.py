@@ -35,14 +35,15 @@ class mfd_opts(ctypes.Structure):
                 ("streams", ctypes.c_int), ("x0", ctypes.c_void_p), ("stall_window", ctypes.c_int),
                 ("learn_steps", ctypes.c_int), ("learn_rate", ctypes.c_float), ("autotune", ctypes.c_int),
                 ("precond", ctypes.c_int), ("mg_cycles", ctypes.c_int), ("mg_smooth", ctypes.c_int),
-                ("mg_sweeps", ctypes.c_int), ("graph", ctypes.c_int), ("cold_start", ctypes.c_int)]
+                ("mg_sweeps", ctypes.c_int), ("graph", ctypes.c_int), ("cold_start", ctypes.c_int),
+                ("balance", ctypes.c_int)]
 
 
 class mfd_kstats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("gamma_doublings", ctypes.c_int), ("gamma", ctypes.c_double),
                 ("max_rel_resid", ctypes.c_double), ("spurious", ctypes.c_int), ("discarded", ctypes.c_int),
                 ("used_fallback", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("ms", ctypes.c_float),
-                ("rejected_steps", ctypes.c_int), ("host_syncs", ctypes.c_int)]
+                ("rejected_steps", ctypes.c_int), ("host_syncs", ctypes.c_int), ("segment_start", ctypes.c_int)]
 
 
 _lib = None
@@ -356,7 +357,8 @@ def _stats_list(st):
     return [dict(iters=s.iters, gamma_doublings=s.gamma_doublings, gamma=s.gamma,
                  max_rel_resid=s.max_rel_resid, spurious=s.spurious, discarded=s.discarded,
                  used_fallback=s.used_fallback, fp64_fallback=s.fp64_fallback, ms=s.ms,
-                 rejected_steps=s.rejected_steps, host_syncs=s.host_syncs) for s in st]
+                 rejected_steps=s.rejected_steps, host_syncs=s.host_syncs, segment_start=s.segment_start)
+            for s in st]
 
 
 def mfd_bands_batch(ctxs, kpts_list, nbands: int, tol: float, opts: mfd_opts | None = None, stream=None,

@@ -13,6 +13,7 @@
 #include <vector>
 #include <atomic>
 #include <initializer_list>
+#include <mutex>
 #include <thread>
 
 #include "../../include/mfdkc.h"
@@ -1018,7 +1019,39 @@ struct Segment {
     int status = MFD_OK;
     int worst = 1;         // 1 all converged, 0 some not, 2 spurious remain
     std::string err;
+    // opts.balance: the segments of one call share a lock over their [k0, k1)
+    // and the k-point each is solving (cur; -1 when done)
+    struct Balance* bal = nullptr;
+    int cur = -1;
 };
+
+struct Balance {
+    std::mutex mu;
+    std::vector<Segment*> segs;
+};
+
+// Under the lock: a segment with nothing left takes the second half of the
+// k-points beyond the one the busiest other segment is solving (at least 2
+// of them; that segment keeps the larger half, which it reaches warm).
+// Returns the new first k-point, or -1 when no segment has 2 left.
+static int steal(Segment* sg) {
+    Segment* v = nullptr;
+    int best = 1;
+    for (Segment* o : sg->bal->segs) {
+        if (o == sg || o->cur < 0) continue;
+        const int rem = o->k1 - (o->cur + 1);
+        if (rem > best) {
+            best = rem;
+            v = o;
+        }
+    }
+    if (!v) return -1;
+    const int mid = v->cur + 1 + (best + 1) / 2;
+    sg->k0 = mid;
+    sg->k1 = v->k1;
+    v->k1 = mid;
+    return mid;
+}
 
 int planewave_start(const mfd_ctx* c, Ws& w, const double* k, int mb, uint64_t seed);
 
@@ -1055,7 +1088,15 @@ void run_segment(Segment* sg) {
         }
     }
     std::vector<double> lam_all(mb);
-    for (int ik = sg->k0; ik < sg->k1; ++ik) {
+    for (int ik = sg->k0;; ++ik) {
+        if (sg->bal) {
+            std::lock_guard<std::mutex> lk(sg->bal->mu);
+            if (ik >= sg->k1) ik = steal(sg);
+            sg->cur = ik;
+            if (ik < 0) break;
+        } else if (ik >= sg->k1) {
+            break;
+        }
         const uint64_t seed_k = o.seed * 1000003ull + 104729ull * (uint64_t)ik;
         int st = MFD_OK;
         bool proposal = false;
@@ -1085,7 +1126,10 @@ void run_segment(Segment* sg) {
             bool used = false;
             st = solve_k(c, w, sg->kpts + 3 * ik, sg->nbands, sg->tol, o, seed_k, ko, proposal, &used,
                          lam_all.data(), &conv);
-            if (!st && ko.stats) ko.stats->used_fallback = (learned && ik > sg->k0 && !used) ? 1 : 0;
+            if (!st && ko.stats) {
+                ko.stats->used_fallback = (learned && ik > sg->k0 && !used) ? 1 : 0;
+                ko.stats->segment_start = (ik == sg->k0 || !o.warm_start) ? 1 : 0;
+            }
             if (!st && learned) {
                 st = w.warm->after_solve(w.V, lam_all.data(), sg->kpts + 3 * ik, o.learn_steps, o.learn_rate,
                                          w.stream);
@@ -1095,6 +1139,10 @@ void run_segment(Segment* sg) {
         if (st) {
             sg->status = st;
             sg->err = g_last_error;
+            if (sg->bal) {
+                std::lock_guard<std::mutex> lk(sg->bal->mu);
+                sg->cur = -1;
+            }
             return;
         }
         if (conv == 0) sg->worst = 0;
@@ -1303,7 +1351,8 @@ int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
     if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0 || o.streams < 1 || o.streams > 16 ||
         o.stall_window < 0 || o.warm_start < 0 || o.warm_start > 2 || o.learn_steps < 0 || o.graph < 0 || o.graph > 1 ||
-        o.cold_start < 0 || o.cold_start > 1 || !(o.learn_rate >= 0.0f))
+        o.cold_start < 0 || o.cold_start > 1 || o.balance < 0 || o.balance > 1 ||
+        (o.balance && o.warm_start == 2) || !(o.learn_rate >= 0.0f))
         return fail(MFD_EINVAL, "bad options");
     const int mb = nbands + o.guard;
     if (mb > MAX_BLOCK) return fail(MFD_EUNSUPPORTED, "nbands + guard exceeds mfd_max_block()");
@@ -1351,6 +1400,7 @@ void mfd_default_opts(mfd_opts* o) {
     o->mg_sweeps = 2;
     o->graph = 0;
     o->cold_start = 0;
+    o->balance = 0;
 }
 
 int mfd_tuning(const mfd_ctx* ctx, int* out) {
@@ -1711,6 +1761,13 @@ int mfd_bands(mfd_ctx* ctx, int nk, const double* kpts, int nbands, double tol, 
         sg.evals = evals;
         sg.evecs = (double2*)evecs;
         sg.stats = stats;
+    }
+    Balance bal;
+    if (o.balance) {
+        for (auto& sg : segs) {
+            sg.bal = &bal;
+            bal.segs.push_back(&sg);
+        }
     }
     return run_segments(segs);
 }

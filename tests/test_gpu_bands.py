@@ -333,3 +333,28 @@ def test_plane_wave_cold_start_on_a_lattice(B):
     e1, s1, st1 = B.mfd_bands(ctx, kp, m, 1e-9, B.default_opts(cold_start=1, streams=2))
     assert st0 == 0 and st1 == 0, (s0, s1)
     assert np.allclose(e0, e1, rtol=1e-8, atol=1e-9)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_balanced_segments(B, precision):
+    """opts.balance = 1 (a stream whose segment is done takes the second half
+    of the k-points ahead of the busiest other one, with a cold start) changes
+    only where segments start: the diamond N = 16 path on 3 streams returns
+    the fixed-segment bands, every k-point is solved, a k-point matches the
+    oracle, and warm_start 2 with balance is refused."""
+    N, m = 16, 6
+    eps = workloads.eps_diamond(N)
+    kp = workloads.kpath("GXMGR", 16)
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    tol = 1e-8 if precision else 1e-10
+    opts = dict(precision=precision, streams=3, guard=2, cold_start=1)
+    e0, s0, st0 = B.mfd_bands(ctx, kp, m, tol, B.default_opts(balance=0, **opts))
+    e1, s1, st1 = B.mfd_bands(ctx, kp, m, tol, B.default_opts(balance=1, **opts))
+    assert st0 == 0 and st1 == 0, (s0, s1)
+    assert all(s["iters"] > 0 and s["max_rel_resid"] <= tol for s in s1)
+    rt = 1e-7 if precision else 1e-9
+    assert np.allclose(e0, e1, rtol=rt, atol=1e-9)
+    lam, _, _ = olob.solve_bands(eps, 1.0, kp[11], m, tol=1e-10)
+    assert np.allclose(e1[11], lam, rtol=rt), (e1[11], lam)
+    with pytest.raises(RuntimeError):
+        B.mfd_bands(ctx, kp[:4], m, tol, B.default_opts(balance=1, warm_start=2, **opts))
