@@ -126,6 +126,7 @@ struct Ws {
     double* host = nullptr;    // pinned: theta | norms | info | column sums
     int nparts_upd = 0, nparts_gram = 0, nparts_col = 0;
     int cap_upd = 0, cap_gram = 0; // workgroups the npart / gpart buffers hold partials for
+    size_t gpart_elems = 0;        // complex elements of gpart
     int stencil_wgs = 2048, fft_xc = 0, upd_rows = 0;   // upd_rows 0: one wave per 16-row strip
     WarmStart* warm = nullptr; // learned warm start (warm_start = 2), allocated on first use
     void* wtmp = nullptr;      // two-pass operator: scratch of this workspace's stream
@@ -275,8 +276,9 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
     auto chk = [&](hipError_t r) { e = r; return r == hipSuccess; };
     if (!(chk(hipStreamCreate(&w->stream)) && chk(hipMalloc(&w->V, n * 6 * mb * sizeof(double2))) &&
           chk(hipMalloc(&w->U, n * 6 * mb * sizeof(double2))) &&
-          chk(hipMalloc(&w->gpart, std::max((size_t)max_gram * K * 2 * K,
-                                            gram_mfma_part_elems((int)K, max_gram)) * sizeof(double2))) &&
+          chk(hipMalloc(&w->gpart, (w->gpart_elems = std::max((size_t)max_gram * K * 2 * K,
+                                                              gram_mfma_part_elems((int)K, max_gram))) *
+                                       sizeof(double2))) &&
           chk(hipMalloc(&w->G, K * 2 * K * sizeof(double2))) && chk(hipMalloc(&w->C, K * mb * sizeof(double2))) &&
           chk(hipMalloc(&w->npart, (size_t)w->cap_upd * 2 * mb * sizeof(double))) &&
           chk(hipMalloc(&w->norms, 2 * mb * sizeof(double))) && chk(hipMalloc(&w->theta, (mb + 1) * sizeof(double))) &&
@@ -434,6 +436,20 @@ BasisMap make_basis(int mb, const std::vector<int>& act, const std::vector<int>&
     return bm;
 }
 
+// Gram workgroups for a basis of K columns: the tuned count (set for the full
+// basis, whose instance fits one workgroup per CU), doubled for bases of at
+// most 32 columns, whose instance leaves LDS and registers for two per CU
+// (at the tuned count half the chip's slots stay empty: 252 -> 193 us at
+// K = 32, N = 64), when the partial-tile buffer holds them.
+int gram_nparts(const Ws& w, int K) {
+    const int T = (K + 15) / 16;
+    if (T <= 2) {
+        const int np = 2 * w.nparts_gram;
+        if ((size_t)(np + 1) * T * (T + 1) * 256 <= w.gpart_elems) return np;
+    }
+    return w.nparts_gram;
+}
+
 // With union_start the W columns hold a proposed start block.  The proposal
 // replaces nothing: when the sum of its Ritz values is below that of X the
 // first Rayleigh-Ritz step runs on span[X, W], otherwise on span[X] alone.
@@ -516,7 +532,8 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         e = mixed ? launch_stencil_f64_s32(p, na, Vi32 + n * mb, Vi32 + n * 4 * mb, c->mu64, s, fl)
                   : launch_stencil<double>(p, na, col(Vi, n, mb), col(Vi, n, 4 * mb), c->mu64, s, fl);
         if (e != hipSuccess) return e;
-        if ((e = launch_gram_mfma(Vi, mixed ? Vi32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s)) != hipSuccess)
+        if ((e = launch_gram_mfma(Vi, mixed ? Vi32 : nullptr, n, n, bm, gram_nparts(w, bm.K), w.gpart, w.G, s)) !=
+            hipSuccess)
             return e;
         RRArgs r2 = ra;
         r2.K = bm.K;
@@ -621,10 +638,10 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             w.prof.end(e0, 0, N3 * (6.0 * rb * na + 24.0), s);
         }
         hipEvent_t e1 = w.prof.begin(s);
-        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s, 1));
+        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, gram_nparts(w, bm.K), w.gpart, w.G, s, 1));
         w.prof.end(e1, 2, 8.0 * (double)n * bm.K * (bm.K + 1), s);   // flops, not bytes
         e1 = w.prof.begin(s);
-        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s, 2));
+        HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, gram_nparts(w, bm.K), w.gpart, w.G, s, 2));
         w.prof.end(e1, 5, 0.0, s);
         if (it == 0 && union_start) {
             const int Kb = bm.K;
@@ -638,7 +655,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             if (!out.proposal_used) {   // X alone
                 act.clear();
                 bm = make_basis(mb, act, pact, mixed);
-                HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, w.nparts_gram, w.gpart, w.G, s));
+                HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, gram_nparts(w, bm.K), w.gpart, w.G, s));
             }
         }
         ra.K = bm.K;
