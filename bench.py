@@ -66,6 +66,9 @@ def parse():
                          "(opts.cold_start = 1) or seeded random values")
     ap.add_argument("--warm", default="prev", choices=["prev", "learned"],
                     help="start block after a segment's first k-point: previous k, or the learned proposal")
+    ap.add_argument("--tuning", default="",
+                    help="JSON object of launch shapes to pin after the warm-up's autotuning (keys of "
+                         "mfd_tuning, e.g. '{\"gram_workgroups\": 512}'); the others keep the tuned values")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the one-step comparison runs (FP64 solve, learned warm start)")
     ap.add_argument("--roofline-nk", type=int, default=6, help="k-points of the single-stream timing pass")
@@ -606,6 +609,12 @@ def main():
         step()
         torch.cuda.synchronize()
         progress(f"warm-up step {i + 1} of {args.warmup} done")
+    if args.tuning:
+        if not B.mfd_tuning(ctx)[0]:
+            step()   # no warm-up step: let the autotuner run once
+        shapes = B.mfd_tuning(ctx)[1]
+        shapes.update(json.loads(args.tuning))
+        B.mfd_set_tuning(ctx, shapes)
     # Per-kernel durations during the timed steps: HIP events recorded by the
     # library around each launch on the stream it is launched on.
     B.mfd_profile(ctx, True)
