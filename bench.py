@@ -58,6 +58,8 @@ def parse():
                     help="extra block columns beyond the bands (16 + 4 = 20 columns: fewest seconds per "
                          "k-point of guard 2..6 on the diamond N = 64 path)")
     ap.add_argument("--streams", type=int, default=12, help="k-path segments solved concurrently")
+    ap.add_argument("--hard-lock", type=int, default=0, choices=[0, 1],
+                    help="1: hard locking once at most 8 bands of a k-point iterate (opts.hard_lock)")
     ap.add_argument("--balance", type=int, default=0, choices=[0, 1],
                     help="1: a stream whose segment is done takes half of the busiest segment's remaining "
                          "k-points (opts.balance); 0: fixed segments")
@@ -539,7 +541,7 @@ def main():
     def make_opts(precision, warm, streams=args.streams):
         return B.default_opts(precision=1 if precision == "mixed" else 0, warm_start=2 if warm == "learned" else 1,
                               seed=0, guard=args.guard, max_iter=500, streams=streams, cold_start=cold(args),
-                              balance=args.balance if warm != "learned" else 0)
+                              balance=args.balance if warm != "learned" else 0, hard_lock=args.hard_lock)
 
     opts = make_opts(args.precision, args.warm)
 
@@ -707,7 +709,7 @@ def main():
                                f"{args.precision}, {args.streams} concurrent k-path segments",
                    "N": N, "nbands": m, "nk": nk, "tol": args.tol, "precision": args.precision,
                    "warm_start": args.warm, "cold_start": args.cold_start, "guard": args.guard, "streams": args.streams,
-                   "balance": args.balance,
+                   "balance": args.balance, "hard_lock": args.hard_lock,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         # the kernels alone: a single-stream pass over the first k-points of
         # the path after the timed steps, HIP events on the launching stream

@@ -120,6 +120,12 @@ typedef struct {
                                  depend on timing, so bands agree between runs to the
                                  tolerance, not bit for bit.  Not with warm_start 2.
                                  0 (default): fixed segments of equal length */
+    int hard_lock;            /* 1: once at most 8 bands of a k-point still iterate, the converged
+                                 ones are locked: their vectors stay as they are and leave the
+                                 Rayleigh-Ritz basis, the new search directions are made
+                                 orthogonal to them, and the block update touches only the bands
+                                 still iterating (a locked band whose fresh residual misses the
+                                 tolerance iterates again).  0 (default): soft locking only */
 } mfd_opts;
 
 typedef struct {

@@ -36,7 +36,7 @@ class mfd_opts(ctypes.Structure):
                 ("learn_steps", ctypes.c_int), ("learn_rate", ctypes.c_float), ("autotune", ctypes.c_int),
                 ("precond", ctypes.c_int), ("mg_cycles", ctypes.c_int), ("mg_smooth", ctypes.c_int),
                 ("mg_sweeps", ctypes.c_int), ("graph", ctypes.c_int), ("cold_start", ctypes.c_int),
-                ("balance", ctypes.c_int)]
+                ("balance", ctypes.c_int), ("hard_lock", ctypes.c_int)]
 
 
 class mfd_kstats(ctypes.Structure):

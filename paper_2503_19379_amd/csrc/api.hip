@@ -132,6 +132,10 @@ struct Ws {
     void* wtmp = nullptr;      // two-pass operator: scratch of this workspace's stream
     MGWork* mg = nullptr;      // multigrid preconditioner work space (precond 1), on first use
     int precond = 0;           // 0 FFT solve, 1 multigrid solve
+    bool hardlock = false;     // opts.hard_lock
+    double* theta_a = nullptr; // hard locking: Ritz values of the bands still iterating (on first use)
+    double2* lpart = nullptr;  // hard locking: per-workgroup partials of X_L^H Y
+    double2* lcoef = nullptr;  // hard locking: X_L^H Y
     MGOpts mgo;
     // graph chunks (opts.graph): two LOBPCG iterations captured once per basis
     // shape and replayed; the key is the shape the graph was captured for
@@ -244,6 +248,7 @@ void ws_free(Ws* w) {
     hipFree(w->V32); hipFree(w->U32); hipFree(w->stage32);
     hipFree(w->npart); hipFree(w->norms); hipFree(w->theta); hipFree(w->info);
     hipFree(w->cpart); hipFree(w->cout); hipFree(w->wtmp);
+    hipFree(w->theta_a); hipFree(w->lpart); hipFree(w->lcoef);
     mg_destroy(w->mg);
     if (w->gexec) hipGraphExecDestroy(w->gexec);
     if (w->host) hipHostFree(w->host);
@@ -285,7 +290,7 @@ int ws_alloc(const mfd_ctx* c, int mb, bool mixed, Ws** out) {
           chk(hipMalloc(&w->info, 16 * sizeof(int))) &&
           chk(hipMalloc(&w->cpart, (size_t)std::max(w->nparts_col, 1024) * 2 * mb * sizeof(double))) &&
           chk(hipMalloc(&w->cout, 2 * mb * sizeof(double))) &&
-          chk(hipHostMalloc(&w->host, (8 * mb + 32) * sizeof(double), hipHostMallocDefault)) &&
+          chk(hipHostMalloc(&w->host, (12 * mb + 64) * sizeof(double), hipHostMallocDefault)) &&
           (!mixed || (chk(hipMalloc(&w->V32, n * 6 * mb * sizeof(float2))) &&
                       chk(hipMalloc(&w->U32, n * 6 * mb * sizeof(float2))))) &&
           (mixed || fft_plane_fits(c->N, 8) || chk(hipMalloc(&w->stage32, n * mb * sizeof(float2)))) &&
@@ -436,6 +441,42 @@ BasisMap make_basis(int mb, const std::vector<int>& act, const std::vector<int>&
     return bm;
 }
 
+// Basis [X_A W_A P_A] of the bands act still iterating under hard locking:
+// basis column t < na is X of band act[t]; the W and P columns follow.
+BasisMap make_basis_hl(int mb, const std::vector<int>& act, const std::vector<int>& pact, bool mixed) {
+    BasisMap bm;
+    const int na = (int)act.size(), np = (int)pact.size();
+    bm.mb = mb;
+    bm.na = na;
+    bm.K = na + na + np;
+    const int K = bm.K;
+    auto vcol = [&](int l) {   // basis column l < K -> column of V
+        if (l < na) return act[l];
+        if (l < 2 * na) return mb + act[l - na];
+        return 2 * mb + pact[l - 2 * na];
+    };
+    int q = 0;
+    auto put = [&](int l) {
+        bm.lc[q] = (short)l;
+        bm.pc[q] = (short)(l < K ? vcol(l) : 3 * mb + vcol(l - K));
+        ++q;
+    };
+    if (mixed) {   // FP64 columns (X, AX) first
+        for (int l = 0; l < na; ++l) put(l);
+        for (int l = 0; l < na; ++l) put(K + l);
+        for (int l = na; l < K; ++l) put(l);
+        for (int l = na; l < K; ++l) put(K + l);
+    } else {
+        for (int l = 0; l < 2 * K; ++l) put(l);
+    }
+    for (int j = 0; j < 32; ++j) bm.tpos[j] = -1;
+    for (int t = 0; t < na; ++t) {
+        bm.tpos[act[t]] = (signed char)t;
+        bm.act[t] = (unsigned char)act[t];
+    }
+    return bm;
+}
+
 // Gram workgroups for a basis of K columns: the tuned count (set for the full
 // basis, whose instance fits one workgroup per CU), doubled for bases of at
 // most 32 columns, whose instance leaves LDS and registers for two per CU
@@ -478,6 +519,12 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     }
     std::vector<int> act, pact;
     bool have_p = false;
+    // Hard locking (w.hardlock): `locked` bands keep X and AX (equal in V and
+    // U, so the update, which skips them, leaves them in place); pvalid: the
+    // bands whose P the last update wrote.
+    const unsigned all_bands = mb >= 32 ? ~0u : (1u << mb) - 1u;
+    bool hard = false;
+    unsigned locked = 0, pvalid = 0;
     if (union_start)
         for (int j = 0; j < mb; ++j) act.push_back(j);
     RRArgs ra;
@@ -582,15 +629,87 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     };
     double rate = 0.85, r_chunk0 = HUGE_VAL;   // residual reduction per iteration, for the chunk length
     int chunk_prev = 0;
+    // lock the bands in `nw`: X, AX copied into U; the P, AP of the bands
+    // still iterating made orthogonal to the new locked vectors
+    auto lock_bands = [&](unsigned nw) -> int {
+        if (!nw) return MFD_OK;
+        if (!w.theta_a) {
+            const size_t npl = 512;
+            if (hipMalloc(&w.theta_a, 64 * sizeof(double)) != hipSuccess ||
+                hipMalloc(&w.lpart, npl * LK_MAXL * LK_MAXT * sizeof(double2)) != hipSuccess ||
+                hipMalloc(&w.lcoef, LK_MAXL * LK_MAXT * sizeof(double2)) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(MFD_ENOMEM, "hard locking: allocation failed");
+            }
+        }
+        LockCols lc;
+        for (int j = 0; j < mb; ++j)
+            if ((nw >> j) & 1u) {
+                HIPCHK(hipMemcpyAsync(col(U, n, j), col(V, n, j), n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(col(U, n, 3 * mb + j), col(V, n, 3 * mb + j), n * sizeof(double2),
+                                      hipMemcpyDeviceToDevice, s));
+                lc.xc[lc.nl] = (short)j;
+                lc.axc[lc.nl] = (short)(3 * mb + j);
+                ++lc.nl;
+            }
+        if (have_p) {
+            for (int j : act)
+                if ((pvalid >> j) & 1u) {
+                    lc.yc[lc.nt] = (short)(2 * mb + j);
+                    lc.zc[lc.nt] = (short)(5 * mb + j);
+                    ++lc.nt;
+                }
+            if (lc.nt) {
+                lc.y32 = mixed ? 1 : 0;
+                lc.zpair = 1;
+                HIPCHK(launch_lock_coef(lc, V, mixed ? V32 : nullptr, n, n, 512, w.lpart, w.lcoef, s));
+                HIPCHK(launch_lock_apply(lc, w.lcoef, V, mixed ? V32 : nullptr, n, n, 1024, s));
+            }
+        }
+        locked |= nw;
+        return MFD_OK;
+    };
+    auto resync_locked = [&]() -> int {   // V's AX was recomputed: U's copies of the locked ones follow
+        for (int j = 0; j < mb; ++j)
+            if ((locked >> j) & 1u)
+                HIPCHK(hipMemcpyAsync(col(U, n, 3 * mb + j), col(V, n, 3 * mb + j), n * sizeof(double2),
+                                      hipMemcpyDeviceToDevice, s));
+        return MFD_OK;
+    };
+    auto leave_hard = [&]() {
+        hard = false;
+        locked = 0;
+        have_p = false;   // P of bands that were locked is missing: restart
+    };
     for (;; ++it) {
         const int rb = mixed ? 8 : 16;   // bytes per complex of the W/AW blocks
+        // Hard locking: from the point where at most LK_NA bands iterate, the
+        // others are locked; bands that iterate again leave the locked set,
+        // and more than LK_NA iterating bands end hard locking
+        if (w.hardlock && it > 0 && have_p && !union_start) {
+            unsigned am = 0;
+            for (int j : act) am |= 1u << j;
+            if (!hard) {
+                if (!act.empty() && (int)act.size() <= LK_NA) {
+                    const int st = lock_bands(all_bands & ~am);
+                    if (st) return st;
+                    hard = true;
+                }
+            } else if (act.empty() || (int)act.size() > LK_NA) {
+                leave_hard();
+            } else {
+                locked &= ~am;
+                const int st = lock_bands(all_bands & ~am & ~locked);
+                if (st) return st;
+            }
+        }
         // Graph chunks: from the third iteration on, several iterations run
         // from one captured graph with no host step between them; the active
         // set is the one of the chunk's start (bands that converge inside a
         // chunk keep iterating until its end).  The chunk's length follows
         // the residual's rate of decrease, so that it ends near convergence.
         bool chunked = false;
-        if (w.graph && it >= 2 && have_p && !act.empty() && !union_start) {
+        if (w.graph && !hard && it >= 2 && have_p && !act.empty() && !union_start) {
             if (chunk_prev > 0 && r_chunk0 < HUGE_VAL && rprev > 0.0)
                 rate = std::min(0.98, std::max(0.3, std::pow(rprev / r_chunk0, 1.0 / chunk_prev)));
             const double left = (rprev > tol) ? std::log(tol / rprev) / std::log(rate) : 1.0;
@@ -609,7 +728,79 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
                 }
             }
         }
-        if (!chunked) {
+        bool hard_step = false;
+        if (!chunked && hard) {
+            // the iteration on the bands still iterating (all W and P
+            // orthogonal to the locked X)
+            const int na = (int)act.size();
+            pact.clear();
+            for (int j : act)
+                if ((pvalid >> j) & 1u) pact.push_back(j);
+            const int np = (int)pact.size();
+            FieldList fl;
+            fl.on = 1;
+            for (int t = 0; t < na; ++t) fl.idx[t] = (unsigned char)act[t];
+            hipEvent_t e0 = w.prof.begin(s);
+            if (w.precond == 1) {
+                if (mixed) HIPCHK(launch_precond_mg<float2>(w.mg, p, w.mgo, na, V32 + n * mb, V32 + n * mb, s, fl));
+                else HIPCHK(launch_precond_mg<double2>(w.mg, p, w.mgo, na, col(V, n, mb), col(V, n, mb), s, fl));
+            } else if (mixed) {
+                HIPCHK(launch_precond<float>(p, na, V32 + n * mb, V32 + n * mb, c->tw32, s, fl));
+            } else {
+                HIPCHK(precond_fp64(c, p, na, col(V, n, mb), w.mixed ? V32 + n * mb : w.stage32, n, fl, s));
+            }
+            w.prof.end(e0, 1, N3 * 3 * rb * 2.0 * na, s);
+            if (locked) {   // W -= X_L (X_L^H W)
+                LockCols lc;
+                for (int j = 0; j < mb; ++j)
+                    if ((locked >> j) & 1u) {
+                        lc.xc[lc.nl] = (short)j;
+                        lc.axc[lc.nl] = (short)(3 * mb + j);
+                        ++lc.nl;
+                    }
+                for (int t = 0; t < na; ++t) lc.yc[lc.nt++] = (short)(mb + act[t]);
+                lc.y32 = mixed ? 1 : 0;
+                HIPCHK(launch_lock_coef(lc, V, mixed ? V32 : nullptr, n, n, 512, w.lpart, w.lcoef, s));
+                HIPCHK(launch_lock_apply(lc, w.lcoef, V, mixed ? V32 : nullptr, n, n, 1024, s));
+            }
+            e0 = w.prof.begin(s);
+            if (mixed) HIPCHK(launch_stencil_f64_s32(p, na, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s, fl));
+            else HIPCHK(launch_stencil<double>(p, na, col(V, n, mb), col(V, n, 4 * mb), c->mu64, s, fl));
+            w.prof.end(e0, 0, N3 * (6.0 * rb * na + 24.0), s);
+            const BasisMap bm = make_basis_hl(mb, act, pact, mixed);
+            hipEvent_t e1 = w.prof.begin(s);
+            HIPCHK(launch_gram_mfma(V, mixed ? V32 : nullptr, n, n, bm, gram_nparts(w, bm.K), w.gpart, w.G, s));
+            w.prof.end(e1, 2, 8.0 * (double)n * bm.K * (bm.K + 1), s);
+            RRArgs r2 = ra;
+            r2.K = bm.K;
+            r2.nw = na;
+            r2.mb = na;
+            r2.theta = w.theta_a;
+            e1 = w.prof.begin(s);
+            HIPCHK(accurate_rr ? launch_rr_jacobi(r2, s) : launch_rr(r2, s));
+            w.prof.end(e1, 3, 0.0, s);
+            LockBasis lb;
+            lb.na = na;
+            lb.K = bm.K;
+            lb.mb = mb;
+            for (int k = 0; k < bm.K; ++k) {
+                const int vc = k < na ? act[k] : (k < 2 * na ? mb + act[k - na] : 2 * mb + pact[k - 2 * na]);
+                lb.sc[k] = (short)vc;
+                lb.ic[k] = (short)(3 * mb + vc);
+                if (mixed && k >= na) lb.f32 |= 1ull << k;
+            }
+            for (int t = 0; t < na; ++t) lb.act[t] = (unsigned char)act[t];
+            e1 = w.prof.begin(s);
+            HIPCHK(launch_lock_update(lb, V, mixed ? V32 : nullptr, U, mixed ? U32 : nullptr, n, n, w.C, w.theta_a,
+                                      1024, w.npart, w.norms, s));
+            w.prof.end(e1, 4, (double)n * (2 * na * 16.0 + 2 * (na + np) * rb + 2 * na * 16.0 + 3 * na * rb), s);
+            std::swap(V, U);
+            if (mixed) std::swap(V32, U32);
+            have_p = true;
+            pvalid = 0;
+            for (int j : act) pvalid |= 1u << j;
+            hard_step = true;
+        } else if (!chunked) {
         // P columns: every update writes P' of every band, so each active band
         // has one from the second iteration on (zero after the first, which the
         // Rayleigh-Ritz step leaves out)
@@ -678,13 +869,34 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         std::swap(V, U);
         if (mixed) std::swap(V32, U32);
         have_p = true;   // the update wrote P', AP' of every band
+        pvalid = all_bands;
         }   // eager iteration
+        int* hinfo = (int*)(w.host + 3 * mb);
+        if (hard_step) {
+            // the iterating bands' Ritz values and norms, scattered to their
+            // bands; the locked ones keep theirs.  The device theta of every
+            // band follows (refreshes and residuals read it).
+            double* tha = w.host + 8 * mb + 32;
+            double* nra = tha + mb;
+            const int na = (int)act.size();
+            HIPCHK(hipMemcpyAsync(tha, w.theta_a, na * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(hfloor, w.theta + mb, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(nra, w.norms, 2 * na * sizeof(double), hipMemcpyDeviceToHost, s));
+            if (trace) HIPCHK(hipMemcpyAsync(hinfo, w.info, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(wsync(w));
+            for (int t = 0; t < na; ++t) {
+                hth[act[t]] = tha[t];
+                hnorm[act[t]] = nra[t];
+                hnorm[mb + act[t]] = nra[na + t];
+            }
+            HIPCHK(hipMemcpyAsync(w.theta, hth, mb * sizeof(double), hipMemcpyHostToDevice, s));
+        } else {
         HIPCHK(hipMemcpyAsync(hth, w.theta, mb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hfloor, w.theta + mb, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
-        int* hinfo = (int*)(w.host + 3 * mb);
         if (trace) HIPCHK(hipMemcpyAsync(hinfo, w.info, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(wsync(w));
+        }
         w.prof.drain();
         double rmax = 0.0;
         bool conv = residuals(&rmax);
@@ -737,6 +949,10 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             if (trace) std::fprintf(stderr, "[%p] it %d: suspect step, Ritz values vs fresh Rayleigh quotients %.3e "
                                     "(scale %.3e)%s\n", (void*)&w, it, dev, scale, reject ? ": rejected" : "");
             if (!reject) {   // the fresh A X' stands in for the tracked one
+                if (hard) {
+                    const int st = resync_locked();
+                    if (st) return st;
+                }
                 HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb),
                                        mixed ? (void*)(V32 + n * mb) : col(V, n, mb), mixed, n, n, mb, w.theta,
                                        w.nparts_col, w.npart, w.norms, s));
@@ -749,6 +965,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         }
         rejected_last = reject;
         if (reject) {
+            if (hard) leave_hard();
             std::swap(V, U);
             if (mixed) std::swap(V32, U32);
             if (mixed && stall_window > 0) {
@@ -780,6 +997,10 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         // the target, the iteration goes on from the refreshed state.
         if (it > 0 && it != last_refresh && (conv || (mixed && it - last_refresh >= 15))) {
             HIPCHK(launch_stencil<double>(p, mb, col(V, n, 0), col(V, n, 3 * mb), c->mu64, s));
+            if (hard) {
+                const int st = resync_locked();
+                if (st) return st;
+            }
             HIPCHK(launch_residual(col(V, n, 0), col(V, n, 3 * mb), mixed ? (void*)(V32 + n * mb) : col(V, n, mb),
                                    mixed, n, n, mb, w.theta, w.nparts_col, w.npart, w.norms, s));
             HIPCHK(hipMemcpyAsync(hnorm, w.norms, 2 * mb * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -803,6 +1024,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         // not halved in stall_window iterations, finish this k-point in FP64
         // from the current X with fresh A X, R = A X - theta X and no P.
         if (mixed && stall_window > 0 && it - best_it >= stall_window) {
+            if (hard) leave_hard();
             mixed = false;
             out.fp64_fallback = true;
             have_p = false;   // no P in FP64 storage yet
@@ -818,6 +1040,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             if (trace) std::fprintf(stderr, "[%p] it %d: mixed precision stalled at %.3e, continuing in FP64\n",
                                     (void*)&w, it, rmax);
         } else if (!mixed && stall_window > 0 && it - best_it >= std::max(stall_window, 40)) {
+            if (hard) leave_hard();
             // FP64 stall (a nearly dependent search direction kept in the
             // basis can hold the Rayleigh-Ritz step at a floor): restart the
             // conjugate directions once from the current X, with fresh A X and
@@ -1080,6 +1303,7 @@ void run_segment(Segment* sg) {
     const mfd_opts& o = sg->opts;
     w.precond = o.precond;
     w.graph = o.graph != 0;
+    w.hardlock = o.hard_lock != 0;
     w.mgo.cycles = o.mg_cycles;
     w.mgo.n1 = w.mgo.n2 = o.mg_smooth;
     w.mgo.sweeps = o.mg_sweeps;
@@ -1368,7 +1592,8 @@ int check_opts(const mfd_ctx* ctx, int nbands, double tol, const mfd_opts& o) {
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MFD_EINVAL, "tol must be finite and > 0");
     if (o.guard < 0 || o.max_iter < 1 || o.max_gamma_doublings < 0 || o.streams < 1 || o.streams > 16 ||
         o.stall_window < 0 || o.warm_start < 0 || o.warm_start > 2 || o.learn_steps < 0 || o.graph < 0 || o.graph > 1 ||
-        o.cold_start < 0 || o.cold_start > 1 || o.balance < 0 || o.balance > 1 ||
+        o.cold_start < 0 || o.cold_start > 1 || o.balance < 0 || o.balance > 1 || o.hard_lock < 0 ||
+        o.hard_lock > 1 ||
         (o.balance && o.warm_start == 2) || !(o.learn_rate >= 0.0f))
         return fail(MFD_EINVAL, "bad options");
     const int mb = nbands + o.guard;
@@ -1418,6 +1643,7 @@ void mfd_default_opts(mfd_opts* o) {
     o->graph = 0;
     o->cold_start = 0;
     o->balance = 0;
+    o->hard_lock = 0;
 }
 
 int mfd_tuning(const mfd_ctx* ctx, int* out) {

@@ -1,0 +1,251 @@
+// Hard locking for the last iterations of a k-point (the block eigensolver of
+// Section 5.1): once at most LK_NA bands still iterate, the converged bands'
+// vectors X_L are frozen and left out of the Rayleigh-Ritz basis, the new
+// search directions are made orthogonal to them, and the update touches only
+// the bands still iterating.  Three kernels, all bound by HBM:
+//   lock_coef:   c = X_L^H Y                  (per-workgroup partial sums)
+//   lock_apply:  Y -= X_L c  (and Z -= A X_L c, keeping Z = A Y)
+//   lock_update: the block update over the basis [X_A W P] of the bands A
+//                still iterating (X', AX', R', P', AP' of those bands only)
+// Y and Z are W (and AW) or P (and AP) columns; in mixed precision they are
+// stored in FP32 and computed on in FP64.
+#include "common.h"
+#include "solver.h"
+
+namespace mfd {
+
+constexpr int LK_NT = 256;
+constexpr int LK_TR = 32;   // rows per LDS tile of lock_coef
+
+// part[w][l * nt + t] = sum over the rows of workgroup w of conj(X_l) Y_t
+__global__ __launch_bounds__(LK_NT) void lock_coef_kernel(LockCols c, const double2* __restrict__ V,
+                                                          const float2* __restrict__ V32, size_t ld, size_t n,
+                                                          size_t rows_per, double2* __restrict__ part) {
+    __shared__ double2 xs[LK_TR][LK_MAXL];
+    __shared__ double2 ys[LK_TR][LK_MAXT];
+    const int tid = threadIdx.x;
+    const int nl = c.nl, nt = c.nt, ncol = nl + nt;
+    const size_t r0 = (size_t)blockIdx.x * rows_per;
+    const size_t r1 = min(n, r0 + rows_per);
+    const int p = tid, l = p / max(nt, 1), t = p % max(nt, 1);
+    const bool mine = p < nl * nt;
+    double2 acc = mk<double2>(0.0, 0.0);
+    constexpr int PE = (LK_TR * (LK_MAXL + LK_MAXT) + LK_NT - 1) / LK_NT;
+    for (size_t s0 = r0; s0 < r1; s0 += LK_TR) {
+        // element e of the tile: row e % LK_TR of column e / LK_TR (X_L first,
+        // then Y); every load of the tile is issued before the LDS writes
+        double2 v[PE];
+#pragma unroll
+        for (int q = 0; q < PE; ++q) {
+            const int e = tid + q * LK_NT;
+            const int r = e % LK_TR, col = min(e / LK_TR, ncol - 1);
+            const size_t row = min(s0 + r, r1 - 1);
+            if (col < nl) {
+                v[q] = V[(size_t)c.xc[col] * ld + row];
+            } else if (c.y32) {
+                const float2 f = V32[(size_t)c.yc[col - nl] * ld + row];
+                v[q] = mk<double2>((double)f.x, (double)f.y);
+            } else {
+                v[q] = V[(size_t)c.yc[col - nl] * ld + row];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PE; ++q) {
+            const int e = tid + q * LK_NT;
+            const int r = e % LK_TR, col = e / LK_TR;
+            if (col >= ncol) continue;
+            const double2 w = (s0 + r < r1) ? v[q] : mk<double2>(0.0, 0.0);
+            if (col < nl) xs[r][col] = w;
+            else ys[r][col - nl] = w;
+        }
+        __syncthreads();
+        if (mine)
+            for (int r = 0; r < LK_TR; ++r) acc = cfmac(acc, xs[r][l], ys[r][t]);
+        __syncthreads();
+    }
+    if (mine) part[(size_t)blockIdx.x * nl * nt + p] = acc;
+}
+
+// Y_t -= sum_l X_l coef[l][t]; with c.zpair also Z_t -= sum_l AX_l coef[l][t]
+__global__ __launch_bounds__(LK_NT) void lock_apply_kernel(LockCols c, const double2* __restrict__ coef,
+                                                           double2* __restrict__ V, float2* __restrict__ V32,
+                                                           size_t ld, size_t n) {
+    __shared__ double2 cf[LK_MAXL * LK_MAXT];
+    const int nl = c.nl, nt = c.nt;
+    for (int e = threadIdx.x; e < nl * nt; e += LK_NT) cf[e] = coef[e];
+    __syncthreads();
+    for (size_t row = (size_t)blockIdx.x * LK_NT + threadIdx.x; row < n; row += (size_t)gridDim.x * LK_NT) {
+        for (int pass = 0; pass < (c.zpair ? 2 : 1); ++pass) {
+            double2 acc[LK_MAXT];
+#pragma unroll
+            for (int t = 0; t < LK_MAXT; ++t) acc[t] = mk<double2>(0.0, 0.0);
+            for (int l = 0; l < nl; ++l) {
+                const double2 x = V[(size_t)(pass ? c.axc[l] : c.xc[l]) * ld + row];
+#pragma unroll
+                for (int t = 0; t < LK_MAXT; ++t)
+                    if (t < nt) acc[t] = cfma(acc[t], x, cf[l * nt + t]);
+            }
+#pragma unroll
+            for (int t = 0; t < LK_MAXT; ++t) {
+                if (t >= nt) continue;
+                const size_t o = (size_t)(pass ? c.zc[t] : c.yc[t]) * ld + row;
+                if (c.y32) {
+                    const float2 y = V32[o];
+                    V32[o] = make_float2((float)((double)y.x - acc[t].x), (float)((double)y.y - acc[t].y));
+                } else {
+                    V[o] = csub(V[o], acc[t]);
+                }
+            }
+        }
+    }
+}
+
+// The update over the basis S = [X_A W_A P] (K columns) and AS: for output t
+// (band act[t]) X'_t = S C[:, t], P'_t = the W, P part of it, the same for
+// the images; R'_t = AX'_t - theta_t X'_t.  Norm partials |R'_t|^2, |X'_t|^2.
+// One row per thread; the basis columns are read in chunks of LK_CH, every
+// load of a chunk issued before its products (the column index is clamped
+// and C's rows past K are zero).
+constexpr int LK_CH = 8;
+__global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const double2* __restrict__ V,
+                                                            const float2* __restrict__ V32, double2* __restrict__ U,
+                                                            float2* __restrict__ U32, size_t ld, size_t n,
+                                                            const double2* __restrict__ Cg,
+                                                            const double* __restrict__ theta,
+                                                            double* __restrict__ npart) {
+    __shared__ double2 cs[LK_MAXK * LK_NA];   // C, rows past K and columns past na zero
+    __shared__ int col[2][LK_MAXK];           // V or V32 column of basis column k (chain 0) and of its image
+    __shared__ unsigned char f32[LK_MAXK];
+    __shared__ double th[LK_NA];
+    __shared__ double red[LK_NT / 64][2 * LK_NA];
+    const int na = b.na, K = b.K, mb = b.mb;
+    for (int e = threadIdx.x; e < LK_MAXK * LK_NA; e += LK_NT) {
+        const int k = e / LK_NA, t = e % LK_NA;
+        cs[e] = (k < K && t < na) ? Cg[(size_t)k * na + t] : mk<double2>(0.0, 0.0);
+    }
+    if (threadIdx.x < LK_MAXK) {
+        const int k = min((int)threadIdx.x, K - 1);
+        col[0][threadIdx.x] = b.sc[k];
+        col[1][threadIdx.x] = b.ic[k];
+        f32[threadIdx.x] = (unsigned char)((b.f32 >> k) & 1ull);
+    }
+    if (threadIdx.x < LK_NA) th[threadIdx.x] = threadIdx.x < (unsigned)na ? theta[threadIdx.x] : 0.0;
+    __shared__ int band[LK_NA];
+    if (threadIdx.x < LK_NA) band[threadIdx.x] = b.act[threadIdx.x < (unsigned)na ? threadIdx.x : 0];
+    __syncthreads();
+    double nr[LK_NA], nx[LK_NA];
+#pragma unroll
+    for (int t = 0; t < LK_NA; ++t) nr[t] = nx[t] = 0.0;
+    const int nch = (K + LK_CH - 1) / LK_CH;
+    for (size_t row = (size_t)blockIdx.x * LK_NT + threadIdx.x; row < n; row += (size_t)gridDim.x * LK_NT) {
+        double2 xo[LK_NA];
+        for (int ch = 0; ch < 2; ++ch) {
+            double2 ax[LK_NA], ap[LK_NA];
+#pragma unroll
+            for (int t = 0; t < LK_NA; ++t) ax[t] = ap[t] = mk<double2>(0.0, 0.0);
+            for (int c0 = 0; c0 < nch * LK_CH; c0 += LK_CH) {
+                double2 sv[LK_CH];
+#pragma unroll
+                for (int q = 0; q < LK_CH; ++q) {
+                    const int k = c0 + q;
+                    const size_t o = (size_t)col[ch][k] * ld + row;
+                    if (f32[k]) {
+                        const float2 f = V32[o];
+                        sv[q] = mk<double2>((double)f.x, (double)f.y);
+                    } else {
+                        sv[q] = V[o];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < LK_CH; ++q) {
+                    const int k = c0 + q;
+#pragma unroll
+                    for (int t = 0; t < LK_NA; ++t) {
+                        const double2 cv = cs[k * LK_NA + t];
+                        ax[t] = cfma(ax[t], sv[q], cv);
+                        if (k >= na) ap[t] = cfma(ap[t], sv[q], cv);   // a W or P column
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < LK_NA; ++t) {
+                if (t >= na) continue;
+                const int bj = band[t];
+                if (ch == 0) {
+                    xo[t] = ax[t];
+                    U[(size_t)bj * ld + row] = ax[t];
+                    if (U32) U32[(size_t)(2 * mb + bj) * ld + row] = make_float2((float)ap[t].x, (float)ap[t].y);
+                    else U[(size_t)(2 * mb + bj) * ld + row] = ap[t];
+                } else {
+                    U[(size_t)(3 * mb + bj) * ld + row] = ax[t];
+                    const double2 res = mk<double2>(ax[t].x - th[t] * xo[t].x, ax[t].y - th[t] * xo[t].y);
+                    if (U32) {
+                        U32[(size_t)(mb + bj) * ld + row] = make_float2((float)res.x, (float)res.y);
+                        U32[(size_t)(5 * mb + bj) * ld + row] = make_float2((float)ap[t].x, (float)ap[t].y);
+                    } else {
+                        U[(size_t)(mb + bj) * ld + row] = res;
+                        U[(size_t)(5 * mb + bj) * ld + row] = ap[t];
+                    }
+                    nr[t] += cabs2(res);
+                    nx[t] += cabs2(xo[t]);
+                }
+            }
+        }
+    }
+    // per-workgroup sums: lanes by shuffles, then the waves in order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < LK_NA; ++t) {
+        double a = nr[t], c = nx[t];
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_down(a, o);
+            c += __shfl_down(c, o);
+        }
+        if (lane == 0) {
+            red[wave][t] = a;
+            red[wave][LK_NA + t] = c;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)(2 * na)) {
+        const int which = threadIdx.x / na, t = threadIdx.x % na;
+        double v = 0.0;
+        for (int w = 0; w < LK_NT / 64; ++w) v += red[w][which * LK_NA + t];
+        npart[(size_t)blockIdx.x * 2 * na + threadIdx.x] = v;
+    }
+}
+
+hipError_t launch_lock_coef(const LockCols& c, const void* V, const void* V32, size_t ld, size_t n, int nparts,
+                            void* part, void* coef, hipStream_t s) {
+    if (c.nl < 1 || c.nl > LK_MAXL || c.nt < 1 || c.nt > LK_MAXT || c.nl * c.nt > LK_NT || nparts < 1 || !n)
+        return hipErrorInvalidValue;
+    const size_t rows_per = ((n + nparts - 1) / nparts + LK_TR - 1) / LK_TR * LK_TR;
+    const int nw = (int)((n + rows_per - 1) / rows_per);
+    hipLaunchKernelGGL(lock_coef_kernel, dim3(nw), dim3(LK_NT), 0, s, c, (const double2*)V, (const float2*)V32, ld,
+                       n, rows_per, (double2*)part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce((const double*)part, nw, 2 * c.nl * c.nt, (double*)coef, s);
+}
+
+hipError_t launch_lock_apply(const LockCols& c, const void* coef, void* V, void* V32, size_t ld, size_t n,
+                             int nblocks, hipStream_t s) {
+    if (c.nl < 1 || c.nl > LK_MAXL || c.nt < 1 || c.nt > LK_MAXT || nblocks < 1 || !n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lock_apply_kernel, dim3(nblocks), dim3(LK_NT), 0, s, c, (const double2*)coef, (double2*)V,
+                       (float2*)V32, ld, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_lock_update(const LockBasis& b, const void* V, const void* V32, void* U, void* U32, size_t ld,
+                              size_t n, const void* C, const double* theta, int nblocks, double* npart, double* norms,
+                              hipStream_t s) {
+    if (b.na < 1 || b.na > LK_NA || b.K < b.na || b.K > LK_MAXK || nblocks < 1 || !n) return hipErrorInvalidValue;
+    if ((V32 == nullptr) != (U32 == nullptr)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lock_update_kernel, dim3(nblocks), dim3(LK_NT), 0, s, b, (const double2*)V,
+                       (const float2*)V32, (double2*)U, (float2*)U32, ld, n, (const double2*)C, theta, npart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(npart, nblocks, 2 * b.na, norms, s);
+}
+
+}  // namespace mfd

@@ -80,4 +80,31 @@ hipError_t launch_rr(const RRArgs& a, hipStream_t s);
 // iterations, where rr.hip's absolute accuracy would bound the residual.
 hipError_t launch_rr_jacobi(const RRArgs& a, hipStream_t s);
 
+// Hard locking of the last iterations (lock.hip).  LK_NA: most bands still
+// iterating when it applies; LK_MAXL: most locked bands.
+constexpr int LK_NA = 8, LK_MAXK = 3 * LK_NA, LK_MAXL = 22, LK_MAXT = LK_NA;
+// Columns of c = X_L^H Y and of Y -= X_L c (Z -= AX_L c with zpair):
+// xc / axc: V columns of X_L and AX_L; yc / zc: columns of Y and Z (V32 with
+// y32, else V).
+struct LockCols {
+    int nl = 0, nt = 0, y32 = 0, zpair = 0;
+    short xc[LK_MAXL], axc[LK_MAXL], yc[LK_MAXT], zc[LK_MAXT];
+};
+hipError_t launch_lock_coef(const LockCols& c, const void* V, const void* V32, size_t ld, size_t n, int nparts,
+                            void* part, void* coef, hipStream_t s);
+hipError_t launch_lock_apply(const LockCols& c, const void* coef, void* V, void* V32, size_t ld, size_t n,
+                             int nblocks, hipStream_t s);
+// Basis [X_A W_A P] of the bands act[0..na) for the hard-locked update: sc /
+// ic the columns of basis column k and of its image (V32 when bit k of f32 is
+// set, else V); C is K x na (row-major), theta the na Ritz values.
+struct LockBasis {
+    int na = 0, K = 0, mb = 0;
+    unsigned long long f32 = 0;
+    short sc[LK_MAXK], ic[LK_MAXK];
+    unsigned char act[LK_NA];
+};
+hipError_t launch_lock_update(const LockBasis& b, const void* V, const void* V32, void* U, void* U32, size_t ld,
+                              size_t n, const void* C, const double* theta, int nblocks, double* npart, double* norms,
+                              hipStream_t s);
+
 }  // namespace mfd

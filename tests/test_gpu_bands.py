@@ -358,3 +358,26 @@ def test_balanced_segments(B, precision):
     assert np.allclose(e1[11], lam, rtol=rt), (e1[11], lam)
     with pytest.raises(RuntimeError):
         B.mfd_bands(ctx, kp[:4], m, tol, B.default_opts(balance=1, warm_start=2, **opts))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hard_lock_matches_soft(B, precision):
+    """opts.hard_lock = 1 (once at most 8 bands iterate, the converged ones
+    are locked and the iteration runs on the rest, its search directions made
+    orthogonal to the locked vectors) returns the soft-locking bands: diamond
+    N = 16, 10 bands + 2 guard on a 10-point path, every k-point converged, and
+    a k-point matches the oracle."""
+    N, m = 16, 10
+    eps = workloads.eps_diamond(N)
+    kp = workloads.kpath("GXMGR", 10)
+    ctx = B.mfd_build(N, 1.0, 2, eps)
+    tol = 1e-8 if precision else 1e-10
+    opts = dict(precision=precision, streams=2, guard=2, cold_start=1)
+    e0, s0, st0 = B.mfd_bands(ctx, kp, m, tol, B.default_opts(hard_lock=0, **opts))
+    e1, s1, st1 = B.mfd_bands(ctx, kp, m, tol, B.default_opts(hard_lock=1, **opts))
+    assert st0 == 0 and st1 == 0, (s0, s1)
+    assert all(s["max_rel_resid"] <= tol for s in s1)
+    rt = 1e-7 if precision else 1e-9
+    assert np.allclose(e0, e1, rtol=rt, atol=1e-9)
+    lam, _, _ = olob.solve_bands(eps, 1.0, kp[6], m, tol=1e-10)
+    assert np.allclose(e1[6], lam, rtol=rt), (e1[6], lam)
