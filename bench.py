@@ -58,7 +58,7 @@ def parse():
                     help="extra block columns beyond the bands (16 + 4 = 20 columns: fewest seconds per "
                          "k-point of guard 2..6 on the diamond N = 64 path)")
     ap.add_argument("--streams", type=int, default=12, help="k-path segments solved concurrently")
-    ap.add_argument("--hard-lock", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--hard-lock", type=int, default=1, choices=[0, 1],
                     help="1: hard locking once at most 8 bands of a k-point iterate (opts.hard_lock)")
     ap.add_argument("--balance", type=int, default=0, choices=[0, 1],
                     help="1: a stream whose segment is done takes half of the busiest segment's remaining "
@@ -102,7 +102,8 @@ def progress(msg):
     """One line on stderr per finished piece of work (the JSON line goes to stdout)."""
     print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
-KERNEL_SOURCES = {"update": "gemm.hip", "gram": "gemm.hip", "stencil": "stencil.hip", "precond": "fft.hip"}
+KERNEL_SOURCES = {"update": ("gemm.hip", "lock.hip"), "gram": ("gemm.hip",), "stencil": ("stencil.hip",),
+                  "precond": ("fft.hip",)}
 
 
 def measured_traffic(workload, precision):
@@ -121,9 +122,12 @@ def measured_traffic(workload, precision):
                 if ":" in line and line.startswith("- "):
                     key, _, val = line[2:].partition(":")
                     fields[key.strip()] = val.strip().strip("`")
-        src_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2503_19379_amd", "csrc", src)
-        with open(src_path, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()   # over the category's source files, in order
+        for name in src:
+            with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2503_19379_amd", "csrc", name),
+                      "rb") as f:
+                h.update(f.read())
+        digest = h.hexdigest()
         if fields.get("source_sha256") == digest and "traffic_bytes_per_launch" in fields:
             out[cat] = float(fields["traffic_bytes_per_launch"])
     return out
@@ -495,7 +499,8 @@ def kernel_table(prof, wall_s=None):
         if cat == "rr":
             e.update(bound="latency", note="one workgroup (one CU); overlaps other segments' kernels")
         elif cat == "other":
-            e.update(bound="latency", note="fixed-order sums of the Gram tiles and of the update's column norms")
+            e.update(bound="latency", note="fixed-order sums of the Gram tiles and of the update's column norms; "
+                     "under hard locking the projections of W (and P) against the locked vectors")
         elif cat == "gram":
             e.update(bound="mfma", achieved=per / avg_s / 1e12, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
                      frac=per / avg_s / FP64_PEAK, per_launch=per,

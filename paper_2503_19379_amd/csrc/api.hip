@@ -662,8 +662,10 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
             if (lc.nt) {
                 lc.y32 = mixed ? 1 : 0;
                 lc.zpair = 1;
+                hipEvent_t ep = w.prof.begin(s);
                 HIPCHK(launch_lock_coef(lc, V, mixed ? V32 : nullptr, n, n, 512, w.lpart, w.lcoef, s));
                 HIPCHK(launch_lock_apply(lc, w.lcoef, V, mixed ? V32 : nullptr, n, n, 1024, s));
+                w.prof.end(ep, 5, 0.0, s);
             }
         }
         locked |= nw;
@@ -760,8 +762,10 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
                     }
                 for (int t = 0; t < na; ++t) lc.yc[lc.nt++] = (short)(mb + act[t]);
                 lc.y32 = mixed ? 1 : 0;
+                hipEvent_t ep = w.prof.begin(s);
                 HIPCHK(launch_lock_coef(lc, V, mixed ? V32 : nullptr, n, n, 512, w.lpart, w.lcoef, s));
                 HIPCHK(launch_lock_apply(lc, w.lcoef, V, mixed ? V32 : nullptr, n, n, 1024, s));
+                w.prof.end(ep, 5, 0.0, s);
             }
             e0 = w.prof.begin(s);
             if (mixed) HIPCHK(launch_stencil_f64_s32(p, na, V32 + n * mb, V32 + n * 4 * mb, c->mu64, s, fl));

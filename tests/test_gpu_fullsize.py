@@ -25,7 +25,7 @@ def B():
     return binding
 
 
-def _check(B, name, precision, rtol, streams=4, tuning=None, guard=2, cold_start=0):
+def _check(B, name, precision, rtol, streams=4, tuning=None, guard=2, cold_start=0, hard_lock=0):
     if not os.path.exists(make_golden.path(name)):
         pytest.skip(f"{name} golden values not written")
     gold = make_golden.load(name)
@@ -36,7 +36,7 @@ def _check(B, name, precision, rtol, streams=4, tuning=None, guard=2, cold_start
     if tuning is not None:
         B.mfd_set_tuning(ctx, tuning)
     opts = B.default_opts(precision=precision, warm_start=1, guard=guard, streams=streams, max_iter=500,
-                          cold_start=cold_start)
+                          cold_start=cold_start, hard_lock=hard_lock)
     ev, st, status = B.mfd_bands(ctx, kp, m, 1e-8, opts)
     assert status == 0, st
     for i, s in enumerate(st):
@@ -59,13 +59,18 @@ def test_diamond_n64_fp64(B):
     """The benchmark workload solved in FP64 throughout (the plain FP64 GPU
     solve the benchmark reports beside the mixed one), in the benchmark's
     launch configuration (12 segments, 4 guard columns, plane-wave cold
-    starts): 1e-10 relative."""
-    _check(B, "diamond_n64", 0, 1e-10, streams=12, guard=4, cold_start=1)
+    starts, hard locking of the last iterations): 1e-10 relative."""
+    _check(B, "diamond_n64", 0, 1e-10, streams=12, guard=4, cold_start=1, hard_lock=1)
 
 
 def test_diamond_n64_mixed(B):
     """The benchmark's own configuration: mixed precision, 12 segments, 4
-    guard columns, plane-wave cold starts."""
+    guard columns, plane-wave cold starts, hard locking."""
+    _check(B, "diamond_n64", 1, 1e-7, streams=12, guard=4, cold_start=1, hard_lock=1)
+
+
+def test_diamond_n64_mixed_soft_locking(B):
+    """The same with soft locking only (the library's default)."""
     _check(B, "diamond_n64", 1, 1e-7, streams=12, guard=4, cold_start=1)
 
 
