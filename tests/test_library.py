@@ -88,7 +88,7 @@ def test_host_side_argument_errors():
     assert h.value is None
     o = b.default_opts()
     assert o.autotune == 1 and o.stall_window == 40 and o.learn_steps == 30
-    assert o.cold_start == 0 and o.balance == 0
+    assert o.cold_start == 0 and o.balance == 0 and o.hard_lock == 0
 
 
 def test_binding_structs_match_the_header(tmp_path):
