@@ -634,7 +634,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
     auto lock_bands = [&](unsigned nw) -> int {
         if (!nw) return MFD_OK;
         if (!w.theta_a) {
-            const size_t npl = 512;
+            const size_t npl = 2048;
             if (hipMalloc(&w.theta_a, 64 * sizeof(double)) != hipSuccess ||
                 hipMalloc(&w.lpart, npl * LK_MAXL * LK_MAXT * sizeof(double2)) != hipSuccess ||
                 hipMalloc(&w.lcoef, LK_MAXL * LK_MAXT * sizeof(double2)) != hipSuccess) {
@@ -663,7 +663,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
                 lc.y32 = mixed ? 1 : 0;
                 lc.zpair = 1;
                 hipEvent_t ep = w.prof.begin(s);
-                HIPCHK(launch_lock_coef(lc, V, mixed ? V32 : nullptr, n, n, 512, w.lpart, w.lcoef, s));
+                HIPCHK(launch_lock_coef(lc, V, mixed ? V32 : nullptr, n, n, 2048, w.lpart, w.lcoef, s));
                 HIPCHK(launch_lock_apply(lc, w.lcoef, V, mixed ? V32 : nullptr, n, n, 1024, s));
                 w.prof.end(ep, 5, 0.0, s);
             }
@@ -763,7 +763,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
                 for (int t = 0; t < na; ++t) lc.yc[lc.nt++] = (short)(mb + act[t]);
                 lc.y32 = mixed ? 1 : 0;
                 hipEvent_t ep = w.prof.begin(s);
-                HIPCHK(launch_lock_coef(lc, V, mixed ? V32 : nullptr, n, n, 512, w.lpart, w.lcoef, s));
+                HIPCHK(launch_lock_coef(lc, V, mixed ? V32 : nullptr, n, n, 2048, w.lpart, w.lcoef, s));
                 HIPCHK(launch_lock_apply(lc, w.lcoef, V, mixed ? V32 : nullptr, n, n, 1024, s));
                 w.prof.end(ep, 5, 0.0, s);
             }

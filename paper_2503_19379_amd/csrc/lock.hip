@@ -17,7 +17,17 @@ namespace mfd {
 constexpr int LK_NT = 256;
 constexpr int LK_TR = 32;   // rows per LDS tile of lock_coef
 
-// part[w][l * nt + t] = sum over the rows of workgroup w of conj(X_l) Y_t
+// Workgroup barrier that orders LDS only: the next tile's global loads stay
+// in flight across it (a full barrier would wait for them too).
+__device__ __forceinline__ void lk_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// part[w][l * nt + t] = sum over the rows of workgroup w of conj(X_l) Y_t.
+// Tiles of LK_TR rows pass through LDS; the next tile's loads are issued
+// before the current tile's products.
 __global__ __launch_bounds__(LK_NT) void lock_coef_kernel(LockCols c, const double2* __restrict__ V,
                                                           const float2* __restrict__ V32, size_t ld, size_t n,
                                                           size_t rows_per, double2* __restrict__ part) {
@@ -31,10 +41,10 @@ __global__ __launch_bounds__(LK_NT) void lock_coef_kernel(LockCols c, const doub
     const bool mine = p < nl * nt;
     double2 acc = mk<double2>(0.0, 0.0);
     constexpr int PE = (LK_TR * (LK_MAXL + LK_MAXT) + LK_NT - 1) / LK_NT;
-    for (size_t s0 = r0; s0 < r1; s0 += LK_TR) {
-        // element e of the tile: row e % LK_TR of column e / LK_TR (X_L first,
-        // then Y); every load of the tile is issued before the LDS writes
-        double2 v[PE];
+    // element e of a tile: row e % LK_TR of column e / LK_TR (X_L first, then
+    // Y); rows past the end are clamped when loaded and zeroed when stored
+    double2 v[PE];
+    auto load = [&](size_t s0) {
 #pragma unroll
         for (int q = 0; q < PE; ++q) {
             const int e = tid + q * LK_NT;
@@ -49,6 +59,9 @@ __global__ __launch_bounds__(LK_NT) void lock_coef_kernel(LockCols c, const doub
                 v[q] = V[(size_t)c.yc[col - nl] * ld + row];
             }
         }
+    };
+    if (r0 < r1) load(r0);
+    for (size_t s0 = r0; s0 < r1; s0 += LK_TR) {
 #pragma unroll
         for (int q = 0; q < PE; ++q) {
             const int e = tid + q * LK_NT;
@@ -58,10 +71,11 @@ __global__ __launch_bounds__(LK_NT) void lock_coef_kernel(LockCols c, const doub
             if (col < nl) xs[r][col] = w;
             else ys[r][col - nl] = w;
         }
-        __syncthreads();
+        lk_lds_barrier();
+        if (s0 + LK_TR < r1) load(s0 + LK_TR);
         if (mine)
             for (int r = 0; r < LK_TR; ++r) acc = cfmac(acc, xs[r][l], ys[r][t]);
-        __syncthreads();
+        lk_lds_barrier();
     }
     if (mine) part[(size_t)blockIdx.x * nl * nt + p] = acc;
 }
