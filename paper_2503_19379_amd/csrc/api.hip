@@ -479,13 +479,15 @@ BasisMap make_basis_hl(int mb, const std::vector<int>& act, const std::vector<in
 
 // Gram workgroups for a basis of K columns: the tuned count (set for the full
 // basis, whose instance fits one workgroup per CU), doubled for bases of at
-// most 32 columns, whose instance leaves LDS and registers for two per CU
+// most 32 columns (four times for at most 16), whose instances leave LDS and
+// registers for two (four) per CU
 // (at the tuned count half the chip's slots stay empty: 252 -> 193 us at
 // K = 32, N = 64), when the partial-tile buffer holds them.
 int gram_nparts(const Ws& w, int K) {
     const int T = (K + 15) / 16;
     if (T <= 2) {
-        const int np = 2 * w.nparts_gram;
+        // one-tile bases (hard locking's small ones) fit four per CU
+        const int np = (T == 1 ? 4 : 2) * w.nparts_gram;
         if ((size_t)(np + 1) * T * (T + 1) * 256 <= w.gpart_elems) return np;
     }
     return w.nparts_gram;

@@ -120,43 +120,49 @@ __global__ __launch_bounds__(LK_NT) void lock_apply_kernel(LockCols c, const dou
 // One row per thread; the basis columns are read in chunks of LK_CH, every
 // load of a chunk issued before its products (the column index is clamped
 // and C's rows past K are zero).
+// NA: the outputs held in registers (4 or LK_NA), so that small sets of
+// iterating bands run at a higher occupancy.
 constexpr int LK_CH = 8;
+template <int NA>
 __global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const double2* __restrict__ V,
                                                             const float2* __restrict__ V32, double2* __restrict__ U,
                                                             float2* __restrict__ U32, size_t ld, size_t n,
                                                             const double2* __restrict__ Cg,
                                                             const double* __restrict__ theta,
                                                             double* __restrict__ npart) {
-    __shared__ double2 cs[LK_MAXK * LK_NA];   // C, rows past K and columns past na zero
-    __shared__ int col[2][LK_MAXK];           // V or V32 column of basis column k (chain 0) and of its image
-    __shared__ unsigned char f32[LK_MAXK];
-    __shared__ double th[LK_NA];
-    __shared__ double red[LK_NT / 64][2 * LK_NA];
+    constexpr int KP = (3 * NA + LK_CH - 1) / LK_CH * LK_CH;   // basis rows held: K <= 3 NA, whole chunks
+    __shared__ double2 cs[KP * NA];   // C, rows past K and columns past na zero
+    __shared__ int col[2][KP];           // V or V32 column of basis column k (chain 0) and of its image
+    __shared__ unsigned char f32[KP];
+    __shared__ double th[NA];
+    __shared__ double red[LK_NT / 64][2 * NA];
     const int na = b.na, K = b.K, mb = b.mb;
-    for (int e = threadIdx.x; e < LK_MAXK * LK_NA; e += LK_NT) {
-        const int k = e / LK_NA, t = e % LK_NA;
+    for (int e = threadIdx.x; e < KP * NA; e += LK_NT) {
+        const int k = e / NA, t = e % NA;
         cs[e] = (k < K && t < na) ? Cg[(size_t)k * na + t] : mk<double2>(0.0, 0.0);
     }
-    if (threadIdx.x < LK_MAXK) {
+    if (threadIdx.x < KP) {
         const int k = min((int)threadIdx.x, K - 1);
         col[0][threadIdx.x] = b.sc[k];
         col[1][threadIdx.x] = b.ic[k];
         f32[threadIdx.x] = (unsigned char)((b.f32 >> k) & 1ull);
     }
-    if (threadIdx.x < LK_NA) th[threadIdx.x] = threadIdx.x < (unsigned)na ? theta[threadIdx.x] : 0.0;
-    __shared__ int band[LK_NA];
-    if (threadIdx.x < LK_NA) band[threadIdx.x] = b.act[threadIdx.x < (unsigned)na ? threadIdx.x : 0];
+    if (threadIdx.x < NA) th[threadIdx.x] = threadIdx.x < (unsigned)na ? theta[threadIdx.x] : 0.0;
+    __shared__ int band[NA];
+    if (threadIdx.x < NA) band[threadIdx.x] = b.act[threadIdx.x < (unsigned)na ? threadIdx.x : 0];
     __syncthreads();
-    double nr[LK_NA], nx[LK_NA];
+    double nr[NA], nx[NA];
 #pragma unroll
-    for (int t = 0; t < LK_NA; ++t) nr[t] = nx[t] = 0.0;
+    for (int t = 0; t < NA; ++t) nr[t] = nx[t] = 0.0;
     const int nch = (K + LK_CH - 1) / LK_CH;
     for (size_t row = (size_t)blockIdx.x * LK_NT + threadIdx.x; row < n; row += (size_t)gridDim.x * LK_NT) {
-        double2 xo[LK_NA];
+        double2 xo[NA];
+#pragma unroll 1
         for (int ch = 0; ch < 2; ++ch) {
-            double2 ax[LK_NA], ap[LK_NA];
+            double2 ax[NA], ap[NA];
 #pragma unroll
-            for (int t = 0; t < LK_NA; ++t) ax[t] = ap[t] = mk<double2>(0.0, 0.0);
+            for (int t = 0; t < NA; ++t) ax[t] = ap[t] = mk<double2>(0.0, 0.0);
+#pragma unroll 1
             for (int c0 = 0; c0 < nch * LK_CH; c0 += LK_CH) {
                 double2 sv[LK_CH];
 #pragma unroll
@@ -174,15 +180,15 @@ __global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const d
                 for (int q = 0; q < LK_CH; ++q) {
                     const int k = c0 + q;
 #pragma unroll
-                    for (int t = 0; t < LK_NA; ++t) {
-                        const double2 cv = cs[k * LK_NA + t];
+                    for (int t = 0; t < NA; ++t) {
+                        const double2 cv = cs[k * NA + t];
                         ax[t] = cfma(ax[t], sv[q], cv);
                         if (k >= na) ap[t] = cfma(ap[t], sv[q], cv);   // a W or P column
                     }
                 }
             }
 #pragma unroll
-            for (int t = 0; t < LK_NA; ++t) {
+            for (int t = 0; t < NA; ++t) {
                 if (t >= na) continue;
                 const int bj = band[t];
                 if (ch == 0) {
@@ -209,7 +215,7 @@ __global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const d
     // per-workgroup sums: lanes by shuffles, then the waves in order
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int t = 0; t < LK_NA; ++t) {
+    for (int t = 0; t < NA; ++t) {
         double a = nr[t], c = nx[t];
         for (int o = 32; o > 0; o >>= 1) {
             a += __shfl_down(a, o);
@@ -217,14 +223,14 @@ __global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const d
         }
         if (lane == 0) {
             red[wave][t] = a;
-            red[wave][LK_NA + t] = c;
+            red[wave][NA + t] = c;
         }
     }
     __syncthreads();
     if (threadIdx.x < (unsigned)(2 * na)) {
         const int which = threadIdx.x / na, t = threadIdx.x % na;
         double v = 0.0;
-        for (int w = 0; w < LK_NT / 64; ++w) v += red[w][which * LK_NA + t];
+        for (int w = 0; w < LK_NT / 64; ++w) v += red[w][which * NA + t];
         npart[(size_t)blockIdx.x * 2 * na + threadIdx.x] = v;
     }
 }
@@ -255,8 +261,10 @@ hipError_t launch_lock_update(const LockBasis& b, const void* V, const void* V32
                               hipStream_t s) {
     if (b.na < 1 || b.na > LK_NA || b.K < b.na || b.K > LK_MAXK || nblocks < 1 || !n) return hipErrorInvalidValue;
     if ((V32 == nullptr) != (U32 == nullptr)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(lock_update_kernel, dim3(nblocks), dim3(LK_NT), 0, s, b, (const double2*)V,
-                       (const float2*)V32, (double2*)U, (float2*)U32, ld, n, (const double2*)C, theta, npart);
+    // a basis of K <= 3 na columns: the 4-output instance when na <= 4
+    auto kern = b.na <= 4 ? lock_update_kernel<4> : lock_update_kernel<LK_NA>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(LK_NT), 0, s, b, (const double2*)V, (const float2*)V32,
+                       (double2*)U, (float2*)U32, ld, n, (const double2*)C, theta, npart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_reduce(npart, nblocks, 2 * b.na, norms, s);
