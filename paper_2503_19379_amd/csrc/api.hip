@@ -638,7 +638,7 @@ int lobpcg_k(mfd_ctx* c, Ws& w, const OpParams& p, int nreq, double tol, int max
         if (!w.theta_a) {
             const size_t npl = 2048;
             if (hipMalloc(&w.theta_a, 64 * sizeof(double)) != hipSuccess ||
-                hipMalloc(&w.lpart, npl * LK_MAXL * LK_MAXT * sizeof(double2)) != hipSuccess ||
+                hipMalloc(&w.lpart, (npl + npl / 64 + 1) * LK_MAXL * LK_MAXT * sizeof(double2)) != hipSuccess ||
                 hipMalloc(&w.lcoef, LK_MAXL * LK_MAXT * sizeof(double2)) != hipSuccess) {
                 (void)hipGetLastError();
                 return fail(MFD_ENOMEM, "hard locking: allocation failed");

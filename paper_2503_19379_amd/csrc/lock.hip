@@ -235,6 +235,20 @@ __global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const d
     }
 }
 
+// First stage of the fixed-order sum of many partials: group g of LK_GS
+// consecutive partials into tmp[g] (one thread per column); the groups are
+// then summed by launch_reduce.
+constexpr int LK_GS = 64;
+__global__ __launch_bounds__(64) void lock_sum_kernel(const double* __restrict__ in, int nparts, int ncols,
+                                                      double* __restrict__ tmp) {
+    const int c = blockIdx.x * 64 + threadIdx.x, g = blockIdx.y;
+    if (c >= ncols) return;
+    const int w1 = min(nparts, (g + 1) * LK_GS);
+    double v = 0.0;
+    for (int w = g * LK_GS; w < w1; ++w) v += in[(size_t)w * ncols + c];
+    tmp[(size_t)g * ncols + c] = v;
+}
+
 hipError_t launch_lock_coef(const LockCols& c, const void* V, const void* V32, size_t ld, size_t n, int nparts,
                             void* part, void* coef, hipStream_t s) {
     if (c.nl < 1 || c.nl > LK_MAXL || c.nt < 1 || c.nt > LK_MAXT || c.nl * c.nt > LK_NT || nparts < 1 || !n)
@@ -245,7 +259,14 @@ hipError_t launch_lock_coef(const LockCols& c, const void* V, const void* V32, s
                        n, rows_per, (double2*)part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_reduce((const double*)part, nw, 2 * c.nl * c.nt, (double*)coef, s);
+    // part holds nparts + nparts / LK_GS + 1 partial sets: the group sums
+    // follow the workgroups' partials
+    const int ncols = 2 * c.nl * c.nt, ng = (nw + LK_GS - 1) / LK_GS;
+    double* tmp = (double*)part + (size_t)nw * ncols;
+    hipLaunchKernelGGL(lock_sum_kernel, dim3((ncols + 63) / 64, ng), dim3(64), 0, s, (const double*)part, nw, ncols,
+                       tmp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_reduce(tmp, ng, ncols, (double*)coef, s);
 }
 
 hipError_t launch_lock_apply(const LockCols& c, const void* coef, void* V, void* V32, size_t ld, size_t n,

@@ -90,6 +90,7 @@ struct LockCols {
     int nl = 0, nt = 0, y32 = 0, zpair = 0;
     short xc[LK_MAXL], axc[LK_MAXL], yc[LK_MAXT], zc[LK_MAXT];
 };
+// part: room for nparts + nparts / 64 + 1 sets of nl x nt partial sums
 hipError_t launch_lock_coef(const LockCols& c, const void* V, const void* V32, size_t ld, size_t n, int nparts,
                             void* part, void* coef, hipStream_t s);
 hipError_t launch_lock_apply(const LockCols& c, const void* coef, void* V, void* V32, size_t ld, size_t n,
