@@ -81,8 +81,19 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const double* __restr
     const int cl = threadIdx.x % CG, g = threadIdx.x / CG;
     const int c = blockIdx.x * CG + cl;
     double s = 0.0;
-    if (c < ncols)
-        for (int w = g; w < nparts; w += RG) s += in[(size_t)w * ncols + c];
+    if (c < ncols) {
+        // eight loads in flight ahead of their adds; the adds keep the order
+        // w = g, g + RG, ... so the sum does not depend on the batching
+        int w = g;
+        for (; w + 7 * RG < nparts; w += 8 * RG) {
+            double t[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) t[j] = in[(size_t)(w + j * RG) * ncols + c];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += t[j];
+        }
+        for (; w < nparts; w += RG) s += in[(size_t)w * ncols + c];
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = RG / 2; h > 0; h >>= 1) {

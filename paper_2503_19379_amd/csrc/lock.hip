@@ -27,54 +27,65 @@ __device__ __forceinline__ void lk_lds_barrier() {
 
 // part[w][l * nt + t] = sum over the rows of workgroup w of conj(X_l) Y_t.
 // Tiles of LK_TR rows pass through LDS; the next tile's loads are issued
-// before the current tile's products.
+// before the current tile's products.  Each load slot q reads one column
+// for the whole kernel (X_L slots first, then one Y slot), so its address is
+// set once before the tile loop and every load in the loop is unconditional:
+// no load waits for another.
+constexpr int LK_QX = (LK_TR * LK_MAXL + LK_NT - 1) / LK_NT;   // X_L slots per thread
+static_assert(LK_TR * LK_MAXT == LK_NT, "one Y slot per thread");
 __global__ __launch_bounds__(LK_NT) void lock_coef_kernel(LockCols c, const double2* __restrict__ V,
                                                           const float2* __restrict__ V32, size_t ld, size_t n,
                                                           size_t rows_per, double2* __restrict__ part) {
     __shared__ double2 xs[LK_TR][LK_MAXL];
     __shared__ double2 ys[LK_TR][LK_MAXT];
     const int tid = threadIdx.x;
-    const int nl = c.nl, nt = c.nt, ncol = nl + nt;
+    const int nl = c.nl, nt = c.nt;
     const size_t r0 = (size_t)blockIdx.x * rows_per;
     const size_t r1 = min(n, r0 + rows_per);
     const int p = tid, l = p / max(nt, 1), t = p % max(nt, 1);
     const bool mine = p < nl * nt;
     double2 acc = mk<double2>(0.0, 0.0);
-    constexpr int PE = (LK_TR * (LK_MAXL + LK_MAXT) + LK_NT - 1) / LK_NT;
-    // element e of a tile: row e % LK_TR of column e / LK_TR (X_L first, then
-    // Y); rows past the end are clamped when loaded and zeroed when stored
-    double2 v[PE];
-    auto load = [&](size_t s0) {
+    // slot q of X_L: element tid + q LK_NT = row r (its low bits) of column
+    // xcol[q] (clamped to the last column, stored only when in range); the
+    // Y slot: row r of column ycol
+    const int r = tid % LK_TR;
+    const double2* xp[LK_QX];
 #pragma unroll
-        for (int q = 0; q < PE; ++q) {
-            const int e = tid + q * LK_NT;
-            const int r = e % LK_TR, col = min(e / LK_TR, ncol - 1);
-            const size_t row = min(s0 + r, r1 - 1);
-            if (col < nl) {
-                v[q] = V[(size_t)c.xc[col] * ld + row];
-            } else if (c.y32) {
-                const float2 f = V32[(size_t)c.yc[col - nl] * ld + row];
-                v[q] = mk<double2>((double)f.x, (double)f.y);
-            } else {
-                v[q] = V[(size_t)c.yc[col - nl] * ld + row];
-            }
-        }
+    for (int q = 0; q < LK_QX; ++q) xp[q] = V + (size_t)c.xc[min((tid + q * LK_NT) / LK_TR, nl - 1)] * ld;
+    // Y is read as two 8-byte halves of an element of es bytes (an FP32
+    // element's second half is its first again), so that its load does not
+    // depend on the precision either
+    const int ycol = min(tid / LK_TR, nt - 1);
+    const bool y32 = c.y32 != 0;
+    const size_t es = y32 ? sizeof(float2) : sizeof(double2);
+    const char* yp = y32 ? (const char*)(V32 + (size_t)c.yc[ycol] * ld) : (const char*)(V + (size_t)c.yc[ycol] * ld);
+    double2 vx[LK_QX];
+    uint2 ylo = make_uint2(0u, 0u), yhi = make_uint2(0u, 0u);
+    auto load = [&](size_t s0) {
+        const size_t row = min(s0 + r, r1 - 1);
+#pragma unroll
+        for (int q = 0; q < LK_QX; ++q) vx[q] = xp[q][row];
+        const char* e = yp + row * es;
+        ylo = *(const uint2*)e;
+        yhi = *(const uint2*)(e + (es - sizeof(uint2)));
     };
     if (r0 < r1) load(r0);
     for (size_t s0 = r0; s0 < r1; s0 += LK_TR) {
+        const bool live = s0 + r < r1;
 #pragma unroll
-        for (int q = 0; q < PE; ++q) {
-            const int e = tid + q * LK_NT;
-            const int r = e % LK_TR, col = e / LK_TR;
-            if (col >= ncol) continue;
-            const double2 w = (s0 + r < r1) ? v[q] : mk<double2>(0.0, 0.0);
-            if (col < nl) xs[r][col] = w;
-            else ys[r][col - nl] = w;
+        for (int q = 0; q < LK_QX; ++q) {
+            const int col = (tid + q * LK_NT) / LK_TR;
+            if (col < nl) xs[r][col] = live ? vx[q] : mk<double2>(0.0, 0.0);
+        }
+        if (tid / LK_TR < nt) {
+            const double2 w = y32 ? mk<double2>((double)__uint_as_float(ylo.x), (double)__uint_as_float(ylo.y))
+                                  : mk<double2>(__hiloint2double(ylo.y, ylo.x), __hiloint2double(yhi.y, yhi.x));
+            ys[r][ycol] = live ? w : mk<double2>(0.0, 0.0);
         }
         lk_lds_barrier();
         if (s0 + LK_TR < r1) load(s0 + LK_TR);
         if (mine)
-            for (int r = 0; r < LK_TR; ++r) acc = cfmac(acc, xs[r][l], ys[r][t]);
+            for (int k = 0; k < LK_TR; ++k) acc = cfmac(acc, xs[k][l], ys[k][t]);
         lk_lds_barrier();
     }
     if (mine) part[(size_t)blockIdx.x * nl * nt + p] = acc;
@@ -132,8 +143,11 @@ __global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const d
                                                             double* __restrict__ npart) {
     constexpr int KP = (3 * NA + LK_CH - 1) / LK_CH * LK_CH;   // basis rows held: K <= 3 NA, whole chunks
     __shared__ double2 cs[KP * NA];   // C, rows past K and columns past na zero
-    __shared__ int col[2][KP];           // V or V32 column of basis column k (chain 0) and of its image
-    __shared__ unsigned char f32[KP];
+    // basis column k (chain 0) and its image (chain 1): the byte offset of its
+    // V or V32 column from V, and log2 of its element size (3 for FP32, 4 for
+    // FP64); every load goes through V, so it stays a global load
+    __shared__ long long boff[2][KP];
+    __shared__ int esh[KP];
     __shared__ double th[NA];
     __shared__ double red[LK_NT / 64][2 * NA];
     const int na = b.na, K = b.K, mb = b.mb;
@@ -143,9 +157,11 @@ __global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const d
     }
     if (threadIdx.x < KP) {
         const int k = min((int)threadIdx.x, K - 1);
-        col[0][threadIdx.x] = b.sc[k];
-        col[1][threadIdx.x] = b.ic[k];
-        f32[threadIdx.x] = (unsigned char)((b.f32 >> k) & 1ull);
+        const bool h = (b.f32 >> k) & 1ull;
+        const char* v0 = (const char*)V;
+        boff[0][threadIdx.x] = h ? (const char*)(V32 + (size_t)b.sc[k] * ld) - v0 : (const char*)(V + (size_t)b.sc[k] * ld) - v0;
+        boff[1][threadIdx.x] = h ? (const char*)(V32 + (size_t)b.ic[k] * ld) - v0 : (const char*)(V + (size_t)b.ic[k] * ld) - v0;
+        esh[threadIdx.x] = h ? 3 : 4;
     }
     if (threadIdx.x < NA) th[threadIdx.x] = threadIdx.x < (unsigned)na ? theta[threadIdx.x] : 0.0;
     __shared__ int band[NA];
@@ -164,17 +180,27 @@ __global__ __launch_bounds__(LK_NT) void lock_update_kernel(LockBasis b, const d
             for (int t = 0; t < NA; ++t) ax[t] = ap[t] = mk<double2>(0.0, 0.0);
 #pragma unroll 1
             for (int c0 = 0; c0 < nch * LK_CH; c0 += LK_CH) {
+                // every column read as two 8-byte halves (an FP32 element's
+                // second half is its first again): the chunk's loads do not
+                // depend on the precision and none waits for another
+                uint2 lo[LK_CH], hi[LK_CH];
+                bool h32[LK_CH];
+#pragma unroll
+                for (int q = 0; q < LK_CH; ++q) {
+                    const int k = c0 + q, sh = esh[k];
+                    const char* e = (const char*)V + boff[ch][k] + (row << sh);
+                    h32[q] = sh == 3;
+                    lo[q] = *(const uint2*)e;
+                    hi[q] = *(const uint2*)(e + ((sh - 3) << 3));
+                }
+                __builtin_amdgcn_sched_barrier(0);   // keep the chunk's loads ahead of its products
                 double2 sv[LK_CH];
 #pragma unroll
                 for (int q = 0; q < LK_CH; ++q) {
-                    const int k = c0 + q;
-                    const size_t o = (size_t)col[ch][k] * ld + row;
-                    if (f32[k]) {
-                        const float2 f = V32[o];
-                        sv[q] = mk<double2>((double)f.x, (double)f.y);
-                    } else {
-                        sv[q] = V[o];
-                    }
+                    const double fr = (double)__uint_as_float(lo[q].x), fi = (double)__uint_as_float(lo[q].y);
+                    const double dr = __hiloint2double(lo[q].y, lo[q].x), di = __hiloint2double(hi[q].y, hi[q].x);
+                    sv[q].x = h32[q] ? fr : dr;
+                    sv[q].y = h32[q] ? fi : di;
                 }
 #pragma unroll
                 for (int q = 0; q < LK_CH; ++q) {
@@ -245,7 +271,15 @@ __global__ __launch_bounds__(64) void lock_sum_kernel(const double* __restrict__
     if (c >= ncols) return;
     const int w1 = min(nparts, (g + 1) * LK_GS);
     double v = 0.0;
-    for (int w = g * LK_GS; w < w1; ++w) v += in[(size_t)w * ncols + c];
+    int w = g * LK_GS;
+    for (; w + 8 <= w1; w += 8) {   // eight loads in flight, added in order
+        double t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] = in[(size_t)(w + j) * ncols + c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v += t[j];
+    }
+    for (; w < w1; ++w) v += in[(size_t)w * ncols + c];
     tmp[(size_t)g * ncols + c] = v;
 }
 
@@ -280,7 +314,8 @@ hipError_t launch_lock_apply(const LockCols& c, const void* coef, void* V, void*
 hipError_t launch_lock_update(const LockBasis& b, const void* V, const void* V32, void* U, void* U32, size_t ld,
                               size_t n, const void* C, const double* theta, int nblocks, double* npart, double* norms,
                               hipStream_t s) {
-    if (b.na < 1 || b.na > LK_NA || b.K < b.na || b.K > LK_MAXK || nblocks < 1 || !n) return hipErrorInvalidValue;
+    // the kernel holds K <= 3 na basis columns ([X_A W_A P_A])
+    if (b.na < 1 || b.na > LK_NA || b.K < b.na || b.K > 3 * b.na || nblocks < 1 || !n) return hipErrorInvalidValue;
     if ((V32 == nullptr) != (U32 == nullptr)) return hipErrorInvalidValue;
     // a basis of K <= 3 na columns: the 4-output instance when na <= 4
     auto kern = b.na <= 4 ? lock_update_kernel<4> : lock_update_kernel<LK_NA>;
