@@ -381,3 +381,23 @@ def test_hard_lock_matches_soft(B, precision):
     assert np.allclose(e0, e1, rtol=rt, atol=1e-9)
     lam, _, _ = olob.solve_bands(eps, 1.0, kp[6], m, tol=1e-10)
     assert np.allclose(e1[6], lam, rtol=rt), (e1[6], lam)
+
+
+@pytest.mark.parametrize("hard", [0, 1])
+def test_repeated_solves_bit_identical(B, hard):
+    """With the launch shapes fixed (autotune off), the same band solve on
+    concurrent segments gives the same iteration counts and the same
+    eigenvalue bits when repeated: every sum runs in a fixed order and no
+    segment reads another's buffers (diamond N = 16, 10 bands + 2 guard,
+    10 k-points on 3 segments, mixed precision)."""
+    N, m = 16, 10
+    ctx = B.mfd_build(N, 1.0, 2, workloads.eps_diamond(N))
+    kp = workloads.kpath("GXMGR", 10)
+    o = B.default_opts(precision=1, streams=3, guard=2, cold_start=1, hard_lock=hard, autotune=0)
+    runs = [B.mfd_bands(ctx, kp, m, 1e-8, o) for _ in range(3)]
+    for ev, st, status in runs:
+        assert status == 0
+    its0 = [s["iters"] for s in runs[0][1]]
+    for ev, st, _ in runs[1:]:
+        assert [s["iters"] for s in st] == its0
+        assert np.array_equal(ev, runs[0][0])
